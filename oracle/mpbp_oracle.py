@@ -1,0 +1,335 @@
+"""Plain FP64 CPU oracle of the multi-peak Bragg ptychography objective and gradient.
+
+TEST INFRASTRUCTURE.  This module is the slow, obviously correct reference that the GPU
+library is checked against.  Only the test suite, the package smoke check and the
+benchmark's CPU-baseline leg may import it; the product path never does.  It shares no
+code with the GPU library: it computes its own index tables, in numpy float64 /
+complex128, with plain loops over peaks, frames and z-slices.
+
+What it computes (Kandel et al., "Imaging extended single crystal lattice distortion
+fields with multi-peak Bragg ptychography"):
+
+* eq. (1) and eq. (3): the per-peak object O_m = alpha_m * chi * exp(i G_m . u), with
+  G_m in rad/nm (the paper's 2*pi folded into G) and alpha given for every peak;
+* eq. (2): intensity I_{m,j} = |F R_m diag(P_m) S_{m,j} O_m|^2 with background b = 0.
+  S_{m,j} selects the probe window of scan position j (section 4: raster scan), the
+  probe is constant along the incident beam x3 (section 4), and R_m projects the
+  illuminated slices along the exit beam: slice z lands s_m(z) pixels over, an integer
+  lateral shear, inside a D_m x D_m window centred on the probe support.  F is the
+  orthonormal 2D DFT with kernel exp(-2 pi i k.x / D), DC at index 0;
+* eq. (4): f = 1/2 sum_{m,j} || I^{1/2} - y^{1/2} ||^2, summed (not averaged) over the
+  listed frames as in the minibatch sums of eq. (11);
+* the gradient of f with respect to u (3 components), chi and alpha: the exact adjoint of
+  the chain above (the paper obtains it by automatic differentiation).
+
+Complex gradients use the convention g = df/dRe + i df/dIm.
+"""
+import math
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------------
+# Index tables (the shift operator S and the exit-beam projection R of eq. (2)).
+# ---------------------------------------------------------------------------------
+
+def round_half_away(v):
+    """Round a double to the nearest integer, halves away from zero.
+
+    Written with floor and an exact fractional part so that 0.49999999999999994 rounds
+    to 0 (floor(v + 0.5) would give 1).
+    """
+    a = abs(float(v))
+    f = math.floor(a)
+    r = f + (1 if (a - f) >= 0.5 else 0)
+    return int(-r if v < 0 else r)
+
+
+def window_offset(det, probe_n):
+    """Top-left of the probe support inside the D x D exit-wave window (centred)."""
+    return (det - probe_n) // 2
+
+
+def shear_table(nz, shear):
+    """s_m(z) = (rha((z - nz//2) * t_y), rha((z - nz//2) * t_x)) for z = 0..nz-1."""
+    zref = nz // 2
+    out = np.zeros((nz, 2), dtype=np.int64)
+    for z in range(nz):
+        dz = float(z - zref)
+        out[z, 0] = round_half_away(dz * float(shear[0]))
+        out[z, 1] = round_half_away(dz * float(shear[1]))
+    return out
+
+
+def scan_positions(scan_n, scan_step, scan_origin):
+    """Top-left object voxel (py, px) of the probe support for each raster frame."""
+    rows, cols = int(scan_n[0]), int(scan_n[1])
+    out = np.zeros((rows * cols, 2), dtype=np.int64)
+    for iy in range(rows):
+        for ix in range(cols):
+            out[iy * cols + ix, 0] = int(scan_origin[0]) + iy * int(scan_step[0])
+            out[iy * cols + ix, 1] = int(scan_origin[1]) + ix * int(scan_step[1])
+    return out
+
+
+class FootprintError(ValueError):
+    """The sheared probe support of some slice leaves the detector window."""
+
+
+def tables(problem):
+    """All integer tables of a workload.
+
+    Returns dict with
+      scan   [F][2] int: (py, px) per global frame (peaks concatenated, raster order)
+      shear  [M][nz][2] int: s_m(z)
+      y_off  [M+1] int: element offset of peak m's intensities in the ragged y array
+      peak_of_frame [F] int, local_index [F] int
+      offset [M] int: window offset c_m
+    Raises FootprintError when a sheared support leaves its window.
+    """
+    m_count = problem.n_peaks
+    scans, peak_of, local = [], [], []
+    shear = np.zeros((m_count, problem.nz, 2), dtype=np.int64)
+    y_off = np.zeros(m_count + 1, dtype=np.int64)
+    offs = np.zeros(m_count, dtype=np.int64)
+    for m in range(m_count):
+        det = int(problem.det[m])
+        c = window_offset(det, problem.probe_n)
+        if c < 0:
+            raise FootprintError(f"peak {m}: probe support {problem.probe_n} > window {det}")
+        offs[m] = c
+        shear[m] = shear_table(problem.nz, problem.shear[m])
+        lo = shear[m].min(axis=0)
+        hi = shear[m].max(axis=0)
+        if (c + lo < 0).any() or (c + problem.probe_n - 1 + hi > det - 1).any():
+            raise FootprintError(f"peak {m}: sheared support leaves the {det}x{det} window")
+        pos = scan_positions(problem.scan_n[m], problem.scan_step[m], problem.scan_origin[m])
+        scans.append(pos)
+        peak_of.append(np.full(len(pos), m, dtype=np.int64))
+        local.append(np.arange(len(pos), dtype=np.int64))
+        y_off[m + 1] = y_off[m] + len(pos) * det * det
+    return {
+        "scan": np.concatenate(scans),
+        "shear": shear,
+        "y_off": y_off,
+        "peak_of_frame": np.concatenate(peak_of),
+        "local_index": np.concatenate(local),
+        "offset": offs,
+    }
+
+
+# ---------------------------------------------------------------------------------
+# Forward model, eq. (1)-(3) and eq. (2).
+# ---------------------------------------------------------------------------------
+
+def phases(u, g):
+    """phi_m = G_m . u for every voxel, u of shape [3][nz][ny][nx]."""
+    return g[0] * u[0] + g[1] * u[1] + g[2] * u[2]
+
+
+def objects(u, chi, alpha, problem):
+    """O_m = alpha_m * chi * exp(i G_m . u), complex128 [M][nz][ny][nx] (eq. (3))."""
+    u = np.asarray(u, dtype=np.float64)
+    chi = np.asarray(chi, dtype=np.float64)
+    out = np.empty((problem.n_peaks,) + chi.shape, dtype=np.complex128)
+    for m in range(problem.n_peaks):
+        out[m] = float(alpha[m]) * chi * np.exp(1j * phases(u, problem.g[m]))
+    return out
+
+
+def _support_block(p0, n, size):
+    """Valid probe rows [a0, a1) of a support of n starting at object row p0."""
+    a0 = max(0, -p0)
+    a1 = min(n, size - p0)
+    return a0, max(a0, a1)
+
+
+def exit_wave(o_m, probe_m, py, px, shear_m, det):
+    """R diag(P) S O for one frame: the D x D exit wave.
+
+    For every slice z and probe pixel (a, b) with an in-grid object voxel,
+      psi[a + c + s_y(z), b + c + s_x(z)] += P[a, b] * O[z, py + a, px + b].
+    """
+    nz, ny, nx = o_m.shape
+    n = probe_m.shape[0]
+    c = window_offset(det, n)
+    psi = np.zeros((det, det), dtype=np.complex128)
+    a0, a1 = _support_block(py, n, ny)
+    b0, b1 = _support_block(px, n, nx)
+    if a1 <= a0 or b1 <= b0:
+        return psi
+    for z in range(nz):
+        sy, sx = int(shear_m[z, 0]), int(shear_m[z, 1])
+        psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1] += (
+            probe_m[a0:a1, b0:b1] * o_m[z, py + a0:py + a1, px + b0:px + b1])
+    return psi
+
+
+def back_project(g_psi, probe_m, py, px, shear_m, g_o_m):
+    """Adjoint of exit_wave, accumulated into g_o_m in place:
+      g_O[z, py + a, px + b] += conj(P[a, b]) * g_psi[a + c + s_y(z), b + c + s_x(z)].
+    """
+    nz, ny, nx = g_o_m.shape
+    n = probe_m.shape[0]
+    det = g_psi.shape[0]
+    c = window_offset(det, n)
+    a0, a1 = _support_block(py, n, ny)
+    b0, b1 = _support_block(px, n, nx)
+    if a1 <= a0 or b1 <= b0:
+        return
+    pc = np.conj(probe_m[a0:a1, b0:b1])
+    for z in range(nz):
+        sy, sx = int(shear_m[z, 0]), int(shear_m[z, 1])
+        g_o_m[z, py + a0:py + a1, px + b0:px + b1] += (
+            pc * g_psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1])
+
+
+def far_field(psi):
+    """F psi: orthonormal 2D DFT, kernel exp(-2 pi i k.x / D), DC at [0, 0]."""
+    return np.fft.fft2(psi, norm="ortho")
+
+
+def far_field_adjoint(g):
+    """F^H g (the inverse orthonormal DFT)."""
+    return np.fft.ifft2(g, norm="ortho")
+
+
+def amplitude_residual(psi_ff, y):
+    """Per-frame term of eq. (4) and its gradient with respect to the far field.
+
+    Returns (f_frame, R) with f_frame = 1/2 sum (|Psi| - sqrt(y))^2 and
+    R = (|Psi| - sqrt(y)) * Psi / |Psi| (0 where |Psi| = 0).
+    """
+    a = np.abs(psi_ff)
+    r = a - np.sqrt(np.asarray(y, dtype=np.float64))
+    f = 0.5 * float(np.sum(r * r))
+    safe = np.where(a > 0.0, a, 1.0)
+    grad = np.where(a > 0.0, r * psi_ff / safe, 0.0)
+    return f, grad
+
+
+# ---------------------------------------------------------------------------------
+# Whole objective and gradient.
+# ---------------------------------------------------------------------------------
+
+def _frame_list(problem, frames):
+    if frames is None:
+        return list(range(problem.n_frames()))
+    frames = [int(f) for f in frames]
+    if len(set(frames)) != len(frames):
+        raise ValueError("duplicate frame ids")
+    for f in frames:
+        if not 0 <= f < problem.n_frames():
+            raise ValueError(f"frame id {f} out of range")
+    return frames
+
+
+def frame_data(y, tab, problem, fid):
+    """The D x D intensities of global frame `fid` from the ragged y array."""
+    m = int(tab["peak_of_frame"][fid])
+    j = int(tab["local_index"][fid])
+    det = int(problem.det[m])
+    start = int(tab["y_off"][m]) + j * det * det
+    return np.asarray(y[start:start + det * det], dtype=np.float64).reshape(det, det)
+
+
+def model_intensity(u, chi, alpha, probe, problem, frames=None):
+    """I_{m,j} of eq. (2) (b = 0) for the listed frames: list of D x D float64 arrays."""
+    tab = tables(problem)
+    obj = objects(u, chi, alpha, problem)
+    probe = np.asarray(probe, dtype=np.complex128)
+    out = []
+    for fid in _frame_list(problem, frames):
+        m = int(tab["peak_of_frame"][fid])
+        py, px = (int(v) for v in tab["scan"][fid])
+        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]))
+        out.append(np.abs(far_field(psi)) ** 2)
+    return out
+
+
+def loss(u, chi, alpha, probe, y, problem, frames=None):
+    """f of eq. (4) over the listed frames (all when None).
+
+    Returns (f, per_frame) with per_frame the list of per-frame terms.
+    """
+    tab = tables(problem)
+    obj = objects(u, chi, alpha, problem)
+    probe = np.asarray(probe, dtype=np.complex128)
+    per = []
+    for fid in _frame_list(problem, frames):
+        m = int(tab["peak_of_frame"][fid])
+        py, px = (int(v) for v in tab["scan"][fid])
+        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]))
+        f, _ = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid))
+        per.append(f)
+    return float(sum(per)), per
+
+
+def object_gradient(u, chi, alpha, probe, y, problem, frames=None):
+    """f and g_O,m = df/dO_m (complex, [M][nz][ny][nx]) summed over the listed frames."""
+    tab = tables(problem)
+    obj = objects(u, chi, alpha, problem)
+    probe = np.asarray(probe, dtype=np.complex128)
+    g_obj = np.zeros_like(obj)
+    per = []
+    for fid in _frame_list(problem, frames):
+        m = int(tab["peak_of_frame"][fid])
+        py, px = (int(v) for v in tab["scan"][fid])
+        det = int(problem.det[m])
+        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], det)
+        f, grad_ff = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid))
+        per.append(f)
+        back_project(far_field_adjoint(grad_ff), probe[m], py, px, tab["shear"][m], g_obj[m])
+    return float(sum(per)), per, g_obj, obj
+
+
+def loss_grad(u, chi, alpha, probe, y, problem, frames=None):
+    """f and its gradient with respect to u, chi and alpha.
+
+    Chain rule through O_m = alpha_m chi exp(i phi_m), phi_m = G_m . u:
+      df/dphi_m   = Im(g_O,m * conj(O_m))
+      df/du_c     = sum_m G_m,c * df/dphi_m
+      df/dchi     = sum_m Re(conj(g_O,m) * alpha_m * exp(i phi_m))
+      df/dalpha_m = sum_voxels Re(conj(g_O,m) * chi * exp(i phi_m))
+    Returns dict(loss, frame_loss, grad_u [3][nz][ny][nx], grad_chi, grad_alpha [M]).
+    """
+    f, per, g_obj, obj = object_gradient(u, chi, alpha, probe, y, problem, frames)
+    u = np.asarray(u, dtype=np.float64)
+    chi = np.asarray(chi, dtype=np.float64)
+    grad_u = np.zeros(u.shape)
+    grad_chi = np.zeros(chi.shape)
+    grad_alpha = np.zeros(problem.n_peaks)
+    for m in range(problem.n_peaks):
+        e = np.exp(1j * phases(u, problem.g[m]))
+        dphi = np.imag(g_obj[m] * np.conj(obj[m]))
+        for c in range(3):
+            grad_u[c] += problem.g[m][c] * dphi
+        grad_chi += np.real(np.conj(g_obj[m]) * float(alpha[m]) * e)
+        grad_alpha[m] = float(np.sum(np.real(np.conj(g_obj[m]) * chi * e)))
+    return {
+        "loss": f,
+        "frame_loss": np.asarray(per),
+        "grad_u": grad_u,
+        "grad_chi": grad_chi,
+        "grad_alpha": grad_alpha,
+    }
+
+
+def loss_grad_ztied(u2, chi2, alpha, probe, y, problem, frames=None):
+    """The membrane parameterisation of section 3 (unknowns per lateral pixel, constant
+    along x3): u2 [3][1][ny][nx], chi2 [1][ny][nx] broadcast over z; gradients are the
+    z-sums of the per-voxel gradients."""
+    nz = problem.nz
+    u = np.broadcast_to(np.asarray(u2, dtype=np.float64), (3, nz) + tuple(np.shape(u2)[2:]))
+    chi = np.broadcast_to(np.asarray(chi2, dtype=np.float64), (nz,) + tuple(np.shape(chi2)[1:]))
+    r = loss_grad(u, chi, alpha, probe, y, problem, frames)
+    r["grad_u"] = r["grad_u"].sum(axis=1, keepdims=True)
+    r["grad_chi"] = r["grad_chi"].sum(axis=0, keepdims=True)
+    return r
+
+
+def step(params, grads, eta):
+    """Plain gradient step p <- p - eta * g for (u, chi, alpha) with eta = (eta_u,
+    eta_chi, eta_alpha)."""
+    return tuple(np.asarray(p, dtype=np.float64) - float(e) * np.asarray(g, dtype=np.float64)
+                 for p, g, e in zip(params, grads, eta))
