@@ -1,0 +1,159 @@
+/*
+ * mpbp.h - C-ABI of the MI355X (gfx950) library for the multi-peak Bragg ptychography
+ * (MPBP) objective and its gradient.
+ *
+ * The operation (Kandel et al., "Imaging extended single crystal lattice distortion
+ * fields with multi-peak Bragg ptychography", sections 2-3):
+ *
+ *   eq. (1), eq. (3)  O_m(r)  = alpha_m * chi(r) * exp(i G_m . u(r))   (G_m in rad/nm)
+ *   eq. (2)           I_{m,j} = | F R_m diag(P_m) S_{m,j} O_m |^2       (background b = 0)
+ *   eq. (4)           f       = 1/2 sum_{m,j} || I_{m,j}^{1/2} - y_{m,j}^{1/2} ||^2
+ *   eq. (11)          minibatch: f and its gradient summed over a subset of the frames
+ *
+ * S_{m,j} places the probe support (probe_n x probe_n) at scan position j of peak m's
+ * raster.  The probe is constant along the incident beam x3 (section 4).  R_m projects
+ * the illuminated object along the exit beam: slice z is offset laterally by the
+ * integer shear s_m(z) = round_half_away((z - nz/2) * t_m), inside a D_m x D_m
+ * exit-wave window whose probe support starts at c_m = (D_m - probe_n) / 2.  F is the
+ * orthonormal 2D DFT, kernel exp(-2 pi i k.x / D), DC at index [0][0] (no shift); the
+ * measured intensities y use the same unshifted layout.
+ *
+ * Layouts (all row-major, x fastest; "(dev)" = device memory of the plan's GPU,
+ * "(host)" = host memory).  The caller owns every buffer it passes.
+ *   u       (dev) float [3][nz][ny][nx]       displacement components (x, y, z), nm
+ *   chi     (dev) float [nz][ny][nx]          amplitude chi >= 0
+ *   alpha   (dev) float [n_peaks]             per-peak scale alpha_m > 0
+ *   probe   (dev) complex64 [n_peaks][probe_n][probe_n], interleaved (re, im) floats
+ *   y       (dev) float, ragged: peaks concatenated, peak m holds
+ *                 [frames_m][D_m][D_m]; offsets from mpbp_tables (y_off)
+ *   frames  (host) int32 [n_frames]: global frame ids (peak-major, raster order within
+ *                 a peak: id = y_off-order index), no duplicates; NULL = all frames
+ * Gradients are written (not accumulated) in the layouts of u, chi and alpha.
+ *
+ * Calls on one plan must be serialised by the caller; work is enqueued on `stream`
+ * (a hipStream_t; NULL = the default stream) and returns without waiting, except
+ * where stated.  Every argument is validated on the host before anything is enqueued,
+ * so a call that returns an error has done no work.  No C++ exception crosses this
+ * interface.  mpbp_last_error() describes the last failure of the calling thread.
+ */
+#ifndef MPBP_H
+#define MPBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpbp_plan_t* mpbp_plan;
+
+typedef enum {
+  MPBP_OK = 0,
+  MPBP_ERR_INVALID = 1,      /* null pointer, bad option, bad or duplicate frame id     */
+  MPBP_ERR_SHAPE = 2,        /* a size is out of range                                  */
+  MPBP_ERR_FOOTPRINT = 3,    /* a sheared probe support leaves its detector window      */
+  MPBP_ERR_DEVICE = 4,       /* HIP failure, or a compute call on a host-only plan      */
+  MPBP_ERR_NOMEM = 5,        /* device or host allocation failed                        */
+  MPBP_ERR_UNSUPPORTED = 6   /* valid but outside what the kernels implement            */
+} mpbp_status;
+
+/* One Bragg peak m (sections 2-3; eq. (2) operators S and R). */
+typedef struct {
+  double  g[3];              /* G_m in rad/nm, lab frame (x1, x2, x3); phase = G_m . u     */
+  double  shear[2];          /* t_m = (t_y, t_x): exit-beam lateral offset per slice, voxels*/
+  int32_t det;               /* D_m: detector / exit-wave window size (square)             */
+  int32_t scan_n[2];         /* raster (rows, cols); local frame j = row * cols + col      */
+  int32_t scan_step[2];      /* raster step (rows, cols), voxels                           */
+  int32_t scan_origin[2];    /* object voxel of the probe support's top-left, frame 0     */
+} mpbp_peak;
+
+typedef struct {
+  int32_t nz, ny, nx;        /* object grid                                                */
+  int32_t probe_n;           /* probe support (square)                                     */
+  int32_t n_peaks;
+  const mpbp_peak* peaks;    /* (host) [n_peaks]; copied by mpbp_plan_create               */
+  uint32_t flags;            /* reserved, must be 0                                        */
+} mpbp_problem;
+
+/* Options of mpbp_set_option / mpbp_get_option. */
+enum {
+  MPBP_OPT_PATH = 1,         /* 0 = batched fused path (default), 1 = plain path: one
+                                launch per stage per peak and scan position              */
+  MPBP_OPT_GRAPH = 2,        /* 1 = replay full-batch calls from a captured hipGraph
+                                (default 1), 0 = direct launches                          */
+  MPBP_OPT_XCD_ORDER = 3     /* 1 = hand each XCD a contiguous band of frames (default) */
+};
+
+/* Validate `problem`, build the integer tables (scan offsets, shear offsets, ragged y
+   offsets) and, for device >= 0, allocate the plan's device workspace on that GPU.
+   device = -1 makes a host-only plan: tables and validation only; compute calls then
+   return MPBP_ERR_DEVICE.  Errors: MPBP_ERR_INVALID (null pointers, flags),
+   MPBP_ERR_SHAPE (non-positive sizes, D outside the supported set), MPBP_ERR_FOOTPRINT,
+   MPBP_ERR_DEVICE, MPBP_ERR_NOMEM.  On success *out owns the plan. */
+mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan* out);
+
+/* Release the plan and its device workspace (waits for the plan's work to finish).
+   NULL is ignored. */
+void mpbp_plan_destroy(mpbp_plan plan);
+
+/* Number of frames (sum over peaks of rows * cols); -1 for a NULL plan. */
+int64_t mpbp_num_frames(mpbp_plan plan);
+
+/* Length in floats of the ragged intensity array y; -1 for a NULL plan. */
+int64_t mpbp_intensity_size(mpbp_plan plan);
+
+/* Copy the plan's integer tables to host memory (each pointer may be NULL):
+     scan_yx  (host) int32 [n_frames][2]       (py, px) of each global frame
+     shear_yx (host) int32 [n_peaks][nz][2]    s_m(z) = (s_y, s_x)
+     y_off    (host) int64 [n_peaks + 1]       element offset of peak m in y
+   These are the shift operator S and projection R of eq. (2) in integer form.
+   Synchronous, host-only. */
+mpbp_status mpbp_tables(mpbp_plan plan, int32_t* scan_yx, int32_t* shear_yx, int64_t* y_off);
+
+/* Forward model and objective, eq. (2) and eq. (4), over the listed frames.
+     loss            (dev) double scalar: f summed over the frames, or NULL
+     frame_loss      (dev) float [n_frames] per-frame terms in list order, or NULL
+     model_intensity (dev) float, ragged like y: I_{m,j} of the listed frames is written
+                     (other frames untouched), or NULL
+   y may be NULL only when loss and frame_loss are both NULL.
+   n_frames is ignored when frames is NULL. */
+mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi,
+                         const float* alpha, const void* probe, const float* y,
+                         const int32_t* frames, int64_t n_frames,
+                         double* loss, float* frame_loss, float* model_intensity,
+                         void* stream);
+
+/* Objective and its gradient (the adjoint of eq. (2)-(4)) over the listed frames:
+     df/du_c     = sum_m G_m,c Im(g_O,m conj(O_m))
+     df/dchi     = sum_m Re(conj(g_O,m) alpha_m exp(i G_m . u))
+     df/dalpha_m = sum_voxels Re(conj(g_O,m) chi exp(i G_m . u))
+   with g_O,m = df/dO_m.  loss (dev double) and frame_loss (dev float [n_frames]) may be
+   NULL; grad_u (dev float [3][nz][ny][nx]), grad_chi (dev float [nz][ny][nx]) and
+   grad_alpha (dev float [n_peaks]) are required and overwritten. */
+mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi,
+                           const float* alpha, const void* probe, const float* y,
+                           const int32_t* frames, int64_t n_frames,
+                           double* loss, float* frame_loss,
+                           float* grad_u, float* grad_chi, float* grad_alpha,
+                           void* stream);
+
+/* Plain gradient step in place, p <- p - eta_p * g_p, for (u, chi, alpha) with
+   eta = (eta_u, eta_chi, eta_alpha) (host float[3]); the update of Algorithm 1 without
+   Adam's moments.  All six device pointers are required. */
+mpbp_status mpbp_step(mpbp_plan plan, float* u, float* chi, float* alpha,
+                      const float* grad_u, const float* grad_chi, const float* grad_alpha,
+                      const float* eta, void* stream);
+
+/* Set / read a plan option (MPBP_OPT_*).  MPBP_ERR_INVALID for an unknown option or
+   value. */
+mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value);
+mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char* mpbp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPBP_H */

@@ -1,0 +1,191 @@
+"""ctypes binding of libmpbp.so (include/mpbp.h).
+
+Argument marshalling only: every computation runs in the library's HIP kernels.  Device
+buffers are torch CUDA tensors (PyTorch provides device memory and streams); the
+functions keep the C names.  A missing library raises at import: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmpbp.so")
+
+MPBP_OK = 0
+STATUS_NAMES = {0: "MPBP_OK", 1: "MPBP_ERR_INVALID", 2: "MPBP_ERR_SHAPE", 3: "MPBP_ERR_FOOTPRINT",
+                4: "MPBP_ERR_DEVICE", 5: "MPBP_ERR_NOMEM", 6: "MPBP_ERR_UNSUPPORTED"}
+MPBP_OPT_PATH = 1
+MPBP_OPT_GRAPH = 2
+MPBP_OPT_XCD_ORDER = 3
+
+EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
+            "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",
+            "mpbp_get_option", "mpbp_last_error")
+
+
+class mpbp_peak(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double * 3), ("shear", ctypes.c_double * 2), ("det", ctypes.c_int32),
+                ("scan_n", ctypes.c_int32 * 2), ("scan_step", ctypes.c_int32 * 2),
+                ("scan_origin", ctypes.c_int32 * 2)]
+
+
+class mpbp_problem(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("ny", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("probe_n", ctypes.c_int32), ("n_peaks", ctypes.c_int32),
+                ("peaks", ctypes.POINTER(mpbp_peak)), ("flags", ctypes.c_uint32)]
+
+
+class MPBPError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2312_14907_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32p, st = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int
+    lib.mpbp_plan_create.argtypes = [ctypes.POINTER(mpbp_problem), ctypes.c_int, ctypes.POINTER(vp)]
+    lib.mpbp_plan_create.restype = st
+    lib.mpbp_plan_destroy.argtypes = [vp]
+    lib.mpbp_plan_destroy.restype = None
+    lib.mpbp_num_frames.argtypes = [vp]
+    lib.mpbp_num_frames.restype = i64
+    lib.mpbp_intensity_size.argtypes = [vp]
+    lib.mpbp_intensity_size.restype = i64
+    lib.mpbp_tables.argtypes = [vp, vp, vp, vp]
+    lib.mpbp_tables.restype = st
+    lib.mpbp_forward.argtypes = [vp, vp, vp, vp, vp, vp, i32p, i64, vp, vp, vp, vp]
+    lib.mpbp_forward.restype = st
+    lib.mpbp_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, i32p, i64, vp, vp, vp, vp, vp, vp]
+    lib.mpbp_loss_grad.restype = st
+    lib.mpbp_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_float), vp]
+    lib.mpbp_step.restype = st
+    lib.mpbp_set_option.argtypes = [vp, ctypes.c_int, i64]
+    lib.mpbp_set_option.restype = st
+    lib.mpbp_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
+    lib.mpbp_get_option.restype = st
+    lib.mpbp_last_error.argtypes = []
+    lib.mpbp_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def mpbp_last_error():
+    return lib.mpbp_last_error().decode()
+
+
+def _check(status):
+    if status != MPBP_OK:
+        raise MPBPError(status, mpbp_last_error())
+
+
+def _ptr(t):
+    """Device (or host) address of a tensor / array, or None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_problem_struct(problem):
+    """mpbp_problem for a geometry object with attributes nz, ny, nx, probe_n, g, shear,
+    det, scan_n, scan_step, scan_origin (as built by synth.make_problem)."""
+    m = int(np.asarray(problem.g).shape[0])
+    peaks = (mpbp_peak * m)()
+    for k in range(m):
+        pk = peaks[k]
+        for c in range(3):
+            pk.g[c] = float(problem.g[k][c])
+        for c in range(2):
+            pk.shear[c] = float(problem.shear[k][c])
+            pk.scan_n[c] = int(problem.scan_n[k][c])
+            pk.scan_step[c] = int(problem.scan_step[k][c])
+            pk.scan_origin[c] = int(problem.scan_origin[k][c])
+        pk.det = int(problem.det[k])
+    prob = mpbp_problem(int(problem.nz), int(problem.ny), int(problem.nx), int(problem.probe_n), m,
+                        ctypes.cast(peaks, ctypes.POINTER(mpbp_peak)), 0)
+    prob._peaks_keepalive = peaks
+    return prob
+
+
+class Plan:
+    """A library plan (mpbp_plan) for one workload geometry on one device (-1: host only)."""
+
+    def __init__(self, problem, device=0):
+        self._struct = make_problem_struct(problem)
+        h = ctypes.c_void_p()
+        _check(lib.mpbp_plan_create(ctypes.byref(self._struct), int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+        self.nz, self.ny, self.nx = int(problem.nz), int(problem.ny), int(problem.nx)
+        self.probe_n = int(problem.probe_n)
+        self.n_peaks = int(np.asarray(problem.g).shape[0])
+        self.n_frames = int(lib.mpbp_num_frames(h))
+        self.intensity_size = int(lib.mpbp_intensity_size(h))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.mpbp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mpbp_tables(self):
+        scan = np.zeros((self.n_frames, 2), dtype=np.int32)
+        shear = np.zeros((self.n_peaks, self.nz, 2), dtype=np.int32)
+        y_off = np.zeros(self.n_peaks + 1, dtype=np.int64)
+        _check(lib.mpbp_tables(self.handle, scan.ctypes.data, shear.ctypes.data, y_off.ctypes.data))
+        return scan, shear, y_off
+
+    @staticmethod
+    def _frames(frames):
+        if frames is None:
+            return None, 0, None
+        arr = np.ascontiguousarray(np.asarray(frames, dtype=np.int32))
+        return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(arr.size), arr
+
+    def mpbp_forward(self, u, chi, alpha, probe, y=None, frames=None, loss=None, frame_loss=None,
+                     model_intensity=None, stream=None):
+        fp, n, keep = self._frames(frames)
+        _check(lib.mpbp_forward(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(probe), _ptr(y),
+                                fp, n, _ptr(loss), _ptr(frame_loss), _ptr(model_intensity),
+                                _stream(stream)))
+        del keep
+
+    def mpbp_loss_grad(self, u, chi, alpha, probe, y, grad_u, grad_chi, grad_alpha, frames=None,
+                       loss=None, frame_loss=None, stream=None):
+        fp, n, keep = self._frames(frames)
+        _check(lib.mpbp_loss_grad(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(probe), _ptr(y),
+                                  fp, n, _ptr(loss), _ptr(frame_loss), _ptr(grad_u), _ptr(grad_chi),
+                                  _ptr(grad_alpha), _stream(stream)))
+        del keep
+
+    def mpbp_step(self, u, chi, alpha, grad_u, grad_chi, grad_alpha, eta, stream=None):
+        e = (ctypes.c_float * 3)(*[float(v) for v in eta])
+        _check(lib.mpbp_step(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(grad_u),
+                             _ptr(grad_chi), _ptr(grad_alpha), e, _stream(stream)))
+
+    def mpbp_set_option(self, option, value):
+        _check(lib.mpbp_set_option(self.handle, int(option), int(value)))
+
+    def mpbp_get_option(self, option):
+        v = ctypes.c_int64()
+        _check(lib.mpbp_get_option(self.handle, int(option), ctypes.byref(v)))
+        return int(v.value)

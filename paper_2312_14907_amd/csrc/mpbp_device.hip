@@ -1,0 +1,608 @@
+// mpbp_device.hip - HIP kernels (gfx950) of the MPBP objective-and-gradient path.
+//
+//   k_object   eq. (1)/(3): O_m = alpha_m chi exp(i G_m . u) for every voxel and peak
+//   k_frames   one workgroup per frame (m, j): eq. (2) forward model, eq. (4) residual,
+//              and the adjoint back to the exit-wave footprint
+//   k_grad     gather back-projection of the footprint gradients over all frames that
+//              cover a voxel tile, then the chain rule to df/du, df/dchi, df/dalpha
+//   k_finalize deterministic FP64 sums of the per-frame losses and alpha partials
+//   k_step     p <- p - eta g
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mpbp_dft.hpp"
+#include "mpbp_kernels.hpp"
+#include "mpbp_launch.hpp"
+
+namespace mpbp {
+
+// ------------------------------------------------------------------ object build ---
+__global__ __launch_bounds__(256) void k_object(const float* __restrict__ u,
+                                                const float* __restrict__ chi,
+                                                const float* __restrict__ alpha,
+                                                const PeakDev* __restrict__ peaks, int n_peaks,
+                                                long long nvox, float* __restrict__ obj) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvox) return;
+  float ux = u[v], uy = u[nvox + v], uz = u[2 * nvox + v];
+  float ch = chi[v];
+  for (int m = 0; m < n_peaks; ++m) {
+    float phi = peaks[m].gx * ux + peaks[m].gy * uy + peaks[m].gz * uz;
+    float s, c;
+    sincosf(phi, &s, &c);
+    float a = alpha[m] * ch;
+    float2* o = reinterpret_cast<float2*>(obj) + (long long)m * nvox + v;
+    *o = make_float2(a * c, a * s);
+  }
+}
+
+// ------------------------------------------------------------------- frame kernel ---
+template <int D> struct ColLen { static constexpr int L = 64; };
+template <> struct ColLen<32> { static constexpr int L = 32; };
+template <> struct ColLen<96> { static constexpr int L = 96; };
+
+__device__ __forceinline__ int frame_block_index(int b, int n, int xcd) {
+  if (!xcd) return b;
+  // Blocks are dispatched round-robin over the 8 XCDs: give XCD k the contiguous run
+  // of frames [k * per, (k + 1) * per) so overlapping windows share that XCD's L2.
+  int per = n >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <int D>
+__device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
+  using RC = LineCfg<D>;
+  constexpr int RP = RC::P, RQ = RC::Q, RT = RC::TPL;
+  constexpr int RV = RP > RQ ? RP : RQ;
+  constexpr int L = ColLen<D>::L;
+  constexpr int R = D / L;
+  using CC = LineCfg<L>;
+  constexpr int CP = CC::P, CQ = CC::Q, CT = CC::TPL;
+  constexpr int CV = CP > CQ ? CP : CQ;
+  constexpr int NT = kFrameThreads;
+  constexpr int RLINES = NT / RT;
+  constexpr int CLINES = NT / CT;
+  constexpr int EXL = RQ * (RP + 1);  // exchange buffer per row line
+
+  const int tid = threadIdx.x;
+  const int np = A.np, nz = A.nz;
+  const int fy = pk.fy, fx = pk.fx, fxp = pk.fxp;
+  const int m = A.peak_of[fid];
+  const int py = A.scan[2 * fid], px = A.scan[2 * fid + 1];
+  const int j = fid - pk.frame_base;
+
+  // LDS layout (complex units): twiddles | footprint gradient | chunk | exchange | shear
+  cplx* twD = sm;
+  cplx* gacc = twD + D;
+  cplx* Tr = gacc + (A.grad ? fy * fx : 0);
+  cplx* exch = Tr + L * fxp;
+  const int exch_sz = RLINES * EXL > np * np ? RLINES * EXL : np * np;
+  int2* sh = reinterpret_cast<int2*>(exch + exch_sz);
+  cplx* Ps = exch;  // probe staged in the exchange area during the projection
+
+  // twiddles w_D^k = exp(-2 pi i k / D)
+  for (int k = tid; k < D; k += NT) {
+    double s, c;
+    sincospi(-2.0 * (double)k / (double)D, &s, &c);
+    twD[k] = {(float)c, (float)s};
+  }
+  const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
+  for (int k = tid; k < np * np; k += NT) Ps[k] = probe[k];
+  for (int z = tid; z < nz; z += NT) {
+    const int* s = A.shear + 2 * (m * nz + z);
+    sh[z] = make_int2(s[0], s[1]);
+  }
+  if (A.grad)
+    for (int k = tid; k < fy * fx; k += NT) gacc[k] = {0.f, 0.f};
+  __syncthreads();
+
+  // ---- eq. (2): R diag(P) S O -> exit wave on the footprint (gather over slices) ----
+  cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
+  const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * A.ny * A.nx;
+  for (int p = tid; p < fy * fx; p += NT) {
+    int qy = p / fx, qx = p - qy * fx;
+    cplx acc = {0.f, 0.f};
+    for (int z = 0; z < nz; ++z) {
+      int2 s = sh[z];
+      int a = qy + pk.miny - s.x;
+      int b = qx + pk.minx - s.y;
+      if ((unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np) {
+        int oy = py + a, ox = px + b;
+        if ((unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx) {
+          cplx o = O[((long long)z * A.ny + oy) * A.nx + ox];
+          cplx pr = Ps[a * np + b];
+          acc = cadd(acc, cmul(pr, o));
+        }
+      }
+    }
+    slot[p] = acc;
+  }
+  __syncthreads();
+
+  const bool has_y = A.y != nullptr;
+  const float* yf = has_y ? A.y + pk.y_off + (long long)j * D * D : nullptr;
+  float* mif = A.mi ? A.mi + pk.y_off + (long long)j * D * D : nullptr;
+  const float invD = 1.0f / (float)D;
+  const float invD2 = invD * invD;
+  double lsum = 0.0;
+
+  for (int r = 0; r < R; ++r) {
+    // ---- column pass: rows k = R k' + r of the y-direction DFT of the footprint ----
+    {
+      const int line = tid / CT, t = tid % CT;
+      for (int col0 = 0; col0 < fx; col0 += CLINES) {
+        const int col = col0 + line;
+        const bool on = col < fx;
+        cplx v[CV];
+        if (on && t < CQ) {
+#pragma unroll
+          for (int a = 0; a < CP; ++a) {
+            int n1 = t + CQ * a;
+            cplx s = {0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              int n = n1 + L * q;
+              int rr = n - pk.r0;
+              if ((unsigned)rr < (unsigned)fy) s = cadd(s, cmul(slot[rr * fx + col], twD[(n * r) % D]));
+            }
+            v[a] = s;
+          }
+          DFT<CP, false>::run(v);
+#pragma unroll
+          for (int c = 0; c < CP; ++c) Tr[(c + CP * t) * fxp + col] = cmul(v[c], twD[t * c * R]);
+        }
+        wave_sync();
+        if (on && t < CP) {
+#pragma unroll
+          for (int b = 0; b < CQ; ++b) v[b] = Tr[(t + CP * b) * fxp + col];
+          DFT<CQ, false>::run(v);
+#pragma unroll
+          for (int d = 0; d < CQ; ++d) Tr[(t + CP * d) * fxp + col] = v[d];
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+
+    // ---- row pass: x-direction DFT, modulus residual (eq. (4)), inverse DFT ----
+    {
+      const int line = tid / RT, t = tid % RT;
+      cplx* ex = exch + line * EXL;
+      for (int k0 = 0; k0 < L; k0 += RLINES) {
+        const int kp = k0 + line;
+        const int k = R * kp + r;
+        float yv[RQ];
+        if (has_y && t < RP) {
+#pragma unroll
+          for (int d = 0; d < RQ; ++d) yv[d] = yf[(long long)k * D + t + RP * d];
+        }
+        cplx v[RV];
+        if (t < RQ) {
+#pragma unroll
+          for (int a = 0; a < RP; ++a) {
+            int cc = t + RQ * a - pk.c0;
+            v[a] = ((unsigned)cc < (unsigned)fx) ? Tr[kp * fxp + cc] : cplx{0.f, 0.f};
+          }
+          DFT<RP, false>::run(v);
+#pragma unroll
+          for (int c = 0; c < RP; ++c) ex[t * (RP + 1) + c] = cmul(v[c], twD[t * c]);
+        }
+        wave_sync();
+        if (t < RP) {
+#pragma unroll
+          for (int b = 0; b < RQ; ++b) v[b] = ex[b * (RP + 1) + t];
+          DFT<RQ, false>::run(v);
+          float rowl = 0.f;
+#pragma unroll
+          for (int d = 0; d < RQ; ++d) {
+            cplx X = v[d];
+            float a2 = (X.x * X.x + X.y * X.y) * invD2;   // |Psi|^2, Psi = X / D
+            if (mif) mif[(long long)k * D + t + RP * d] = a2;
+            if (has_y) {
+              float A = sqrtf(a2);
+              float res = A - sqrtf(yv[d]);
+              rowl += 0.5f * res * res;
+              float coef = A > 0.f ? res / A * invD : 0.f;
+              v[d] = cscale(X, coef);
+            }
+          }
+          lsum += (double)rowl;
+        }
+        if (A.grad) {
+          if (t < RP) {
+            DFT<RQ, true>::run(v);
+#pragma unroll
+            for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t] = v[b];
+          }
+          wave_sync();
+          if (t < RQ) {
+#pragma unroll
+            for (int c = 0; c < RP; ++c) v[c] = cmulc(ex[t * (RP + 1) + c], twD[t * c]);
+            DFT<RP, true>::run(v);
+#pragma unroll
+            for (int a = 0; a < RP; ++a) {
+              int cc = t + RQ * a - pk.c0;
+              if ((unsigned)cc < (unsigned)fx) Tr[kp * fxp + cc] = v[a];
+            }
+          }
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+
+    // ---- adjoint column pass: accumulate this chunk's share of the footprint gradient ----
+    if (A.grad) {
+      const int line = tid / CT, t = tid % CT;
+      for (int col0 = 0; col0 < fx; col0 += CLINES) {
+        const int col = col0 + line;
+        const bool on = col < fx;
+        cplx v[CV];
+        if (on && t < CP) {
+#pragma unroll
+          for (int d = 0; d < CQ; ++d) v[d] = Tr[(t + CP * d) * fxp + col];
+          DFT<CQ, true>::run(v);
+#pragma unroll
+          for (int b = 0; b < CQ; ++b) Tr[(t + CP * b) * fxp + col] = v[b];
+        }
+        wave_sync();
+        if (on && t < CQ) {
+#pragma unroll
+          for (int c = 0; c < CP; ++c) v[c] = cmulc(Tr[(c + CP * t) * fxp + col], twD[t * c * R]);
+          DFT<CP, true>::run(v);
+#pragma unroll
+          for (int a = 0; a < CP; ++a) {
+            int n1 = t + CQ * a;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              int n = n1 + L * q;
+              int rr = n - pk.r0;
+              if ((unsigned)rr < (unsigned)fy) {
+                cplx* g = gacc + rr * fx + col;
+                *g = cadd(*g, cmulc(v[a], twD[(n * r) % D]));
+              }
+            }
+          }
+        }
+        wave_sync();
+      }
+      __syncthreads();
+    }
+  }
+
+  if (A.grad) {
+    for (int p = tid; p < fy * fx; p += NT) slot[p] = cscale(gacc[p], invD);
+  }
+
+  if (has_y) {
+    // workgroup sum of the per-lane losses (fixed order)
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(exch);
+    if ((tid & 63) == 0) red[tid >> 6] = lsum;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w];
+      A.floss[fid] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFrameThreads) void k_frames(FrameArgs A) {
+  extern __shared__ cplx smem[];
+  const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
+  if (idx >= A.n_list) return;
+  const int fid = A.list[idx];
+  const PeakDev pk = A.peaks[A.peak_of[fid]];
+  switch (pk.D) {
+    case 32: frame_body<32>(A, pk, fid, smem); break;
+    case 64: frame_body<64>(A, pk, fid, smem); break;
+    case 96: frame_body<96>(A, pk, fid, smem); break;
+    case 128: frame_body<128>(A, pk, fid, smem); break;
+    case 192: frame_body<192>(A, pk, fid, smem); break;
+    case 256: frame_body<256>(A, pk, fid, smem); break;
+    default: break;
+  }
+}
+
+// -------------------------------------------- gather back-projection + chain rule ---
+__device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
+  int q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+__device__ __forceinline__ float block_sum_f(float v, float* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float s = 0.f;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_grad(GradArgs A) {
+  extern __shared__ cplx smem[];
+  const int np = A.np, nz = A.nz;
+  const int RW = kGradTX + A.maxspan_x;
+  const int RH = kGradTY + A.maxspan_y;
+  cplx* Ps = smem;                                   // np * np
+  int2* sh = reinterpret_cast<int2*>(Ps + np * np);  // nz
+  cplx* reg = reinterpret_cast<cplx*>(sh + nz);      // RH * RW
+  float* red = reinterpret_cast<float*>(reg + RH * RW);
+
+  const int tid = threadIdx.x;
+  const int tx = tid % kGradTX, ty = (tid / kGradTX) % kGradTY, tz = tid / (kGradTX * kGradTY);
+  const int bx = blockIdx.x % A.tiles_x, by = blockIdx.x / A.tiles_x;
+  const int x0 = bx * kGradTX, y0 = by * kGradTY;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool inb = x < A.nx && y < A.ny;
+  const long long nvox = (long long)nz * A.ny * A.nx;
+
+  float apart_acc[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) apart_acc[m] = 0.f;
+
+  for (int zb = 0; zb < nz; zb += kGradZB) {
+    float gux[kGradZPer], guy[kGradZPer], guz[kGradZPer], gch[kGradZPer];
+#pragma unroll
+    for (int i = 0; i < kGradZPer; ++i) gux[i] = guy[i] = guz[i] = gch[i] = 0.f;
+
+    for (int m = 0; m < A.n_peaks; ++m) {
+      const PeakDev pk = A.peaks[m];
+      __syncthreads();
+      const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
+      for (int k = tid; k < np * np; k += blockDim.x) Ps[k] = probe[k];
+      for (int z = tid; z < nz; z += blockDim.x) {
+        const int* s = A.shear + 2 * (m * nz + z);
+        sh[z] = make_int2(s[0], s[1]);
+      }
+      cplx acc[kGradZPer];
+#pragma unroll
+      for (int i = 0; i < kGradZPer; ++i) acc[i] = {0.f, 0.f};
+
+      const int iy_lo = max(0, -floordiv(-(y0 - np + 1 - pk.oy), pk.sy));
+      const int iy_hi = min(pk.rows - 1, floordiv(y0 + kGradTY - 1 - pk.oy, pk.sy));
+      const int ix_lo = max(0, -floordiv(-(x0 - np + 1 - pk.ox), pk.sx));
+      const int ix_hi = min(pk.cols - 1, floordiv(x0 + kGradTX - 1 - pk.ox, pk.sx));
+      for (int iy = iy_lo; iy <= iy_hi; ++iy) {
+        for (int ix = ix_lo; ix <= ix_hi; ++ix) {
+          const int j = iy * pk.cols + ix;
+          const int fid = pk.frame_base + j;
+          if (!A.active[fid]) continue;
+          const int py = pk.oy + iy * pk.sy, px = pk.ox + ix * pk.sx;
+          const int a_lo = max(0, y0 - py), a_hi = min(np, y0 + kGradTY - py);
+          const int b_lo = max(0, x0 - px), b_hi = min(np, x0 + kGradTX - px);
+          if (a_hi <= a_lo || b_hi <= b_lo) continue;
+          const int rh = a_hi - a_lo + pk.spany, rw = b_hi - b_lo + pk.spanx;
+          const cplx* slot = reinterpret_cast<const cplx*>(A.slots) + pk.slot_off +
+                             (long long)j * pk.fy * pk.fx;
+          __syncthreads();
+          for (int k = tid; k < rh * rw; k += blockDim.x) {
+            int rr = k / rw, cc = k - rr * rw;
+            reg[rr * RW + cc] = slot[(a_lo + rr) * pk.fx + b_lo + cc];
+          }
+          __syncthreads();
+          const int a = y - py, b = x - px;
+          if (inb && a >= a_lo && a < a_hi && b >= b_lo && b < b_hi) {
+            const cplx p = Ps[a * np + b];
+#pragma unroll
+            for (int i = 0; i < kGradZPer; ++i) {
+              const int z = zb + tz + kGradTZ * i;
+              if (z < nz) {
+                int2 s = sh[z];
+                int fr = a - a_lo + s.x - pk.miny;
+                int fc = b - b_lo + s.y - pk.minx;
+                acc[i] = cadd(acc[i], cmulc(reg[fr * RW + fc], p));   // conj(P) g_psi
+              }
+            }
+          }
+        }
+      }
+      // chain rule through O_m = alpha_m chi exp(i G_m . u)
+      float ap = 0.f;
+      if (inb) {
+        const float al = A.alpha[m];
+#pragma unroll
+        for (int i = 0; i < kGradZPer; ++i) {
+          const int z = zb + tz + kGradTZ * i;
+          if (z < nz) {
+            const long long v = ((long long)z * A.ny + y) * A.nx + x;
+            const float ux = A.u[v], uy = A.u[nvox + v], uzv = A.u[2 * nvox + v];
+            const float ch = A.chi[v];
+            const float phi = pk.gx * ux + pk.gy * uy + pk.gz * uzv;
+            float s, c;
+            sincosf(phi, &s, &c);
+            const cplx g = acc[i];
+            const float re = g.x * c + g.y * s;          // Re(conj(g) e^{i phi})
+            const float dphi = al * ch * (g.y * c - g.x * s);  // Im(g conj(O))
+            gux[i] += pk.gx * dphi;
+            guy[i] += pk.gy * dphi;
+            guz[i] += pk.gz * dphi;
+            gch[i] += al * re;
+            ap += ch * re;
+          }
+        }
+      }
+#pragma unroll
+      for (int mm = 0; mm < 16; ++mm)
+        if (mm == m) apart_acc[mm] += ap;
+    }
+    if (inb) {
+#pragma unroll
+      for (int i = 0; i < kGradZPer; ++i) {
+        const int z = zb + tz + kGradTZ * i;
+        if (z < nz) {
+          const long long v = ((long long)z * A.ny + y) * A.nx + x;
+          A.grad_u[v] = gux[i];
+          A.grad_u[nvox + v] = guy[i];
+          A.grad_u[2 * nvox + v] = guz[i];
+          A.grad_chi[v] = gch[i];
+        }
+      }
+    }
+  }
+  for (int m = 0; m < A.n_peaks; ++m) {
+    float v = 0.f;
+#pragma unroll
+    for (int mm = 0; mm < 16; ++mm)
+      if (mm == m) v = apart_acc[mm];
+    float s = block_sum_f(v, red);
+    if (tid == 0) A.alpha_part[(long long)blockIdx.x * A.n_peaks + m] = (double)s;
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------- finalize ---
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ floss,
+                                                  const int* __restrict__ out_list, int n_out,
+                                                  double* loss, float* frame_loss,
+                                                  const double* __restrict__ apart, int n_part,
+                                                  int n_peaks, float* grad_alpha) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  if (loss || frame_loss) {
+    double s = 0.0;
+    for (int i = tid; i < n_out; i += 256) {
+      double v = floss[out_list ? out_list[i] : i];
+      s += v;
+      if (frame_loss) frame_loss[i] = (float)v;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0 && loss) *loss = red[0];
+    __syncthreads();
+  }
+  if (grad_alpha) {
+    for (int m = 0; m < n_peaks; ++m) {
+      double s = 0.0;
+      for (int i = tid; i < n_part; i += 256) s += apart[(long long)i * n_peaks + m];
+      red[tid] = s;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+      }
+      if (tid == 0) grad_alpha[m] = (float)red[0];
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_step(float* __restrict__ p, const float* __restrict__ g,
+                                              long long n, float eta) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = p[i] - eta * g[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill_u8(unsigned char* p, long long n, unsigned char v) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_mark_active(unsigned char* act, const int* list, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) act[list[i]] = 1;
+}
+
+// ------------------------------------------------------------------ host launchers ---
+static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
+                         int n_peaks, long long nvox, float* obj, hipStream_t s) {
+  k_object<<<dim3(nblk(nvox, 256)), dim3(256), 0, s>>>(u, chi, alpha, peaks, n_peaks, nvox, obj);
+  return hipGetLastError();
+}
+
+hipError_t launch_frames(const FrameArgs& a, int lds_bytes, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_frames, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
+  if (grid == 0) return hipSuccess;
+  k_frames<<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_grad, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  unsigned grid = (unsigned)(a.tiles_x * a.tiles_y);
+  k_grad<<<dim3(grid), dim3(kGradTX * kGradTY * kGradTZ), lds_bytes, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
+                           float* frame_loss, const double* apart, int n_part, int n_peaks,
+                           float* grad_alpha, hipStream_t s) {
+  k_finalize<<<dim3(1), dim3(256), 0, s>>>(floss, out_list, n_out, loss, frame_loss, apart, n_part, n_peaks, grad_alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(float* p, const float* g, long long n, float eta, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_step<<<dim3(nblk(n, 256)), dim3(256), 0, s>>>(p, g, n, eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_active(unsigned char* act, long long n_frames, const int* list, int n,
+                              hipStream_t s) {
+  k_fill_u8<<<dim3(nblk(n_frames, 256)), dim3(256), 0, s>>>(act, n_frames, (unsigned char)0);
+  if (n > 0) k_mark_active<<<dim3(nblk(n, 256)), dim3(256), 0, s>>>(act, list, n);
+  return hipGetLastError();
+}
+
+}  // namespace mpbp
+
+namespace mpbp {
+
+template <int D>
+static int lds_for(int fy, int fx, int fxp, int np, int nz, bool grad) {
+  using RC = LineCfg<D>;
+  constexpr int L = ColLen<D>::L;
+  constexpr int RLINES = kFrameThreads / RC::TPL;
+  constexpr int EXL = RC::Q * (RC::P + 1);
+  const long long exch = RLINES * EXL > np * np ? RLINES * EXL : np * np;
+  const long long cpx = D + (grad ? (long long)fy * fx : 0) + (long long)L * fxp + exch;
+  return (int)(cpx * 8 + (long long)nz * 8);
+}
+
+int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad) {
+  switch (D) {
+    case 32: return lds_for<32>(fy, fx, fxp, np, nz, grad);
+    case 64: return lds_for<64>(fy, fx, fxp, np, nz, grad);
+    case 96: return lds_for<96>(fy, fx, fxp, np, nz, grad);
+    case 128: return lds_for<128>(fy, fx, fxp, np, nz, grad);
+    case 192: return lds_for<192>(fy, fx, fxp, np, nz, grad);
+    case 256: return lds_for<256>(fy, fx, fxp, np, nz, grad);
+    default: return -1;
+  }
+}
+
+int frame_chunk_len(int D) {
+  switch (D) {
+    case 32: return ColLen<32>::L;
+    case 64: return ColLen<64>::L;
+    case 96: return ColLen<96>::L;
+    case 128: return ColLen<128>::L;
+    case 192: return ColLen<192>::L;
+    case 256: return ColLen<256>::L;
+    default: return -1;
+  }
+}
+
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x) {
+  return np * np * 8 + nz * 8 + (kGradTY + maxspan_y) * (kGradTX + maxspan_x) * 8 + 64;
+}
+
+}  // namespace mpbp

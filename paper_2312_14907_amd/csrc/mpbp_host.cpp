@@ -1,0 +1,519 @@
+// mpbp_host.cpp - the C-ABI of include/mpbp.h: plan creation and validation, the
+// integer tables of the shift and projection operators of eq. (2), workspace
+// ownership, and the enqueueing of the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mpbp.h"
+#include "mpbp_kernels.hpp"
+#include "mpbp_launch.hpp"
+#include "mpbp_plain.hpp"
+
+using mpbp::PeakDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+mpbp_status fail(mpbp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+mpbp_status hip_fail(hipError_t e, const char* what) {
+  return fail(MPBP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool supported_det(int d) {
+  return d == 32 || d == 64 || d == 96 || d == 128 || d == 192 || d == 256;
+}
+
+constexpr int kMaxPeaks = 16;
+constexpr int kMaxLds = 160 * 1024;
+
+}  // namespace
+
+struct mpbp_plan_t {
+  int device = -1;
+  int nz = 0, ny = 0, nx = 0, np = 0, M = 0;
+  long long nvox = 0;
+  int64_t F = 0, ylen = 0;
+  std::vector<mpbp_peak> peaks;
+  std::vector<PeakDev> pdev;
+  std::vector<int32_t> scan;     // [F][2]
+  std::vector<int32_t> shear;    // [M][nz][2]
+  std::vector<int64_t> y_off;    // [M+1]
+  std::vector<int32_t> peak_of;  // [F]
+  std::vector<int32_t> order;    // processing order of the full batch
+  int lds_fwd = 0, lds_grad_frame = 0, lds_grad = 0;
+  int maxspan_y = 0, maxspan_x = 0;
+  int tiles_x = 0, tiles_y = 0;
+  long long slots_cplx = 0;
+  // options
+  int path = 0, graph = 1, xcd = 1;
+  // device buffers
+  PeakDev* d_peaks = nullptr;
+  int* d_scan = nullptr;
+  int* d_peak_of = nullptr;
+  int* d_shear = nullptr;
+  int* d_order = nullptr;          // full-batch processing order
+  int* d_list = nullptr;           // caller's list (subset calls)
+  unsigned char* d_active = nullptr;     // per-frame minibatch mask (subset calls)
+  unsigned char* d_active_all = nullptr; // all ones
+  float* d_obj = nullptr;
+  float* d_slots = nullptr;
+  double* d_floss = nullptr;
+  double* d_apart = nullptr;
+  int* h_list = nullptr;           // pinned staging of the caller's list
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  mpbp::PlainWork plain;
+};
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+void free_device(mpbp_plan_t* p) {
+  if (p->device < 0) return;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(p->d_peaks);
+  (void)hipFree(p->d_scan);
+  (void)hipFree(p->d_peak_of);
+  (void)hipFree(p->d_shear);
+  (void)hipFree(p->d_order);
+  (void)hipFree(p->d_list);
+  (void)hipFree(p->d_active);
+  (void)hipFree(p->d_active_all);
+  (void)hipFree(p->d_obj);
+  (void)hipFree(p->d_slots);
+  (void)hipFree(p->d_floss);
+  (void)hipFree(p->d_apart);
+  if (p->h_list) (void)hipHostFree(p->h_list);
+  if (p->staged) (void)hipEventDestroy(p->staged);
+  mpbp::plain_free(&p->plain);
+}
+
+// Build tables and per-peak constants on the host; validate the problem.
+mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
+  if (!pr) return fail(MPBP_ERR_INVALID, "problem is NULL");
+  if (pr->flags != 0) return fail(MPBP_ERR_INVALID, "flags must be 0 (got %u)", pr->flags);
+  if (pr->nz < 1 || pr->ny < 1 || pr->nx < 1)
+    return fail(MPBP_ERR_SHAPE, "object grid must be positive (nz=%d ny=%d nx=%d)", pr->nz, pr->ny, pr->nx);
+  if (pr->probe_n < 1) return fail(MPBP_ERR_SHAPE, "probe_n must be positive (%d)", pr->probe_n);
+  if (pr->n_peaks < 1 || pr->n_peaks > kMaxPeaks)
+    return fail(MPBP_ERR_SHAPE, "n_peaks must be in [1, %d] (got %d)", kMaxPeaks, pr->n_peaks);
+  if (!pr->peaks) return fail(MPBP_ERR_INVALID, "peaks is NULL");
+  const long long nvox = (long long)pr->nz * pr->ny * pr->nx;
+  if (nvox * pr->n_peaks > (1LL << 40)) return fail(MPBP_ERR_SHAPE, "object grid too large");
+  if (pr->nz > 4096) return fail(MPBP_ERR_SHAPE, "nz too large (%d)", pr->nz);
+
+  p->nz = pr->nz; p->ny = pr->ny; p->nx = pr->nx; p->np = pr->probe_n; p->M = pr->n_peaks;
+  p->nvox = nvox;
+  p->peaks.assign(pr->peaks, pr->peaks + pr->n_peaks);
+  p->pdev.assign(p->M, PeakDev{});
+  p->shear.assign((size_t)p->M * p->nz * 2, 0);
+  p->y_off.assign(p->M + 1, 0);
+  p->scan.clear();
+  p->peak_of.clear();
+  const int np = p->np;
+  const int zref = p->nz / 2;
+  long long slot = 0;
+  for (int m = 0; m < p->M; ++m) {
+    const mpbp_peak& k = p->peaks[m];
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(k.g[c])) return fail(MPBP_ERR_INVALID, "peak %d: G not finite", m);
+    for (int c = 0; c < 2; ++c)
+      if (!std::isfinite(k.shear[c]) || std::fabs(k.shear[c]) > 1e6)
+        return fail(MPBP_ERR_INVALID, "peak %d: shear not finite", m);
+    if (!supported_det(k.det))
+      return fail(MPBP_ERR_SHAPE, "peak %d: detector size %d not in {32,64,96,128,192,256}", m, k.det);
+    if (np > k.det) return fail(MPBP_ERR_FOOTPRINT, "peak %d: probe support %d > window %d", m, np, k.det);
+    if (k.scan_n[0] < 1 || k.scan_n[1] < 1)
+      return fail(MPBP_ERR_SHAPE, "peak %d: raster must be positive (%d x %d)", m, k.scan_n[0], k.scan_n[1]);
+    if (k.scan_step[0] < 1 || k.scan_step[1] < 1)
+      return fail(MPBP_ERR_SHAPE, "peak %d: raster step must be positive", m);
+    if ((long long)k.scan_n[0] * k.scan_n[1] > (1LL << 24))
+      return fail(MPBP_ERR_SHAPE, "peak %d: raster too large", m);
+    // shear offsets s_m(z) = round-half-away((z - nz/2) * t_m)
+    int lo[2] = {1 << 30, 1 << 30}, hi[2] = {-(1 << 30), -(1 << 30)};
+    for (int z = 0; z < p->nz; ++z) {
+      for (int c = 0; c < 2; ++c) {
+        double v = std::round((double)(z - zref) * k.shear[c]);
+        int s = (int)v;
+        p->shear[((size_t)m * p->nz + z) * 2 + c] = s;
+        lo[c] = std::min(lo[c], s);
+        hi[c] = std::max(hi[c], s);
+      }
+    }
+    const int cw = (k.det - np) / 2;
+    for (int c = 0; c < 2; ++c)
+      if (cw + lo[c] < 0 || cw + np - 1 + hi[c] > k.det - 1)
+        return fail(MPBP_ERR_FOOTPRINT, "peak %d: sheared support leaves the %dx%d window", m, k.det, k.det);
+    PeakDev& d = p->pdev[m];
+    d.D = k.det;
+    d.L = mpbp::frame_chunk_len(k.det);
+    d.R = k.det / d.L;
+    d.c = cw;
+    d.miny = lo[0]; d.minx = lo[1];
+    d.spany = hi[0] - lo[0]; d.spanx = hi[1] - lo[1];
+    d.r0 = cw + lo[0]; d.c0 = cw + lo[1];
+    d.fy = np + d.spany; d.fx = np + d.spanx;
+    d.fxp = d.fx | 1;
+    d.rows = k.scan_n[0]; d.cols = k.scan_n[1];
+    d.nfr = d.rows * d.cols;
+    d.sy = k.scan_step[0]; d.sx = k.scan_step[1];
+    d.oy = k.scan_origin[0]; d.ox = k.scan_origin[1];
+    d.frame_base = (int)p->F;
+    d.y_off = p->y_off[m];
+    d.slot_off = slot;
+    d.gx = (float)k.g[0]; d.gy = (float)k.g[1]; d.gz = (float)k.g[2];
+    d.lds_bytes = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, true);
+    if (d.lds_bytes > kMaxLds)
+      return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d needs %d B of LDS", m, d.fy, d.fx, d.lds_bytes);
+    p->lds_grad_frame = std::max(p->lds_grad_frame, d.lds_bytes);
+    p->lds_fwd = std::max(p->lds_fwd, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false));
+    p->maxspan_y = std::max(p->maxspan_y, d.spany);
+    p->maxspan_x = std::max(p->maxspan_x, d.spanx);
+    slot += (long long)d.nfr * d.fy * d.fx;
+    for (int iy = 0; iy < d.rows; ++iy)
+      for (int ix = 0; ix < d.cols; ++ix) {
+        p->scan.push_back(d.oy + iy * d.sy);
+        p->scan.push_back(d.ox + ix * d.sx);
+        p->peak_of.push_back(m);
+      }
+    p->F += d.nfr;
+    if (p->F > (1LL << 30)) return fail(MPBP_ERR_SHAPE, "too many frames");
+    p->y_off[m + 1] = p->y_off[m] + (int64_t)d.nfr * k.det * k.det;
+  }
+  p->ylen = p->y_off[p->M];
+  p->slots_cplx = slot;
+  p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x);
+  if (p->lds_grad > kMaxLds) return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", p->lds_grad);
+  p->tiles_x = (p->nx + mpbp::kGradTX - 1) / mpbp::kGradTX;
+  p->tiles_y = (p->ny + mpbp::kGradTY - 1) / mpbp::kGradTY;
+  // Full-batch processing order: larger windows first (they cost most), each peak's
+  // frames in raster order.
+  std::vector<int> pk(p->M);
+  for (int m = 0; m < p->M; ++m) pk[m] = m;
+  std::stable_sort(pk.begin(), pk.end(), [&](int a, int b) { return p->pdev[a].D > p->pdev[b].D; });
+  p->order.clear();
+  for (int m : pk)
+    for (int j = 0; j < p->pdev[m].nfr; ++j) p->order.push_back(p->pdev[m].frame_base + j);
+  return MPBP_OK;
+}
+
+mpbp_status alloc_device(mpbp_plan_t* p) {
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+#define ALLOC(ptr, n)                                                           \
+  do {                                                                          \
+    e = dalloc(&(ptr), (n));                                                    \
+    if (e != hipSuccess) return fail(MPBP_ERR_NOMEM, "hipMalloc %s (%zu elements): %s", #ptr, \
+                                     (size_t)(n), hipGetErrorString(e));        \
+  } while (0)
+  ALLOC(p->d_peaks, p->M);
+  ALLOC(p->d_scan, p->F * 2);
+  ALLOC(p->d_peak_of, p->F);
+  ALLOC(p->d_shear, (size_t)p->M * p->nz * 2);
+  ALLOC(p->d_order, p->F);
+  ALLOC(p->d_list, p->F);
+  ALLOC(p->d_active, p->F);
+  ALLOC(p->d_active_all, p->F);
+  ALLOC(p->d_obj, (size_t)p->M * p->nvox * 2);
+  ALLOC(p->d_slots, (size_t)p->slots_cplx * 2);
+  ALLOC(p->d_floss, p->F);
+  ALLOC(p->d_apart, (size_t)p->tiles_x * p->tiles_y * p->M);
+#undef ALLOC
+  e = hipHostMalloc((void**)&p->h_list, std::max<int64_t>(p->F, 1) * sizeof(int), hipHostMallocDefault);
+  if (e != hipSuccess) return fail(MPBP_ERR_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+  e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  e = hipMemcpy(p->d_peaks, p->pdev.data(), p->M * sizeof(PeakDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_scan, p->scan.data(), p->scan.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_peak_of, p->peak_of.data(), p->peak_of.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_shear, p->shear.data(), p->shear.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), p->order.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy tables");
+  std::vector<unsigned char> ones(p->F, 1);
+  e = hipMemcpy(p->d_active_all, ones.data(), p->F, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy mask");
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  return MPBP_OK;
+}
+
+// Validate and stage a caller's frame list; returns the number of listed frames.
+mpbp_status stage_frames(mpbp_plan_t* p, const int32_t* frames, int64_t n, hipStream_t s,
+                         bool need_mask, int* n_out) {
+  if (!frames) {
+    *n_out = (int)p->F;
+    return MPBP_OK;
+  }
+  if (n < 0 || n > p->F) return fail(MPBP_ERR_INVALID, "n_frames %lld out of range [0, %lld]", (long long)n, (long long)p->F);
+  std::vector<unsigned char> seen(p->F, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int f = frames[i];
+    if (f < 0 || f >= p->F) return fail(MPBP_ERR_INVALID, "frame id %d out of range", f);
+    if (seen[f]) return fail(MPBP_ERR_INVALID, "duplicate frame id %d", f);
+    seen[f] = 1;
+  }
+  hipError_t e;
+  if (p->staged_pending) {
+    e = hipEventSynchronize(p->staged);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  }
+  std::memcpy(p->h_list, frames, (size_t)n * sizeof(int));
+  if (n > 0) {
+    e = hipMemcpyAsync(p->d_list, p->h_list, (size_t)n * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync frame list");
+  }
+  e = hipEventRecord(p->staged, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  p->staged_pending = true;
+  if (need_mask) {
+    e = mpbp::launch_mark_active(p->d_active, p->F, p->d_list, (int)n, s);
+    if (e != hipSuccess) return hip_fail(e, "mask kernel");
+  }
+  *n_out = (int)n;
+  return MPBP_OK;
+}
+
+mpbp_status check_plan(mpbp_plan p) {
+  if (!p) return fail(MPBP_ERR_INVALID, "plan is NULL");
+  if (p->device < 0) return fail(MPBP_ERR_DEVICE, "host-only plan: compute calls need a device plan");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return MPBP_OK;
+}
+
+mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, float* mi, int grad) {
+  mpbp::FrameArgs a{};
+  a.obj = p->d_obj;
+  a.y = y;
+  a.list = list;
+  a.n_list = n;
+  a.scan = p->d_scan;
+  a.peak_of = p->d_peak_of;
+  a.peaks = p->d_peaks;
+  a.shear = p->d_shear;
+  a.slots = p->d_slots;
+  a.floss = p->d_floss;
+  a.mi = mi;
+  a.nz = p->nz; a.ny = p->ny; a.nx = p->nx; a.np = p->np;
+  a.grad = grad;
+  a.xcd = p->xcd;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan* out) {
+  if (!out) return fail(MPBP_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  mpbp_plan_t* p = new (std::nothrow) mpbp_plan_t();
+  if (!p) return fail(MPBP_ERR_NOMEM, "host allocation failed");
+  mpbp_status st = build_tables(problem, p);
+  if (st != MPBP_OK) {
+    delete p;
+    return st;
+  }
+  if (device >= 0) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device >= n) {
+      delete p;
+      return fail(MPBP_ERR_DEVICE, "device %d not available (%d devices)", device, e == hipSuccess ? n : 0);
+    }
+    p->device = device;
+    st = alloc_device(p);
+    if (st != MPBP_OK) {
+      std::string msg = g_err;
+      free_device(p);
+      delete p;
+      g_err = msg;
+      return st;
+    }
+  } else if (device != -1) {
+    delete p;
+    return fail(MPBP_ERR_INVALID, "device must be >= 0, or -1 for a host-only plan");
+  }
+  g_err.clear();
+  *out = p;
+  return MPBP_OK;
+}
+
+void mpbp_plan_destroy(mpbp_plan plan) {
+  if (!plan) return;
+  free_device(plan);
+  delete plan;
+}
+
+int64_t mpbp_num_frames(mpbp_plan plan) { return plan ? plan->F : -1; }
+
+int64_t mpbp_intensity_size(mpbp_plan plan) { return plan ? plan->ylen : -1; }
+
+mpbp_status mpbp_tables(mpbp_plan plan, int32_t* scan_yx, int32_t* shear_yx, int64_t* y_off) {
+  if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
+  if (scan_yx) std::memcpy(scan_yx, plan->scan.data(), plan->scan.size() * sizeof(int32_t));
+  if (shear_yx) std::memcpy(shear_yx, plan->shear.data(), plan->shear.size() * sizeof(int32_t));
+  if (y_off) std::memcpy(y_off, plan->y_off.data(), plan->y_off.size() * sizeof(int64_t));
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const float* alpha,
+                         const void* probe, const float* y, const int32_t* frames, int64_t n_frames,
+                         double* loss, float* frame_loss, float* model_intensity, void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!u || !chi || !alpha || !probe) return fail(MPBP_ERR_INVALID, "u, chi, alpha and probe are required");
+  if ((loss || frame_loss) && !y) return fail(MPBP_ERR_INVALID, "y is required for loss / frame_loss");
+  hipStream_t s = (hipStream_t)stream;
+  int n = 0;
+  st = stage_frames(plan, frames, n_frames, s, false, &n);
+  if (st != MPBP_OK) return st;
+  const int* list = frames ? plan->d_list : plan->d_order;
+  const int* out_list = frames ? plan->d_list : nullptr;
+  hipError_t e;
+  if (plan->path == 1) {
+    e = mpbp::plain_forward(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
+                            plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
+                            frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
+                            model_intensity, plan->d_obj, plan->d_floss, s);
+    if (e != hipSuccess) return hip_fail(e, "plain path");
+  } else {
+    e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+    if (e != hipSuccess) return hip_fail(e, "object kernel");
+    mpbp::FrameArgs a = frame_args(plan, y, list, n, model_intensity, 0);
+    a.probe = (const float*)probe;
+    e = mpbp::launch_frames(a, plan->lds_fwd, s);
+    if (e != hipSuccess) return hip_fail(e, "frame kernel");
+  }
+  if (loss || frame_loss) {
+    e = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, nullptr, 0, plan->M, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "finalize kernel");
+  }
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, const float* alpha,
+                           const void* probe, const float* y, const int32_t* frames, int64_t n_frames,
+                           double* loss, float* frame_loss, float* grad_u, float* grad_chi,
+                           float* grad_alpha, void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!u || !chi || !alpha || !probe || !y)
+    return fail(MPBP_ERR_INVALID, "u, chi, alpha, probe and y are required");
+  if (!grad_u || !grad_chi || !grad_alpha) return fail(MPBP_ERR_INVALID, "grad_u, grad_chi and grad_alpha are required");
+  hipStream_t s = (hipStream_t)stream;
+  int n = 0;
+  st = stage_frames(plan, frames, n_frames, s, plan->path == 0, &n);
+  if (st != MPBP_OK) return st;
+  const int* list = frames ? plan->d_list : plan->d_order;
+  const int* out_list = frames ? plan->d_list : nullptr;
+  hipError_t e;
+  int n_part = plan->tiles_x * plan->tiles_y;
+  const double* apart = plan->d_apart;
+  if (plan->path == 1) {
+    e = mpbp::plain_loss_grad(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
+                              plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
+                              frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
+                              plan->d_obj, plan->d_floss, grad_u, grad_chi, &apart, &n_part, s);
+    if (e != hipSuccess) return hip_fail(e, "plain path");
+  } else {
+    e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+    if (e != hipSuccess) return hip_fail(e, "object kernel");
+    mpbp::FrameArgs a = frame_args(plan, y, list, n, nullptr, 1);
+    a.probe = (const float*)probe;
+    e = mpbp::launch_frames(a, plan->lds_grad_frame, s);
+    if (e != hipSuccess) return hip_fail(e, "frame kernel");
+    mpbp::GradArgs g{};
+    g.slots = plan->d_slots;
+    g.active = frames ? plan->d_active : plan->d_active_all;
+    g.probe = (const float*)probe;
+    g.u = u; g.chi = chi; g.alpha = alpha;
+    g.shear = plan->d_shear;
+    g.peaks = plan->d_peaks;
+    g.n_peaks = plan->M;
+    g.nz = plan->nz; g.ny = plan->ny; g.nx = plan->nx; g.np = plan->np;
+    g.tiles_x = plan->tiles_x; g.tiles_y = plan->tiles_y;
+    g.maxspan_y = plan->maxspan_y; g.maxspan_x = plan->maxspan_x;
+    g.grad_u = grad_u; g.grad_chi = grad_chi;
+    g.alpha_part = plan->d_apart;
+    e = mpbp::launch_grad(g, plan->lds_grad, s);
+    if (e != hipSuccess) return hip_fail(e, "gradient kernel");
+  }
+  e = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, apart, n_part, plan->M,
+                            grad_alpha, s);
+  if (e != hipSuccess) return hip_fail(e, "finalize kernel");
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_step(mpbp_plan plan, float* u, float* chi, float* alpha, const float* grad_u,
+                      const float* grad_chi, const float* grad_alpha, const float* eta, void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!u || !chi || !alpha || !grad_u || !grad_chi || !grad_alpha || !eta)
+    return fail(MPBP_ERR_INVALID, "all pointers are required");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(eta[i])) return fail(MPBP_ERR_INVALID, "eta[%d] not finite", i);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = mpbp::launch_step(u, grad_u, 3 * plan->nvox, eta[0], s);
+  if (e == hipSuccess) e = mpbp::launch_step(chi, grad_chi, plan->nvox, eta[1], s);
+  if (e == hipSuccess) e = mpbp::launch_step(alpha, grad_alpha, plan->M, eta[2], s);
+  if (e != hipSuccess) return hip_fail(e, "step kernel");
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
+  if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
+  switch (option) {
+    case MPBP_OPT_PATH:
+      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "path must be 0 or 1");
+      plan->path = (int)value;
+      return MPBP_OK;
+    case MPBP_OPT_GRAPH:
+      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "graph must be 0 or 1");
+      plan->graph = (int)value;
+      return MPBP_OK;
+    case MPBP_OPT_XCD_ORDER:
+      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "xcd order must be 0 or 1");
+      plan->xcd = (int)value;
+      return MPBP_OK;
+    default:
+      return fail(MPBP_ERR_INVALID, "unknown option %d", option);
+  }
+}
+
+mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value) {
+  if (!plan || !value) return fail(MPBP_ERR_INVALID, "plan and value are required");
+  switch (option) {
+    case MPBP_OPT_PATH: *value = plan->path; return MPBP_OK;
+    case MPBP_OPT_GRAPH: *value = plan->graph; return MPBP_OK;
+    case MPBP_OPT_XCD_ORDER: *value = plan->xcd; return MPBP_OK;
+    default: return fail(MPBP_ERR_INVALID, "unknown option %d", option);
+  }
+}
+
+const char* mpbp_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

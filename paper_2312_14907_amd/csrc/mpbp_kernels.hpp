@@ -1,0 +1,70 @@
+// mpbp_kernels.hpp - device-side data structures shared by the kernels and the host.
+#pragma once
+#include <stdint.h>
+
+namespace mpbp {
+
+// Per-peak constants, built on the host from the plan's tables.
+struct PeakDev {
+  int D;            // detector / exit-wave window
+  int R;            // number of residue chunks of the detector rows (D = R * L)
+  int L;            // rows per chunk
+  int c;            // window offset of the probe support: (D - Np) / 2
+  int miny, minx;   // minimum shear over z
+  int spany, spanx; // max - min shear
+  int r0, c0;       // footprint origin in the window: c + min shear
+  int fy, fx;       // footprint: Np + span
+  int fxp;          // padded row stride of the chunk buffer (complex)
+  int nfr;          // frames of this peak
+  int frame_base;   // global id of this peak's frame 0
+  int rows, cols;   // raster
+  int sy, sx;       // raster step
+  int oy, ox;       // raster origin
+  long long y_off;  // element offset of this peak's frames in y
+  long long slot_off;  // complex offset of frame 0's footprint slot in the workspace
+  float gx, gy, gz; // Bragg vector (rad/nm)
+  int lds_bytes;    // dynamic LDS the frame kernel needs for this peak
+};
+
+struct FrameArgs {
+  const float* obj;        // complex64 [M][nz][ny][nx] (interleaved)
+  const float* probe;      // complex64 [M][np][np]
+  const float* y;          // ragged intensities (may be null)
+  const int* list;         // global frame ids to process
+  int n_list;
+  const int* scan;         // [F][2] (py, px)
+  const int* peak_of;      // [F]
+  const PeakDev* peaks;    // [M]
+  const int* shear;        // [M][nz][2]
+  float* slots;            // complex64 footprint slots (exit wave, then its gradient)
+  double* floss;           // [n_list] per-frame loss (list order)
+  float* mi;               // model intensity (ragged like y) or null
+  int nz, ny, nx, np;
+  int grad;                // 1: also compute the footprint gradient
+  int xcd;                 // XCD-aware block order
+};
+
+struct GradArgs {
+  const float* slots;      // complex64 footprint gradients
+  const unsigned char* active;  // [F] 1 if the frame is in the minibatch
+  const float* probe;
+  const float* u;
+  const float* chi;
+  const float* alpha;
+  const int* shear;
+  const PeakDev* peaks;
+  int n_peaks;
+  int nz, ny, nx, np;
+  int tiles_x, tiles_y;
+  int maxspan_y, maxspan_x;  // largest shear span over peaks
+  float* grad_u;
+  float* grad_chi;
+  double* alpha_part;      // [n_blocks][M]
+};
+
+constexpr int kFrameThreads = 256;
+constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 4;  // 256 threads
+constexpr int kGradZB = 32;                             // z per pass of the grad kernel
+constexpr int kGradZPer = kGradZB / kGradTZ;            // z per thread per pass
+
+}  // namespace mpbp

@@ -1,0 +1,27 @@
+// mpbp_launch.hpp - host-callable launchers of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mpbp_kernels.hpp"
+
+namespace mpbp {
+
+hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
+                         int n_peaks, long long nvox, float* obj, hipStream_t s);
+hipError_t launch_frames(const FrameArgs& a, int lds_bytes, hipStream_t s);
+hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s);
+hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
+                           float* frame_loss, const double* apart, int n_part, int n_peaks,
+                           float* grad_alpha, hipStream_t s);
+hipError_t launch_step(float* p, const float* g, long long n, float eta, hipStream_t s);
+hipError_t launch_mark_active(unsigned char* act, long long n_frames, const int* list, int n,
+                              hipStream_t s);
+
+// Dynamic LDS of the frame kernel for one peak (bytes); must match frame_body's layout.
+int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad);
+// Rows per residue chunk of the detector (the column-transform length).
+int frame_chunk_len(int D);
+// Dynamic LDS of the gradient kernel (bytes).
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x);
+
+}  // namespace mpbp

@@ -1,0 +1,119 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, builds the
+integer tables bit-exactly as the oracle does, and rejects bad descriptors with the
+documented status codes.  No compute call runs here (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synth import CONFIG_NAMES, get_config, make_problem
+from synth.inputs import Problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+B = pytest.importorskip("paper_2312_14907_amd.binding")
+from oracle import mpbp_oracle as O  # noqa: E402
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "mpbp.h")).read()
+    declared = set(re.findall(r"\b(mpbp_[a-z_]+)\s*\(", header))
+    assert declared == set(B.EXPORTED)
+    lib = ctypes.CDLL(B.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+
+
+def _supported_problem(shears, dets=(32, 64), nz=7):
+    return Problem("abi", nz, 40, 37, 12, np.array([[3.0, -2.0, 1.0], [0.5, 4.0, -1.5]]),
+                   np.array(shears, dtype=np.float64), np.array(dets), np.array([[4, 3], [3, 5]]),
+                   np.array([[7, 9], [11, 6]]), np.array([[-3, 2], [1, -4]]))
+
+
+@pytest.mark.parametrize("name", CONFIG_NAMES)
+def test_tables_bit_exact_against_oracle(name):
+    prob = make_problem(get_config(name))
+    plan = B.Plan(prob, device=-1)
+    scan, shear, y_off = plan.mpbp_tables()
+    tab = O.tables(prob)
+    np.testing.assert_array_equal(scan, tab["scan"])
+    np.testing.assert_array_equal(shear, tab["shear"])
+    np.testing.assert_array_equal(y_off, tab["y_off"])
+    assert plan.n_frames == prob.n_frames()
+    assert plan.intensity_size == int(tab["y_off"][-1])
+    plan.close()
+
+
+@pytest.mark.parametrize("shears", [
+    ((0.5, -0.5), (1.5, 2.5)),               # exact halves round away from zero
+    ((0.49999999999999994, -1.0 / 3.0), (0.7, -0.35)),
+    ((0.0, 0.0), (-1.25, 0.75)),
+])
+def test_tables_half_cases(shears):
+    prob = _supported_problem(shears)
+    plan = B.Plan(prob, device=-1)
+    scan, shear, y_off = plan.mpbp_tables()
+    tab = O.tables(prob)
+    np.testing.assert_array_equal(shear, tab["shear"])
+    np.testing.assert_array_equal(scan, tab["scan"])
+    np.testing.assert_array_equal(y_off, tab["y_off"])
+
+
+def _status_of(problem_struct, device=-1):
+    h = ctypes.c_void_p()
+    st = B.lib.mpbp_plan_create(ctypes.byref(problem_struct) if problem_struct is not None else None,
+                                device, ctypes.byref(h))
+    if st == 0:
+        B.lib.mpbp_plan_destroy(h)
+    return st, B.mpbp_last_error()
+
+
+def test_descriptor_validation_codes():
+    good = _supported_problem(((0.3, 0.2), (0.1, -0.4)))
+    assert _status_of(B.make_problem_struct(good))[0] == 0
+    assert _status_of(None)[0] == 1                       # NULL problem
+    s = B.make_problem_struct(good)
+    s.flags = 4
+    assert _status_of(s)[0] == 1                          # reserved flags
+    bad = _supported_problem(((0.3, 0.2), (0.1, -0.4)), dets=(32, 48))
+    st, msg = _status_of(B.make_problem_struct(bad))
+    assert st == 2 and "48" in msg                        # unsupported detector size
+    bad = _supported_problem(((4.0, 0.2), (0.1, -0.4)))   # shear of 12 px leaves a 32 window
+    st, msg = _status_of(B.make_problem_struct(bad))
+    assert st == 3 and "window" in msg
+    s = B.make_problem_struct(good)
+    s.probe_n = 40                                        # support larger than the window
+    assert _status_of(s)[0] == 3
+    s = B.make_problem_struct(good)
+    s.n_peaks = 0
+    assert _status_of(s)[0] == 2
+    s = B.make_problem_struct(good)
+    s.nz = 0
+    assert _status_of(s)[0] == 2
+    s = B.make_problem_struct(good)
+    s.peaks[1].scan_step[0] = 0
+    assert _status_of(s)[0] == 2
+    s = B.make_problem_struct(good)
+    s.peaks[0].g[1] = float("nan")
+    assert _status_of(s)[0] == 1
+    assert _status_of(B.make_problem_struct(good), device=-2)[0] == 1
+
+
+def test_host_only_plan_refuses_compute_and_options():
+    plan = B.Plan(_supported_problem(((0.3, 0.2), (0.1, -0.4))), device=-1)
+    with pytest.raises(B.MPBPError) as e:
+        plan.mpbp_forward(np.zeros(1, np.float32), np.zeros(1, np.float32), np.zeros(1, np.float32),
+                          np.zeros(1, np.float32), stream=0)
+    assert e.value.status == 4
+    with pytest.raises(B.MPBPError) as e:
+        plan.mpbp_set_option(99, 0)
+    assert e.value.status == 1
+    with pytest.raises(B.MPBPError):
+        plan.mpbp_set_option(B.MPBP_OPT_PATH, 2)
+    plan.mpbp_set_option(B.MPBP_OPT_PATH, 1)
+    assert plan.mpbp_get_option(B.MPBP_OPT_PATH) == 1
+    assert plan.mpbp_get_option(B.MPBP_OPT_GRAPH) == 1
+    assert B.lib.mpbp_num_frames(None) == -1
+    assert B.lib.mpbp_intensity_size(None) == -1
+    B.lib.mpbp_plan_destroy(None)
