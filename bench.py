@@ -1,0 +1,238 @@
+"""Benchmark of the MPBP loss-and-gradient evaluation on one MI355X.
+
+One step = one mpbp_loss_grad call over every frame (all Bragg peaks, all scan
+positions) of the workload, inputs resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5_full]
+                    [--no-cpu-baseline] [--no-plain]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (disabled in this build):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+METRIC = "loss+gradient scan-positions/s at stated tol; batched-fused vs plain, % HBM peak"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="c5_full")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0 = auto)")
+    return p.parse_args()
+
+
+def frame_kernel_work(prob, tab_shear):
+    """Algorithmic HBM bytes and nominal FLOPs of the per-frame kernel for all frames.
+
+    Bytes per frame: the measured intensities, 4 D^2 (read once).  FLOPs per frame
+    (5 N log2 N per complex N-point transform): forward and adjoint transforms of the
+    F_x footprint columns and of all D rows, 12 per detector pixel for the modulus
+    residual, 8 per complex multiply-add of the sheared projection (Np^2 Nz).
+    """
+    import math
+    import numpy as np
+    nbytes, flops = 0.0, 0.0
+    for m in range(prob.n_peaks):
+        d = int(prob.det[m])
+        nfr = int(prob.scan_n[m, 0] * prob.scan_n[m, 1])
+        span_x = int(tab_shear[m, :, 1].max() - tab_shear[m, :, 1].min())
+        fx = prob.probe_n + span_x
+        fft = 5.0 * d * math.log2(d)
+        per = 2 * fx * fft + 2 * d * fft + 12.0 * d * d + 8.0 * prob.probe_n ** 2 * prob.nz
+        nbytes += nfr * 4.0 * d * d
+        flops += nfr * per
+    return nbytes, flops
+
+
+def step_bytes(prob):
+    """Algorithmic HBM bytes of one loss+gradient step: y once, plus 32 B per voxel
+    (read u and chi, write their gradients), plus the probe."""
+    nvox = prob.nz * prob.ny * prob.nx
+    y = sum(4.0 * int(prob.det[m]) ** 2 * int(prob.scan_n[m, 0] * prob.scan_n[m, 1])
+            for m in range(prob.n_peaks))
+    return y + 32.0 * nvox + 8.0 * prob.n_peaks * prob.probe_n ** 2
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mpbp_device.hip", "mpbp_dft.hpp", "mpbp_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2312_14907_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the frame kernel from the committed counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"k_frames_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel source sha256\[:16\]:\s*([0-9a-f]{16})", text)
+    t = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def make_inputs(name, torch):
+    """Seeded synthetic workload on the device; y = Poisson counts of the library's
+    own forward model at the true fields."""
+    import numpy as np
+    from paper_2312_14907_amd.binding import Plan
+    from synth import get_config, make_fields, make_problem
+    cfg = get_config(name)
+    prob = make_problem(cfg)
+    f = make_fields(cfg, prob)
+    plan = Plan(prob, 0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    u_true, chi, alpha, probe = d(f["u"]), d(f["chi"]), d(f["alpha"]), d(f["probe"])
+    inten = torch.zeros(plan.intensity_size, dtype=torch.float32, device="cuda:0")
+    plan.mpbp_forward(u_true, chi, alpha, probe, model_intensity=inten)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(cfg["seed"])
+    y = torch.poisson(inten, generator=g) if cfg["noise"] else inten.clone()
+    del inten
+    u = d((f["u"] + f["delta"]).astype(np.float32))
+    torch.cuda.synchronize()
+    return cfg, prob, f, plan, (u, chi, alpha, probe, y)
+
+
+def time_steps(plan, args_t, steps, warmup, torch):
+    u, chi, alpha, probe, y = args_t
+    gu, gc, ga = torch.empty_like(u), torch.empty_like(chi), torch.empty_like(alpha)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        plan.mpbp_loss_grad(u, chi, alpha, probe, y, gu, gc, ga, loss=loss)
+    torch.cuda.synchronize()
+    plan.mpbp_stage_times()                      # reset accumulators
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.mpbp_loss_grad(u, chi, alpha, probe, y, gu, gc, ga, loss=loss)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, plan.mpbp_stage_times(), float(loss.item())
+
+
+def cpu_baseline(prob, f, y_dev, n_frames):
+    """The FP64 oracle on a minibatch of the workload's frames (single process)."""
+    import numpy as np
+    from oracle import mpbp_oracle as O
+
+    class DeviceY:
+        def __init__(self, t):
+            self.t = t
+
+        def __getitem__(self, sl):
+            return self.t[sl].cpu().numpy()
+
+    u = (f["u"] + f["delta"]).astype(np.float32)
+    frames = list(range(n_frames))
+    t0 = time.perf_counter()
+    O.loss_grad(u, f["chi"], f["alpha"], f["probe"], DeviceY(y_dev), prob, frames=frames)
+    dt = time.perf_counter() - t0
+    return n_frames / dt, dt
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2312_14907_amd.binding import MPBP_OPT_PATH, MPBP_OPT_PROFILE
+
+    cfg, prob, f, plan, args_t = make_inputs(args.workload, torch)
+    plan.mpbp_set_option(MPBP_OPT_PROFILE, 1)
+    dt, stages, loss = time_steps(plan, args_t, args.steps, args.warmup, torch)
+    nfr = prob.n_frames()
+    value = nfr * args.steps / dt
+    ms_step = 1e3 * dt / args.steps
+
+    _, shear_tab, _ = plan.mpbp_tables()
+    fk_bytes, fk_flops = frame_kernel_work(prob, shear_tab)
+    fk_ms, fk_n = stages["frames"]
+    fk_avg_s = fk_ms / max(fk_n, 1) / 1e3
+    achieved_tflops = fk_flops / fk_avg_s / 1e12
+    achieved_gbps = fk_bytes / fk_avg_s / 1e9
+    traffic = measured_traffic(args.workload)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "scan-positions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "peaks": prob.n_peaks,
+            "object_zyx": [prob.nz, prob.ny, prob.nx],
+            "frames": nfr,
+            "detector": sorted(set(int(d) for d in prob.det)),
+            "probe": prob.probe_n,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_frames",
+            "achieved": round(achieved_tflops, 3),
+            "peak": round(ALU_PEAK_TFLOPS, 2),
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tflops / ALU_PEAK_TFLOPS, 4),
+            "traffic": traffic,
+            "hbm_achieved_GBps": round(achieved_gbps, 1),
+            "hbm_frac": round(achieved_gbps / HBM_PEAK_GBPS, 4),
+            "avg_launch_ms": round(fk_avg_s * 1e3, 4),
+        },
+        "hbm_step": {
+            "algorithmic_bytes": step_bytes(prob),
+            "achieved_GBps": round(step_bytes(prob) / (dt / args.steps) / 1e9, 1),
+            "frac": round(step_bytes(prob) / (dt / args.steps) / 1e9 / HBM_PEAK_GBPS, 4),
+        },
+        "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
+        "loss": loss,
+    }
+
+    if not args.no_plain:
+        plan.mpbp_set_option(MPBP_OPT_PATH, 1)
+        pdt, _, ploss = time_steps(plan, args_t, 1, 1, torch)
+        plan.mpbp_set_option(MPBP_OPT_PATH, 0)
+        out["plain"] = {"value": round(nfr / pdt, 1), "ms_per_step": round(1e3 * pdt, 2),
+                        "speedup_fused_vs_plain": round((nfr / pdt and value / (nfr / pdt)), 2),
+                        "loss_rel_diff": abs(ploss - loss) / abs(loss)}
+
+    if not args.no_cpu_baseline:
+        n = args.cpu_frames or (1024 if prob.n_frames() >= 1024 else prob.n_frames())
+        rate, cdt = cpu_baseline(prob, f, args_t[4], n)
+        out["cpu_baseline"] = {
+            "value": round(rate, 2), "unit": "scan-positions/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle loss+gradient over the first {n} frames (a minibatch of "
+                      f"{args.workload}), including its whole-volume object build and chain "
+                      f"rule: {cdt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

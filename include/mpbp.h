@@ -81,7 +81,19 @@ enum {
                                 launch per stage per peak and scan position              */
   MPBP_OPT_GRAPH = 2,        /* 1 = replay full-batch calls from a captured hipGraph
                                 (default 1), 0 = direct launches                          */
-  MPBP_OPT_XCD_ORDER = 3     /* 1 = hand each XCD a contiguous band of frames (default) */
+  MPBP_OPT_XCD_ORDER = 3,    /* 1 = hand each XCD a contiguous band of frames (default) */
+  MPBP_OPT_PROFILE = 4       /* 1 = record HIP events around every kernel stage on the
+                                call's stream (read with mpbp_stage_times); default 0    */
+};
+
+/* Kernel stages timed under MPBP_OPT_PROFILE. */
+enum {
+  MPBP_STAGE_OBJECT = 0,     /* per-peak object build, eq. (1)/(3)                        */
+  MPBP_STAGE_FRAMES = 1,     /* per-frame forward model, residual and adjoint, eq. (2)-(4)*/
+  MPBP_STAGE_GRAD = 2,       /* back-projection gather and chain rule                     */
+  MPBP_STAGE_FINALIZE = 3,   /* FP64 reductions                                           */
+  MPBP_STAGE_PLAIN = 4,      /* the whole plain path (MPBP_OPT_PATH = 1)                 */
+  MPBP_NUM_STAGES = 5
 };
 
 /* Validate `problem`, build the integer tables (scan offsets, shear offsets, ragged y
@@ -148,6 +160,14 @@ mpbp_status mpbp_step(mpbp_plan plan, float* u, float* chi, float* alpha,
    value. */
 mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value);
 mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value);
+
+/* Accumulated device time of each stage (MPBP_STAGE_*) over the calls enqueued since
+   the previous mpbp_stage_times call while MPBP_OPT_PROFILE was 1:
+     ms     (host) double [MPBP_NUM_STAGES]  summed milliseconds
+     counts (host) int64  [MPBP_NUM_STAGES]  number of launches timed
+   Waits for the recorded events, then resets the accumulators.  Either pointer may be
+   NULL. */
+mpbp_status mpbp_stage_times(mpbp_plan plan, double* ms, int64_t* counts);
 
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* mpbp_last_error(void);

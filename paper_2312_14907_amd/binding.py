@@ -18,10 +18,12 @@ STATUS_NAMES = {0: "MPBP_OK", 1: "MPBP_ERR_INVALID", 2: "MPBP_ERR_SHAPE", 3: "MP
 MPBP_OPT_PATH = 1
 MPBP_OPT_GRAPH = 2
 MPBP_OPT_XCD_ORDER = 3
+MPBP_OPT_PROFILE = 4
+STAGES = ("object", "frames", "grad", "finalize", "plain")
 
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
             "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",
-            "mpbp_get_option", "mpbp_last_error")
+            "mpbp_get_option", "mpbp_stage_times", "mpbp_last_error")
 
 
 class mpbp_peak(ctypes.Structure):
@@ -67,6 +69,8 @@ def _load():
     lib.mpbp_set_option.restype = st
     lib.mpbp_get_option.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i64)]
     lib.mpbp_get_option.restype = st
+    lib.mpbp_stage_times.argtypes = [vp, vp, vp]
+    lib.mpbp_stage_times.restype = st
     lib.mpbp_last_error.argtypes = []
     lib.mpbp_last_error.restype = ctypes.c_char_p
     return lib
@@ -184,6 +188,13 @@ class Plan:
 
     def mpbp_set_option(self, option, value):
         _check(lib.mpbp_set_option(self.handle, int(option), int(value)))
+
+    def mpbp_stage_times(self):
+        """{stage: (total_ms, launches)} accumulated since the previous call."""
+        ms = np.zeros(len(STAGES), dtype=np.float64)
+        n = np.zeros(len(STAGES), dtype=np.int64)
+        _check(lib.mpbp_stage_times(self.handle, ms.ctypes.data, n.ctypes.data))
+        return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(STAGES)}
 
     def mpbp_get_option(self, option):
         v = ctypes.c_int64()

@@ -81,6 +81,13 @@ struct mpbp_plan_t {
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   mpbp::PlainWork plain;
+  // stage timing (MPBP_OPT_PROFILE)
+  int profile = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  size_t ev_used = 0;
+  double stage_ms[MPBP_NUM_STAGES] = {0};
+  int64_t stage_n[MPBP_NUM_STAGES] = {0};
 };
 
 namespace {
@@ -106,6 +113,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_slots);
   (void)hipFree(p->d_floss);
   (void)hipFree(p->d_apart);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->h_list) (void)hipHostFree(p->h_list);
   if (p->staged) (void)hipEventDestroy(p->staged);
   mpbp::plain_free(&p->plain);
@@ -304,6 +312,31 @@ mpbp_status check_plan(mpbp_plan p) {
   return MPBP_OK;
 }
 
+// Stage timer: records an event pair around the enclosed launches when profiling.
+struct StageTimer {
+  mpbp_plan_t* p;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(mpbp_plan_t* p_, int stage_, hipStream_t s_) : p(p_), stage(stage_), s(s_) {
+    if (!p->profile) return;
+    while (p->ev_pool.size() < p->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      p->ev_pool.push_back(e);
+    }
+    a = p->ev_pool[p->ev_used];
+    b = p->ev_pool[p->ev_used + 1];
+    p->ev_used += 2;
+    (void)hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    p->ev_pending.push_back({stage, {a, b}});
+  }
+};
+
 mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, float* mi, int grad) {
   mpbp::FrameArgs a{};
   a.obj = p->d_obj;
@@ -395,20 +428,28 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
   const int* out_list = frames ? plan->d_list : nullptr;
   hipError_t e;
   if (plan->path == 1) {
+    StageTimer t(plan, MPBP_STAGE_PLAIN, s);
     e = mpbp::plain_forward(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                             plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                             frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
                             model_intensity, plan->d_obj, plan->d_floss, s);
     if (e != hipSuccess) return hip_fail(e, "plain path");
   } else {
-    e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+    {
+      StageTimer t(plan, MPBP_STAGE_OBJECT, s);
+      e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "object kernel");
     mpbp::FrameArgs a = frame_args(plan, y, list, n, model_intensity, 0);
     a.probe = (const float*)probe;
-    e = mpbp::launch_frames(a, plan->lds_fwd, s);
+    {
+      StageTimer t(plan, MPBP_STAGE_FRAMES, s);
+      e = mpbp::launch_frames(a, plan->lds_fwd, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "frame kernel");
   }
   if (loss || frame_loss) {
+    StageTimer t(plan, MPBP_STAGE_FINALIZE, s);
     e = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, nullptr, 0, plan->M, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "finalize kernel");
   }
@@ -434,17 +475,24 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
   int n_part = plan->tiles_x * plan->tiles_y;
   const double* apart = plan->d_apart;
   if (plan->path == 1) {
+    StageTimer t(plan, MPBP_STAGE_PLAIN, s);
     e = mpbp::plain_loss_grad(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                               plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                               frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
                               plan->d_obj, plan->d_floss, grad_u, grad_chi, &apart, &n_part, s);
     if (e != hipSuccess) return hip_fail(e, "plain path");
   } else {
-    e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+    {
+      StageTimer t(plan, MPBP_STAGE_OBJECT, s);
+      e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "object kernel");
     mpbp::FrameArgs a = frame_args(plan, y, list, n, nullptr, 1);
     a.probe = (const float*)probe;
-    e = mpbp::launch_frames(a, plan->lds_grad_frame, s);
+    {
+      StageTimer t(plan, MPBP_STAGE_FRAMES, s);
+      e = mpbp::launch_frames(a, plan->lds_grad_frame, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "frame kernel");
     mpbp::GradArgs g{};
     g.slots = plan->d_slots;
@@ -459,11 +507,17 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     g.maxspan_y = plan->maxspan_y; g.maxspan_x = plan->maxspan_x;
     g.grad_u = grad_u; g.grad_chi = grad_chi;
     g.alpha_part = plan->d_apart;
-    e = mpbp::launch_grad(g, plan->lds_grad, s);
+    {
+      StageTimer t(plan, MPBP_STAGE_GRAD, s);
+      e = mpbp::launch_grad(g, plan->lds_grad, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "gradient kernel");
   }
-  e = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, apart, n_part, plan->M,
-                            grad_alpha, s);
+  {
+    StageTimer t(plan, MPBP_STAGE_FINALIZE, s);
+    e = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, apart, n_part, plan->M,
+                              grad_alpha, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "finalize kernel");
   return MPBP_OK;
 }
@@ -499,6 +553,10 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "xcd order must be 0 or 1");
       plan->xcd = (int)value;
       return MPBP_OK;
+    case MPBP_OPT_PROFILE:
+      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "profile must be 0 or 1");
+      plan->profile = (int)value;
+      return MPBP_OK;
     default:
       return fail(MPBP_ERR_INVALID, "unknown option %d", option);
   }
@@ -510,8 +568,32 @@ mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value) {
     case MPBP_OPT_PATH: *value = plan->path; return MPBP_OK;
     case MPBP_OPT_GRAPH: *value = plan->graph; return MPBP_OK;
     case MPBP_OPT_XCD_ORDER: *value = plan->xcd; return MPBP_OK;
+    case MPBP_OPT_PROFILE: *value = plan->profile; return MPBP_OK;
     default: return fail(MPBP_ERR_INVALID, "unknown option %d", option);
   }
+}
+
+mpbp_status mpbp_stage_times(mpbp_plan plan, double* ms, int64_t* counts) {
+  if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
+  if (plan->device >= 0) (void)hipSetDevice(plan->device);
+  for (auto& pe : plan->ev_pending) {
+    hipError_t e = hipEventSynchronize(pe.second.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, pe.second.first, pe.second.second);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    plan->stage_ms[pe.first] += t;
+    plan->stage_n[pe.first] += 1;
+  }
+  plan->ev_pending.clear();
+  plan->ev_used = 0;
+  for (int i = 0; i < MPBP_NUM_STAGES; ++i) {
+    if (ms) ms[i] = plan->stage_ms[i];
+    if (counts) counts[i] = plan->stage_n[i];
+    plan->stage_ms[i] = 0.0;
+    plan->stage_n[i] = 0;
+  }
+  return MPBP_OK;
 }
 
 const char* mpbp_last_error(void) { return g_err.c_str(); }
