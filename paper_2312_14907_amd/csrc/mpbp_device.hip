@@ -100,20 +100,25 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
   const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * A.ny * A.nx;
   for (int p = tid; p < fy * fx; p += NT) {
-    int qy = p / fx, qx = p - qy * fx;
+    const int qy = p / fx, qx = p - qy * fx;
+    const int by = qy + pk.miny, bx = qx + pk.minx;
     cplx acc = {0.f, 0.f};
-    for (int z = 0; z < nz; ++z) {
-      int2 s = sh[z];
-      int a = qy + pk.miny - s.x;
-      int b = qx + pk.minx - s.y;
-      if ((unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np) {
-        int oy = py + a, ox = px + b;
-        if ((unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx) {
-          cplx o = O[((long long)z * A.ny + oy) * A.nx + ox];
-          cplx pr = Ps[a * np + b];
-          acc = cadd(acc, cmul(pr, o));
-        }
+    constexpr int ZU = 8;
+    for (int z0 = 0; z0 < nz; z0 += ZU) {
+      cplx o[ZU], pr[ZU];
+#pragma unroll
+      for (int k = 0; k < ZU; ++k) {
+        const int z = z0 + k;
+        const int2 s = sh[z < nz ? z : 0];
+        const int a = by - s.x, b = bx - s.y;
+        const int oy = py + a, ox = px + b;
+        const bool ok = z < nz && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np &&
+                        (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
+        o[k] = O[ok ? ((long long)z * A.ny + oy) * A.nx + ox : 0];
+        pr[k] = ok ? Ps[a * np + b] : cplx{0.f, 0.f};
       }
+#pragma unroll
+      for (int k = 0; k < ZU; ++k) acc = cadd(acc, cmul(pr[k], o[k]));
     }
     slot[p] = acc;
   }
@@ -124,7 +129,18 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   float* mif = A.mi ? A.mi + pk.y_off + (long long)j * D * D : nullptr;
   const float invD = 1.0f / (float)D;
   const float invD2 = invD * invD;
+  const int r0m = pk.r0 % L;
   double lsum = 0.0;
+
+  // Intensities are prefetched one row-iteration ahead (across chunk boundaries) so the
+  // HBM latency overlaps the transforms of the current rows.
+  const int rline = tid / RT, rt = tid % RT;
+  float ynext[RQ];
+  if (has_y && rt < RP) {
+    const float* yr = yf + (long long)(R * rline) * D;
+#pragma unroll
+    for (int d = 0; d < RQ; ++d) ynext[d] = yr[rt + RP * d];
+  }
 
   for (int r = 0; r < R; ++r) {
     // ---- column pass: rows k = R k' + r of the y-direction DFT of the footprint ----
@@ -137,14 +153,12 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         if (on && t < CQ) {
 #pragma unroll
           for (int a = 0; a < CP; ++a) {
-            int n1 = t + CQ * a;
+            // footprint rows n = r0 + rr with n = t + CQ a (mod L)
+            int rr = t + CQ * a - r0m;
+            rr += rr < 0 ? L : 0;
             cplx s = {0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-              int n = n1 + L * q;
-              int rr = n - pk.r0;
-              if ((unsigned)rr < (unsigned)fy) s = cadd(s, cmul(slot[rr * fx + col], twD[(n * r) % D]));
-            }
+            for (; rr < fy; rr += L)
+              s = cadd(s, cmul(slot[rr * fx + col], twD[((pk.r0 + rr) * r) % D]));
             v[a] = s;
           }
           DFT<CP, false>::run(v);
@@ -172,9 +186,16 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         const int kp = k0 + line;
         const int k = R * kp + r;
         float yv[RQ];
-        if (has_y && t < RP) {
 #pragma unroll
-          for (int d = 0; d < RQ; ++d) yv[d] = yf[(long long)k * D + t + RP * d];
+        for (int d = 0; d < RQ; ++d) yv[d] = ynext[d];
+        {
+          const int nk0 = k0 + RLINES < L ? k0 + RLINES : 0;
+          const int nr = k0 + RLINES < L ? r : r + 1;
+          if (has_y && t < RP && nr < R) {
+            const float* yr = yf + (long long)(R * (nk0 + line) + nr) * D;
+#pragma unroll
+            for (int d = 0; d < RQ; ++d) ynext[d] = yr[t + RP * d];
+          }
         }
         cplx v[RV];
         if (t < RQ) {
@@ -195,15 +216,18 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           float rowl = 0.f;
 #pragma unroll
           for (int d = 0; d < RQ; ++d) {
-            cplx X = v[d];
-            float a2 = (X.x * X.x + X.y * X.y) * invD2;   // |Psi|^2, Psi = X / D
-            if (mif) mif[(long long)k * D + t + RP * d] = a2;
+            // X = D Psi.  r = |Psi| - sqrt(y); gradient r X / |X| (0 where |X|^2 is
+            // below the smallest normal float, i.e. Psi = 0 in this precision).
+            const cplx X = v[d];
+            const float s2 = X.x * X.x + X.y * X.y;
+            if (mif) mif[(long long)k * D + t + RP * d] = s2 * invD2;
             if (has_y) {
-              float A = sqrtf(a2);
-              float res = A - sqrtf(yv[d]);
-              rowl += 0.5f * res * res;
-              float coef = A > 0.f ? res / A * invD : 0.f;
-              v[d] = cscale(X, coef);
+              const bool nzr = s2 >= 1.17549435e-38f;
+              const float rinv = __builtin_amdgcn_rsqf(nzr ? s2 : 1.0f);
+              const float A = nzr ? s2 * rinv * invD : 0.f;
+              const float res = A - __builtin_amdgcn_sqrtf(yv[d]);
+              rowl = fmaf(0.5f * res, res, rowl);
+              v[d] = cscale(X, nzr ? res * rinv : 0.f);
             }
           }
           lsum += (double)rowl;
@@ -252,15 +276,11 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           DFT<CP, true>::run(v);
 #pragma unroll
           for (int a = 0; a < CP; ++a) {
-            int n1 = t + CQ * a;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-              int n = n1 + L * q;
-              int rr = n - pk.r0;
-              if ((unsigned)rr < (unsigned)fy) {
-                cplx* g = gacc + rr * fx + col;
-                *g = cadd(*g, cmulc(v[a], twD[(n * r) % D]));
-              }
+            int rr = t + CQ * a - r0m;
+            rr += rr < 0 ? L : 0;
+            for (; rr < fy; rr += L) {
+              cplx* g = gacc + rr * fx + col;
+              *g = cadd(*g, cmulc(v[a], twD[((pk.r0 + rr) * r) % D]));
             }
           }
         }
@@ -289,21 +309,15 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   }
 }
 
+// One instance per detector size: the frames of a size class form one launch.
+template <int D>
 __global__ __launch_bounds__(kFrameThreads) void k_frames(FrameArgs A) {
   extern __shared__ cplx smem[];
   const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
   if (idx >= A.n_list) return;
   const int fid = A.list[idx];
   const PeakDev pk = A.peaks[A.peak_of[fid]];
-  switch (pk.D) {
-    case 32: frame_body<32>(A, pk, fid, smem); break;
-    case 64: frame_body<64>(A, pk, fid, smem); break;
-    case 96: frame_body<96>(A, pk, fid, smem); break;
-    case 128: frame_body<128>(A, pk, fid, smem); break;
-    case 192: frame_body<192>(A, pk, fid, smem); break;
-    case 256: frame_body<256>(A, pk, fid, smem); break;
-    default: break;
-  }
+  frame_body<D>(A, pk, fid, smem);
 }
 
 // -------------------------------------------- gather back-projection + chain rule ---
@@ -319,30 +333,41 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
   __syncthreads();
   float s = 0.f;
   for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_grad(GradArgs A) {
+__global__ __launch_bounds__(kGradThreads) void k_grad(GradArgs A) {
   extern __shared__ cplx smem[];
   const int np = A.np, nz = A.nz;
   const int RW = kGradTX + A.maxspan_x;
-  const int RH = kGradTY + A.maxspan_y;
+  const int RS = (kGradTY + A.maxspan_y) * RW;       // one staged region (complex)
   cplx* Ps = smem;                                   // np * np
   int2* sh = reinterpret_cast<int2*>(Ps + np * np);  // nz
-  cplx* reg = reinterpret_cast<cplx*>(sh + nz);      // RH * RW
-  float* red = reinterpret_cast<float*>(reg + RH * RW);
+  cplx* reg = reinterpret_cast<cplx*>(sh + nz);      // kGradBatch * RS
+  double* apl = reinterpret_cast<double*>(reg + kGradBatch * RS);  // alpha partials
+  float* red = reinterpret_cast<float*>(apl + kMaxPeaksDev);       // block reduction
+  // per staged frame: py, px, a_lo, b_lo, rows, cols, slot offset (2 ints); two buffers
+  int* meta = reinterpret_cast<int*>(red + 16);
+  unsigned char* actf = reinterpret_cast<unsigned char*>(meta + 2 * kGradBatch * 8);  // candidates
 
   const int tid = threadIdx.x;
   const int tx = tid % kGradTX, ty = (tid / kGradTX) % kGradTY, tz = tid / (kGradTX * kGradTY);
-  const int bx = blockIdx.x % A.tiles_x, by = blockIdx.x / A.tiles_x;
+  // Tiles are handed out so that each XCD (blocks are dispatched round-robin over the
+  // 8 XCDs) walks a contiguous band of tile rows: neighbouring tiles read the same
+  // frames' footprints, which then stay in that XCD's L2.
+  const int tile = frame_block_index(blockIdx.x, gridDim.x, 1);
+  if (tile >= A.tiles_x * A.tiles_y) return;
+  const int bx = tile % A.tiles_x, by = tile / A.tiles_x;
   const int x0 = bx * kGradTX, y0 = by * kGradTY;
   const int x = x0 + tx, y = y0 + ty;
   const bool inb = x < A.nx && y < A.ny;
   const long long nvox = (long long)nz * A.ny * A.nx;
-
-  float apart_acc[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) apart_acc[m] = 0.f;
+  // this thread's element positions in a staged region (row-major with stride RW)
+  const int e0r = tid / RW, e0c = tid - e0r * RW;
+  const int e1 = tid + kGradThreads;
+  const int e1r = e1 / RW, e1c = e1 - e1r * RW;
+  if (tid < kMaxPeaksDev) apl[tid] = 0.0;
 
   for (int zb = 0; zb < nz; zb += kGradZB) {
     float gux[kGradZPer], guy[kGradZPer], guz[kGradZPer], gch[kGradZPer];
@@ -351,72 +376,106 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs A) {
 
     for (int m = 0; m < A.n_peaks; ++m) {
       const PeakDev pk = A.peaks[m];
-      __syncthreads();
-      const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
-      for (int k = tid; k < np * np; k += blockDim.x) Ps[k] = probe[k];
-      for (int z = tid; z < nz; z += blockDim.x) {
-        const int* s = A.shear + 2 * (m * nz + z);
-        sh[z] = make_int2(s[0], s[1]);
-      }
-      cplx acc[kGradZPer];
-#pragma unroll
-      for (int i = 0; i < kGradZPer; ++i) acc[i] = {0.f, 0.f};
-
+      // Frames of this peak whose windows meet the tile: a rectangle of the raster.
       const int iy_lo = max(0, -floordiv(-(y0 - np + 1 - pk.oy), pk.sy));
       const int iy_hi = min(pk.rows - 1, floordiv(y0 + kGradTY - 1 - pk.oy, pk.sy));
       const int ix_lo = max(0, -floordiv(-(x0 - np + 1 - pk.ox), pk.sx));
       const int ix_hi = min(pk.cols - 1, floordiv(x0 + kGradTX - 1 - pk.ox, pk.sx));
-      for (int iy = iy_lo; iy <= iy_hi; ++iy) {
-        for (int ix = ix_lo; ix <= ix_hi; ++ix) {
-          const int j = iy * pk.cols + ix;
-          const int fid = pk.frame_base + j;
-          if (!A.active[fid]) continue;
-          const int py = pk.oy + iy * pk.sy, px = pk.ox + ix * pk.sx;
-          const int a_lo = max(0, y0 - py), a_hi = min(np, y0 + kGradTY - py);
-          const int b_lo = max(0, x0 - px), b_hi = min(np, x0 + kGradTX - px);
-          if (a_hi <= a_lo || b_hi <= b_lo) continue;
-          const int rh = a_hi - a_lo + pk.spany, rw = b_hi - b_lo + pk.spanx;
-          const cplx* slot = reinterpret_cast<const cplx*>(A.slots) + pk.slot_off +
-                             (long long)j * pk.fy * pk.fx;
-          __syncthreads();
-          for (int k = tid; k < rh * rw; k += blockDim.x) {
-            int rr = k / rw, cc = k - rr * rw;
-            reg[rr * RW + cc] = slot[(a_lo + rr) * pk.fx + b_lo + cc];
-          }
-          __syncthreads();
-          const int a = y - py, b = x - px;
-          if (inb && a >= a_lo && a < a_hi && b >= b_lo && b < b_hi) {
-            const cplx p = Ps[a * np + b];
+      const int ncx = ix_hi - ix_lo + 1;
+      const int ncand = (iy_hi >= iy_lo && ncx > 0) ? (iy_hi - iy_lo + 1) * ncx : 0;
+      __syncthreads();
+      const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
+      for (int k = tid; k < np * np; k += kGradThreads) Ps[k] = probe[k];
+      for (int z = tid; z < nz; z += kGradThreads) {
+        const int* s = A.shear + 2 * (m * nz + z);
+        sh[z] = make_int2(s[0], s[1]);
+      }
+      // minibatch flags of the candidate frames, loaded in parallel
+      for (int c = tid; c < ncand; c += kGradThreads) {
+        const int cy = iy_lo + c / ncx, cx = ix_lo + c % ncx;
+        actf[c] = A.active[pk.frame_base + cy * pk.cols + cx];
+      }
+      cplx acc[kGradZPer];
 #pragma unroll
-            for (int i = 0; i < kGradZPer; ++i) {
-              const int z = zb + tz + kGradTZ * i;
-              if (z < nz) {
-                int2 s = sh[z];
-                int fr = a - a_lo + s.x - pk.miny;
-                int fc = b - b_lo + s.y - pk.minx;
-                acc[i] = cadd(acc[i], cmulc(reg[fr * RW + fc], p));   // conj(P) g_psi
+      for (int i = 0; i < kGradZPer; ++i) acc[i] = {0.f, 0.f};
+      __syncthreads();
+
+      int iy = iy_lo, ix = ix_lo, ci = 0;
+      int par = 0;
+      while (iy <= iy_hi && ix <= ix_hi) {
+        // Collect up to kGradBatch frames of the minibatch (the same walk in every lane;
+        // lane 0 records them in the buffer this batch owns).
+        int* mb = meta + par * kGradBatch * 8;
+        par ^= 1;
+        int nb = 0;
+        while (nb < kGradBatch && iy <= iy_hi) {
+          const int cy = iy, cx = ix;
+          if (++ix > ix_hi) { ix = ix_lo; ++iy; }
+          const int j = cy * pk.cols + cx;
+          if (!actf[ci++]) continue;
+          if (tid == 0) {
+            const int py = pk.oy + cy * pk.sy, px = pk.ox + cx * pk.sx;
+            const int al = max(0, y0 - py), bl = max(0, x0 - px);
+            const long long so = pk.slot_off + (long long)j * pk.fy * pk.fx + al * pk.fx + bl;
+            int* q = mb + nb * 8;
+            q[0] = py; q[1] = px; q[2] = al; q[3] = bl;
+            q[4] = min(np, y0 + kGradTY - py) - al + pk.spany;
+            q[5] = min(np, x0 + kGradTX - px) - bl + pk.spanx;
+            q[6] = (int)(so & 0x7fffffff);
+            q[7] = (int)(so >> 31);
+          }
+          ++nb;
+        }
+        if (nb == 0) break;
+        __syncthreads();
+#pragma unroll 1
+        for (int k = 0; k < nb; ++k) {
+          const int* q = mb + k * 8;
+          const long long so = (long long)q[6] | ((long long)q[7] << 31);
+          const cplx* slot = reinterpret_cast<const cplx*>(A.slots) + so;
+          if (e0r < q[4] && e0c < q[5]) reg[k * RS + e0r * RW + e0c] = slot[e0r * pk.fx + e0c];
+          if (e1r < q[4] && e1c < q[5]) reg[k * RS + e1r * RW + e1c] = slot[e1r * pk.fx + e1c];
+        }
+        __syncthreads();
+        if (inb) {
+#pragma unroll 1
+          for (int k = 0; k < nb; ++k) {
+            const int* q = mb + k * 8;
+            const int a = y - q[0], b = x - q[1];
+            if ((unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np) {
+              const cplx p = Ps[a * np + b];
+              const cplx* rg = reg + k * RS + (a - q[2] - pk.miny) * RW + (b - q[3] - pk.minx);
+#pragma unroll
+              for (int i = 0; i < kGradZPer; ++i) {
+                const int z = zb + tz + kGradTZ * i;
+                if (z < nz) {
+                  const int2 s = sh[z];
+                  acc[i] = cadd(acc[i], cmulc(rg[s.x * RW + s.y], p));   // conj(P) g_psi
+                }
               }
             }
           }
         }
       }
-      // chain rule through O_m = alpha_m chi exp(i G_m . u)
+      // chain rule through O_m = alpha_m chi exp(i G_m . u); 32-bit voxel offsets from
+      // uniform bases (the plan limits 3 * nvox to 2^32)
       float ap = 0.f;
       if (inb) {
         const float al = A.alpha[m];
+        const unsigned nv = (unsigned)nvox;
 #pragma unroll
         for (int i = 0; i < kGradZPer; ++i) {
           const int z = zb + tz + kGradTZ * i;
           if (z < nz) {
-            const long long v = ((long long)z * A.ny + y) * A.nx + x;
-            const float ux = A.u[v], uy = A.u[nvox + v], uzv = A.u[2 * nvox + v];
+            const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
+            const float ux = A.u[v], uy = A.u[nv + v], uzv = A.u[2u * nv + v];
             const float ch = A.chi[v];
             const float phi = pk.gx * ux + pk.gy * uy + pk.gz * uzv;
             float s, c;
-            sincosf(phi, &s, &c);
+            __sincosf(phi, &s, &c);
             const cplx g = acc[i];
-            const float re = g.x * c + g.y * s;          // Re(conj(g) e^{i phi})
-            const float dphi = al * ch * (g.y * c - g.x * s);  // Im(g conj(O))
+            const float re = g.x * c + g.y * s;                 // Re(conj(g) e^{i phi})
+            const float dphi = al * ch * (g.y * c - g.x * s);   // Im(g conj(O))
             gux[i] += pk.gx * dphi;
             guy[i] += pk.gy * dphi;
             guz[i] += pk.gz * dphi;
@@ -425,33 +484,26 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs A) {
           }
         }
       }
-#pragma unroll
-      for (int mm = 0; mm < 16; ++mm)
-        if (mm == m) apart_acc[mm] += ap;
+      const float apb = block_sum_f(ap, red);
+      if (tid == 0) apl[m] += (double)apb;
     }
     if (inb) {
+      const unsigned nv = (unsigned)nvox;
 #pragma unroll
       for (int i = 0; i < kGradZPer; ++i) {
         const int z = zb + tz + kGradTZ * i;
         if (z < nz) {
-          const long long v = ((long long)z * A.ny + y) * A.nx + x;
+          const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
           A.grad_u[v] = gux[i];
-          A.grad_u[nvox + v] = guy[i];
-          A.grad_u[2 * nvox + v] = guz[i];
+          A.grad_u[nv + v] = guy[i];
+          A.grad_u[2u * nv + v] = guz[i];
           A.grad_chi[v] = gch[i];
         }
       }
     }
   }
-  for (int m = 0; m < A.n_peaks; ++m) {
-    float v = 0.f;
-#pragma unroll
-    for (int mm = 0; mm < 16; ++mm)
-      if (mm == m) v = apart_acc[mm];
-    float s = block_sum_f(v, red);
-    if (tid == 0) A.alpha_part[(long long)blockIdx.x * A.n_peaks + m] = (double)s;
-    __syncthreads();
-  }
+  __syncthreads();
+  if (tid < A.n_peaks) A.alpha_part[(long long)tile * A.n_peaks + tid] = apl[tid];
 }
 
 // --------------------------------------------------------------------- finalize ---
@@ -519,16 +571,30 @@ hipError_t launch_object(const float* u, const float* chi, const float* alpha, c
   return hipGetLastError();
 }
 
-hipError_t launch_frames(const FrameArgs& a, int lds_bytes, hipStream_t s) {
+template <int D>
+static hipError_t launch_frames_d(const FrameArgs& a, int lds_bytes, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_frames, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_frames<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
     attr_set = true;
   }
-  unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
+  const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
-  k_frames<<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);
+  k_frames<D><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);
   return hipGetLastError();
+}
+
+hipError_t launch_frames(int D, const FrameArgs& a, int lds_bytes, hipStream_t s) {
+  switch (D) {
+    case 32: return launch_frames_d<32>(a, lds_bytes, s);
+    case 64: return launch_frames_d<64>(a, lds_bytes, s);
+    case 96: return launch_frames_d<96>(a, lds_bytes, s);
+    case 128: return launch_frames_d<128>(a, lds_bytes, s);
+    case 192: return launch_frames_d<192>(a, lds_bytes, s);
+    case 256: return launch_frames_d<256>(a, lds_bytes, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s) {
@@ -537,8 +603,8 @@ hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s) {
     (void)hipFuncSetAttribute((const void*)k_grad, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  unsigned grid = (unsigned)(a.tiles_x * a.tiles_y);
-  k_grad<<<dim3(grid), dim3(kGradTX * kGradTY * kGradTZ), lds_bytes, s>>>(a);
+  const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
+  k_grad<<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);
   return hipGetLastError();
 }
 
@@ -601,8 +667,9 @@ int frame_chunk_len(int D) {
   }
 }
 
-int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x) {
-  return np * np * 8 + nz * 8 + (kGradTY + maxspan_y) * (kGradTX + maxspan_x) * 8 + 64;
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand) {
+  return np * np * 8 + nz * 8 + kGradBatch * (kGradTY + maxspan_y) * (kGradTX + maxspan_x) * 8 +
+         kMaxPeaksDev * 8 + 64 + 2 * kGradBatch * 8 * 4 + max_cand;
 }
 
 }  // namespace mpbp

@@ -58,8 +58,12 @@ struct mpbp_plan_t {
   std::vector<int64_t> y_off;    // [M+1]
   std::vector<int32_t> peak_of;  // [F]
   std::vector<int32_t> order;    // processing order of the full batch
+  struct SizeClass { int D, begin, count, lds_fwd, lds_grad; };
+  std::vector<SizeClass> classes;      // full batch: frames of one detector size, in `order`
+  std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch
   int lds_fwd = 0, lds_grad_frame = 0, lds_grad = 0;
   int maxspan_y = 0, maxspan_x = 0;
+  int max_cand = 0;
   int tiles_x = 0, tiles_y = 0;
   long long slots_cplx = 0;
   // options
@@ -71,6 +75,7 @@ struct mpbp_plan_t {
   int* d_shear = nullptr;
   int* d_order = nullptr;          // full-batch processing order
   int* d_list = nullptr;           // caller's list (subset calls)
+  int* d_list_sorted = nullptr;    // the caller's list grouped by detector size
   unsigned char* d_active = nullptr;     // per-frame minibatch mask (subset calls)
   unsigned char* d_active_all = nullptr; // all ones
   float* d_obj = nullptr;
@@ -107,6 +112,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_shear);
   (void)hipFree(p->d_order);
   (void)hipFree(p->d_list);
+  (void)hipFree(p->d_list_sorted);
   (void)hipFree(p->d_active);
   (void)hipFree(p->d_active_all);
   (void)hipFree(p->d_obj);
@@ -131,6 +137,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   if (!pr->peaks) return fail(MPBP_ERR_INVALID, "peaks is NULL");
   const long long nvox = (long long)pr->nz * pr->ny * pr->nx;
   if (nvox * pr->n_peaks > (1LL << 40)) return fail(MPBP_ERR_SHAPE, "object grid too large");
+  if (3 * nvox >= (1LL << 32)) return fail(MPBP_ERR_UNSUPPORTED, "3 * nz * ny * nx must be below 2^32");
   if (pr->nz > 4096) return fail(MPBP_ERR_SHAPE, "nz too large (%d)", pr->nz);
 
   p->nz = pr->nz; p->ny = pr->ny; p->nx = pr->nx; p->np = pr->probe_n; p->M = pr->n_peaks;
@@ -213,7 +220,16 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   }
   p->ylen = p->y_off[p->M];
   p->slots_cplx = slot;
-  p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x);
+  if ((mpbp::kGradTY + p->maxspan_y) * (mpbp::kGradTX + p->maxspan_x) > 2 * mpbp::kGradThreads)
+    return fail(MPBP_ERR_UNSUPPORTED, "shear spans %d x %d exceed the gradient kernel's staging tile",
+                p->maxspan_y, p->maxspan_x);
+  p->max_cand = 0;
+  for (const auto& d : p->pdev) {
+    const int cy = std::min(d.rows, (mpbp::kGradTY + np - 2) / d.sy + 2);
+    const int cx = std::min(d.cols, (mpbp::kGradTX + np - 2) / d.sx + 2);
+    p->max_cand = std::max(p->max_cand, cy * cx);
+  }
+  p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand);
   if (p->lds_grad > kMaxLds) return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", p->lds_grad);
   p->tiles_x = (p->nx + mpbp::kGradTX - 1) / mpbp::kGradTX;
   p->tiles_y = (p->ny + mpbp::kGradTY - 1) / mpbp::kGradTY;
@@ -223,8 +239,18 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   for (int m = 0; m < p->M; ++m) pk[m] = m;
   std::stable_sort(pk.begin(), pk.end(), [&](int a, int b) { return p->pdev[a].D > p->pdev[b].D; });
   p->order.clear();
-  for (int m : pk)
-    for (int j = 0; j < p->pdev[m].nfr; ++j) p->order.push_back(p->pdev[m].frame_base + j);
+  p->classes.clear();
+  for (int m : pk) {
+    const PeakDev& d = p->pdev[m];
+    const int lf = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false);
+    if (p->classes.empty() || p->classes.back().D != d.D)
+      p->classes.push_back({d.D, (int)p->order.size(), 0, 0, 0});
+    auto& c = p->classes.back();
+    c.count += d.nfr;
+    c.lds_fwd = std::max(c.lds_fwd, lf);
+    c.lds_grad = std::max(c.lds_grad, d.lds_bytes);
+    for (int j = 0; j < d.nfr; ++j) p->order.push_back(d.frame_base + j);
+  }
   return MPBP_OK;
 }
 
@@ -243,6 +269,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_shear, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_order, p->F);
   ALLOC(p->d_list, p->F);
+  ALLOC(p->d_list_sorted, p->F);
   ALLOC(p->d_active, p->F);
   ALLOC(p->d_active_all, p->F);
   ALLOC(p->d_obj, (size_t)p->M * p->nvox * 2);
@@ -250,7 +277,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_floss, p->F);
   ALLOC(p->d_apart, (size_t)p->tiles_x * p->tiles_y * p->M);
 #undef ALLOC
-  e = hipHostMalloc((void**)&p->h_list, std::max<int64_t>(p->F, 1) * sizeof(int), hipHostMallocDefault);
+  e = hipHostMalloc((void**)&p->h_list, std::max<int64_t>(2 * p->F, 1) * sizeof(int), hipHostMallocDefault);
   if (e != hipSuccess) return fail(MPBP_ERR_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
   e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
   if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -289,8 +316,22 @@ mpbp_status stage_frames(mpbp_plan_t* p, const int32_t* frames, int64_t n, hipSt
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
   }
   std::memcpy(p->h_list, frames, (size_t)n * sizeof(int));
+  // grouped by detector size in the order of the full-batch classes
+  int* sorted = p->h_list + p->F;
+  int pos = 0;
+  p->sub_classes.clear();
+  for (const auto& c : p->classes) {
+    mpbp_plan_t::SizeClass sc = c;
+    sc.begin = pos;
+    for (int64_t i = 0; i < n; ++i)
+      if (p->pdev[p->peak_of[frames[i]]].D == c.D) sorted[pos++] = frames[i];
+    sc.count = pos - sc.begin;
+    p->sub_classes.push_back(sc);
+  }
   if (n > 0) {
     e = hipMemcpyAsync(p->d_list, p->h_list, (size_t)n * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->d_list_sorted, sorted, (size_t)n * sizeof(int), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync frame list");
   }
   e = hipEventRecord(p->staged, s);
@@ -336,6 +377,21 @@ struct StageTimer {
     p->ev_pending.push_back({stage, {a, b}});
   }
 };
+
+// Enqueue the per-frame kernel for every detector-size class of the call.
+hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset, bool grad, hipStream_t s) {
+  const auto& cls = subset ? p->sub_classes : p->classes;
+  const int* list = subset ? p->d_list_sorted : p->d_order;
+  for (const auto& c : cls) {
+    if (c.count == 0) continue;
+    mpbp::FrameArgs a = base;
+    a.list = list + c.begin;
+    a.n_list = c.count;
+    hipError_t e = mpbp::launch_frames(c.D, a, grad ? c.lds_grad : c.lds_fwd, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, float* mi, int grad) {
   mpbp::FrameArgs a{};
@@ -444,7 +500,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
     a.probe = (const float*)probe;
     {
       StageTimer t(plan, MPBP_STAGE_FRAMES, s);
-      e = mpbp::launch_frames(a, plan->lds_fwd, s);
+      e = enqueue_frames(plan, a, frames != nullptr, false, s);
     }
     if (e != hipSuccess) return hip_fail(e, "frame kernel");
   }
@@ -491,7 +547,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     a.probe = (const float*)probe;
     {
       StageTimer t(plan, MPBP_STAGE_FRAMES, s);
-      e = mpbp::launch_frames(a, plan->lds_grad_frame, s);
+      e = enqueue_frames(plan, a, frames != nullptr, true, s);
     }
     if (e != hipSuccess) return hip_fail(e, "frame kernel");
     mpbp::GradArgs g{};
@@ -505,6 +561,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     g.nz = plan->nz; g.ny = plan->ny; g.nx = plan->nx; g.np = plan->np;
     g.tiles_x = plan->tiles_x; g.tiles_y = plan->tiles_y;
     g.maxspan_y = plan->maxspan_y; g.maxspan_x = plan->maxspan_x;
+    g.max_cand = plan->max_cand;
     g.grad_u = grad_u; g.grad_chi = grad_chi;
     g.alpha_part = plan->d_apart;
     {

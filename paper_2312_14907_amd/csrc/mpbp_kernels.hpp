@@ -57,14 +57,18 @@ struct GradArgs {
   int nz, ny, nx, np;
   int tiles_x, tiles_y;
   int maxspan_y, maxspan_x;  // largest shear span over peaks
+  int max_cand;              // largest number of frames of one peak meeting one tile
   float* grad_u;
   float* grad_chi;
   double* alpha_part;      // [n_blocks][M]
 };
 
 constexpr int kFrameThreads = 256;
-constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 4;  // 256 threads
+constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 8;  // 512 threads
+constexpr int kGradThreads = kGradTX * kGradTY * kGradTZ;
 constexpr int kGradZB = 32;                             // z per pass of the grad kernel
 constexpr int kGradZPer = kGradZB / kGradTZ;            // z per thread per pass
+constexpr int kGradBatch = 8;                           // frames staged per barrier pair
+constexpr int kMaxPeaksDev = 16;
 
 }  // namespace mpbp

@@ -8,7 +8,8 @@ namespace mpbp {
 
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
                          int n_peaks, long long nvox, float* obj, hipStream_t s);
-hipError_t launch_frames(const FrameArgs& a, int lds_bytes, hipStream_t s);
+// Frames of one detector size D (a.list holds only such frames).
+hipError_t launch_frames(int D, const FrameArgs& a, int lds_bytes, hipStream_t s);
 hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
@@ -22,6 +23,6 @@ int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad);
 // Rows per residue chunk of the detector (the column-transform length).
 int frame_chunk_len(int D);
 // Dynamic LDS of the gradient kernel (bytes).
-int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x);
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand);
 
 }  // namespace mpbp
