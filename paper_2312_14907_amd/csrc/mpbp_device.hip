@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+#include <vector>
+
 #include "mpbp_dft.hpp"
 #include "mpbp_kernels.hpp"
 #include "mpbp_launch.hpp"
@@ -49,7 +52,13 @@ __device__ __forceinline__ int frame_block_index(int b, int n, int xcd) {
   return (b & 7) * per + (b >> 3);
 }
 
-template <int D>
+// FB bounds the footprint (fy, fx <= FB).  The footprint is placed at the window's
+// origin: |Psi| does not depend on where the exit wave sits inside the window (a
+// translation only multiplies Psi by a phase ramp), and the residual r Psi/|Psi| carries
+// the same ramp, which the inverse transform undoes.  With the footprint at the origin,
+// only the first ceil(FB / Q) inputs of each lane are nonzero and only those outputs are
+// needed, so the compiler drops the rest of the first and last DFT stages.
+template <int D, int FB>
 __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
   using RC = LineCfg<D>;
   constexpr int RP = RC::P, RQ = RC::Q, RT = RC::TPL;
@@ -63,28 +72,40 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   constexpr int RLINES = NT / RT;
   constexpr int CLINES = NT / CT;
   constexpr int EXL = RQ * (RP + 1);  // exchange buffer per row line
+  constexpr int NAR = (FB + RQ - 1) / RQ < RP ? (FB + RQ - 1) / RQ : RP;  // live row inputs
+  constexpr int NAC = (FB + CQ - 1) / CQ < CP ? (FB + CQ - 1) / CQ : CP;  // live column inputs
 
   const int tid = threadIdx.x;
   const int np = A.np, nz = A.nz;
   const int fy = pk.fy, fx = pk.fx, fxp = pk.fxp;
+  // chunk row k starts at k * fxp + k / 8: the skew spreads the column pass's lanes
+  // (8 rows apart) over the LDS banks
+  auto TRI = [fxp](int k) { return k * fxp + (k >> 3); };
   const int m = A.peak_of[fid];
   const int py = A.scan[2 * fid], px = A.scan[2 * fid + 1];
   const int j = fid - pk.frame_base;
 
-  // LDS layout (complex units): twiddles | footprint gradient | chunk | exchange | shear
-  cplx* twD = sm;
-  cplx* gacc = twD + D;
+  // LDS layout (complex units):
+  //   tw2  [D]      row twiddles, tw2[c * RQ + t] = w_D^{t c} (lane-contiguous)
+  //   twc  [L]      column twiddles, twc[c * CQ + t] = w_L^{t c}
+  //   ftw  [R][fy]  residue-fold twiddles w_D^{rr r}
+  //   gacc [fy][fx] footprint gradient
+  //   Tr   [L][fxp] chunk of the column-transformed footprint, row k at k*fxp + k/8
+  //   exch          per-line exchange buffers (probe staged here during the projection)
+  //   sh   [nz]     shear offsets
+  cplx* tw2 = sm;
+  cplx* twc = tw2 + D;
+  cplx* ftw = twc + L;
+  cplx* gacc = ftw + R * fy;
   cplx* Tr = gacc + (A.grad ? fy * fx : 0);
-  cplx* exch = Tr + L * fxp;
+  cplx* exch = Tr + L * fxp + L / 8;
   const int exch_sz = RLINES * EXL > np * np ? RLINES * EXL : np * np;
   int2* sh = reinterpret_cast<int2*>(exch + exch_sz);
   cplx* Ps = exch;  // probe staged in the exchange area during the projection
 
-  // twiddles w_D^k = exp(-2 pi i k / D)
-  for (int k = tid; k < D; k += NT) {
-    double s, c;
-    sincospi(-2.0 * (double)k / (double)D, &s, &c);
-    twD[k] = {(float)c, (float)s};
+  {
+    const cplx* tsrc = reinterpret_cast<const cplx*>(A.tw) + pk.tw_off;
+    for (int k = tid; k < D + L + R * fy; k += NT) tw2[k] = tsrc[k];
   }
   const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
   for (int k = tid; k < np * np; k += NT) Ps[k] = probe[k];
@@ -129,7 +150,6 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   float* mif = A.mi ? A.mi + pk.y_off + (long long)j * D * D : nullptr;
   const float invD = 1.0f / (float)D;
   const float invD2 = invD * invD;
-  const int r0m = pk.r0 % L;
   double lsum = 0.0;
 
   // Intensities are prefetched one row-iteration ahead (across chunk boundaries) so the
@@ -153,25 +173,24 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         if (on && t < CQ) {
 #pragma unroll
           for (int a = 0; a < CP; ++a) {
-            // footprint rows n = r0 + rr with n = t + CQ a (mod L)
-            int rr = t + CQ * a - r0m;
-            rr += rr < 0 ? L : 0;
+            // footprint rows rr = t + CQ a (mod L)
             cplx s = {0.f, 0.f};
-            for (; rr < fy; rr += L)
-              s = cadd(s, cmul(slot[rr * fx + col], twD[((pk.r0 + rr) * r) % D]));
+            if (a < NAC)
+              for (int rr = t + CQ * a; rr < fy; rr += L)
+                s = cadd(s, cmul(slot[rr * fx + col], ftw[r * fy + rr]));
             v[a] = s;
           }
           DFT<CP, false>::run(v);
 #pragma unroll
-          for (int c = 0; c < CP; ++c) Tr[(c + CP * t) * fxp + col] = cmul(v[c], twD[t * c * R]);
+          for (int c = 0; c < CP; ++c) Tr[TRI(c + CP * t) + col] = cmul(v[c], twc[c * CQ + t]);
         }
         wave_sync();
         if (on && t < CP) {
 #pragma unroll
-          for (int b = 0; b < CQ; ++b) v[b] = Tr[(t + CP * b) * fxp + col];
+          for (int b = 0; b < CQ; ++b) v[b] = Tr[TRI(t + CP * b) + col];
           DFT<CQ, false>::run(v);
 #pragma unroll
-          for (int d = 0; d < CQ; ++d) Tr[(t + CP * d) * fxp + col] = v[d];
+          for (int d = 0; d < CQ; ++d) Tr[TRI(t + CP * d) + col] = v[d];
         }
         wave_sync();
       }
@@ -201,12 +220,12 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         if (t < RQ) {
 #pragma unroll
           for (int a = 0; a < RP; ++a) {
-            int cc = t + RQ * a - pk.c0;
-            v[a] = ((unsigned)cc < (unsigned)fx) ? Tr[kp * fxp + cc] : cplx{0.f, 0.f};
+            const int cc = t + RQ * a;
+            v[a] = (a < NAR && cc < fx) ? Tr[TRI(kp) + cc] : cplx{0.f, 0.f};
           }
           DFT<RP, false>::run(v);
 #pragma unroll
-          for (int c = 0; c < RP; ++c) ex[t * (RP + 1) + c] = cmul(v[c], twD[t * c]);
+          for (int c = 0; c < RP; ++c) ex[t * (RP + 1) + c] = cmul(v[c], tw2[c * RQ + t]);
         }
         wave_sync();
         if (t < RP) {
@@ -241,12 +260,12 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           wave_sync();
           if (t < RQ) {
 #pragma unroll
-            for (int c = 0; c < RP; ++c) v[c] = cmulc(ex[t * (RP + 1) + c], twD[t * c]);
+            for (int c = 0; c < RP; ++c) v[c] = cmulc(ex[t * (RP + 1) + c], tw2[c * RQ + t]);
             DFT<RP, true>::run(v);
 #pragma unroll
-            for (int a = 0; a < RP; ++a) {
-              int cc = t + RQ * a - pk.c0;
-              if ((unsigned)cc < (unsigned)fx) Tr[kp * fxp + cc] = v[a];
+            for (int a = 0; a < NAR; ++a) {
+              const int cc = t + RQ * a;
+              if (cc < fx) Tr[TRI(kp) + cc] = v[a];
             }
           }
         }
@@ -264,23 +283,21 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         cplx v[CV];
         if (on && t < CP) {
 #pragma unroll
-          for (int d = 0; d < CQ; ++d) v[d] = Tr[(t + CP * d) * fxp + col];
+          for (int d = 0; d < CQ; ++d) v[d] = Tr[TRI(t + CP * d) + col];
           DFT<CQ, true>::run(v);
 #pragma unroll
-          for (int b = 0; b < CQ; ++b) Tr[(t + CP * b) * fxp + col] = v[b];
+          for (int b = 0; b < CQ; ++b) Tr[TRI(t + CP * b) + col] = v[b];
         }
         wave_sync();
         if (on && t < CQ) {
 #pragma unroll
-          for (int c = 0; c < CP; ++c) v[c] = cmulc(Tr[(c + CP * t) * fxp + col], twD[t * c * R]);
+          for (int c = 0; c < CP; ++c) v[c] = cmulc(Tr[TRI(c + CP * t) + col], twc[c * CQ + t]);
           DFT<CP, true>::run(v);
 #pragma unroll
-          for (int a = 0; a < CP; ++a) {
-            int rr = t + CQ * a - r0m;
-            rr += rr < 0 ? L : 0;
-            for (; rr < fy; rr += L) {
+          for (int a = 0; a < NAC; ++a) {
+            for (int rr = t + CQ * a; rr < fy; rr += L) {
               cplx* g = gacc + rr * fx + col;
-              *g = cadd(*g, cmulc(v[a], twD[((pk.r0 + rr) * r) % D]));
+              *g = cadd(*g, cmulc(v[a], ftw[r * fy + rr]));
             }
           }
         }
@@ -310,14 +327,14 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
 }
 
 // One instance per detector size: the frames of a size class form one launch.
-template <int D>
+template <int D, int FB>
 __global__ __launch_bounds__(kFrameThreads) void k_frames(FrameArgs A) {
   extern __shared__ cplx smem[];
   const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
   if (idx >= A.n_list) return;
   const int fid = A.list[idx];
   const PeakDev pk = A.peaks[A.peak_of[fid]];
-  frame_body<D>(A, pk, fid, smem);
+  frame_body<D, FB>(A, pk, fid, smem);
 }
 
 // -------------------------------------------- gather back-projection + chain rule ---
@@ -571,30 +588,38 @@ hipError_t launch_object(const float* u, const float* chi, const float* alpha, c
   return hipGetLastError();
 }
 
-template <int D>
+template <int D, int FB>
 static hipError_t launch_frames_d(const FrameArgs& a, int lds_bytes, hipStream_t s) {
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_frames<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_frames<D, FB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
-  k_frames<D><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);
+  k_frames<D, FB><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_frames(int D, const FrameArgs& a, int lds_bytes, hipStream_t s) {
-  switch (D) {
-    case 32: return launch_frames_d<32>(a, lds_bytes, s);
-    case 64: return launch_frames_d<64>(a, lds_bytes, s);
-    case 96: return launch_frames_d<96>(a, lds_bytes, s);
-    case 128: return launch_frames_d<128>(a, lds_bytes, s);
-    case 192: return launch_frames_d<192>(a, lds_bytes, s);
-    case 256: return launch_frames_d<256>(a, lds_bytes, s);
-    default: return hipErrorInvalidValue;
-  }
+int frame_bound(int D, int f) {
+  if (D == 32) return 32;
+  if (f <= 48) return 48;
+  if (f <= 64) return 64;
+  return D;
+}
+
+hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s) {
+#define MPBP_CASE(d, fb) \
+  if (D == d && FB == fb) return launch_frames_d<d, fb>(a, lds_bytes, s);
+  MPBP_CASE(32, 32)
+  MPBP_CASE(64, 48) MPBP_CASE(64, 64)
+  MPBP_CASE(96, 48) MPBP_CASE(96, 64) MPBP_CASE(96, 96)
+  MPBP_CASE(128, 48) MPBP_CASE(128, 64) MPBP_CASE(128, 128)
+  MPBP_CASE(192, 48) MPBP_CASE(192, 64) MPBP_CASE(192, 192)
+  MPBP_CASE(256, 48) MPBP_CASE(256, 64) MPBP_CASE(256, 256)
+#undef MPBP_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s) {
@@ -639,7 +664,8 @@ static int lds_for(int fy, int fx, int fxp, int np, int nz, bool grad) {
   constexpr int RLINES = kFrameThreads / RC::TPL;
   constexpr int EXL = RC::Q * (RC::P + 1);
   const long long exch = RLINES * EXL > np * np ? RLINES * EXL : np * np;
-  const long long cpx = D + (grad ? (long long)fy * fx : 0) + (long long)L * fxp + exch;
+  const long long cpx = D + L + (long long)(D / L) * fy + (grad ? (long long)fy * fx : 0) +
+                        (long long)L * fxp + L / 8 + exch;
   return (int)(cpx * 8 + (long long)nz * 8);
 }
 
@@ -652,6 +678,37 @@ int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad) {
     case 192: return lds_for<192>(fy, fx, fxp, np, nz, grad);
     case 256: return lds_for<256>(fy, fx, fxp, np, nz, grad);
     default: return -1;
+  }
+}
+
+template <int D>
+static void twiddles_for(int fy, std::vector<float>& out) {
+  using RC = LineCfg<D>;
+  constexpr int L = ColLen<D>::L;
+  constexpr int R = D / L;
+  using CC = LineCfg<L>;
+  auto w = [&](long long k, int n) {   // exp(-2 pi i k / n), in double
+    const double a = -2.0 * M_PI * (double)(k % n) / (double)n;
+    out.push_back((float)std::cos(a));
+    out.push_back((float)std::sin(a));
+  };
+  for (int c = 0; c < RC::P; ++c)
+    for (int t = 0; t < RC::Q; ++t) w((long long)t * c, D);
+  for (int c = 0; c < CC::P; ++c)
+    for (int t = 0; t < CC::Q; ++t) w((long long)t * c, L);
+  for (int r = 0; r < R; ++r)
+    for (int rr = 0; rr < fy; ++rr) w((long long)rr * r, D);
+}
+
+bool frame_twiddles(int D, int fy, std::vector<float>& out) {
+  switch (D) {
+    case 32: twiddles_for<32>(fy, out); return true;
+    case 64: twiddles_for<64>(fy, out); return true;
+    case 96: twiddles_for<96>(fy, out); return true;
+    case 128: twiddles_for<128>(fy, out); return true;
+    case 192: twiddles_for<192>(fy, out); return true;
+    case 256: twiddles_for<256>(fy, out); return true;
+    default: return false;
   }
 }
 

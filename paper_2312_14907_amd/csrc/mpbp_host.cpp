@@ -58,7 +58,7 @@ struct mpbp_plan_t {
   std::vector<int64_t> y_off;    // [M+1]
   std::vector<int32_t> peak_of;  // [F]
   std::vector<int32_t> order;    // processing order of the full batch
-  struct SizeClass { int D, begin, count, lds_fwd, lds_grad; };
+  struct SizeClass { int D, FB, begin, count, lds_fwd, lds_grad; };
   std::vector<SizeClass> classes;      // full batch: frames of one detector size, in `order`
   std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch
   int lds_fwd = 0, lds_grad_frame = 0, lds_grad = 0;
@@ -82,6 +82,8 @@ struct mpbp_plan_t {
   float* d_slots = nullptr;
   double* d_floss = nullptr;
   double* d_apart = nullptr;
+  float* d_tw = nullptr;           // twiddle tables of all peaks
+  std::vector<float> tw;
   int* h_list = nullptr;           // pinned staging of the caller's list
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
@@ -119,6 +121,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_slots);
   (void)hipFree(p->d_floss);
   (void)hipFree(p->d_apart);
+  (void)hipFree(p->d_tw);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->h_list) (void)hipHostFree(p->h_list);
   if (p->staged) (void)hipEventDestroy(p->staged);
@@ -148,6 +151,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   p->y_off.assign(p->M + 1, 0);
   p->scan.clear();
   p->peak_of.clear();
+  p->tw.clear();
   const int np = p->np;
   const int zref = p->nz / 2;
   long long slot = 0;
@@ -200,6 +204,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     d.y_off = p->y_off[m];
     d.slot_off = slot;
     d.gx = (float)k.g[0]; d.gy = (float)k.g[1]; d.gz = (float)k.g[2];
+    d.tw_off = (long long)(p->tw.size() / 2);
+    mpbp::frame_twiddles(d.D, d.fy, p->tw);
     d.lds_bytes = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, true);
     if (d.lds_bytes > kMaxLds)
       return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d needs %d B of LDS", m, d.fy, d.fx, d.lds_bytes);
@@ -237,14 +243,21 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   // frames in raster order.
   std::vector<int> pk(p->M);
   for (int m = 0; m < p->M; ++m) pk[m] = m;
-  std::stable_sort(pk.begin(), pk.end(), [&](int a, int b) { return p->pdev[a].D > p->pdev[b].D; });
+  auto fb = [&](int m) {
+    const PeakDev& d = p->pdev[m];
+    return mpbp::frame_bound(d.D, std::max(d.fy, d.fx));
+  };
+  std::stable_sort(pk.begin(), pk.end(), [&](int a, int b) {
+    if (p->pdev[a].D != p->pdev[b].D) return p->pdev[a].D > p->pdev[b].D;
+    return fb(a) < fb(b);
+  });
   p->order.clear();
   p->classes.clear();
   for (int m : pk) {
     const PeakDev& d = p->pdev[m];
     const int lf = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false);
-    if (p->classes.empty() || p->classes.back().D != d.D)
-      p->classes.push_back({d.D, (int)p->order.size(), 0, 0, 0});
+    if (p->classes.empty() || p->classes.back().D != d.D || p->classes.back().FB != fb(m))
+      p->classes.push_back({d.D, fb(m), (int)p->order.size(), 0, 0, 0});
     auto& c = p->classes.back();
     c.count += d.nfr;
     c.lds_fwd = std::max(c.lds_fwd, lf);
@@ -276,6 +289,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_slots, (size_t)p->slots_cplx * 2);
   ALLOC(p->d_floss, p->F);
   ALLOC(p->d_apart, (size_t)p->tiles_x * p->tiles_y * p->M);
+  ALLOC(p->d_tw, p->tw.size());
 #undef ALLOC
   e = hipHostMalloc((void**)&p->h_list, std::max<int64_t>(2 * p->F, 1) * sizeof(int), hipHostMallocDefault);
   if (e != hipSuccess) return fail(MPBP_ERR_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
@@ -286,6 +300,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   if (e == hipSuccess) e = hipMemcpy(p->d_peak_of, p->peak_of.data(), p->peak_of.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_shear, p->shear.data(), p->shear.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), p->order.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_tw, p->tw.data(), p->tw.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy tables");
   std::vector<unsigned char> ones(p->F, 1);
   e = hipMemcpy(p->d_active_all, ones.data(), p->F, hipMemcpyHostToDevice);
@@ -324,7 +339,10 @@ mpbp_status stage_frames(mpbp_plan_t* p, const int32_t* frames, int64_t n, hipSt
     mpbp_plan_t::SizeClass sc = c;
     sc.begin = pos;
     for (int64_t i = 0; i < n; ++i)
-      if (p->pdev[p->peak_of[frames[i]]].D == c.D) sorted[pos++] = frames[i];
+      if (p->pdev[p->peak_of[frames[i]]].D == c.D &&
+          mpbp::frame_bound(c.D, std::max(p->pdev[p->peak_of[frames[i]]].fy,
+                                          p->pdev[p->peak_of[frames[i]]].fx)) == c.FB)
+        sorted[pos++] = frames[i];
     sc.count = pos - sc.begin;
     p->sub_classes.push_back(sc);
   }
@@ -387,7 +405,7 @@ hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset,
     mpbp::FrameArgs a = base;
     a.list = list + c.begin;
     a.n_list = c.count;
-    hipError_t e = mpbp::launch_frames(c.D, a, grad ? c.lds_grad : c.lds_fwd, s);
+    hipError_t e = mpbp::launch_frames(c.D, c.FB, a, grad ? c.lds_grad : c.lds_fwd, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -405,6 +423,7 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   a.shear = p->d_shear;
   a.slots = p->d_slots;
   a.floss = p->d_floss;
+  a.tw = p->d_tw;
   a.mi = mi;
   a.nz = p->nz; a.ny = p->ny; a.nx = p->nx; a.np = p->np;
   a.grad = grad;

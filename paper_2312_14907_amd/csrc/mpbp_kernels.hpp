@@ -24,6 +24,7 @@ struct PeakDev {
   long long slot_off;  // complex offset of frame 0's footprint slot in the workspace
   float gx, gy, gz; // Bragg vector (rad/nm)
   int lds_bytes;    // dynamic LDS the frame kernel needs for this peak
+  long long tw_off; // complex offset of this peak's twiddle tables (D + L + R * fy)
 };
 
 struct FrameArgs {
@@ -37,7 +38,8 @@ struct FrameArgs {
   const PeakDev* peaks;    // [M]
   const int* shear;        // [M][nz][2]
   float* slots;            // complex64 footprint slots (exit wave, then its gradient)
-  double* floss;           // [n_list] per-frame loss (list order)
+  double* floss;           // per-frame loss, indexed by global frame id
+  const float* tw;         // complex64 twiddle tables of all peaks
   float* mi;               // model intensity (ragged like y) or null
   int nz, ny, nx, np;
   int grad;                // 1: also compute the footprint gradient

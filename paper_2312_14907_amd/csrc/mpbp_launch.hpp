@@ -2,14 +2,18 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "mpbp_kernels.hpp"
 
 namespace mpbp {
 
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
                          int n_peaks, long long nvox, float* obj, hipStream_t s);
-// Frames of one detector size D (a.list holds only such frames).
-hipError_t launch_frames(int D, const FrameArgs& a, int lds_bytes, hipStream_t s);
+// Frames of one detector size D whose footprints fit FB x FB (a.list holds only such
+// frames); FB = frame_bound(D, largest footprint side).
+hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s);
+int frame_bound(int D, int footprint);
 hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
@@ -20,6 +24,10 @@ hipError_t launch_mark_active(unsigned char* act, long long n_frames, const int*
 
 // Dynamic LDS of the frame kernel for one peak (bytes); must match frame_body's layout.
 int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad);
+// Append the frame kernel's twiddle tables of one peak (complex64 as float pairs):
+// row twiddles [D], column twiddles [L], residue-fold twiddles [R][fy] (footprint at
+// the window origin).
+bool frame_twiddles(int D, int fy, std::vector<float>& out);
 // Rows per residue chunk of the detector (the column-transform length).
 int frame_chunk_len(int D);
 // Dynamic LDS of the gradient kernel (bytes).
