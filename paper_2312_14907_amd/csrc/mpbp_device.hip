@@ -71,8 +71,13 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   constexpr int NT = kFrameThreads;
   constexpr int RLINES = NT / RT;
   constexpr int CLINES = NT / CT;
-  constexpr int EXL = RQ * (RP + 1);  // exchange buffer per row line
+  constexpr int EXL = RQ * (RP + 1);  // exchange buffer per row line (floats: one part at a time)
   constexpr int NAR = (FB + RQ - 1) / RQ < RP ? (FB + RQ - 1) / RQ : RP;  // live row inputs
+  // lane t takes part in a pass of Q (or P) lanes; true for every lane when Q == TPL
+  auto rowq = [](int t) { return RQ == RT || t < RQ; };
+  auto rowp = [](int t) { return RP == RT || t < RP; };
+  auto colq = [](int t) { return CQ == CT || t < CQ; };
+  auto colp = [](int t) { return CP == CT || t < CP; };
   constexpr int NAC = (FB + CQ - 1) / CQ < CP ? (FB + CQ - 1) / CQ : CP;  // live column inputs
 
   const int tid = threadIdx.x;
@@ -89,26 +94,28 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   //   tw2  [D]      row twiddles, tw2[c * RQ + t] = w_D^{t c} (lane-contiguous)
   //   twc  [L]      column twiddles, twc[c * CQ + t] = w_L^{t c}
   //   ftw  [R][fy]  residue-fold twiddles w_D^{rr r}
+  //   psi  [fy][fx] exit wave on the footprint
   //   gacc [fy][fx] footprint gradient
   //   Tr   [L][fxp] chunk of the column-transformed footprint, row k at k*fxp + k/8
-  //   exch          per-line exchange buffers (probe staged here during the projection)
+  //   exch          per-line exchange buffers (with Tr: staged slices during the projection)
   //   sh   [nz]     shear offsets
   cplx* tw2 = sm;
   cplx* twc = tw2 + D;
   cplx* ftw = twc + L;
-  cplx* gacc = ftw + R * fy;
+  cplx* psi = ftw + R * fy;
+  cplx* gacc = psi + fy * fx;
   cplx* Tr = gacc + (A.grad ? fy * fx : 0);
   cplx* exch = Tr + L * fxp + L / 8;
-  const int exch_sz = RLINES * EXL > np * np ? RLINES * EXL : np * np;
+  // the exchange area also holds (with the chunk buffer before it) kProjG staged slices
+  const int exch_min = kProjG * np * np - (L * fxp + L / 8);
+  const int exch_sz = (RLINES * EXL + 1) / 2 > exch_min ? (RLINES * EXL + 1) / 2 : exch_min;
   int2* sh = reinterpret_cast<int2*>(exch + exch_sz);
-  cplx* Ps = exch;  // probe staged in the exchange area during the projection
 
   {
     const cplx* tsrc = reinterpret_cast<const cplx*>(A.tw) + pk.tw_off;
     for (int k = tid; k < D + L + R * fy; k += NT) tw2[k] = tsrc[k];
   }
   const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
-  for (int k = tid; k < np * np; k += NT) Ps[k] = probe[k];
   for (int z = tid; z < nz; z += NT) {
     const int* s = A.shear + 2 * (m * nz + z);
     sh[z] = make_int2(s[0], s[1]);
@@ -120,28 +127,90 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   // ---- eq. (2): R diag(P) S O -> exit wave on the footprint (gather over slices) ----
   cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
   const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * A.ny * A.nx;
-  for (int p = tid; p < fy * fx; p += NT) {
-    const int qy = p / fx, qx = p - qy * fx;
-    const int by = qy + pk.miny, bx = qx + pk.minx;
-    cplx acc = {0.f, 0.f};
-    constexpr int ZU = 8;
-    for (int z0 = 0; z0 < nz; z0 += ZU) {
-      cplx o[ZU], pr[ZU];
+  // The illuminated slices W_z = P * O[z, window] are staged kProjG at a time in the
+  // chunk / exchange area (idle during the projection), the next group's object values
+  // already in flight in registers; each lane then gathers its footprint pixels
+  //   psi[q] += W_z[q + min shear - s(z)]   (zero outside the probe support).
+  // Addresses are clamped and contributions selected, so the gather has no branches
+  // and all slices' LDS reads are in flight together.
+  {
+    const int np2 = np * np;
+    cplx* Wb = Tr;
+    const int* shz = A.shear + 2 * m * nz;   // uniform: scalar loads
+    cplx pv[kProjE];
+    int off[kProjE];
 #pragma unroll
-      for (int k = 0; k < ZU; ++k) {
-        const int z = z0 + k;
-        const int2 s = sh[z < nz ? z : 0];
-        const int a = by - s.x, b = bx - s.y;
-        const int oy = py + a, ox = px + b;
-        const bool ok = z < nz && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np &&
-                        (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
-        o[k] = O[ok ? ((long long)z * A.ny + oy) * A.nx + ox : 0];
-        pr[k] = ok ? Ps[a * np + b] : cplx{0.f, 0.f};
-      }
-#pragma unroll
-      for (int k = 0; k < ZU; ++k) acc = cadd(acc, cmul(pr[k], o[k]));
+    for (int i = 0; i < kProjE; ++i) {
+      const int e = tid + NT * i;
+      const int a = e / np, b = e - (e / np) * np;
+      const int oy = py + a, ox = px + b;
+      const bool ok = e < np2 && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
+      pv[i] = ok ? probe[e < np2 ? e : 0] : cplx{0.f, 0.f};
+      off[i] = ok ? oy * A.nx + ox : 0;
     }
-    slot[p] = acc;
+    const long long plane = (long long)A.ny * A.nx;
+    cplx on[kProjG][kProjE];
+#pragma unroll
+    for (int g = 0; g < kProjG; ++g)
+#pragma unroll
+      for (int i = 0; i < kProjE; ++i) on[g][i] = O[(long long)(g < nz ? g : 0) * plane + off[i]];
+    int pby[kProjPix], pbx[kProjPix];
+    bool pok[kProjPix];
+#pragma unroll
+    for (int h = 0; h < kProjPix; ++h) {
+      const int p = tid + NT * h;
+      pok[h] = p < fy * fx;
+      const int qy = p / fx;
+      pby[h] = qy + pk.miny;
+      pbx[h] = p - qy * fx + pk.minx;
+      if (pok[h]) psi[p] = {0.f, 0.f};
+    }
+    for (int z0 = 0; z0 < nz; z0 += kProjG) {
+      __syncthreads();
+#pragma unroll
+      for (int g = 0; g < kProjG; ++g)
+#pragma unroll
+        for (int i = 0; i < kProjE; ++i)
+          if (tid + NT * i < np2) Wb[g * np2 + tid + NT * i] = cmul(pv[i], on[g][i]);
+#pragma unroll
+      for (int g = 0; g < kProjG; ++g) {
+        const int z = z0 + kProjG + g;
+        const long long zo = (long long)(z < nz ? z : 0) * plane;
+#pragma unroll
+        for (int i = 0; i < kProjE; ++i) on[g][i] = O[zo + off[i]];
+      }
+      int ssy[kProjG], ssx[kProjG];
+      bool zok[kProjG];
+#pragma unroll
+      for (int g = 0; g < kProjG; ++g) {
+        const int z = z0 + g;
+        zok[g] = z < nz;
+        ssy[g] = shz[2 * (zok[g] ? z : 0)];
+        ssx[g] = shz[2 * (zok[g] ? z : 0) + 1];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < kProjPix; ++h) {
+        cplx w[kProjG];
+        bool ok[kProjG];
+#pragma unroll
+        for (int g = 0; g < kProjG; ++g) {
+          const int a = pby[h] - ssy[g], b = pbx[h] - ssx[g];
+          ok[g] = zok[g] && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
+          w[g] = Wb[g * np2 + (ok[g] ? a * np + b : 0)];
+        }
+        cplx acc = {0.f, 0.f};
+#pragma unroll
+        for (int g = 0; g < kProjG; ++g) {
+          acc.x += ok[g] ? w[g].x : 0.f;
+          acc.y += ok[g] ? w[g].y : 0.f;
+        }
+        if (pok[h]) {
+          const int p = tid + NT * h;
+          psi[p] = cadd(psi[p], acc);
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -156,10 +225,10 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   // HBM latency overlaps the transforms of the current rows.
   const int rline = tid / RT, rt = tid % RT;
   float ynext[RQ];
-  if (has_y && rt < RP) {
+  if (has_y && rowp(rt)) {
     const float* yr = yf + (long long)(R * rline) * D;
 #pragma unroll
-    for (int d = 0; d < RQ; ++d) ynext[d] = yr[rt + RP * d];
+    for (int d = 0; d < RQ; ++d) ynext[d] = __builtin_nontemporal_load(yr + rt + RP * d);
   }
 
   for (int r = 0; r < R; ++r) {
@@ -170,14 +239,23 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         const int col = col0 + line;
         const bool on = col < fx;
         cplx v[CV];
-        if (on && t < CQ) {
+        if (on && colq(t)) {
 #pragma unroll
           for (int a = 0; a < CP; ++a) {
             // footprint rows rr = t + CQ a (mod L)
             cplx s = {0.f, 0.f};
-            if (a < NAC)
-              for (int rr = t + CQ * a; rr < fy; rr += L)
-                s = cadd(s, cmul(slot[rr * fx + col], ftw[r * fy + rr]));
+            if (a < NAC) {
+              if constexpr (FB <= L) {
+                const int rr = t + CQ * a;
+                const bool ok = rr < fy;
+                const cplx pv = psi[(ok ? rr : 0) * fx + col];
+                const cplx tv = ftw[r * fy + (ok ? rr : 0)];
+                s = ok ? cmul(pv, tv) : cplx{0.f, 0.f};
+              } else {
+                for (int rr = t + CQ * a; rr < fy; rr += L)
+                  s = cadd(s, cmul(psi[rr * fx + col], ftw[r * fy + rr]));
+              }
+            }
             v[a] = s;
           }
           DFT<CP, false>::run(v);
@@ -185,7 +263,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           for (int c = 0; c < CP; ++c) Tr[TRI(c + CP * t) + col] = cmul(v[c], twc[c * CQ + t]);
         }
         wave_sync();
-        if (on && t < CP) {
+        if (on && colp(t)) {
 #pragma unroll
           for (int b = 0; b < CQ; ++b) v[b] = Tr[TRI(t + CP * b) + col];
           DFT<CQ, false>::run(v);
@@ -198,9 +276,11 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
     __syncthreads();
 
     // ---- row pass: x-direction DFT, modulus residual (eq. (4)), inverse DFT ----
+    // The exchange between the two passes moves real parts, then imaginary parts,
+    // through a per-line float buffer (all lanes of a line are in one wavefront).
     {
       const int line = tid / RT, t = tid % RT;
-      cplx* ex = exch + line * EXL;
+      float* ex = reinterpret_cast<float*>(exch) + line * EXL;
       for (int k0 = 0; k0 < L; k0 += RLINES) {
         const int kp = k0 + line;
         const int k = R * kp + r;
@@ -210,27 +290,46 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         {
           const int nk0 = k0 + RLINES < L ? k0 + RLINES : 0;
           const int nr = k0 + RLINES < L ? r : r + 1;
-          if (has_y && t < RP && nr < R) {
+          if (has_y && rowp(t) && nr < R) {
             const float* yr = yf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
-            for (int d = 0; d < RQ; ++d) ynext[d] = yr[t + RP * d];
+            for (int d = 0; d < RQ; ++d) ynext[d] = __builtin_nontemporal_load(yr + t + RP * d);
           }
         }
         cplx v[RV];
-        if (t < RQ) {
+        if (rowq(t)) {
 #pragma unroll
           for (int a = 0; a < RP; ++a) {
             const int cc = t + RQ * a;
-            v[a] = (a < NAR && cc < fx) ? Tr[TRI(kp) + cc] : cplx{0.f, 0.f};
+            if (a < NAR) {
+              const cplx tv = Tr[TRI(kp) + (cc < fx ? cc : 0)];
+              v[a] = cc < fx ? tv : cplx{0.f, 0.f};
+            } else {
+              v[a] = {0.f, 0.f};
+            }
           }
           DFT<RP, false>::run(v);
 #pragma unroll
-          for (int c = 0; c < RP; ++c) ex[t * (RP + 1) + c] = cmul(v[c], tw2[c * RQ + t]);
+          for (int c = 0; c < RP; ++c) {
+            v[c] = cmul(v[c], tw2[c * RQ + t]);
+            ex[t * (RP + 1) + c] = v[c].x;
+          }
         }
         wave_sync();
-        if (t < RP) {
+        float re[RQ];
+        if (rowp(t)) {
 #pragma unroll
-          for (int b = 0; b < RQ; ++b) v[b] = ex[b * (RP + 1) + t];
+          for (int b = 0; b < RQ; ++b) re[b] = ex[b * (RP + 1) + t];
+        }
+        wave_sync();
+        if (rowq(t)) {
+#pragma unroll
+          for (int c = 0; c < RP; ++c) ex[t * (RP + 1) + c] = v[c].y;
+        }
+        wave_sync();
+        if (rowp(t)) {
+#pragma unroll
+          for (int b = 0; b < RQ; ++b) v[b] = {re[b], ex[b * (RP + 1) + t]};
           DFT<RQ, false>::run(v);
           float rowl = 0.f;
 #pragma unroll
@@ -252,15 +351,27 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           lsum += (double)rowl;
         }
         if (A.grad) {
-          if (t < RP) {
+          wave_sync();
+          if (rowp(t)) {
             DFT<RQ, true>::run(v);
 #pragma unroll
-            for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t] = v[b];
+            for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t] = v[b].x;
           }
           wave_sync();
-          if (t < RQ) {
+          float rex[RP];
+          if (rowq(t)) {
 #pragma unroll
-            for (int c = 0; c < RP; ++c) v[c] = cmulc(ex[t * (RP + 1) + c], tw2[c * RQ + t]);
+            for (int c = 0; c < RP; ++c) rex[c] = ex[t * (RP + 1) + c];
+          }
+          wave_sync();
+          if (rowp(t)) {
+#pragma unroll
+            for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t] = v[b].y;
+          }
+          wave_sync();
+          if (rowq(t)) {
+#pragma unroll
+            for (int c = 0; c < RP; ++c) v[c] = cmulc(cplx{rex[c], ex[t * (RP + 1) + c]}, tw2[c * RQ + t]);
             DFT<RP, true>::run(v);
 #pragma unroll
             for (int a = 0; a < NAR; ++a) {
@@ -281,7 +392,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         const int col = col0 + line;
         const bool on = col < fx;
         cplx v[CV];
-        if (on && t < CP) {
+        if (on && colp(t)) {
 #pragma unroll
           for (int d = 0; d < CQ; ++d) v[d] = Tr[TRI(t + CP * d) + col];
           DFT<CQ, true>::run(v);
@@ -289,15 +400,31 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           for (int b = 0; b < CQ; ++b) Tr[TRI(t + CP * b) + col] = v[b];
         }
         wave_sync();
-        if (on && t < CQ) {
+        if (on && colq(t)) {
 #pragma unroll
           for (int c = 0; c < CP; ++c) v[c] = cmulc(Tr[TRI(c + CP * t) + col], twc[c * CQ + t]);
           DFT<CP, true>::run(v);
+          if constexpr (FB <= L) {
+            cplx gv[NAC], tv[NAC];
 #pragma unroll
-          for (int a = 0; a < NAC; ++a) {
-            for (int rr = t + CQ * a; rr < fy; rr += L) {
-              cplx* g = gacc + rr * fx + col;
-              *g = cadd(*g, cmulc(v[a], ftw[r * fy + rr]));
+            for (int a = 0; a < NAC; ++a) {
+              const int rr = t + CQ * a;
+              const int rc = rr < fy ? rr : 0;
+              gv[a] = gacc[rc * fx + col];
+              tv[a] = ftw[r * fy + rc];
+            }
+#pragma unroll
+            for (int a = 0; a < NAC; ++a) {
+              const int rr = t + CQ * a;
+              if (rr < fy) gacc[rr * fx + col] = cadd(gv[a], cmulc(v[a], tv[a]));
+            }
+          } else {
+#pragma unroll
+            for (int a = 0; a < NAC; ++a) {
+              for (int rr = t + CQ * a; rr < fy; rr += L) {
+                cplx* g = gacc + rr * fx + col;
+                *g = cadd(*g, cmulc(v[a], ftw[r * fy + rr]));
+              }
             }
           }
         }
@@ -663,9 +790,10 @@ static int lds_for(int fy, int fx, int fxp, int np, int nz, bool grad) {
   constexpr int L = ColLen<D>::L;
   constexpr int RLINES = kFrameThreads / RC::TPL;
   constexpr int EXL = RC::Q * (RC::P + 1);
-  const long long exch = RLINES * EXL > np * np ? RLINES * EXL : np * np;
-  const long long cpx = D + L + (long long)(D / L) * fy + (grad ? (long long)fy * fx : 0) +
-                        (long long)L * fxp + L / 8 + exch;
+  const long long exch_min = (long long)kProjG * np * np - ((long long)L * fxp + L / 8);
+  const long long exch = (RLINES * EXL + 1) / 2 > exch_min ? (RLINES * EXL + 1) / 2 : exch_min;
+  const long long cpx = D + L + (long long)(D / L) * fy + (long long)fy * fx +
+                        (grad ? (long long)fy * fx : 0) + (long long)L * fxp + L / 8 + exch;
   return (int)(cpx * 8 + (long long)nz * 8);
 }
 

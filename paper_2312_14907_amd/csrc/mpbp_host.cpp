@@ -135,6 +135,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   if (pr->nz < 1 || pr->ny < 1 || pr->nx < 1)
     return fail(MPBP_ERR_SHAPE, "object grid must be positive (nz=%d ny=%d nx=%d)", pr->nz, pr->ny, pr->nx);
   if (pr->probe_n < 1) return fail(MPBP_ERR_SHAPE, "probe_n must be positive (%d)", pr->probe_n);
+  if (pr->probe_n * pr->probe_n > mpbp::kProjE * mpbp::kFrameThreads)
+    return fail(MPBP_ERR_UNSUPPORTED, "probe_n %d above the supported 32", pr->probe_n);
   if (pr->n_peaks < 1 || pr->n_peaks > kMaxPeaks)
     return fail(MPBP_ERR_SHAPE, "n_peaks must be in [1, %d] (got %d)", kMaxPeaks, pr->n_peaks);
   if (!pr->peaks) return fail(MPBP_ERR_INVALID, "peaks is NULL");
@@ -195,6 +197,9 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     d.spany = hi[0] - lo[0]; d.spanx = hi[1] - lo[1];
     d.r0 = cw + lo[0]; d.c0 = cw + lo[1];
     d.fy = np + d.spany; d.fx = np + d.spanx;
+    if (d.fy * d.fx > mpbp::kProjPix * mpbp::kFrameThreads)
+      return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d above %d pixels", m, d.fy, d.fx,
+                  mpbp::kProjPix * mpbp::kFrameThreads);
     d.fxp = d.fx | 1;
     d.rows = k.scan_n[0]; d.cols = k.scan_n[1];
     d.nfr = d.rows * d.cols;

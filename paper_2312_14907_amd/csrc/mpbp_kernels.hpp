@@ -66,6 +66,9 @@ struct GradArgs {
 };
 
 constexpr int kFrameThreads = 256;
+constexpr int kProjG = 4;     // slices staged per projection step
+constexpr int kProjE = 4;     // probe pixels staged per lane (probe_n^2 <= 4 * 256)
+constexpr int kProjPix = 8;   // footprint pixels per lane (fy * fx <= 8 * 256)
 constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 8;  // 512 threads
 constexpr int kGradThreads = kGradTX * kGradTY * kGradTZ;
 constexpr int kGradZB = 32;                             // z per pass of the grad kernel
