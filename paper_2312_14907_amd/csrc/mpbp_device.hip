@@ -107,7 +107,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   cplx* Tr = gacc + (A.grad ? fy * fx : 0);
   cplx* exch = Tr + L * fxp + L / 8;
   // the exchange area also holds (with the chunk buffer before it) kProjG staged slices
-  const int exch_min = kProjG * np * np - (L * fxp + L / 8);
+  const int exch_min = kProjG * (np + 1) * (np + 1) - (L * fxp + L / 8);
   const int exch_sz = (RLINES * EXL + 1) / 2 > exch_min ? (RLINES * EXL + 1) / 2 : exch_min;
   int2* sh = reinterpret_cast<int2*>(exch + exch_sz);
 
@@ -131,14 +131,20 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   // chunk / exchange area (idle during the projection), the next group's object values
   // already in flight in registers; each lane then gathers its footprint pixels
   //   psi[q] += W_z[q + min shear - s(z)]   (zero outside the probe support).
-  // Addresses are clamped and contributions selected, so the gather has no branches
-  // and all slices' LDS reads are in flight together.
+  // A staged slice is (np + 1) x (np + 1) with a zero last row and column: offsets
+  // outside the support are clamped onto them, so the gather has no tests or branches.
   {
+    const int np1 = np + 1;
+    const int sw = np1 * np1;
     const int np2 = np * np;
     cplx* Wb = Tr;
     const int* shz = A.shear + 2 * m * nz;   // uniform: scalar loads
+    for (int k = tid; k < kProjG * (2 * np + 1); k += NT) {
+      const int g = k / (2 * np + 1), e = k - g * (2 * np + 1);
+      Wb[g * sw + (e <= np ? np * np1 + e : (e - np - 1) * np1 + np)] = {0.f, 0.f};
+    }
     cplx pv[kProjE];
-    int off[kProjE];
+    int off[kProjE], wo[kProjE];
 #pragma unroll
     for (int i = 0; i < kProjE; ++i) {
       const int e = tid + NT * i;
@@ -147,23 +153,25 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
       const bool ok = e < np2 && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
       pv[i] = ok ? probe[e < np2 ? e : 0] : cplx{0.f, 0.f};
       off[i] = ok ? oy * A.nx + ox : 0;
+      wo[i] = e < np2 ? a * np1 + b : -1;
     }
     const long long plane = (long long)A.ny * A.nx;
     cplx on[kProjG][kProjE];
 #pragma unroll
-    for (int g = 0; g < kProjG; ++g)
+    for (int g = 0; g < kProjG; ++g) {
+      const cplx* Oz = O + (long long)(g < nz ? g : 0) * plane;
 #pragma unroll
-      for (int i = 0; i < kProjE; ++i) on[g][i] = O[(long long)(g < nz ? g : 0) * plane + off[i]];
+      for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
+    }
     int pby[kProjPix], pbx[kProjPix];
-    bool pok[kProjPix];
+    cplx acc[kProjPix];
 #pragma unroll
     for (int h = 0; h < kProjPix; ++h) {
       const int p = tid + NT * h;
-      pok[h] = p < fy * fx;
       const int qy = p / fx;
       pby[h] = qy + pk.miny;
       pbx[h] = p - qy * fx + pk.minx;
-      if (pok[h]) psi[p] = {0.f, 0.f};
+      acc[h] = {0.f, 0.f};
     }
     for (int z0 = 0; z0 < nz; z0 += kProjG) {
       __syncthreads();
@@ -171,46 +179,38 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
       for (int g = 0; g < kProjG; ++g)
 #pragma unroll
         for (int i = 0; i < kProjE; ++i)
-          if (tid + NT * i < np2) Wb[g * np2 + tid + NT * i] = cmul(pv[i], on[g][i]);
+          if (wo[i] >= 0) Wb[g * sw + wo[i]] = (z0 + g < nz) ? cmul(pv[i], on[g][i]) : cplx{0.f, 0.f};
 #pragma unroll
       for (int g = 0; g < kProjG; ++g) {
         const int z = z0 + kProjG + g;
-        const long long zo = (long long)(z < nz ? z : 0) * plane;
+        const cplx* Oz = O + (long long)(z < nz ? z : 0) * plane;
 #pragma unroll
-        for (int i = 0; i < kProjE; ++i) on[g][i] = O[zo + off[i]];
+        for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
       }
       int ssy[kProjG], ssx[kProjG];
-      bool zok[kProjG];
 #pragma unroll
       for (int g = 0; g < kProjG; ++g) {
-        const int z = z0 + g;
-        zok[g] = z < nz;
-        ssy[g] = shz[2 * (zok[g] ? z : 0)];
-        ssx[g] = shz[2 * (zok[g] ? z : 0) + 1];
+        const int z = z0 + g < nz ? z0 + g : 0;
+        ssy[g] = shz[2 * z];
+        ssx[g] = shz[2 * z + 1];
       }
       __syncthreads();
 #pragma unroll
       for (int h = 0; h < kProjPix; ++h) {
         cplx w[kProjG];
-        bool ok[kProjG];
 #pragma unroll
         for (int g = 0; g < kProjG; ++g) {
-          const int a = pby[h] - ssy[g], b = pbx[h] - ssx[g];
-          ok[g] = zok[g] && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
-          w[g] = Wb[g * np2 + (ok[g] ? a * np + b : 0)];
+          const unsigned a = min((unsigned)(pby[h] - ssy[g]), (unsigned)np);
+          const unsigned b = min((unsigned)(pbx[h] - ssx[g]), (unsigned)np);
+          w[g] = Wb[g * sw + (int)(a * np1 + b)];
         }
-        cplx acc = {0.f, 0.f};
 #pragma unroll
-        for (int g = 0; g < kProjG; ++g) {
-          acc.x += ok[g] ? w[g].x : 0.f;
-          acc.y += ok[g] ? w[g].y : 0.f;
-        }
-        if (pok[h]) {
-          const int p = tid + NT * h;
-          psi[p] = cadd(psi[p], acc);
-        }
+        for (int g = 0; g < kProjG; ++g) acc[h] = cadd(acc[h], w[g]);
       }
     }
+#pragma unroll
+    for (int h = 0; h < kProjPix; ++h)
+      if (tid + NT * h < fy * fx) psi[tid + NT * h] = acc[h];
   }
   __syncthreads();
 
@@ -790,7 +790,7 @@ static int lds_for(int fy, int fx, int fxp, int np, int nz, bool grad) {
   constexpr int L = ColLen<D>::L;
   constexpr int RLINES = kFrameThreads / RC::TPL;
   constexpr int EXL = RC::Q * (RC::P + 1);
-  const long long exch_min = (long long)kProjG * np * np - ((long long)L * fxp + L / 8);
+  const long long exch_min = (long long)kProjG * (np + 1) * (np + 1) - ((long long)L * fxp + L / 8);
   const long long exch = (RLINES * EXL + 1) / 2 > exch_min ? (RLINES * EXL + 1) / 2 : exch_min;
   const long long cpx = D + L + (long long)(D / L) * fy + (long long)fy * fx +
                         (grad ? (long long)fy * fx : 0) + (long long)L * fxp + L / 8 + exch;
