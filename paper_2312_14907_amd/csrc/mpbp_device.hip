@@ -481,7 +481,7 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
   return s;
 }
 
-__global__ __launch_bounds__(kGradThreads) void k_grad(GradArgs A) {
+__global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   extern __shared__ cplx smem[];
   const int np = A.np, nz = A.nz;
   const int RW = kGradTX + A.maxspan_x;
@@ -491,9 +491,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(GradArgs A) {
   cplx* reg = reinterpret_cast<cplx*>(sh + nz);      // kGradBatch * RS
   double* apl = reinterpret_cast<double*>(reg + kGradBatch * RS);  // alpha partials
   float* red = reinterpret_cast<float*>(apl + kMaxPeaksDev);       // block reduction
-  // per staged frame: py, px, a_lo, b_lo, rows, cols, slot offset (2 ints); two buffers
-  int* meta = reinterpret_cast<int*>(red + 16);
-  unsigned char* actf = reinterpret_cast<unsigned char*>(meta + 2 * kGradBatch * 8);  // candidates
+  unsigned char* actf = reinterpret_cast<unsigned char*>(red + 16);  // candidate frames' flags
 
   const int tid = threadIdx.x;
   const int tx = tid % kGradTX, ty = (tid / kGradTX) % kGradTY, tz = tid / (kGradTX * kGradTY);
@@ -544,60 +542,76 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(GradArgs A) {
       for (int i = 0; i < kGradZPer; ++i) acc[i] = {0.f, 0.f};
       __syncthreads();
 
+      // this lane's slices: shear offsets in registers
+      int zsy[kGradZPer], zsx[kGradZPer];
+#pragma unroll
+      for (int i = 0; i < kGradZPer; ++i) {
+        const int z = zb + tz + kGradTZ * i;
+        zsy[i] = sh[z < nz ? z : 0].x - pk.miny;
+        zsx[i] = sh[z < nz ? z : 0].y - pk.minx;
+      }
       int iy = iy_lo, ix = ix_lo, ci = 0;
-      int par = 0;
       while (iy <= iy_hi && ix <= ix_hi) {
-        // Collect up to kGradBatch frames of the minibatch (the same walk in every lane;
-        // lane 0 records them in the buffer this batch owns).
-        int* mb = meta + par * kGradBatch * 8;
-        par ^= 1;
+        // Collect up to kGradBatch frames of the minibatch.  The walk is uniform, so its
+        // results (frame position, staged rows / cols, slot offset) stay scalar.
         int nb = 0;
-        while (nb < kGradBatch && iy <= iy_hi) {
-          const int cy = iy, cx = ix;
-          if (++ix > ix_hi) { ix = ix_lo; ++iy; }
-          const int j = cy * pk.cols + cx;
-          if (!actf[ci++]) continue;
-          if (tid == 0) {
+        int fpy[kGradBatch], fpx[kGradBatch], fal[kGradBatch], fbl[kGradBatch], frh[kGradBatch],
+            frw[kGradBatch];
+        long long fso[kGradBatch];
+#pragma unroll
+        for (int k = 0; k < kGradBatch; ++k) {
+          fpy[k] = fpx[k] = fal[k] = fbl[k] = frh[k] = frw[k] = 0;
+          fso[k] = 0;
+          while (nb == k && iy <= iy_hi) {
+            const int cy = iy, cx = ix;
+            if (++ix > ix_hi) { ix = ix_lo; ++iy; }
+            const int j = cy * pk.cols + cx;
+            const int act = __builtin_amdgcn_readfirstlane((int)actf[ci]);
+            ++ci;
+            if (!act) continue;
             const int py = pk.oy + cy * pk.sy, px = pk.ox + cx * pk.sx;
-            const int al = max(0, y0 - py), bl = max(0, x0 - px);
-            const long long so = pk.slot_off + (long long)j * pk.fy * pk.fx + al * pk.fx + bl;
-            int* q = mb + nb * 8;
-            q[0] = py; q[1] = px; q[2] = al; q[3] = bl;
-            q[4] = min(np, y0 + kGradTY - py) - al + pk.spany;
-            q[5] = min(np, x0 + kGradTX - px) - bl + pk.spanx;
-            q[6] = (int)(so & 0x7fffffff);
-            q[7] = (int)(so >> 31);
+            fpy[k] = py; fpx[k] = px;
+            fal[k] = max(0, y0 - py);
+            fbl[k] = max(0, x0 - px);
+            frh[k] = min(np, y0 + kGradTY - py) - fal[k] + pk.spany;
+            frw[k] = min(np, x0 + kGradTX - px) - fbl[k] + pk.spanx;
+            fso[k] = pk.slot_off + (long long)j * pk.fy * pk.fx + fal[k] * pk.fx + fbl[k];
+            nb = k + 1;
           }
-          ++nb;
         }
         if (nb == 0) break;
-        __syncthreads();
-#pragma unroll 1
-        for (int k = 0; k < nb; ++k) {
-          const int* q = mb + k * 8;
-          const long long so = (long long)q[6] | ((long long)q[7] << 31);
-          const cplx* slot = reinterpret_cast<const cplx*>(A.slots) + so;
-          if (e0r < q[4] && e0c < q[5]) reg[k * RS + e0r * RW + e0c] = slot[e0r * pk.fx + e0c];
-          if (e1r < q[4] && e1c < q[5]) reg[k * RS + e1r * RW + e1c] = slot[e1r * pk.fx + e1c];
+        // stage: all loads first, then the LDS stores
+        cplx st0[kGradBatch], st1[kGradBatch];
+        const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
+#pragma unroll
+        for (int k = 0; k < kGradBatch; ++k) {
+          const bool ok0 = k < nb && e0r < frh[k] && e0c < frw[k];
+          const bool ok1 = k < nb && e1r < frh[k] && e1c < frw[k];
+          st0[k] = slots[fso[k] + (ok0 ? e0r * pk.fx + e0c : 0)];
+          st1[k] = slots[fso[k] + (ok1 ? e1r * pk.fx + e1c : 0)];
         }
         __syncthreads();
-        if (inb) {
-#pragma unroll 1
-          for (int k = 0; k < nb; ++k) {
-            const int* q = mb + k * 8;
-            const int a = y - q[0], b = x - q[1];
-            if ((unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np) {
-              const cplx p = Ps[a * np + b];
-              const cplx* rg = reg + k * RS + (a - q[2] - pk.miny) * RW + (b - q[3] - pk.minx);
 #pragma unroll
-              for (int i = 0; i < kGradZPer; ++i) {
-                const int z = zb + tz + kGradTZ * i;
-                if (z < nz) {
-                  const int2 s = sh[z];
-                  acc[i] = cadd(acc[i], cmulc(rg[s.x * RW + s.y], p));   // conj(P) g_psi
-                }
-              }
-            }
+        for (int k = 0; k < kGradBatch; ++k) {
+          if (k < nb && e0r < frh[k] && e0c < frw[k]) reg[k * RS + e0r * RW + e0c] = st0[k];
+          if (k < nb && e1r < frh[k] && e1c < frw[k]) reg[k * RS + e1r * RW + e1c] = st1[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kGradBatch; ++k) {
+          if (k < nb) {
+            const int a = y - fpy[k], b = x - fpx[k];
+            const bool inw = inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
+            // lanes outside this frame's window read a staged entry and weight it by 0
+            const int ac = inw ? a : fal[k], bc = inw ? b : fbl[k];
+            const cplx pr = Ps[ac * np + bc];
+            const cplx p = inw ? pr : cplx{0.f, 0.f};
+            const cplx* rg = reg + k * RS + (ac - fal[k]) * RW + (bc - fbl[k]);
+            cplx gv[kGradZPer];
+#pragma unroll
+            for (int i = 0; i < kGradZPer; ++i) gv[i] = rg[zsy[i] * RW + zsx[i]];
+#pragma unroll
+            for (int i = 0; i < kGradZPer; ++i) acc[i] = cadd(acc[i], cmulc(gv[i], p));   // conj(P) g_psi
           }
         }
       }
@@ -854,7 +868,7 @@ int frame_chunk_len(int D) {
 
 int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand) {
   return np * np * 8 + nz * 8 + kGradBatch * (kGradTY + maxspan_y) * (kGradTX + maxspan_x) * 8 +
-         kMaxPeaksDev * 8 + 64 + 2 * kGradBatch * 8 * 4 + max_cand;
+         kMaxPeaksDev * 8 + 64 + max_cand;
 }
 
 }  // namespace mpbp
