@@ -488,8 +488,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   const int RS = (kGradTY + A.maxspan_y) * RW;       // one staged region (complex)
   cplx* Ps = smem;                                   // np * np
   int2* sh = reinterpret_cast<int2*>(Ps + np * np);  // nz
-  cplx* reg = reinterpret_cast<cplx*>(sh + nz);      // kGradBatch * RS
-  double* apl = reinterpret_cast<double*>(reg + kGradBatch * RS);  // alpha partials
+  double* apl = reinterpret_cast<double*>(sh + nz);  // alpha partials
   float* red = reinterpret_cast<float*>(apl + kMaxPeaksDev);       // block reduction
   unsigned char* actf = reinterpret_cast<unsigned char*>(red + 16);  // candidate frames' flags
 
@@ -550,70 +549,48 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
         zsy[i] = sh[z < nz ? z : 0].x - pk.miny;
         zsx[i] = sh[z < nz ? z : 0].y - pk.minx;
       }
+      // Frames of the minibatch, kGradBatch at a time (uniform walk, scalar results).
+      // Each lane reads its footprint-gradient values straight from the frame's slot:
+      // a wavefront covers a 4 x 16 voxel patch at one slice, so its reads are rows.
+      const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
       int iy = iy_lo, ix = ix_lo, ci = 0;
-      while (iy <= iy_hi && ix <= ix_hi) {
-        // Collect up to kGradBatch frames of the minibatch.  The walk is uniform, so its
-        // results (frame position, staged rows / cols, slot offset) stay scalar.
+      while (iy <= iy_hi) {
         int nb = 0;
-        int fpy[kGradBatch], fpx[kGradBatch], fal[kGradBatch], fbl[kGradBatch], frh[kGradBatch],
-            frw[kGradBatch];
+        int fpy[kGradBatch], fpx[kGradBatch];
         long long fso[kGradBatch];
 #pragma unroll
         for (int k = 0; k < kGradBatch; ++k) {
-          fpy[k] = fpx[k] = fal[k] = fbl[k] = frh[k] = frw[k] = 0;
+          fpy[k] = fpx[k] = 0;
           fso[k] = 0;
           while (nb == k && iy <= iy_hi) {
             const int cy = iy, cx = ix;
             if (++ix > ix_hi) { ix = ix_lo; ++iy; }
-            const int j = cy * pk.cols + cx;
             const int act = __builtin_amdgcn_readfirstlane((int)actf[ci]);
             ++ci;
             if (!act) continue;
-            const int py = pk.oy + cy * pk.sy, px = pk.ox + cx * pk.sx;
-            fpy[k] = py; fpx[k] = px;
-            fal[k] = max(0, y0 - py);
-            fbl[k] = max(0, x0 - px);
-            frh[k] = min(np, y0 + kGradTY - py) - fal[k] + pk.spany;
-            frw[k] = min(np, x0 + kGradTX - px) - fbl[k] + pk.spanx;
-            fso[k] = pk.slot_off + (long long)j * pk.fy * pk.fx + fal[k] * pk.fx + fbl[k];
+            fpy[k] = pk.oy + cy * pk.sy;
+            fpx[k] = pk.ox + cx * pk.sx;
+            fso[k] = pk.slot_off + (long long)(cy * pk.cols + cx) * pk.fy * pk.fx;
             nb = k + 1;
           }
         }
         if (nb == 0) break;
-        // stage: all loads first, then the LDS stores
-        cplx st0[kGradBatch], st1[kGradBatch];
-        const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
+        cplx gv[kGradBatch][kGradZPer], pv[kGradBatch];
 #pragma unroll
         for (int k = 0; k < kGradBatch; ++k) {
-          const bool ok0 = k < nb && e0r < frh[k] && e0c < frw[k];
-          const bool ok1 = k < nb && e1r < frh[k] && e1c < frw[k];
-          st0[k] = slots[fso[k] + (ok0 ? e0r * pk.fx + e0c : 0)];
-          st1[k] = slots[fso[k] + (ok1 ? e1r * pk.fx + e1c : 0)];
+          const int a = y - fpy[k], b = x - fpx[k];
+          const bool inw = k < nb && inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
+          const int ac = inw ? a : 0, bc = inw ? b : 0;
+          const cplx pr = Ps[ac * np + bc];
+          pv[k] = inw ? pr : cplx{0.f, 0.f};
+          const cplx* sl = slots + fso[k];
+#pragma unroll
+          for (int i = 0; i < kGradZPer; ++i) gv[k][i] = sl[(ac + zsy[i]) * pk.fx + bc + zsx[i]];
         }
-        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kGradBatch; ++k) {
-          if (k < nb && e0r < frh[k] && e0c < frw[k]) reg[k * RS + e0r * RW + e0c] = st0[k];
-          if (k < nb && e1r < frh[k] && e1c < frw[k]) reg[k * RS + e1r * RW + e1c] = st1[k];
-        }
-        __syncthreads();
+        for (int k = 0; k < kGradBatch; ++k)
 #pragma unroll
-        for (int k = 0; k < kGradBatch; ++k) {
-          if (k < nb) {
-            const int a = y - fpy[k], b = x - fpx[k];
-            const bool inw = inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
-            // lanes outside this frame's window read a staged entry and weight it by 0
-            const int ac = inw ? a : fal[k], bc = inw ? b : fbl[k];
-            const cplx pr = Ps[ac * np + bc];
-            const cplx p = inw ? pr : cplx{0.f, 0.f};
-            const cplx* rg = reg + k * RS + (ac - fal[k]) * RW + (bc - fbl[k]);
-            cplx gv[kGradZPer];
-#pragma unroll
-            for (int i = 0; i < kGradZPer; ++i) gv[i] = rg[zsy[i] * RW + zsx[i]];
-#pragma unroll
-            for (int i = 0; i < kGradZPer; ++i) acc[i] = cadd(acc[i], cmulc(gv[i], p));   // conj(P) g_psi
-          }
-        }
+          for (int i = 0; i < kGradZPer; ++i) acc[i] = cadd(acc[i], cmulc(gv[k][i], pv[k]));   // conj(P) g_psi
       }
       // chain rule through O_m = alpha_m chi exp(i G_m . u); 32-bit voxel offsets from
       // uniform bases (the plan limits 3 * nvox to 2^32)
@@ -867,8 +844,9 @@ int frame_chunk_len(int D) {
 }
 
 int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand) {
-  return np * np * 8 + nz * 8 + kGradBatch * (kGradTY + maxspan_y) * (kGradTX + maxspan_x) * 8 +
-         kMaxPeaksDev * 8 + 64 + max_cand;
+  (void)maxspan_y;
+  (void)maxspan_x;
+  return np * np * 8 + nz * 8 + kMaxPeaksDev * 8 + 64 + max_cand;
 }
 
 }  // namespace mpbp

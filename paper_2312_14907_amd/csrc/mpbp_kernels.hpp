@@ -73,7 +73,7 @@ constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 8;  // 512 threads
 constexpr int kGradThreads = kGradTX * kGradTY * kGradTZ;
 constexpr int kGradZB = 32;                             // z per pass of the grad kernel
 constexpr int kGradZPer = kGradZB / kGradTZ;            // z per thread per pass
-constexpr int kGradBatch = 4;                           // frames staged per barrier pair
+constexpr int kGradBatch = 2;                           // frames staged per barrier pair
 constexpr int kMaxPeaksDev = 16;
 
 }  // namespace mpbp
