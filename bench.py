@@ -215,6 +215,12 @@ def main():
         "loss": loss,
     }
 
+    # the same steps replayed from the captured graph (no stage events)
+    plan.mpbp_set_option(MPBP_OPT_PROFILE, 0)
+    gdt, _, _ = time_steps(plan, args_t, args.steps, 1, torch)
+    out["graph_replay"] = {"ms_per_step": round(1e3 * gdt / args.steps, 4),
+                           "value": round(nfr * args.steps / gdt, 1)}
+
     if not args.no_plain:
         plan.mpbp_set_option(MPBP_OPT_PATH, 1)
         pdt, _, ploss = time_steps(plan, args_t, 1, 1, torch)

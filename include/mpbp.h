@@ -79,8 +79,15 @@ typedef struct {
 enum {
   MPBP_OPT_PATH = 1,         /* 0 = batched fused path (default), 1 = plain path: one
                                 launch per stage per peak and scan position              */
-  MPBP_OPT_GRAPH = 2,        /* 1 = replay full-batch calls from a captured hipGraph
-                                (default 1), 0 = direct launches                          */
+  MPBP_OPT_GRAPH = 2,        /* 1 (default): a full-batch fused call (frames = NULL) is
+                                captured into a hipGraph on first use for its set of
+                                buffer addresses and replayed afterwards; the detector-
+                                size classes run as parallel graph branches.  At most 8
+                                graphs are kept per plan (least recently used dropped,
+                                after a device synchronisation).  Subset calls, the plain
+                                path and profiled calls launch directly.  0 = direct
+                                launches always (and drop the plan's graphs).  Results
+                                are bitwise those of direct launches.                    */
   MPBP_OPT_XCD_ORDER = 3,    /* 1 = hand each XCD a contiguous band of frames (default) */
   MPBP_OPT_PROFILE = 4       /* 1 = record HIP events around every kernel stage on the
                                 call's stream (read with mpbp_stage_times); default 0    */

@@ -708,12 +708,6 @@ hipError_t launch_object(const float* u, const float* chi, const float* alpha, c
 
 template <int D, int FB>
 static hipError_t launch_frames_d(const FrameArgs& a, int lds_bytes, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_frames<D, FB>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
   const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
   k_frames<D, FB><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);
@@ -727,25 +721,45 @@ int frame_bound(int D, int f) {
   return D;
 }
 
+// Every compiled (D, FB) instance of the frame kernel.
+#define MPBP_FRAME_INSTANCES(X)             \
+  X(32, 32)                                 \
+  X(64, 48) X(64, 64)                       \
+  X(96, 48) X(96, 64) X(96, 96)             \
+  X(128, 48) X(128, 64) X(128, 128)         \
+  X(192, 48) X(192, 64) X(192, 192)         \
+  X(256, 48) X(256, 64) X(256, 256)
+
 hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s) {
 #define MPBP_CASE(d, fb) \
   if (D == d && FB == fb) return launch_frames_d<d, fb>(a, lds_bytes, s);
-  MPBP_CASE(32, 32)
-  MPBP_CASE(64, 48) MPBP_CASE(64, 64)
-  MPBP_CASE(96, 48) MPBP_CASE(96, 64) MPBP_CASE(96, 96)
-  MPBP_CASE(128, 48) MPBP_CASE(128, 64) MPBP_CASE(128, 128)
-  MPBP_CASE(192, 48) MPBP_CASE(192, 64) MPBP_CASE(192, 192)
-  MPBP_CASE(256, 48) MPBP_CASE(256, 64) MPBP_CASE(256, 256)
+  MPBP_FRAME_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
   return hipErrorInvalidValue;
 }
 
+bool frame_instance(int D, int FB) {
+#define MPBP_CASE(d, fb) \
+  if (D == d && FB == fb) return true;
+  MPBP_FRAME_INSTANCES(MPBP_CASE)
+#undef MPBP_CASE
+  return false;
+}
+
+hipError_t prepare_kernels() {
+  hipError_t e = hipSuccess;
+#define MPBP_CASE(d, fb)                                                                     \
+  if (e == hipSuccess)                                                                       \
+    e = hipFuncSetAttribute((const void*)k_frames<d, fb>,                                    \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  MPBP_FRAME_INSTANCES(MPBP_CASE)
+#undef MPBP_CASE
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_grad, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  return e;
+}
+
 hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_grad, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
   const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
   k_grad<<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);
   return hipGetLastError();

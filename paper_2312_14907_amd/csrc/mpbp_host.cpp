@@ -43,6 +43,25 @@ bool supported_det(int d) {
 
 constexpr int kMaxPeaks = 16;
 constexpr int kMaxLds = 160 * 1024;
+constexpr size_t kMaxGraphs = 8;   // captured full-batch calls kept per plan
+
+// What a captured full-batch call depends on besides the plan: the call kind, the
+// caller's buffer addresses and the launch options.  A replay reads and writes the
+// buffers at these addresses, so equal keys mean equal work.
+struct GraphKey {
+  int kind = 0;                    // 0: mpbp_forward, 1: mpbp_loss_grad
+  int xcd = 0;
+  const void* ptr[11] = {};
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && xcd == o.xcd && std::memcmp(ptr, o.ptr, sizeof(ptr)) == 0;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+  uint64_t used = 0;
+};
 
 }  // namespace
 
@@ -95,6 +114,13 @@ struct mpbp_plan_t {
   size_t ev_used = 0;
   double stage_ms[MPBP_NUM_STAGES] = {0};
   int64_t stage_n[MPBP_NUM_STAGES] = {0};
+  // captured full-batch calls (MPBP_OPT_GRAPH)
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t cap = nullptr;              // capture stream
+  std::vector<hipStream_t> forks;         // one per extra size class
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork_ev = nullptr;
 };
 
 namespace {
@@ -104,10 +130,22 @@ hipError_t dalloc(T** p, size_t n) {
   return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
 }
 
+void clear_graphs(mpbp_plan_t* p) {
+  if (p->graphs.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+}
+
 void free_device(mpbp_plan_t* p) {
   if (p->device < 0) return;
   (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
+  clear_graphs(p);
+  for (hipStream_t f : p->forks) (void)hipStreamDestroy(f);
+  for (hipEvent_t e : p->joins) (void)hipEventDestroy(e);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
   (void)hipFree(p->d_peaks);
   (void)hipFree(p->d_scan);
   (void)hipFree(p->d_peak_of);
@@ -275,6 +313,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
 mpbp_status alloc_device(mpbp_plan_t* p) {
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = mpbp::prepare_kernels();
+  if (e != hipSuccess) return hip_fail(e, "kernel attributes");
 #define ALLOC(ptr, n)                                                           \
   do {                                                                          \
     e = dalloc(&(ptr), (n));                                                    \
@@ -401,19 +441,38 @@ struct StageTimer {
   }
 };
 
-// Enqueue the per-frame kernel for every detector-size class of the call.
-hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset, bool grad, hipStream_t s) {
+// Enqueue the per-frame kernel for every detector-size class of the call.  With
+// `branch` (graph capture), the classes after the first run on fork streams joined back
+// into `s`, so the captured graph holds them as parallel nodes: the classes write
+// disjoint slots and frame losses.
+hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset, bool grad, hipStream_t s,
+                          bool branch = false) {
   const auto& cls = subset ? p->sub_classes : p->classes;
   const int* list = subset ? p->d_list_sorted : p->d_order;
+  hipError_t e = hipSuccess;
+  if (branch) e = hipEventRecord(p->fork_ev, s);
+  size_t k = 0;
+  bool first = true;
   for (const auto& c : cls) {
     if (c.count == 0) continue;
     mpbp::FrameArgs a = base;
     a.list = list + c.begin;
     a.n_list = c.count;
-    hipError_t e = mpbp::launch_frames(c.D, c.FB, a, grad ? c.lds_grad : c.lds_fwd, s);
+    hipStream_t t = s;
+    if (branch && !first) {
+      t = p->forks[k];
+      if (e == hipSuccess) e = hipStreamWaitEvent(t, p->fork_ev, 0);
+    }
+    if (e == hipSuccess) e = mpbp::launch_frames(c.D, c.FB, a, grad ? c.lds_grad : c.lds_fwd, t);
+    if (branch && !first) {
+      if (e == hipSuccess) e = hipEventRecord(p->joins[k], t);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, p->joins[k], 0);
+      ++k;
+    }
+    first = false;
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return e;
 }
 
 mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, float* mi, int grad) {
@@ -434,6 +493,133 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   a.grad = grad;
   a.xcd = p->xcd;
   return a;
+}
+
+// The batched fused path's launches of one mpbp_forward call.  `what` names the stage
+// that failed.
+hipError_t enqueue_forward(mpbp_plan p, const float* u, const float* chi, const float* alpha,
+                           const float* probe, const float* y, const int* list, int n, bool subset,
+                           float* model_intensity, hipStream_t s, bool branch, const char** what) {
+  hipError_t e;
+  {
+    StageTimer t(p, MPBP_STAGE_OBJECT, s);
+    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->d_obj, s);
+  }
+  if (e != hipSuccess) return *what = "object kernel", e;
+  mpbp::FrameArgs a = frame_args(p, y, list, n, model_intensity, 0);
+  a.probe = probe;
+  {
+    StageTimer t(p, MPBP_STAGE_FRAMES, s);
+    e = enqueue_frames(p, a, subset, false, s, branch);
+  }
+  if (e != hipSuccess) return *what = "frame kernel", e;
+  return hipSuccess;
+}
+
+// The batched fused path's launches of one mpbp_loss_grad call, finalize excluded.
+hipError_t enqueue_loss_grad(mpbp_plan p, const float* u, const float* chi, const float* alpha,
+                             const float* probe, const float* y, const int* list, int n, bool subset,
+                             float* grad_u, float* grad_chi, hipStream_t s, bool branch,
+                             const char** what) {
+  hipError_t e;
+  {
+    StageTimer t(p, MPBP_STAGE_OBJECT, s);
+    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->d_obj, s);
+  }
+  if (e != hipSuccess) return *what = "object kernel", e;
+  mpbp::FrameArgs a = frame_args(p, y, list, n, nullptr, 1);
+  a.probe = probe;
+  {
+    StageTimer t(p, MPBP_STAGE_FRAMES, s);
+    e = enqueue_frames(p, a, subset, true, s, branch);
+  }
+  if (e != hipSuccess) return *what = "frame kernel", e;
+  mpbp::GradArgs g{};
+  g.slots = p->d_slots;
+  g.active = subset ? p->d_active : p->d_active_all;
+  g.probe = probe;
+  g.u = u; g.chi = chi; g.alpha = alpha;
+  g.shear = p->d_shear;
+  g.peaks = p->d_peaks;
+  g.n_peaks = p->M;
+  g.nz = p->nz; g.ny = p->ny; g.nx = p->nx; g.np = p->np;
+  g.tiles_x = p->tiles_x; g.tiles_y = p->tiles_y;
+  g.maxspan_y = p->maxspan_y; g.maxspan_x = p->maxspan_x;
+  g.max_cand = p->max_cand;
+  g.grad_u = grad_u; g.grad_chi = grad_chi;
+  g.alpha_part = p->d_apart;
+  {
+    StageTimer t(p, MPBP_STAGE_GRAD, s);
+    e = mpbp::launch_grad(g, p->lds_grad, s);
+  }
+  if (e != hipSuccess) return *what = "gradient kernel", e;
+  return hipSuccess;
+}
+
+// Full-batch fused calls are replayed from captured graphs unless profiling (which
+// times each stage with events) or the plain path is selected.
+bool use_graph(mpbp_plan p, const int32_t* frames) {
+  return p->graph && !p->profile && p->path == 0 && frames == nullptr;
+}
+
+mpbp_status ensure_capture_streams(mpbp_plan p) {
+  hipError_t e = hipSuccess;
+  if (!p->cap) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+  if (e == hipSuccess && !p->fork_ev) e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+  const size_t need = p->classes.empty() ? 0 : p->classes.size() - 1;
+  while (e == hipSuccess && p->forks.size() < need) {
+    hipStream_t f = nullptr;
+    hipEvent_t j = nullptr;
+    e = hipStreamCreateWithFlags(&f, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    p->forks.push_back(f);
+    e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+    if (e != hipSuccess) break;
+    p->joins.push_back(j);
+  }
+  if (p->joins.size() < p->forks.size()) e = hipErrorOutOfMemory;
+  return e == hipSuccess ? MPBP_OK : hip_fail(e, "capture streams");
+}
+
+// Replay the graph captured for `key`, capturing it first (from `enqueue`, run on the
+// plan's capture stream) if it is not cached.  The least recently used graph is
+// dropped beyond kMaxGraphs (after a device synchronisation).
+template <class Enqueue>
+mpbp_status run_graph(mpbp_plan p, const GraphKey& key, hipStream_t s, Enqueue&& enqueue) {
+  hipError_t e;
+  for (auto& g : p->graphs) {
+    if (g.key == key) {
+      g.used = ++p->graph_clock;
+      e = hipGraphLaunch(g.exec, s);
+      return e == hipSuccess ? MPBP_OK : hip_fail(e, "hipGraphLaunch");
+    }
+  }
+  mpbp_status st = ensure_capture_streams(p);
+  if (st != MPBP_OK) return st;
+  e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  const char* what = "capture";
+  const hipError_t le = enqueue(p->cap, &what);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->cap, &graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return le != hipSuccess ? hip_fail(le, what) : hip_fail(e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  if (p->graphs.size() >= kMaxGraphs) {
+    auto old = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                [](const GraphEntry& a, const GraphEntry& b) { return a.used < b.used; });
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(old->exec);
+    p->graphs.erase(old);
+  }
+  p->graphs.push_back({key, exec, ++p->graph_clock});
+  e = hipGraphLaunch(exec, s);
+  return e == hipSuccess ? MPBP_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 }  // namespace
@@ -514,19 +700,27 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
                             frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
                             model_intensity, plan->d_obj, plan->d_floss, s);
     if (e != hipSuccess) return hip_fail(e, "plain path");
+  } else if (use_graph(plan, frames)) {
+    GraphKey key;
+    key.kind = 0;
+    key.xcd = plan->xcd;
+    const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, model_intensity};
+    std::copy(std::begin(ptrs), std::end(ptrs), key.ptr);
+    return run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
+      hipError_t le = enqueue_forward(plan, u, chi, alpha, (const float*)probe, y, list, n, false,
+                                      model_intensity, cs, true, what);
+      if (le == hipSuccess && (loss || frame_loss)) {
+        le = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, nullptr, 0, plan->M,
+                                   nullptr, cs);
+        if (le != hipSuccess) *what = "finalize kernel";
+      }
+      return le;
+    });
   } else {
-    {
-      StageTimer t(plan, MPBP_STAGE_OBJECT, s);
-      e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
-    }
-    if (e != hipSuccess) return hip_fail(e, "object kernel");
-    mpbp::FrameArgs a = frame_args(plan, y, list, n, model_intensity, 0);
-    a.probe = (const float*)probe;
-    {
-      StageTimer t(plan, MPBP_STAGE_FRAMES, s);
-      e = enqueue_frames(plan, a, frames != nullptr, false, s);
-    }
-    if (e != hipSuccess) return hip_fail(e, "frame kernel");
+    const char* what = "";
+    e = enqueue_forward(plan, u, chi, alpha, (const float*)probe, y, list, n, frames != nullptr,
+                        model_intensity, s, false, &what);
+    if (e != hipSuccess) return hip_fail(e, what);
   }
   if (loss || frame_loss) {
     StageTimer t(plan, MPBP_STAGE_FINALIZE, s);
@@ -561,38 +755,27 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
                               frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
                               plan->d_obj, plan->d_floss, grad_u, grad_chi, &apart, &n_part, s);
     if (e != hipSuccess) return hip_fail(e, "plain path");
+  } else if (use_graph(plan, frames)) {
+    GraphKey key;
+    key.kind = 1;
+    key.xcd = plan->xcd;
+    const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, grad_u, grad_chi, grad_alpha};
+    std::copy(std::begin(ptrs), std::end(ptrs), key.ptr);
+    return run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
+      hipError_t le = enqueue_loss_grad(plan, u, chi, alpha, (const float*)probe, y, list, n, false,
+                                        grad_u, grad_chi, cs, true, what);
+      if (le == hipSuccess) {
+        le = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, apart, n_part, plan->M,
+                                   grad_alpha, cs);
+        if (le != hipSuccess) *what = "finalize kernel";
+      }
+      return le;
+    });
   } else {
-    {
-      StageTimer t(plan, MPBP_STAGE_OBJECT, s);
-      e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
-    }
-    if (e != hipSuccess) return hip_fail(e, "object kernel");
-    mpbp::FrameArgs a = frame_args(plan, y, list, n, nullptr, 1);
-    a.probe = (const float*)probe;
-    {
-      StageTimer t(plan, MPBP_STAGE_FRAMES, s);
-      e = enqueue_frames(plan, a, frames != nullptr, true, s);
-    }
-    if (e != hipSuccess) return hip_fail(e, "frame kernel");
-    mpbp::GradArgs g{};
-    g.slots = plan->d_slots;
-    g.active = frames ? plan->d_active : plan->d_active_all;
-    g.probe = (const float*)probe;
-    g.u = u; g.chi = chi; g.alpha = alpha;
-    g.shear = plan->d_shear;
-    g.peaks = plan->d_peaks;
-    g.n_peaks = plan->M;
-    g.nz = plan->nz; g.ny = plan->ny; g.nx = plan->nx; g.np = plan->np;
-    g.tiles_x = plan->tiles_x; g.tiles_y = plan->tiles_y;
-    g.maxspan_y = plan->maxspan_y; g.maxspan_x = plan->maxspan_x;
-    g.max_cand = plan->max_cand;
-    g.grad_u = grad_u; g.grad_chi = grad_chi;
-    g.alpha_part = plan->d_apart;
-    {
-      StageTimer t(plan, MPBP_STAGE_GRAD, s);
-      e = mpbp::launch_grad(g, plan->lds_grad, s);
-    }
-    if (e != hipSuccess) return hip_fail(e, "gradient kernel");
+    const char* what = "";
+    e = enqueue_loss_grad(plan, u, chi, alpha, (const float*)probe, y, list, n, frames != nullptr, grad_u,
+                          grad_chi, s, false, &what);
+    if (e != hipSuccess) return hip_fail(e, what);
   }
   {
     StageTimer t(plan, MPBP_STAGE_FINALIZE, s);
@@ -629,6 +812,10 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
     case MPBP_OPT_GRAPH:
       if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "graph must be 0 or 1");
       plan->graph = (int)value;
+      if (!value && plan->device >= 0) {
+        (void)hipSetDevice(plan->device);
+        clear_graphs(plan);
+      }
       return MPBP_OK;
     case MPBP_OPT_XCD_ORDER:
       if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "xcd order must be 0 or 1");

@@ -8,6 +8,12 @@
 
 namespace mpbp {
 
+// Allow the frame and gradient kernels the full 160 KB of LDS on the current device.
+// Called once per plan, before any launch (and before any graph capture).
+hipError_t prepare_kernels();
+// True if the frame kernel is compiled for detector size D and footprint bound FB.
+bool frame_instance(int D, int FB);
+
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
                          int n_peaks, long long nvox, float* obj, hipStream_t s);
 // Frames of one detector size D whose footprints fit FB x FB (a.list holds only such

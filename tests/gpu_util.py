@@ -77,3 +77,21 @@ def assert_grad_close(got, ref, name, rtol=GRAD_RTOL, mask=None):
 
 def assert_loss_close(got, ref, name="loss", rtol=LOSS_RTOL):
     assert abs(got - ref) <= rtol * abs(ref), f"{name}: {got!r} vs {ref!r} (rel {abs(got - ref) / abs(ref):.3e})"
+
+
+def speckle_y(prob, seed):
+    """Speckle-like Poisson counts under a centred envelope, ragged over peaks."""
+    import torch
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    parts = []
+    for m in range(prob.n_peaks):
+        d = int(prob.det[m])
+        nfr = int(prob.scan_n[m, 0] * prob.scan_n[m, 1])
+        k = torch.fft.fftfreq(d, device="cuda:0") * d
+        env = torch.exp(-(k[:, None] ** 2 + k[None, :] ** 2) / (2.0 * (d / 10.0) ** 2))
+        env = env * (1e5 / d ** 2) / env.mean()
+        lam = torch.empty((nfr, d, d), device="cuda:0").exponential_(1.0, generator=g) * env
+        parts.append(torch.poisson(lam, generator=g).reshape(-1))
+        del lam
+    return torch.cat(parts).contiguous()

@@ -18,7 +18,8 @@ import pytest
 from oracle import mpbp_oracle as O
 from synth import get_config, make_fields, make_problem, photon_rng, poisson_counts
 from tests.conftest import ragged
-from tests.gpu_util import (assert_grad_close, assert_loss_close, dev, gpu_loss_grad, host, say)
+from tests.gpu_util import (assert_grad_close, assert_loss_close, dev, gpu_loss_grad, host, say,
+                            speckle_y)
 
 pytestmark = pytest.mark.gpu
 
@@ -36,23 +37,6 @@ class DeviceY:
 
     def __getitem__(self, sl):
         return self.t[sl].cpu().numpy()
-
-
-def speckle_y(prob, seed):
-    """Speckle-like Poisson counts under a centred envelope, ragged over peaks."""
-    g = torch.Generator(device="cuda:0")
-    g.manual_seed(seed)
-    parts = []
-    for m in range(prob.n_peaks):
-        d = int(prob.det[m])
-        nfr = int(prob.scan_n[m, 0] * prob.scan_n[m, 1])
-        k = torch.fft.fftfreq(d, device="cuda:0") * d
-        env = torch.exp(-(k[:, None] ** 2 + k[None, :] ** 2) / (2.0 * (d / 10.0) ** 2))
-        env = env * (1e5 / d ** 2) / env.mean()
-        lam = torch.empty((nfr, d, d), device="cuda:0").exponential_(1.0, generator=g) * env
-        parts.append(torch.poisson(lam, generator=g).reshape(-1))
-        del lam
-    return torch.cat(parts).contiguous()
 
 
 def covering_frames(prob, tab, yy, xx):

@@ -83,8 +83,9 @@ def test_descriptor_validation_codes():
     st, msg = _status_of(B.make_problem_struct(bad))
     assert st == 3 and "window" in msg
     s = B.make_problem_struct(good)
-    s.probe_n = 40                                        # support larger than the window
-    assert _status_of(s)[0] == 3
+    s.probe_n = 40                                        # above the kernels' 32 x 32 support
+    st, msg = _status_of(s)
+    assert st == 6 and "probe_n" in msg
     s = B.make_problem_struct(good)
     s.n_peaks = 0
     assert _status_of(s)[0] == 2
