@@ -33,6 +33,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0 = auto)")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="first run a plain elementwise copy (out = -in) of this many MiB, the "
+                        "known-size reference for HBM byte counters")
     return p.parse_args()
 
 
@@ -159,6 +162,15 @@ def main():
     from paper_2312_14907_amd.binding import MPBP_OPT_PATH, MPBP_OPT_PROFILE
 
     cfg, prob, f, plan, args_t = make_inputs(args.workload, torch)
+    calib = None
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)          # reads and writes n * 4 bytes
+        torch.cuda.synchronize()
+        del src, dst
+        calib = {"kernel": "torch neg (elementwise)", "bytes_read": 4 * n, "bytes_written": 4 * n}
     plan.mpbp_set_option(MPBP_OPT_PROFILE, 1)
     dt, stages, loss = time_steps(plan, args_t, args.steps, args.warmup, torch)
     nfr = prob.n_frames()
@@ -214,6 +226,8 @@ def main():
         "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
         "loss": loss,
     }
+    if calib:
+        out["calibration"] = calib
 
     # the same steps replayed from the captured graph (no stage events)
     plan.mpbp_set_option(MPBP_OPT_PROFILE, 0)
