@@ -32,6 +32,7 @@ def parse():
     p.add_argument("--workload", default="c5_full")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
+    p.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
     p.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0 = auto)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="first run a plain elementwise copy (out = -in) of this many MiB, the "
@@ -171,6 +172,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         calib = {"kernel": "torch neg (elementwise)", "bytes_read": 4 * n, "bytes_written": 4 * n}
+    if not args.no_autotune:
+        plan.mpbp_autotune(*args_t)
+    tuning = plan.mpbp_tuning()
     plan.mpbp_set_option(MPBP_OPT_PROFILE, 1)
     dt, stages, loss = time_steps(plan, args_t, args.steps, args.warmup, torch)
     nfr = prob.n_frames()
@@ -225,6 +229,9 @@ def main():
         },
         "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
         "loss": loss,
+        "launch": {"source": tuning["source"], "grad_batch": tuning["grad_batch"],
+                   "frame_classes": [{k: c[k] for k in ("D", "frames", "FB", "G", "xcd", "us")}
+                                     for c in tuning["classes"]]},
     }
     if calib:
         out["calibration"] = calib

@@ -89,8 +89,11 @@ enum {
                                 launches always (and drop the plan's graphs).  Results
                                 are bitwise those of direct launches.                    */
   MPBP_OPT_XCD_ORDER = 3,    /* 1 = hand each XCD a contiguous band of frames (default) */
-  MPBP_OPT_PROFILE = 4       /* 1 = record HIP events around every kernel stage on the
+  MPBP_OPT_PROFILE = 4,      /* 1 = record HIP events around every kernel stage on the
                                 call's stream (read with mpbp_stage_times); default 0    */
+  MPBP_OPT_GRAD_BATCH = 5    /* frames whose footprint gradients the back-projection
+                                kernel reads per step of its frame walk: 1, 2 (default)
+                                or 4; set by mpbp_autotune                               */
 };
 
 /* Kernel stages timed under MPBP_OPT_PROFILE. */
@@ -175,6 +178,34 @@ mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value);
    Waits for the recorded events, then resets the accumulators.  Either pointer may be
    NULL. */
 mpbp_status mpbp_stage_times(mpbp_plan plan, double* ms, int64_t* counts);
+
+/* Autotuner.  Times every compiled launch variant of the per-frame kernel for each
+   detector-size class of the plan (footprint bound, projection slab depth = object
+   slices staged per step, XCD-aware frame order) and of the back-projection kernel
+   (frames read per step), on the caller's inputs (layouts as in mpbp_loss_grad; y is
+   required), and keeps the fastest for later calls.  Every variant computes the same
+   result.  Synchronous: waits for `stream`.  Allocates and frees a gradient scratch
+   of 16 * nz * ny * nx bytes.  If the environment variable MPBP_TUNE_CACHE names a
+   file, the choices are written there (one line per kernel, keyed by GPU architecture
+   and shapes) and mpbp_plan_create applies matching lines to later plans.
+   Drops the plan's captured graphs. */
+mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi,
+                          const float* alpha, const void* probe, const float* y,
+                          void* stream);
+
+/* Select a frame-kernel variant by hand for size class `size_class` (the order of
+   the "classes" list of mpbp_tuning): compiled footprint bound (>= the class's
+   smallest, see mpbp_tuning "key"), slab depth (2 or 4) and XCD order (0 or 1).
+   MPBP_ERR_UNSUPPORTED if that variant is not compiled or does not fit in LDS. */
+mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound, int slab,
+                             int xcd_order);
+
+/* The plan's launch parameters as a JSON object: source ("default", "cache",
+   "autotune" or "manual"), grad_batch, per size class {D, key, frames, fy, fx, FB, G,
+   xcd, us} and the candidates the last mpbp_autotune timed.  Writes at most `cap`
+   bytes (NUL-terminated) to buf (may be NULL) and the size needed, NUL included, to
+   *len (may be NULL); MPBP_ERR_INVALID if cap is too small for the text. */
+mpbp_status mpbp_tuning(mpbp_plan plan, char* buf, int64_t cap, int64_t* len);
 
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* mpbp_last_error(void);

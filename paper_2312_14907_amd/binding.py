@@ -19,11 +19,13 @@ MPBP_OPT_PATH = 1
 MPBP_OPT_GRAPH = 2
 MPBP_OPT_XCD_ORDER = 3
 MPBP_OPT_PROFILE = 4
+MPBP_OPT_GRAD_BATCH = 5
 STAGES = ("object", "frames", "grad", "finalize", "plain")
 
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
             "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",
-            "mpbp_get_option", "mpbp_stage_times", "mpbp_last_error")
+            "mpbp_get_option", "mpbp_stage_times", "mpbp_autotune", "mpbp_set_variant", "mpbp_tuning",
+            "mpbp_last_error")
 
 
 class mpbp_peak(ctypes.Structure):
@@ -71,6 +73,12 @@ def _load():
     lib.mpbp_get_option.restype = st
     lib.mpbp_stage_times.argtypes = [vp, vp, vp]
     lib.mpbp_stage_times.restype = st
+    lib.mpbp_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.mpbp_autotune.restype = st
+    lib.mpbp_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.mpbp_set_variant.restype = st
+    lib.mpbp_tuning.argtypes = [vp, ctypes.c_char_p, i64, ctypes.POINTER(i64)]
+    lib.mpbp_tuning.restype = st
     lib.mpbp_last_error.argtypes = []
     lib.mpbp_last_error.restype = ctypes.c_char_p
     return lib
@@ -195,6 +203,23 @@ class Plan:
         n = np.zeros(len(STAGES), dtype=np.int64)
         _check(lib.mpbp_stage_times(self.handle, ms.ctypes.data, n.ctypes.data))
         return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(STAGES)}
+
+    def mpbp_autotune(self, u, chi, alpha, probe, y, stream=None):
+        _check(lib.mpbp_autotune(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(probe), _ptr(y),
+                                 _stream(stream)))
+
+    def mpbp_set_variant(self, size_class, footprint_bound, slab, xcd_order):
+        _check(lib.mpbp_set_variant(self.handle, int(size_class), int(footprint_bound), int(slab),
+                                    int(xcd_order)))
+
+    def mpbp_tuning(self):
+        """The plan's launch parameters (dict, from the library's JSON text)."""
+        import json
+        n = ctypes.c_int64()
+        _check(lib.mpbp_tuning(self.handle, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(int(n.value))
+        _check(lib.mpbp_tuning(self.handle, buf, int(n.value), ctypes.byref(n)))
+        return json.loads(buf.value.decode())
 
     def mpbp_get_option(self, option):
         v = ctypes.c_int64()

@@ -11,7 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmpbp.so")
-SOURCES = ["mpbp_device.hip", "mpbp_plain.hip", "mpbp_host.cpp"]
+SOURCES = ["mpbp_frames_256.hip", "mpbp_frames_192.hip", "mpbp_frames_128.hip", "mpbp_frames_96.hip",
+           "mpbp_frames_64.hip", "mpbp_frames_32.hip", "mpbp_device.hip", "mpbp_plain.hip", "mpbp_host.cpp"]
 ARCH = os.environ.get("MPBP_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.
@@ -29,8 +30,9 @@ def hipcc():
     return p
 
 
-def build(verbose=False, jobs=3):
+def build(verbose=False, jobs=None):
     """Compile every source to an object in parallel, then link libmpbp.so."""
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1))
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -77,9 +78,21 @@ struct mpbp_plan_t {
   std::vector<int64_t> y_off;    // [M+1]
   std::vector<int32_t> peak_of;  // [F]
   std::vector<int32_t> order;    // processing order of the full batch
-  struct SizeClass { int D, FB, begin, count, lds_fwd, lds_grad; };
+  // Frames of one detector size D and smallest footprint bound `key`, with the launch
+  // parameters in use (compiled footprint bound FB >= key, slab depth G, XCD order).
+  struct SizeClass {
+    int D, key, begin, count;
+    int fy, fx;                        // largest footprint over the class's peaks
+    int FB, G, xcd;
+    int lds_fwd[5], lds_grad[5];       // dynamic LDS per slab depth (index G)
+    double tuned_us;                   // autotuned launch time (0: not tuned)
+  };
   std::vector<SizeClass> classes;      // full batch: frames of one detector size, in `order`
   std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch
+  int grad_batch = mpbp::kDefaultGradBatch;
+  double grad_tuned_us = 0.0;
+  std::string tune_source = "default";
+  std::string tune_report;             // candidates timed by the last mpbp_autotune
   int lds_fwd = 0, lds_grad_frame = 0, lds_grad = 0;
   int maxspan_y = 0, maxspan_x = 0;
   int max_cand = 0;
@@ -249,11 +262,12 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     d.gx = (float)k.g[0]; d.gy = (float)k.g[1]; d.gz = (float)k.g[2];
     d.tw_off = (long long)(p->tw.size() / 2);
     mpbp::frame_twiddles(d.D, d.fy, p->tw);
-    d.lds_bytes = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, true);
+    d.lds_bytes = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, true, mpbp::kDefaultSlab);
     if (d.lds_bytes > kMaxLds)
       return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d needs %d B of LDS", m, d.fy, d.fx, d.lds_bytes);
     p->lds_grad_frame = std::max(p->lds_grad_frame, d.lds_bytes);
-    p->lds_fwd = std::max(p->lds_fwd, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false));
+    p->lds_fwd = std::max(p->lds_fwd, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false,
+                                                            mpbp::kDefaultSlab));
     p->maxspan_y = std::max(p->maxspan_y, d.spany);
     p->maxspan_x = std::max(p->maxspan_x, d.spanx);
     slot += (long long)d.nfr * d.fy * d.fx;
@@ -298,13 +312,24 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   p->classes.clear();
   for (int m : pk) {
     const PeakDev& d = p->pdev[m];
-    const int lf = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false);
-    if (p->classes.empty() || p->classes.back().D != d.D || p->classes.back().FB != fb(m))
-      p->classes.push_back({d.D, fb(m), (int)p->order.size(), 0, 0, 0});
+    if (p->classes.empty() || p->classes.back().D != d.D || p->classes.back().key != fb(m)) {
+      mpbp_plan_t::SizeClass c{};
+      c.D = d.D;
+      c.key = fb(m);
+      c.begin = (int)p->order.size();
+      c.FB = c.key;
+      c.G = mpbp::kDefaultSlab;
+      c.xcd = p->xcd;
+      p->classes.push_back(c);
+    }
     auto& c = p->classes.back();
     c.count += d.nfr;
-    c.lds_fwd = std::max(c.lds_fwd, lf);
-    c.lds_grad = std::max(c.lds_grad, d.lds_bytes);
+    c.fy = std::max(c.fy, d.fy);
+    c.fx = std::max(c.fx, d.fx);
+    for (int G : mpbp::kSlabDepths) {
+      c.lds_fwd[G] = std::max(c.lds_fwd[G], mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false, G));
+      c.lds_grad[G] = std::max(c.lds_grad[G], mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, true, G));
+    }
     for (int j = 0; j < d.nfr; ++j) p->order.push_back(d.frame_base + j);
   }
   return MPBP_OK;
@@ -386,7 +411,7 @@ mpbp_status stage_frames(mpbp_plan_t* p, const int32_t* frames, int64_t n, hipSt
     for (int64_t i = 0; i < n; ++i)
       if (p->pdev[p->peak_of[frames[i]]].D == c.D &&
           mpbp::frame_bound(c.D, std::max(p->pdev[p->peak_of[frames[i]]].fy,
-                                          p->pdev[p->peak_of[frames[i]]].fx)) == c.FB)
+                                          p->pdev[p->peak_of[frames[i]]].fx)) == c.key)
         sorted[pos++] = frames[i];
     sc.count = pos - sc.begin;
     p->sub_classes.push_back(sc);
@@ -458,12 +483,13 @@ hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset,
     mpbp::FrameArgs a = base;
     a.list = list + c.begin;
     a.n_list = c.count;
+    a.xcd = c.xcd;
     hipStream_t t = s;
     if (branch && !first) {
       t = p->forks[k];
       if (e == hipSuccess) e = hipStreamWaitEvent(t, p->fork_ev, 0);
     }
-    if (e == hipSuccess) e = mpbp::launch_frames(c.D, c.FB, a, grad ? c.lds_grad : c.lds_fwd, t);
+    if (e == hipSuccess) e = mpbp::launch_frames(c.D, c.FB, c.G, a, grad ? c.lds_grad[c.G] : c.lds_fwd[c.G], t);
     if (branch && !first) {
       if (e == hipSuccess) e = hipEventRecord(p->joins[k], t);
       if (e == hipSuccess) e = hipStreamWaitEvent(s, p->joins[k], 0);
@@ -493,6 +519,25 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   a.grad = grad;
   a.xcd = p->xcd;
   return a;
+}
+
+mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const float* alpha,
+                         const float* probe, bool subset, float* grad_u, float* grad_chi) {
+  mpbp::GradArgs g{};
+  g.slots = p->d_slots;
+  g.active = subset ? p->d_active : p->d_active_all;
+  g.probe = probe;
+  g.u = u; g.chi = chi; g.alpha = alpha;
+  g.shear = p->d_shear;
+  g.peaks = p->d_peaks;
+  g.n_peaks = p->M;
+  g.nz = p->nz; g.ny = p->ny; g.nx = p->nx; g.np = p->np;
+  g.tiles_x = p->tiles_x; g.tiles_y = p->tiles_y;
+  g.maxspan_y = p->maxspan_y; g.maxspan_x = p->maxspan_x;
+  g.max_cand = p->max_cand;
+  g.grad_u = grad_u; g.grad_chi = grad_chi;
+  g.alpha_part = p->d_apart;
+  return g;
 }
 
 // The batched fused path's launches of one mpbp_forward call.  `what` names the stage
@@ -534,23 +579,10 @@ hipError_t enqueue_loss_grad(mpbp_plan p, const float* u, const float* chi, cons
     e = enqueue_frames(p, a, subset, true, s, branch);
   }
   if (e != hipSuccess) return *what = "frame kernel", e;
-  mpbp::GradArgs g{};
-  g.slots = p->d_slots;
-  g.active = subset ? p->d_active : p->d_active_all;
-  g.probe = probe;
-  g.u = u; g.chi = chi; g.alpha = alpha;
-  g.shear = p->d_shear;
-  g.peaks = p->d_peaks;
-  g.n_peaks = p->M;
-  g.nz = p->nz; g.ny = p->ny; g.nx = p->nx; g.np = p->np;
-  g.tiles_x = p->tiles_x; g.tiles_y = p->tiles_y;
-  g.maxspan_y = p->maxspan_y; g.maxspan_x = p->maxspan_x;
-  g.max_cand = p->max_cand;
-  g.grad_u = grad_u; g.grad_chi = grad_chi;
-  g.alpha_part = p->d_apart;
+  const mpbp::GradArgs g = grad_args(p, u, chi, alpha, probe, subset, grad_u, grad_chi);
   {
     StageTimer t(p, MPBP_STAGE_GRAD, s);
-    e = mpbp::launch_grad(g, p->lds_grad, s);
+    e = mpbp::launch_grad(p->grad_batch, g, p->lds_grad, s);
   }
   if (e != hipSuccess) return *what = "gradient kernel", e;
   return hipSuccess;
@@ -622,6 +654,126 @@ mpbp_status run_graph(mpbp_plan p, const GraphKey& key, hipStream_t s, Enqueue&&
   return e == hipSuccess ? MPBP_OK : hip_fail(e, "hipGraphLaunch");
 }
 
+// ---- launch-parameter tuning ----------------------------------------------------
+
+// Compiled footprint bounds a class may use (>= its smallest bound), and whether a
+// variant fits the LDS of a CU.
+std::vector<int> class_bounds(const mpbp_plan_t::SizeClass& c) {
+  std::vector<int> out;
+  for (int fb : {32, 48, 64, c.D})
+    if (fb >= c.key && std::find(out.begin(), out.end(), fb) == out.end()) {
+      bool any = false;
+      for (int G : mpbp::kSlabDepths) any = any || mpbp::frame_instance(c.D, fb, G);
+      if (any) out.push_back(fb);
+    }
+  return out;
+}
+
+bool variant_ok(const mpbp_plan_t::SizeClass& c, int fb, int G) {
+  return fb >= c.key && G >= 0 && G < 5 && mpbp::frame_instance(c.D, fb, G) && c.lds_grad[G] > 0 &&
+         c.lds_grad[G] <= kMaxLds && c.lds_fwd[G] <= kMaxLds;
+}
+
+std::string device_arch(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+std::string frames_key(const mpbp_plan_t* p, const mpbp_plan_t::SizeClass& c, const std::string& arch) {
+  char buf[192];
+  snprintf(buf, sizeof(buf), "frames %s D=%d key=%d fy=%d fx=%d np=%d nz=%d", arch.c_str(), c.D, c.key, c.fy,
+           c.fx, p->np, p->nz);
+  return buf;
+}
+
+std::string grad_key(const mpbp_plan_t* p, const std::string& arch) {
+  char buf[192];
+  snprintf(buf, sizeof(buf), "grad %s nz=%d ny=%d nx=%d np=%d M=%d spany=%d spanx=%d", arch.c_str(), p->nz,
+           p->ny, p->nx, p->np, p->M, p->maxspan_y, p->maxspan_x);
+  return buf;
+}
+
+// The tuning cache is a text file named by MPBP_TUNE_CACHE: one line per tuned kernel,
+// "<key> | <parameters>", keyed by GPU architecture and the shapes the kernel's speed
+// depends on.
+std::vector<std::pair<std::string, std::string>> read_cache(const char* path) {
+  std::vector<std::pair<std::string, std::string>> out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    const size_t bar = l.find(" | ");
+    if (bar != std::string::npos) out.push_back({l.substr(0, bar), l.substr(bar + 3)});
+  }
+  std::fclose(f);
+  return out;
+}
+
+void load_tuning(mpbp_plan_t* p) {
+  const char* path = std::getenv("MPBP_TUNE_CACHE");
+  if (!path || !*path) return;
+  const auto entries = read_cache(path);
+  if (entries.empty()) return;
+  const std::string arch = device_arch(p->device);
+  bool used = false;
+  for (auto& c : p->classes) {
+    const std::string k = frames_key(p, c, arch);
+    for (const auto& e : entries) {
+      int fb = 0, G = 0, xcd = 0;
+      double us = 0.0;
+      if (e.first == k && std::sscanf(e.second.c_str(), "FB=%d G=%d xcd=%d us=%lf", &fb, &G, &xcd, &us) == 4 &&
+          variant_ok(c, fb, G) && (xcd == 0 || xcd == 1)) {
+        c.FB = fb; c.G = G; c.xcd = xcd; c.tuned_us = us;
+        used = true;
+      }
+    }
+  }
+  const std::string gk = grad_key(p, arch);
+  for (const auto& e : entries) {
+    int b = 0;
+    double us = 0.0;
+    if (e.first == gk && std::sscanf(e.second.c_str(), "batch=%d us=%lf", &b, &us) == 2 && (b == 1 || b == 2 || b == 4)) {
+      p->grad_batch = b;
+      p->grad_tuned_us = us;
+      used = true;
+    }
+  }
+  if (used) p->tune_source = "cache";
+}
+
+void save_tuning(const mpbp_plan_t* p) {
+  const char* path = std::getenv("MPBP_TUNE_CACHE");
+  if (!path || !*path) return;
+  auto entries = read_cache(path);
+  const std::string arch = device_arch(p->device);
+  auto put = [&](const std::string& k, const std::string& v) {
+    for (auto& e : entries)
+      if (e.first == k) {
+        e.second = v;
+        return;
+      }
+    entries.push_back({k, v});
+  };
+  char buf[128];
+  for (const auto& c : p->classes) {
+    if (c.count == 0) continue;
+    snprintf(buf, sizeof(buf), "FB=%d G=%d xcd=%d us=%.2f", c.FB, c.G, c.xcd, c.tuned_us);
+    put(frames_key(p, c, arch), buf);
+  }
+  snprintf(buf, sizeof(buf), "batch=%d us=%.2f", p->grad_batch, p->grad_tuned_us);
+  put(grad_key(p, arch), buf);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto& e : entries) std::fprintf(f, "%s | %s\n", e.first.c_str(), e.second.c_str());
+  std::fclose(f);
+  (void)std::rename(tmp.c_str(), path);
+}
+
 }  // namespace
 
 extern "C" {
@@ -652,6 +804,7 @@ mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan*
       g_err = msg;
       return st;
     }
+    load_tuning(p);
   } else if (device != -1) {
     delete p;
     return fail(MPBP_ERR_INVALID, "device must be >= 0, or -1 for a host-only plan");
@@ -820,10 +973,24 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
     case MPBP_OPT_XCD_ORDER:
       if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "xcd order must be 0 or 1");
       plan->xcd = (int)value;
+      for (auto& c : plan->classes) c.xcd = (int)value;
+      if (plan->device >= 0) {
+        (void)hipSetDevice(plan->device);
+        clear_graphs(plan);
+      }
       return MPBP_OK;
     case MPBP_OPT_PROFILE:
       if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "profile must be 0 or 1");
       plan->profile = (int)value;
+      return MPBP_OK;
+    case MPBP_OPT_GRAD_BATCH:
+      if (value != 1 && value != 2 && value != 4) return fail(MPBP_ERR_INVALID, "grad batch must be 1, 2 or 4");
+      plan->grad_batch = (int)value;
+      plan->tune_source = "manual";
+      if (plan->device >= 0) {
+        (void)hipSetDevice(plan->device);
+        clear_graphs(plan);
+      }
       return MPBP_OK;
     default:
       return fail(MPBP_ERR_INVALID, "unknown option %d", option);
@@ -837,6 +1004,7 @@ mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value) {
     case MPBP_OPT_GRAPH: *value = plan->graph; return MPBP_OK;
     case MPBP_OPT_XCD_ORDER: *value = plan->xcd; return MPBP_OK;
     case MPBP_OPT_PROFILE: *value = plan->profile; return MPBP_OK;
+    case MPBP_OPT_GRAD_BATCH: *value = plan->grad_batch; return MPBP_OK;
     default: return fail(MPBP_ERR_INVALID, "unknown option %d", option);
   }
 }
@@ -860,6 +1028,143 @@ mpbp_status mpbp_stage_times(mpbp_plan plan, double* ms, int64_t* counts) {
     if (counts) counts[i] = plan->stage_n[i];
     plan->stage_ms[i] = 0.0;
     plan->stage_n[i] = 0;
+  }
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, const float* alpha,
+                          const void* probe, const float* y, void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!u || !chi || !alpha || !probe || !y) return fail(MPBP_ERR_INVALID, "u, chi, alpha, probe and y are required");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float* gbuf = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    if (gbuf) (void)hipFree(gbuf);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  };
+  // one warm-up launch, then the mean of `reps` launches
+  auto time_us = [&](auto&& launch, int reps, double* us) -> hipError_t {
+    hipError_t r = launch();
+    if (r == hipSuccess) r = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && r == hipSuccess; ++i) r = launch();
+    if (r == hipSuccess) r = hipEventRecord(e1, s);
+    if (r == hipSuccess) r = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+    *us = 1e3 * (double)ms / reps;
+    return r;
+  };
+  e = hipMalloc((void**)&gbuf, (size_t)4 * plan->nvox * sizeof(float));
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(MPBP_ERR_NOMEM, "hipMalloc gradient scratch: %s", hipGetErrorString(e));
+  }
+  e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+  std::string rep = "[";
+  char buf[160];
+  for (size_t ci = 0; ci < plan->classes.size() && e == hipSuccess; ++ci) {
+    auto& c = plan->classes[ci];
+    if (c.count == 0) continue;
+    double best = 1e300;
+    int bfb = c.FB, bg = c.G, bx = c.xcd;
+    for (int fb : class_bounds(c))
+      for (int G : mpbp::kSlabDepths)
+        for (int xcd = 0; xcd < 2 && e == hipSuccess; ++xcd) {
+          if (!variant_ok(c, fb, G)) continue;
+          mpbp::FrameArgs a = frame_args(plan, y, plan->d_order + c.begin, c.count, nullptr, 1);
+          a.probe = (const float*)probe;
+          a.xcd = xcd;
+          double us = 0.0;
+          e = time_us([&]() { return mpbp::launch_frames(c.D, fb, G, a, c.lds_grad[G], s); }, 3, &us);
+          snprintf(buf, sizeof(buf), "%s{\"class\": %zu, \"FB\": %d, \"G\": %d, \"xcd\": %d, \"us\": %.2f}",
+                   rep.size() > 1 ? ", " : "", ci, fb, G, xcd, us);
+          rep += buf;
+          if (e == hipSuccess && us < best) {
+            best = us;
+            bfb = fb; bg = G; bx = xcd;
+          }
+        }
+    c.FB = bfb; c.G = bg; c.xcd = bx; c.tuned_us = best;
+  }
+  if (e == hipSuccess) {
+    // the gradient kernel, on the footprint gradients the frame launches left in the slots
+    const mpbp::GradArgs g = grad_args(plan, u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * plan->nvox);
+    double best = 1e300;
+    int bb = plan->grad_batch;
+    for (int B : mpbp::kGradBatches) {
+      if (e != hipSuccess) break;
+      double us = 0.0;
+      e = time_us([&]() { return mpbp::launch_grad(B, g, plan->lds_grad, s); }, 3, &us);
+      snprintf(buf, sizeof(buf), "%s{\"grad_batch\": %d, \"us\": %.2f}", rep.size() > 1 ? ", " : "", B, us);
+      rep += buf;
+      if (e == hipSuccess && us < best) {
+        best = us;
+        bb = B;
+      }
+    }
+    plan->grad_batch = bb;
+    plan->grad_tuned_us = best;
+  }
+  cleanup();
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  plan->tune_report = rep + "]";
+  plan->tune_source = "autotune";
+  clear_graphs(plan);
+  save_tuning(plan);
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound, int slab, int xcd_order) {
+  if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
+  if (size_class < 0 || size_class >= (int)plan->classes.size())
+    return fail(MPBP_ERR_INVALID, "size class %d out of range [0, %zu)", size_class, plan->classes.size());
+  auto& c = plan->classes[size_class];
+  if (xcd_order != 0 && xcd_order != 1) return fail(MPBP_ERR_INVALID, "xcd_order must be 0 or 1");
+  if (!variant_ok(c, footprint_bound, slab))
+    return fail(MPBP_ERR_UNSUPPORTED, "no compiled frame kernel for D=%d with footprint bound %d >= %d and slab %d",
+                c.D, footprint_bound, c.key, slab);
+  c.FB = footprint_bound;
+  c.G = slab;
+  c.xcd = xcd_order;
+  c.tuned_us = 0.0;
+  plan->tune_source = "manual";
+  if (plan->device >= 0) {
+    (void)hipSetDevice(plan->device);
+    clear_graphs(plan);
+  }
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_tuning(mpbp_plan plan, char* buf, int64_t cap, int64_t* len) {
+  if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
+  std::string out = "{\"source\": \"" + plan->tune_source + "\", \"grad_batch\": " +
+                    std::to_string(plan->grad_batch) + ", \"classes\": [";
+  char tmp[256];
+  for (size_t i = 0; i < plan->classes.size(); ++i) {
+    const auto& c = plan->classes[i];
+    snprintf(tmp, sizeof(tmp),
+             "%s{\"D\": %d, \"key\": %d, \"frames\": %d, \"fy\": %d, \"fx\": %d, \"FB\": %d, \"G\": %d, "
+             "\"xcd\": %d, \"us\": %.2f}",
+             i ? ", " : "", c.D, c.key, c.count, c.fy, c.fx, c.FB, c.G, c.xcd, c.tuned_us);
+    out += tmp;
+  }
+  snprintf(tmp, sizeof(tmp), "], \"grad_us\": %.2f, \"candidates\": ", plan->grad_tuned_us);
+  out += tmp;
+  out += plan->tune_report.empty() ? "[]" : plan->tune_report;
+  out += "}";
+  if (len) *len = (int64_t)out.size() + 1;
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>((size_t)cap - 1, out.size());
+    std::memcpy(buf, out.data(), n);
+    buf[n] = 0;
+    if ((int64_t)out.size() + 1 > cap) return fail(MPBP_ERR_INVALID, "buffer too small (%zu bytes needed)", out.size() + 1);
   }
   return MPBP_OK;
 }

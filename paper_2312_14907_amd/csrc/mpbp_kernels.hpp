@@ -66,14 +66,16 @@ struct GradArgs {
 };
 
 constexpr int kFrameThreads = 256;
-constexpr int kProjG = 4;     // slices staged per projection step
+constexpr int kSlabDepths[] = {2, 4};   // compiled projection slab depths (slices staged per step)
+constexpr int kDefaultSlab = 4;
 constexpr int kProjE = 4;     // probe pixels staged per lane (probe_n^2 <= 4 * 256)
 constexpr int kProjPix = 8;   // footprint pixels per lane (fy * fx <= 8 * 256)
 constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 8;  // 512 threads
 constexpr int kGradThreads = kGradTX * kGradTY * kGradTZ;
 constexpr int kGradZB = 32;                             // z per pass of the grad kernel
 constexpr int kGradZPer = kGradZB / kGradTZ;            // z per thread per pass
-constexpr int kGradBatch = 2;                           // frames staged per barrier pair
+constexpr int kGradBatches[] = {1, 2, 4};               // compiled frame-walk batch sizes
+constexpr int kDefaultGradBatch = 2;
 constexpr int kMaxPeaksDev = 16;
 
 }  // namespace mpbp

@@ -11,16 +11,19 @@ namespace mpbp {
 // Allow the frame and gradient kernels the full 160 KB of LDS on the current device.
 // Called once per plan, before any launch (and before any graph capture).
 hipError_t prepare_kernels();
-// True if the frame kernel is compiled for detector size D and footprint bound FB.
-bool frame_instance(int D, int FB);
+// True if the frame kernel is compiled for detector size D, footprint bound FB and
+// projection slab depth G.
+bool frame_instance(int D, int FB, int G);
 
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
                          int n_peaks, long long nvox, float* obj, hipStream_t s);
 // Frames of one detector size D whose footprints fit FB x FB (a.list holds only such
-// frames); FB = frame_bound(D, largest footprint side).
-hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s);
+// frames; frame_bound(D, largest footprint side) is the smallest such FB), with G object
+// slices staged per projection step.
+hipError_t launch_frames(int D, int FB, int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
 int frame_bound(int D, int footprint);
-hipError_t launch_grad(const GradArgs& a, int lds_bytes, hipStream_t s);
+// Gradient kernel reading `batch` frames per step of its frame walk (1, 2 or 4).
+hipError_t launch_grad(int batch, const GradArgs& a, int lds_bytes, hipStream_t s);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
                            float* grad_alpha, hipStream_t s);
@@ -28,8 +31,9 @@ hipError_t launch_step(float* p, const float* g, long long n, float eta, hipStre
 hipError_t launch_mark_active(unsigned char* act, long long n_frames, const int* list, int n,
                               hipStream_t s);
 
-// Dynamic LDS of the frame kernel for one peak (bytes); must match frame_body's layout.
-int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad);
+// Dynamic LDS of the frame kernel for one peak and slab depth G (bytes); must match
+// frame_body's layout.
+int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad, int G);
 // Append the frame kernel's twiddle tables of one peak (complex64 as float pairs):
 // row twiddles [D], column twiddles [L], residue-fold twiddles [R][fy] (footprint at
 // the window origin).

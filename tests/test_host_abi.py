@@ -118,3 +118,43 @@ def test_host_only_plan_refuses_compute_and_options():
     assert B.lib.mpbp_num_frames(None) == -1
     assert B.lib.mpbp_intensity_size(None) == -1
     B.lib.mpbp_plan_destroy(None)
+
+
+def test_launch_parameter_api_on_host_plan():
+    """Size classes, variant selection and its validation (no kernel runs)."""
+    prob = make_problem(get_config("c4_batch"))
+    plan = B.Plan(prob, device=-1)
+    t = plan.mpbp_tuning()
+    assert t["source"] == "default" and t["grad_batch"] == 2 and t["candidates"] == []
+    # one class per (detector size, smallest footprint bound); frames add up
+    assert sum(c["frames"] for c in t["classes"]) == plan.n_frames
+    assert [c["D"] for c in t["classes"]] == sorted([c["D"] for c in t["classes"]], reverse=True)
+    for c in t["classes"]:
+        assert c["FB"] == c["key"] and c["G"] == 4 and c["xcd"] == 1
+        assert max(c["fy"], c["fx"]) <= c["key"]
+    k = next(i for i, c in enumerate(t["classes"]) if c["D"] == 256)
+    plan.mpbp_set_variant(k, 256, 2, 0)
+    c = plan.mpbp_tuning()["classes"][k]
+    assert (c["FB"], c["G"], c["xcd"]) == (256, 2, 0)
+    assert plan.mpbp_tuning()["source"] == "manual"
+    for args, status in (((len(t["classes"]), 48, 4, 1), 1),   # class out of range
+                         ((k, 32, 4, 1), 6),                  # bound below the footprint
+                         ((k, 48, 3, 1), 6),                  # slab depth not compiled
+                         ((k, 48, 4, 2), 1)):                 # bad xcd flag
+        with pytest.raises(B.MPBPError) as e:
+            plan.mpbp_set_variant(*args)
+        assert e.value.status == status
+    for v in (1, 2, 4):
+        plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, v)
+        assert plan.mpbp_get_option(B.MPBP_OPT_GRAD_BATCH) == v
+    with pytest.raises(B.MPBPError):
+        plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, 3)
+    with pytest.raises(B.MPBPError) as e:     # autotuning needs a device plan
+        z = np.zeros(1, np.float32)
+        plan.mpbp_autotune(z, z, z, z, z, stream=0)
+    assert e.value.status == 4
+    n = ctypes.c_int64()
+    assert B.lib.mpbp_tuning(plan.handle, None, 0, ctypes.byref(n)) == 0 and n.value > 2
+    small = ctypes.create_string_buffer(8)
+    assert B.lib.mpbp_tuning(plan.handle, small, 8, ctypes.byref(n)) == 1
+    assert len(small.value) == 7
