@@ -21,7 +21,9 @@
  * Layouts (all row-major, x fastest; "(dev)" = device memory of the plan's GPU,
  * "(host)" = host memory).  The caller owns every buffer it passes.
  *   u       (dev) float [3][nz][ny][nx]       displacement components (x, y, z), nm
- *   chi     (dev) float [nz][ny][nx]          amplitude chi >= 0
+ *                 ([3][1][ny][nx] under MPBP_Z_TIED)
+ *   chi     (dev) float [nz][ny][nx]          amplitude chi >= 0 ([1][ny][nx] under
+ *                 MPBP_Z_TIED)
  *   alpha   (dev) float [n_peaks]             per-peak scale alpha_m > 0
  *   probe   (dev) complex64 [n_peaks][probe_n][probe_n], interleaved (re, im) floats
  *   y       (dev) float, ragged: peaks concatenated, peak m holds
@@ -72,8 +74,15 @@ typedef struct {
   int32_t probe_n;           /* probe support (square)                                     */
   int32_t n_peaks;
   const mpbp_peak* peaks;    /* (host) [n_peaks]; copied by mpbp_plan_create               */
-  uint32_t flags;            /* reserved, must be 0                                        */
+  uint32_t flags;            /* 0 or MPBP_Z_TIED                                           */
 } mpbp_problem;
+
+/* Problem flags.
+   MPBP_Z_TIED: the membrane parameterisation (sections 3-4: unknowns per lateral pixel,
+   constant along the incident beam x3).  u is then (dev) float [3][1][ny][nx] and chi
+   [1][ny][nx], both holding for every slice z; grad_u and grad_chi have the same shapes
+   and hold the z-sums of the per-voxel gradients. */
+enum { MPBP_Z_TIED = 1 };
 
 /* Options of mpbp_set_option / mpbp_get_option. */
 enum {
@@ -109,7 +118,7 @@ enum {
 /* Validate `problem`, build the integer tables (scan offsets, shear offsets, ragged y
    offsets) and, for device >= 0, allocate the plan's device workspace on that GPU.
    device = -1 makes a host-only plan: tables and validation only; compute calls then
-   return MPBP_ERR_DEVICE.  Errors: MPBP_ERR_INVALID (null pointers, flags),
+   return MPBP_ERR_DEVICE.  Errors: MPBP_ERR_INVALID (null pointers, unknown flags),
    MPBP_ERR_SHAPE (non-positive sizes, D outside the supported set), MPBP_ERR_FOOTPRINT,
    MPBP_ERR_DEVICE, MPBP_ERR_NOMEM.  On success *out owns the plan. */
 mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan* out);

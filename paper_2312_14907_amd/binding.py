@@ -20,6 +20,7 @@ MPBP_OPT_GRAPH = 2
 MPBP_OPT_XCD_ORDER = 3
 MPBP_OPT_PROFILE = 4
 MPBP_OPT_GRAD_BATCH = 5
+MPBP_Z_TIED = 1
 STAGES = ("object", "frames", "grad", "finalize", "plain")
 
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
@@ -112,7 +113,7 @@ def _stream(stream):
     return torch.cuda.current_stream().cuda_stream
 
 
-def make_problem_struct(problem):
+def make_problem_struct(problem, flags=0):
     """mpbp_problem for a geometry object with attributes nz, ny, nx, probe_n, g, shear,
     det, scan_n, scan_step, scan_origin (as built by synth.make_problem)."""
     m = int(np.asarray(problem.g).shape[0])
@@ -128,16 +129,18 @@ def make_problem_struct(problem):
             pk.scan_origin[c] = int(problem.scan_origin[k][c])
         pk.det = int(problem.det[k])
     prob = mpbp_problem(int(problem.nz), int(problem.ny), int(problem.nx), int(problem.probe_n), m,
-                        ctypes.cast(peaks, ctypes.POINTER(mpbp_peak)), 0)
+                        ctypes.cast(peaks, ctypes.POINTER(mpbp_peak)), int(flags))
     prob._peaks_keepalive = peaks
     return prob
 
 
 class Plan:
-    """A library plan (mpbp_plan) for one workload geometry on one device (-1: host only)."""
+    """A library plan (mpbp_plan) for one workload geometry on one device (-1: host only);
+    flags = MPBP_Z_TIED for fields given per lateral pixel."""
 
-    def __init__(self, problem, device=0):
-        self._struct = make_problem_struct(problem)
+    def __init__(self, problem, device=0, flags=0):
+        self._struct = make_problem_struct(problem, flags)
+        self.flags = int(flags)
         h = ctypes.c_void_p()
         _check(lib.mpbp_plan_create(ctypes.byref(self._struct), int(device), ctypes.byref(h)))
         self.handle = h

@@ -21,15 +21,19 @@
 namespace mpbp {
 
 // ------------------------------------------------------------------ object build ---
+// tied > 0: u and chi are given per lateral pixel ([3][1][ny][nx], [1][ny][nx], with
+// tied = ny * nx) and hold for every slice.
 __global__ __launch_bounds__(256) void k_object(const float* __restrict__ u,
                                                 const float* __restrict__ chi,
                                                 const float* __restrict__ alpha,
                                                 const PeakDev* __restrict__ peaks, int n_peaks,
-                                                long long nvox, float* __restrict__ obj) {
+                                                long long nvox, long long tied, float* __restrict__ obj) {
   long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvox) return;
-  float ux = u[v], uy = u[nvox + v], uz = u[2 * nvox + v];
-  float ch = chi[v];
+  const long long vi = tied ? v % tied : v;
+  const long long us = tied ? tied : nvox;
+  float ux = u[vi], uy = u[us + vi], uz = u[2 * us + vi];
+  float ch = chi[vi];
   for (int m = 0; m < n_peaks; ++m) {
     float phi = peaks[m].gx * ux + peaks[m].gy * uy + peaks[m].gz * uz;
     float s, c;
@@ -69,6 +73,9 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   double* apl = reinterpret_cast<double*>(sh + nz);  // alpha partials
   float* red = reinterpret_cast<float*>(apl + kMaxPeaksDev);       // block reduction
   unsigned char* actf = reinterpret_cast<unsigned char*>(red + 16);  // candidate frames' flags
+  // z-tied: per-thread partial z-sums, reduced over the slice groups at the end
+  float* zred = reinterpret_cast<float*>(actf + ((A.max_cand + 15) & ~15));
+  float tgu[3] = {0.f, 0.f, 0.f}, tgc = 0.f;
 
   const int tid = threadIdx.x;
   const int tx = tid % kGradTX, ty = (tid / kGradTX) % kGradTY, tz = tid / (kGradTX * kGradTY);
@@ -82,6 +89,8 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   const int x = x0 + tx, y = y0 + ty;
   const bool inb = x < A.nx && y < A.ny;
   const long long nvox = (long long)nz * A.ny * A.nx;
+  const unsigned lat = (unsigned)(y * A.nx + x);                 // lateral pixel
+  const unsigned fstride = A.tied ? (unsigned)(A.ny * A.nx) : (unsigned)nvox;   // field component stride
   // this thread's element positions in a staged region (row-major with stride RW)
   const int e0r = tid / RW, e0c = tid - e0r * RW;
   const int e1 = tid + kGradThreads;
@@ -181,8 +190,9 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
           const int z = zb + tz + kGradTZ * i;
           if (z < nz) {
             const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
-            const float ux = A.u[v], uy = A.u[nv + v], uzv = A.u[2u * nv + v];
-            const float ch = A.chi[v];
+            const unsigned vf = A.tied ? lat : v;
+            const float ux = A.u[vf], uy = A.u[fstride + vf], uzv = A.u[2u * fstride + vf];
+            const float ch = A.chi[vf];
             const float phi = pk.gx * ux + pk.gy * uy + pk.gz * uzv;
             float s, c;
             __sincosf(phi, &s, &c);
@@ -200,7 +210,15 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       const float apb = block_sum_f(ap, red);
       if (tid == 0) apl[m] += (double)apb;
     }
-    if (inb) {
+    if (inb && A.tied) {
+#pragma unroll
+      for (int i = 0; i < kGradZPer; ++i) {
+        tgu[0] += gux[i];
+        tgu[1] += guy[i];
+        tgu[2] += guz[i];
+        tgc += gch[i];
+      }
+    } else if (inb) {
       const unsigned nv = (unsigned)nvox;
 #pragma unroll
       for (int i = 0; i < kGradZPer; ++i) {
@@ -216,6 +234,25 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
     }
   }
   __syncthreads();
+  if (A.tied) {
+    // z-sums: add the kGradTZ slice groups of each lateral pixel in a fixed order
+    const int xy = tid % (kGradTX * kGradTY);
+    zred[0 * kGradThreads + tid] = tgu[0];
+    zred[1 * kGradThreads + tid] = tgu[1];
+    zred[2 * kGradThreads + tid] = tgu[2];
+    zred[3 * kGradThreads + tid] = tgc;
+    __syncthreads();
+    if (tz == 0 && inb) {
+      float s[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int g = 0; g < kGradTZ; ++g)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] += zred[c * kGradThreads + g * kGradTX * kGradTY + xy];
+      A.grad_u[lat] = s[0];
+      A.grad_u[fstride + lat] = s[1];
+      A.grad_u[2u * fstride + lat] = s[2];
+      A.grad_chi[lat] = s[3];
+    }
+  }
   if (tid < A.n_peaks) A.alpha_part[(long long)tile * A.n_peaks + tid] = apl[tid];
 }
 
@@ -279,8 +316,8 @@ __global__ __launch_bounds__(256) void k_mark_active(unsigned char* act, const i
 static inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
-                         int n_peaks, long long nvox, float* obj, hipStream_t s) {
-  k_object<<<dim3(nblk(nvox, 256)), dim3(256), 0, s>>>(u, chi, alpha, peaks, n_peaks, nvox, obj);
+                         int n_peaks, long long nvox, long long tied, float* obj, hipStream_t s) {
+  k_object<<<dim3(nblk(nvox, 256)), dim3(256), 0, s>>>(u, chi, alpha, peaks, n_peaks, nvox, tied, obj);
   return hipGetLastError();
 }
 
@@ -435,10 +472,11 @@ int frame_chunk_len(int D) {
   }
 }
 
-int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand) {
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand, bool tied) {
   (void)maxspan_y;
   (void)maxspan_x;
-  return np * np * 8 + nz * 8 + kMaxPeaksDev * 8 + 64 + max_cand;
+  return np * np * 8 + nz * 8 + kMaxPeaksDev * 8 + 64 + ((max_cand + 15) & ~15) +
+         (tied ? 4 * kGradThreads * 4 : 0);
 }
 
 }  // namespace mpbp

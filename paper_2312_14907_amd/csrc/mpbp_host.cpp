@@ -70,6 +70,7 @@ struct mpbp_plan_t {
   int device = -1;
   int nz = 0, ny = 0, nx = 0, np = 0, M = 0;
   long long nvox = 0;
+  long long tied = 0;              // ny * nx under MPBP_Z_TIED, else 0
   int64_t F = 0, ylen = 0;
   std::vector<mpbp_peak> peaks;
   std::vector<PeakDev> pdev;
@@ -182,7 +183,8 @@ void free_device(mpbp_plan_t* p) {
 // Build tables and per-peak constants on the host; validate the problem.
 mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   if (!pr) return fail(MPBP_ERR_INVALID, "problem is NULL");
-  if (pr->flags != 0) return fail(MPBP_ERR_INVALID, "flags must be 0 (got %u)", pr->flags);
+  if (pr->flags & ~(uint32_t)MPBP_Z_TIED)
+    return fail(MPBP_ERR_INVALID, "unknown flags 0x%x (only MPBP_Z_TIED is defined)", pr->flags);
   if (pr->nz < 1 || pr->ny < 1 || pr->nx < 1)
     return fail(MPBP_ERR_SHAPE, "object grid must be positive (nz=%d ny=%d nx=%d)", pr->nz, pr->ny, pr->nx);
   if (pr->probe_n < 1) return fail(MPBP_ERR_SHAPE, "probe_n must be positive (%d)", pr->probe_n);
@@ -198,6 +200,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
 
   p->nz = pr->nz; p->ny = pr->ny; p->nx = pr->nx; p->np = pr->probe_n; p->M = pr->n_peaks;
   p->nvox = nvox;
+  p->tied = (pr->flags & MPBP_Z_TIED) ? (long long)pr->ny * pr->nx : 0;
   p->peaks.assign(pr->peaks, pr->peaks + pr->n_peaks);
   p->pdev.assign(p->M, PeakDev{});
   p->shear.assign((size_t)p->M * p->nz * 2, 0);
@@ -292,7 +295,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     const int cx = std::min(d.cols, (mpbp::kGradTX + np - 2) / d.sx + 2);
     p->max_cand = std::max(p->max_cand, cy * cx);
   }
-  p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand);
+  p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0);
   if (p->lds_grad > kMaxLds) return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", p->lds_grad);
   p->tiles_x = (p->nx + mpbp::kGradTX - 1) / mpbp::kGradTX;
   p->tiles_y = (p->ny + mpbp::kGradTY - 1) / mpbp::kGradTY;
@@ -535,6 +538,7 @@ mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const fl
   g.tiles_x = p->tiles_x; g.tiles_y = p->tiles_y;
   g.maxspan_y = p->maxspan_y; g.maxspan_x = p->maxspan_x;
   g.max_cand = p->max_cand;
+  g.tied = p->tied != 0;
   g.grad_u = grad_u; g.grad_chi = grad_chi;
   g.alpha_part = p->d_apart;
   return g;
@@ -548,7 +552,7 @@ hipError_t enqueue_forward(mpbp_plan p, const float* u, const float* chi, const 
   hipError_t e;
   {
     StageTimer t(p, MPBP_STAGE_OBJECT, s);
-    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->d_obj, s);
+    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, p->d_obj, s);
   }
   if (e != hipSuccess) return *what = "object kernel", e;
   mpbp::FrameArgs a = frame_args(p, y, list, n, model_intensity, 0);
@@ -569,7 +573,7 @@ hipError_t enqueue_loss_grad(mpbp_plan p, const float* u, const float* chi, cons
   hipError_t e;
   {
     StageTimer t(p, MPBP_STAGE_OBJECT, s);
-    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->d_obj, s);
+    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, p->d_obj, s);
   }
   if (e != hipSuccess) return *what = "object kernel", e;
   mpbp::FrameArgs a = frame_args(p, y, list, n, nullptr, 1);
@@ -851,7 +855,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
     e = mpbp::plain_forward(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                             plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                             frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
-                            model_intensity, plan->d_obj, plan->d_floss, s);
+                            model_intensity, plan->d_obj, plan->d_floss, plan->tied, s);
     if (e != hipSuccess) return hip_fail(e, "plain path");
   } else if (use_graph(plan, frames)) {
     GraphKey key;
@@ -906,7 +910,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     e = mpbp::plain_loss_grad(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                               plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                               frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
-                              plan->d_obj, plan->d_floss, grad_u, grad_chi, &apart, &n_part, s);
+                              plan->d_obj, plan->d_floss, grad_u, grad_chi, &apart, &n_part, plan->tied, s);
     if (e != hipSuccess) return hip_fail(e, "plain path");
   } else if (use_graph(plan, frames)) {
     GraphKey key;
@@ -948,8 +952,9 @@ mpbp_status mpbp_step(mpbp_plan plan, float* u, float* chi, float* alpha, const 
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(eta[i])) return fail(MPBP_ERR_INVALID, "eta[%d] not finite", i);
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = mpbp::launch_step(u, grad_u, 3 * plan->nvox, eta[0], s);
-  if (e == hipSuccess) e = mpbp::launch_step(chi, grad_chi, plan->nvox, eta[1], s);
+  const long long nf = plan->tied ? plan->tied : plan->nvox;   // field elements
+  hipError_t e = mpbp::launch_step(u, grad_u, 3 * nf, eta[0], s);
+  if (e == hipSuccess) e = mpbp::launch_step(chi, grad_chi, nf, eta[1], s);
   if (e == hipSuccess) e = mpbp::launch_step(alpha, grad_alpha, plan->M, eta[2], s);
   if (e != hipSuccess) return hip_fail(e, "step kernel");
   return MPBP_OK;
@@ -1061,12 +1066,13 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
     *us = 1e3 * (double)ms / reps;
     return r;
   };
-  e = hipMalloc((void**)&gbuf, (size_t)4 * plan->nvox * sizeof(float));
+  const long long nf = plan->tied ? plan->tied : plan->nvox;   // field elements
+  e = hipMalloc((void**)&gbuf, (size_t)4 * nf * sizeof(float));
   if (e != hipSuccess) {
     cleanup();
     return fail(MPBP_ERR_NOMEM, "hipMalloc gradient scratch: %s", hipGetErrorString(e));
   }
-  e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->d_obj, s);
+  e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->tied, plan->d_obj, s);
   std::string rep = "[";
   char buf[160];
   for (size_t ci = 0; ci < plan->classes.size() && e == hipSuccess; ++ci) {
@@ -1095,7 +1101,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
   }
   if (e == hipSuccess) {
     // the gradient kernel, on the footprint gradients the frame launches left in the slots
-    const mpbp::GradArgs g = grad_args(plan, u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * plan->nvox);
+    const mpbp::GradArgs g = grad_args(plan, u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * nf);
     double best = 1e300;
     int bb = plan->grad_batch;
     for (int B : mpbp::kGradBatches) {

@@ -60,6 +60,7 @@ struct GradArgs {
   int tiles_x, tiles_y;
   int maxspan_y, maxspan_x;  // largest shear span over peaks
   int max_cand;              // largest number of frames of one peak meeting one tile
+  int tied;                  // 1: u, chi and their gradients per lateral pixel (z-sums)
   float* grad_u;
   float* grad_chi;
   double* alpha_part;      // [n_blocks][M]

@@ -15,8 +15,9 @@ hipError_t prepare_kernels();
 // projection slab depth G.
 bool frame_instance(int D, int FB, int G);
 
+// tied = ny * nx for fields given per lateral pixel (the z-tied parameterisation), else 0.
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
-                         int n_peaks, long long nvox, float* obj, hipStream_t s);
+                         int n_peaks, long long nvox, long long tied, float* obj, hipStream_t s);
 // Frames of one detector size D whose footprints fit FB x FB (a.list holds only such
 // frames; frame_bound(D, largest footprint side) is the smallest such FB), with G object
 // slices staged per projection step.
@@ -41,6 +42,6 @@ bool frame_twiddles(int D, int fy, std::vector<float>& out);
 // Rows per residue chunk of the detector (the column-transform length).
 int frame_chunk_len(int D);
 // Dynamic LDS of the gradient kernel (bytes).
-int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand);
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand, bool tied);
 
 }  // namespace mpbp

@@ -151,40 +151,46 @@ __global__ __launch_bounds__(256) void k_pl_zero(float* __restrict__ p, long lon
   if (i < n) p[i] = 0.f;
 }
 
-// Chain rule from g_O,m to df/du, df/dchi and per-block df/dalpha partials.
+// Chain rule from g_O,m to df/du, df/dchi and per-block df/dalpha partials.  One
+// thread per voxel, or (tied = ny * nx) per lateral pixel, summing over the slices.
 __global__ __launch_bounds__(256) void k_pl_chain(const float* __restrict__ gobj,
                                                   const float* __restrict__ u,
                                                   const float* __restrict__ chi,
                                                   const float* __restrict__ alpha,
                                                   const PeakDev* __restrict__ peaks, int M,
-                                                  long long nvox, float* __restrict__ grad_u,
+                                                  long long nvox, long long tied,
+                                                  float* __restrict__ grad_u,
                                                   float* __restrict__ grad_chi,
                                                   double* __restrict__ apart) {
   __shared__ double red[256];
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int tid = threadIdx.x;
-  const bool on = v < nvox;
+  const long long nf = tied ? tied : nvox;      // field elements (and component stride)
+  const long long nslices = tied ? nvox / tied : 1;
+  const bool on = v < nf;
   float gx = 0.f, gy = 0.f, gz = 0.f, gc = 0.f;
   float ux = 0.f, uy = 0.f, uz = 0.f, ch = 0.f;
   if (on) {
-    ux = u[v]; uy = u[nvox + v]; uz = u[2 * nvox + v]; ch = chi[v];
+    ux = u[v]; uy = u[nf + v]; uz = u[2 * nf + v]; ch = chi[v];
   }
   for (int m = 0; m < M; ++m) {
     double ap = 0.0;
     if (on) {
       const PeakDev pk = peaks[m];
-      const cplx g = reinterpret_cast<const cplx*>(gobj)[(long long)m * nvox + v];
       const float phi = pk.gx * ux + pk.gy * uy + pk.gz * uz;
       float s, c;
       sincosf(phi, &s, &c);
       const float al = alpha[m];
-      const float re = g.x * c + g.y * s;
-      const float dphi = al * ch * (g.y * c - g.x * s);
-      gx += pk.gx * dphi;
-      gy += pk.gy * dphi;
-      gz += pk.gz * dphi;
-      gc += al * re;
-      ap = (double)(ch * re);
+      for (long long k = 0; k < nslices; ++k) {
+        const cplx g = reinterpret_cast<const cplx*>(gobj)[(long long)m * nvox + k * nf + v];
+        const float re = g.x * c + g.y * s;
+        const float dphi = al * ch * (g.y * c - g.x * s);
+        gx += pk.gx * dphi;
+        gy += pk.gy * dphi;
+        gz += pk.gz * dphi;
+        gc += al * re;
+        ap += (double)(ch * re);
+      }
     }
     red[tid] = ap;
     __syncthreads();
@@ -197,8 +203,8 @@ __global__ __launch_bounds__(256) void k_pl_chain(const float* __restrict__ gobj
   }
   if (on) {
     grad_u[v] = gx;
-    grad_u[nvox + v] = gy;
-    grad_u[2 * nvox + v] = gz;
+    grad_u[nf + v] = gy;
+    grad_u[2 * nf + v] = gz;
     grad_chi[v] = gc;
   }
 }
@@ -273,11 +279,11 @@ hipError_t plain_forward(PlainWork* w, const PeakDev* hpeaks, const PeakDev* dpe
                          int ny, int nx, int np, const int* dshear, const int32_t* hscan,
                          const int32_t* hpeak_of, const int32_t* frames, int n, const float* u,
                          const float* chi, const float* alpha, const float* probe, const float* y,
-                         float* mi, float* obj, double* floss, hipStream_t s) {
+                         float* mi, float* obj, double* floss, long long tied, hipStream_t s) {
   const long long nvox = (long long)nz * ny * nx;
   hipError_t e = plain_ensure(w, hpeaks, M, nvox, false);
   if (e != hipSuccess) return e;
-  e = launch_object(u, chi, alpha, dpeaks, M, nvox, obj, s);
+  e = launch_object(u, chi, alpha, dpeaks, M, nvox, tied, obj, s);
   if (e != hipSuccess) return e;
   return plain_frames(w, hpeaks, dpeaks, nz, ny, nx, np, dshear, hscan, hpeak_of, frames, n, probe, y,
                       mi, obj, floss, false, s);
@@ -288,18 +294,19 @@ hipError_t plain_loss_grad(PlainWork* w, const PeakDev* hpeaks, const PeakDev* d
                            const int32_t* hpeak_of, const int32_t* frames, int n, const float* u,
                            const float* chi, const float* alpha, const float* probe, const float* y,
                            float* obj, double* floss, float* grad_u, float* grad_chi,
-                           const double** apart, int* n_part, hipStream_t s) {
+                           const double** apart, int* n_part, long long tied, hipStream_t s) {
   const long long nvox = (long long)nz * ny * nx;
   hipError_t e = plain_ensure(w, hpeaks, M, nvox, true);
   if (e != hipSuccess) return e;
-  e = launch_object(u, chi, alpha, dpeaks, M, nvox, obj, s);
+  e = launch_object(u, chi, alpha, dpeaks, M, nvox, tied, obj, s);
   if (e != hipSuccess) return e;
   k_pl_zero<<<dim3((unsigned)((2 * M * nvox + 255) / 256)), dim3(256), 0, s>>>(w->gobj, 2 * M * nvox);
   e = plain_frames(w, hpeaks, dpeaks, nz, ny, nx, np, dshear, hscan, hpeak_of, frames, n, probe, y,
                    nullptr, obj, floss, true, s);
   if (e != hipSuccess) return e;
-  const unsigned nb = (unsigned)((nvox + 255) / 256);
-  k_pl_chain<<<dim3(nb), dim3(256), 0, s>>>(w->gobj, u, chi, alpha, dpeaks, M, nvox, grad_u, grad_chi, w->apart);
+  const unsigned nb = (unsigned)(((tied ? tied : nvox) + 255) / 256);
+  k_pl_chain<<<dim3(nb), dim3(256), 0, s>>>(w->gobj, u, chi, alpha, dpeaks, M, nvox, tied, grad_u, grad_chi,
+                                            w->apart);
   *apart = w->apart;
   *n_part = (int)nb;
   return hipGetLastError();

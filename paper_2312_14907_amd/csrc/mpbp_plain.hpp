@@ -26,13 +26,13 @@ hipError_t plain_forward(PlainWork* w, const PeakDev* hpeaks, const PeakDev* dpe
                          int ny, int nx, int np, const int* dshear, const int32_t* hscan,
                          const int32_t* hpeak_of, const int32_t* frames, int n, const float* u,
                          const float* chi, const float* alpha, const float* probe, const float* y,
-                         float* mi, float* obj, double* floss, hipStream_t s);
+                         float* mi, float* obj, double* floss, long long tied, hipStream_t s);
 
 hipError_t plain_loss_grad(PlainWork* w, const PeakDev* hpeaks, const PeakDev* dpeaks, int M, int nz,
                            int ny, int nx, int np, const int* dshear, const int32_t* hscan,
                            const int32_t* hpeak_of, const int32_t* frames, int n, const float* u,
                            const float* chi, const float* alpha, const float* probe, const float* y,
                            float* obj, double* floss, float* grad_u, float* grad_chi,
-                           const double** apart, int* n_part, hipStream_t s);
+                           const double** apart, int* n_part, long long tied, hipStream_t s);
 
 }  // namespace mpbp

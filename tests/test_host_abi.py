@@ -75,7 +75,9 @@ def test_descriptor_validation_codes():
     assert _status_of(None)[0] == 1                       # NULL problem
     s = B.make_problem_struct(good)
     s.flags = 4
-    assert _status_of(s)[0] == 1                          # reserved flags
+    assert _status_of(s)[0] == 1                          # undefined flag
+    s.flags = B.MPBP_Z_TIED
+    assert _status_of(s)[0] == 0                          # membrane parameterisation
     bad = _supported_problem(((0.3, 0.2), (0.1, -0.4)), dets=(32, 48))
     st, msg = _status_of(B.make_problem_struct(bad))
     assert st == 2 and "48" in msg                        # unsupported detector size
