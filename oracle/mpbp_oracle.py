@@ -333,3 +333,94 @@ def step(params, grads, eta):
     eta_chi, eta_alpha)."""
     return tuple(np.asarray(p, dtype=np.float64) - float(e) * np.asarray(g, dtype=np.float64)
                  for p, g, e in zip(params, grads, eta))
+
+
+# ---------------------------------------------------------------------------------
+# The optimiser around the objective (section 3.3, Algorithm 1).
+# ---------------------------------------------------------------------------------
+
+def adam_update(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, arXiv:1412.6980, their Algorithm 1) of parameter
+    p with gradient g and moments (m, v) at step t >= 1; returns (p', m', v').
+
+      m' = beta1 m + (1 - beta1) g,   v' = beta2 v + (1 - beta2) g^2
+      p' = p - lr * (m' / (1 - beta1^t)) / (sqrt(v' / (1 - beta2^t)) + eps)
+    """
+    p = np.asarray(p, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def log_param_grad(x, grad_x):
+    """Gradient with respect to the log variable x~ of x = exp(x~) (eq. (8)):
+    df/dx~ = x * df/dx."""
+    return np.asarray(x, dtype=np.float64) * np.asarray(grad_x, dtype=np.float64)
+
+
+def adam_reconstruct(u, chi_log, alpha_log, probe, y, problem, order, batch, iterations,
+                     lr=(0.01, 0.1, 0.1), fixed_alpha=0, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Algorithm 1 without the unwrap projection (its line 5): minibatches of `batch`
+    consecutive frames of the shuffled frame order `order` (the shuffle is an input),
+    minibatch gradients summed over the frames (eq. (11)), then Adam on u and on the
+    log variables chi~, alpha~ of eq. (8), alpha of peak `fixed_alpha` held fixed (-1:
+    none).  Returns (u, chi_log, alpha_log, losses) with the minibatch loss of every
+    iteration (evaluated before that iteration's update)."""
+    u = np.array(u, dtype=np.float64)
+    cl = np.array(chi_log, dtype=np.float64)
+    al = np.array(alpha_log, dtype=np.float64)
+    mom = [np.zeros_like(u), np.zeros_like(cl), np.zeros_like(al)]
+    sec = [np.zeros_like(u), np.zeros_like(cl), np.zeros_like(al)]
+    order = np.asarray(order)
+    losses = []
+    for it in range(iterations):
+        start = (it * batch) % len(order)
+        frames = [int(f) for f in order[start:start + batch]]
+        chi, alpha = np.exp(cl), np.exp(al)
+        r = loss_grad(u, chi, alpha, probe, y, problem, frames)
+        losses.append(r["loss"])
+        grads = [r["grad_u"], log_param_grad(chi, r["grad_chi"]), log_param_grad(alpha, r["grad_alpha"])]
+        t = it + 1
+        u, mom[0], sec[0] = adam_update(u, grads[0], mom[0], sec[0], t, lr[0], beta1, beta2, eps)
+        cl, mom[1], sec[1] = adam_update(cl, grads[1], mom[1], sec[1], t, lr[1], beta1, beta2, eps)
+        keep = al[fixed_alpha] if fixed_alpha >= 0 else None
+        keep_m = (mom[2][fixed_alpha], sec[2][fixed_alpha]) if fixed_alpha >= 0 else None
+        al, mom[2], sec[2] = adam_update(al, grads[2], mom[2], sec[2], t, lr[2], beta1, beta2, eps)
+        if fixed_alpha >= 0:
+            al[fixed_alpha] = keep
+            mom[2][fixed_alpha], sec[2][fixed_alpha] = keep_m
+    return u, cl, al, losses
+
+
+def line_search_descent(u, chi, alpha, probe, y, problem, iterations, step0=0.01, c=1e-4,
+                        shrink=0.5, grow=2.0, max_backtracks=30):
+    """Full-batch gradient descent on u (chi, alpha held) with a backtracking (Armijo)
+    step-size search: from u, try u - eta g with eta grown by `grow` from the previous
+    accepted step (first: step0 over the RMS of g) and shrunk by `shrink` until
+    f(u - eta g) <= f(u) - c eta |g|^2.  Returns (u, losses, etas): the loss before each
+    iteration and the accepted step sizes; stops early when no step is accepted."""
+    u = np.array(u, dtype=np.float64)
+    losses, etas = [], []
+    eta = None
+    for _ in range(iterations):
+        r = loss_grad(u, chi, alpha, probe, y, problem)
+        f0, g = r["loss"], r["grad_u"]
+        n2 = float(np.sum(g * g))
+        losses.append(f0)
+        if n2 == 0.0:
+            break
+        eta = step0 / math.sqrt(n2 / g.size) if eta is None else eta * grow
+        for _ in range(max_backtracks):
+            trial = u - eta * g
+            f1, _ = loss(trial, chi, alpha, probe, y, problem)
+            if f1 <= f0 - c * eta * n2:
+                u = trial
+                etas.append(eta)
+                break
+            eta *= shrink
+        else:
+            break
+    return u, losses, etas

@@ -14,7 +14,10 @@ window or the shear) fails at least one of them:
   constant shift) and their consequence sum(df/du) = 0;
 * Euler homogeneity of f in chi and alpha;
 * central finite differences of the full objective;
-* the minibatch sum of eq. (11) over a partition of the frames.
+* the minibatch sum of eq. (11) over a partition of the frames;
+* the optimiser of Algorithm 1: Adam against closed forms (constant gradient, sign
+  steps, a two-step worked example, invariance to gradient scale), the eq. (8) chain
+  rule against finite differences in the log variables, and the loops' invariants.
 """
 import math
 
@@ -433,3 +436,101 @@ def test_exit_wave_pixel_matches_table_1_voxel():
     # exit-wave pixel equals the object voxel.
     pitch_nm = 1.377e-10 * 0.35 / (150 * 55e-6) * 1e9
     assert pitch_nm == pytest.approx(5.84, abs=0.005)
+
+
+# ------------------------------------------------------------------ optimiser ---
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient the bias-corrected moments are g and g^2 at every step,
+    so each Adam update is exactly lr g / (|g| + eps)."""
+    g = np.array([2.5, -0.3, 1e-3, -40.0])
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 8):
+        q, m, v = O.adam_update(p, g, m, v, t, lr=0.1, beta1=0.9, beta2=0.999, eps=1e-8)
+        np.testing.assert_allclose(q - p, -0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+        p = q
+
+
+def test_adam_two_step_worked_example():
+    """beta1 = 1/2, beta2 = 3/4, lr = 1, eps = 0, gradients 1 then 3:
+    m = 1/2, 7/4; v = 1/4, 39/16; corrected m = 1, 7/3; corrected v = 1, 39/7;
+    steps 1 and (7/3) / sqrt(39/7)."""
+    p, m, v = np.zeros(1), np.zeros(1), np.zeros(1)
+    p1, m, v = O.adam_update(p, [1.0], m, v, 1, lr=1.0, beta1=0.5, beta2=0.75, eps=0.0)
+    assert p1[0] == pytest.approx(-1.0, rel=1e-15)
+    assert (m[0], v[0]) == (0.5, 0.25)
+    p2, m, v = O.adam_update(p1, [3.0], m, v, 2, lr=1.0, beta1=0.5, beta2=0.75, eps=0.0)
+    assert (m[0], v[0]) == (1.75, 2.4375)
+    assert p2[0] - p1[0] == pytest.approx(-(7.0 / 3.0) / math.sqrt(39.0 / 7.0), rel=1e-14)
+
+
+def test_adam_scale_invariance_and_sign_steps():
+    rng = np.random.default_rng(5)
+    gs = rng.normal(size=(6, 10))
+    pa = pb = np.zeros(10)
+    ma = va = mb = vb = np.zeros(10)
+    for t, g in enumerate(gs, start=1):
+        pa, ma, va = O.adam_update(pa, g, ma, va, t, lr=0.01, eps=0.0)
+        pb, mb, vb = O.adam_update(pb, 1e4 * g, mb, vb, t, lr=0.01, eps=0.0)
+    np.testing.assert_allclose(pa, pb, rtol=1e-12, atol=1e-15)
+    # no momentum, no averaging: a pure sign step of size lr
+    q, _, _ = O.adam_update(np.zeros(10), gs[0], np.zeros(10), np.zeros(10), 1, lr=0.2, beta1=0.0, beta2=0.0,
+                            eps=0.0)
+    np.testing.assert_allclose(q, -0.2 * np.sign(gs[0]), rtol=1e-15)
+
+
+def test_log_variables_chain_rule_matches_finite_differences():
+    """eq. (8): with chi = exp(chi~), alpha = exp(alpha~), df/dchi~ = chi df/dchi."""
+    prob = tiny_problem()
+    u, chi, alpha, probe = random_fields(prob, seed=41)
+    rng = np.random.default_rng(42)
+    y = ragged(O.model_intensity(u + rng.normal(0, 0.05, size=u.shape), chi * 1.1, alpha * 0.8, probe, prob))
+    cl, al = np.log(chi), np.log(alpha)
+    r = O.loss_grad(u, chi, alpha, probe, y, prob)
+    gcl = O.log_param_grad(chi, r["grad_chi"])
+    gal = O.log_param_grad(alpha, r["grad_alpha"])
+
+    def f(c, a):
+        return O.loss(u, np.exp(c), np.exp(a), probe, y, prob)[0]
+
+    h = 1e-6
+    for _ in range(6):
+        idx = tuple(int(rng.integers(s)) for s in chi.shape)
+        cp, cm = cl.copy(), cl.copy()
+        cp[idx] += h
+        cm[idx] -= h
+        assert (f(cp, al) - f(cm, al)) / (2 * h) == pytest.approx(gcl[idx], abs=1e-6 * np.abs(gcl).max())
+    for m in range(prob.n_peaks):
+        ap, am = al.copy(), al.copy()
+        ap[m] += h
+        am[m] -= h
+        assert (f(cl, ap) - f(cl, am)) / (2 * h) == pytest.approx(gal[m], rel=1e-6)
+
+
+def test_adam_reconstruct_invariants():
+    """Algorithm 1 (no unwrap projection) on a tiny noiseless problem started near the
+    truth: the loss falls, the reference alpha stays fixed, every minibatch is b
+    consecutive frames of the shuffled order."""
+    prob = tiny_problem()
+    u, chi, alpha, probe = random_fields(prob, seed=51)
+    y = ragged(O.model_intensity(u, chi, alpha, probe, prob))
+    rng = np.random.default_rng(52)
+    order = np.concatenate([rng.permutation(prob.n_frames()) for _ in range(12)])
+    u0 = u + rng.normal(0, 0.02, size=u.shape)
+    out_u, cl, al, losses = O.adam_reconstruct(u0, np.log(chi), np.log(alpha) + 0.05, probe, y, prob, order,
+                                               batch=prob.n_frames(), iterations=12, lr=(0.002, 0.01, 0.01),
+                                               fixed_alpha=0)
+    assert al[0] == pytest.approx(np.log(alpha[0]) + 0.05, abs=0.0)
+    assert losses[-1] < 0.5 * losses[0]
+    full = O.loss(u0, chi, alpha * np.exp(0.05), probe, y, prob)[0]
+    assert losses[0] == pytest.approx(full, rel=1e-12)      # batch = all frames: the full loss
+
+
+def test_line_search_descent_invariants():
+    prob = tiny_problem()
+    u, chi, alpha, probe = random_fields(prob, seed=61)
+    y = ragged(O.model_intensity(u, chi, alpha, probe, prob))
+    u0 = u + np.random.default_rng(62).normal(0, 0.03, size=u.shape)
+    out, losses, etas = O.line_search_descent(u0, chi, alpha, probe, y, prob, iterations=8)
+    assert len(etas) == len(losses) == 8
+    assert all(b < a for a, b in zip(losses, losses[1:]))
+    assert O.loss(out, chi, alpha, probe, y, prob)[0] < losses[-1]
