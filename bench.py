@@ -5,6 +5,7 @@ positions) of the workload, inputs resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5_full]
                     [--no-cpu-baseline] [--no-plain]
+    python bench.py --loop 200     # the full-batch descent loop from u = 0 (loss curve)
 """
 import argparse
 import hashlib
@@ -33,6 +34,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
+    p.add_argument("--loop", type=int, default=0,
+                   help="instead of the step benchmark: this many iterations of full-batch gradient "
+                        "descent on u with an Armijo line search from u = 0, and the oracle's iteration "
+                        "time on a one-eighth crop of the workload")
     p.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0 = auto)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="first run a plain elementwise copy (out = -in) of this many MiB, the "
@@ -153,6 +158,62 @@ def cpu_baseline(prob, f, y_dev, n_frames):
     return n_frames / dt, dt
 
 
+def run_loop(args, torch):
+    """Full-batch descent on u from u = 0 (chi and alpha at the truth) with an Armijo
+    line search; the loss curve and the time per iteration, beside the oracle's time per
+    iteration of the same loop on a one-eighth crop (c5_crop8 for c5_full)."""
+    import numpy as np
+    from paper_2312_14907_amd import optim
+    cfg, prob, f, plan, (u, chi, alpha, probe, y) = make_inputs(args.workload, torch)
+    if not args.no_autotune:
+        plan.mpbp_autotune(u, chi, alpha, probe, y)
+    u0 = torch.zeros_like(u)
+    t0 = time.perf_counter()
+    r = optim.line_search_descent(plan, probe, y, u0, chi, alpha, iterations=args.loop)
+    total = time.perf_counter() - t0
+    losses = r["losses"]
+    n = len(r["seconds"])
+    marks = sorted(set(list(range(0, len(losses), max(1, len(losses) // 20))) + [len(losses) - 1]))
+    out = {
+        "loop": "full-batch gradient descent on u with Armijo line search, u0 = 0",
+        "workload": args.workload,
+        "frames": prob.n_frames(),
+        "iterations": n,
+        "seconds_total": round(total, 3),
+        "ms_per_iteration": round(1e3 * float(np.mean(r["seconds"])), 3) if n else None,
+        "evaluations_per_iteration": round(float(np.mean(r["evaluations"])), 3) if n else None,
+        "loss_first": losses[0],
+        "loss_last": losses[-1],
+        "loss_curve": {str(i): losses[i] for i in marks},
+        "launch": plan.mpbp_tuning()["classes"],
+    }
+    if not args.no_cpu_baseline:
+        from oracle import mpbp_oracle as O
+        from synth import make_fields as mf, make_problem as mp
+        from synth.inputs import speckle_counts
+        crop = "c5_crop8" if args.workload == "c5_full" else args.workload
+        ccfg = get_config_named(crop)
+        cprob = mp(ccfg)
+        cf = mf(ccfg, cprob)
+        rng = np.random.default_rng(ccfg["seed"])
+        cy = np.concatenate([speckle_counts(rng, int(cprob.det[m]), int(cprob.scan_n[m].prod()), 1e5).ravel()
+                             for m in range(cprob.n_peaks)])
+        t1 = time.perf_counter()
+        _, cl, _ = O.line_search_descent(np.zeros_like(cf["u"]), cf["chi"], cf["alpha"], cf["probe"], cy, cprob,
+                                         iterations=1)
+        cdt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"kind": "oracle", "cores": 1, "workload": crop, "frames": cprob.n_frames(),
+                               "seconds_per_iteration": round(cdt, 2),
+                               "note": "one iteration of the same loop (one loss+gradient evaluation and the "
+                                       "line-search objective evaluations) on model-free speckle counts"}
+    print(json.dumps(out), flush=True)
+
+
+def get_config_named(name):
+    from synth import get_config
+    return get_config(name)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -161,6 +222,10 @@ def main():
         sys.exit(2)
     import torch
     from paper_2312_14907_amd.binding import MPBP_OPT_PATH, MPBP_OPT_PROFILE
+
+    if args.loop > 0:
+        run_loop(args, torch)
+        return
 
     cfg, prob, f, plan, args_t = make_inputs(args.workload, torch)
     calib = None

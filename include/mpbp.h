@@ -175,6 +175,38 @@ mpbp_status mpbp_step(mpbp_plan plan, float* u, float* chi, float* alpha,
                       const float* grad_u, const float* grad_chi, const float* grad_alpha,
                       const float* eta, void* stream);
 
+/* Adam settings of mpbp_adam_step. */
+typedef struct {
+  float lr[3];             /* step sizes for u, chi (or chi~) and alpha (or alpha~)       */
+  float beta1, beta2, eps; /* Adam moment decays and denominator offset                   */
+  int32_t log_params;      /* 1: optimise chi~ = log chi and alpha~ = log alpha, eq. (8) */
+  int32_t fixed_alpha;     /* peak whose alpha is held fixed (the reference peak), or -1 */
+} mpbp_adam;
+
+/* One Adam update (Kingma and Ba) of (u, chi, alpha) from the gradients of one
+   mpbp_loss_grad call, as in each iteration of Algorithm 1 (minibatch gradients, then
+   Adam); the phase-unwrap projection of that algorithm is not applied.
+     t         step number, 1 for the first update (bias corrections 1 - beta^t);
+               t = 0 initialises instead: zeroes state and, with log_params, writes
+               chi = exp(chi_log) and alpha = exp(alpha_log) (gradients not read, may
+               be NULL)
+     state     (dev) float [2 (4 nf + n_peaks)], zero before t = 1: first moments of u,
+               chi, alpha, then second moments; nf = nz ny nx (ny nx under MPBP_Z_TIED)
+   With log_params = 1 the optimised variables are chi_log and alpha_log (dev, layouts of
+   chi and alpha): the gradients (of f with respect to chi and alpha, at chi =
+   exp(chi_log), alpha = exp(alpha_log)) are taken to the log variables by the chain
+   rule, and chi and alpha are rewritten as exp of the updated log variables, ready for
+   the next mpbp_loss_grad.  With log_params = 0, chi and alpha are updated directly and
+   clamped at 0 (chi_log and alpha_log may be NULL).  u is always updated directly. */
+mpbp_status mpbp_adam_step(mpbp_plan plan, const mpbp_adam* cfg, int64_t t, float* u, float* chi,
+                           float* alpha, float* chi_log, float* alpha_log, float* state,
+                           const float* grad_u, const float* grad_chi, const float* grad_alpha,
+                           void* stream);
+
+/* *out (dev double) = sum over i < n of a[i]^2 for a (dev) float array (a deterministic
+   FP64 sum; used by line searches). */
+mpbp_status mpbp_norm2(mpbp_plan plan, const float* a, int64_t n, double* out, void* stream);
+
 /* Set / read a plan option (MPBP_OPT_*).  MPBP_ERR_INVALID for an unknown option or
    value. */
 mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value);

@@ -26,13 +26,18 @@ STAGES = ("object", "frames", "grad", "finalize", "plain")
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
             "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",
             "mpbp_get_option", "mpbp_stage_times", "mpbp_autotune", "mpbp_set_variant", "mpbp_tuning",
-            "mpbp_last_error")
+            "mpbp_adam_step", "mpbp_norm2", "mpbp_last_error")
 
 
 class mpbp_peak(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double * 3), ("shear", ctypes.c_double * 2), ("det", ctypes.c_int32),
                 ("scan_n", ctypes.c_int32 * 2), ("scan_step", ctypes.c_int32 * 2),
                 ("scan_origin", ctypes.c_int32 * 2)]
+
+
+class mpbp_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 3), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("log_params", ctypes.c_int32), ("fixed_alpha", ctypes.c_int32)]
 
 
 class mpbp_problem(ctypes.Structure):
@@ -80,6 +85,10 @@ def _load():
     lib.mpbp_set_variant.restype = st
     lib.mpbp_tuning.argtypes = [vp, ctypes.c_char_p, i64, ctypes.POINTER(i64)]
     lib.mpbp_tuning.restype = st
+    lib.mpbp_adam_step.argtypes = [vp, ctypes.POINTER(mpbp_adam), i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.mpbp_adam_step.restype = st
+    lib.mpbp_norm2.argtypes = [vp, vp, i64, vp, vp]
+    lib.mpbp_norm2.restype = st
     lib.mpbp_last_error.argtypes = []
     lib.mpbp_last_error.restype = ctypes.c_char_p
     return lib
@@ -196,6 +205,19 @@ class Plan:
         e = (ctypes.c_float * 3)(*[float(v) for v in eta])
         _check(lib.mpbp_step(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(grad_u),
                              _ptr(grad_chi), _ptr(grad_alpha), e, _stream(stream)))
+
+    def mpbp_adam_step(self, cfg, t, u, chi, alpha, chi_log, alpha_log, state, grad_u, grad_chi, grad_alpha,
+                       stream=None):
+        """cfg: dict with lr (3), beta1, beta2, eps, log_params, fixed_alpha."""
+        c = mpbp_adam((ctypes.c_float * 3)(*[float(v) for v in cfg["lr"]]), float(cfg.get("beta1", 0.9)),
+                      float(cfg.get("beta2", 0.999)), float(cfg.get("eps", 1e-8)), int(cfg.get("log_params", 1)),
+                      int(cfg.get("fixed_alpha", -1)))
+        _check(lib.mpbp_adam_step(self.handle, ctypes.byref(c), int(t), _ptr(u), _ptr(chi), _ptr(alpha),
+                                  _ptr(chi_log), _ptr(alpha_log), _ptr(state), _ptr(grad_u), _ptr(grad_chi),
+                                  _ptr(grad_alpha), _stream(stream)))
+
+    def mpbp_norm2(self, a, out, n=None, stream=None):
+        _check(lib.mpbp_norm2(self.handle, _ptr(a), int(a.numel() if n is None else n), _ptr(out), _stream(stream)))
 
     def mpbp_set_option(self, option, value):
         _check(lib.mpbp_set_option(self.handle, int(option), int(value)))

@@ -7,9 +7,12 @@
 //              cover a voxel tile, then the chain rule to df/du, df/dchi, df/dalpha
 //   k_finalize deterministic FP64 sums of the per-frame losses and alpha partials
 //   k_step     p <- p - eta g
+//   k_adam     one Adam update (Kingma and Ba), optionally of a log-parameter (eq. (8))
+//   k_norm2    deterministic FP64 sum of squares (two passes)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -302,6 +305,78 @@ __global__ __launch_bounds__(256) void k_step(float* __restrict__ p, const float
   if (i < n) p[i] = p[i] - eta * g[i];
 }
 
+// Adam on n parameters p with gradient g of f with respect to the model variable.
+// log_mode: p is the log of the model variable x = exp(p) (eq. (8)); the gradient is
+// taken to p by df/dp = x df/dx, and x is rewritten from the updated p.  Otherwise p is
+// the model variable and, with project, is clamped at 0 after the step.  c1 = 1 - b1^t,
+// c2 = 1 - b2^t (bias corrections).  Element `fixed` (or none if < 0) is left alone.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ x,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, long long n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2,
+                                              int log_mode, int project, long long fixed) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || i == fixed) return;
+  float gi = g[i];
+  if (log_mode) gi *= x[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  if (log_mode) {
+    x[i] = expf(pi);
+  } else if (project) {
+    pi = fmaxf(pi, 0.f);
+  }
+  p[i] = pi;
+}
+
+// x = exp(xlog) (eq. (8)), and a plain fill (graph-safe zeroing of optimiser state).
+__global__ __launch_bounds__(256) void k_exp(float* __restrict__ x, const float* __restrict__ xlog, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = expf(xlog[i]);
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Sum of squares: per-block FP64 partials in a fixed order, then one block adds them.
+__global__ __launch_bounds__(256) void k_norm2_part(const float* __restrict__ a, long long n,
+                                                    double* __restrict__ part) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + tid; i < n; i += (long long)gridDim.x * 256) {
+    const double q = (double)a[i];
+    s += q * q;
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_norm2_final(const double* __restrict__ part, int n_part,
+                                                     double* __restrict__ out) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < n_part; i += 256) s += part[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) *out = red[0];
+}
+
 __global__ __launch_bounds__(256) void k_fill_u8(unsigned char* p, long long n, unsigned char v) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -390,6 +465,34 @@ hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, 
 hipError_t launch_step(float* p, const float* g, long long n, float eta, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_step<<<dim3(nblk(n, 256)), dim3(256), 0, s>>>(p, g, n, eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, float* x, float* m, float* v, const float* g, long long n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, int log_mode, int project,
+                       long long fixed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_adam<<<dim3(nblk(n, 256)), dim3(256), 0, s>>>(p, x, m, v, g, n, lr, b1, b2, eps, c1, c2, log_mode, project,
+                                                  fixed);
+  return hipGetLastError();
+}
+
+hipError_t launch_exp(float* x, const float* xlog, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_exp<<<dim3(nblk(n, 256)), dim3(256), 0, s>>>(x, xlog, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_fill_f32<<<dim3(nblk(n, 256)), dim3(256), 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(const float* a, long long n, double* part, int max_part, double* out, hipStream_t s) {
+  const int nb = (int)std::min<long long>(std::max<long long>(nblk(n, 256), 1), max_part);
+  k_norm2_part<<<dim3(nb), dim3(256), 0, s>>>(a, n, part);
+  k_norm2_final<<<dim3(1), dim3(256), 0, s>>>(part, nb, out);
   return hipGetLastError();
 }
 

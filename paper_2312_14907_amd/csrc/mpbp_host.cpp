@@ -45,6 +45,7 @@ bool supported_det(int d) {
 constexpr int kMaxPeaks = 16;
 constexpr int kMaxLds = 160 * 1024;
 constexpr size_t kMaxGraphs = 8;   // captured full-batch calls kept per plan
+constexpr int kRedParts = 1024;    // block partials of mpbp_norm2
 
 // What a captured full-batch call depends on besides the plan: the call kind, the
 // caller's buffer addresses and the launch options.  A replay reads and writes the
@@ -115,6 +116,7 @@ struct mpbp_plan_t {
   float* d_slots = nullptr;
   double* d_floss = nullptr;
   double* d_apart = nullptr;
+  double* d_red = nullptr;         // sum-of-squares partials (kRedParts)
   float* d_tw = nullptr;           // twiddle tables of all peaks
   std::vector<float> tw;
   int* h_list = nullptr;           // pinned staging of the caller's list
@@ -173,6 +175,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_slots);
   (void)hipFree(p->d_floss);
   (void)hipFree(p->d_apart);
+  (void)hipFree(p->d_red);
   (void)hipFree(p->d_tw);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->h_list) (void)hipHostFree(p->h_list);
@@ -362,6 +365,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_slots, (size_t)p->slots_cplx * 2);
   ALLOC(p->d_floss, p->F);
   ALLOC(p->d_apart, (size_t)p->tiles_x * p->tiles_y * p->M);
+  ALLOC(p->d_red, kRedParts);
   ALLOC(p->d_tw, p->tw.size());
 #undef ALLOC
   e = hipHostMalloc((void**)&p->h_list, std::max<int64_t>(2 * p->F, 1) * sizeof(int), hipHostMallocDefault);
@@ -957,6 +961,65 @@ mpbp_status mpbp_step(mpbp_plan plan, float* u, float* chi, float* alpha, const 
   if (e == hipSuccess) e = mpbp::launch_step(chi, grad_chi, nf, eta[1], s);
   if (e == hipSuccess) e = mpbp::launch_step(alpha, grad_alpha, plan->M, eta[2], s);
   if (e != hipSuccess) return hip_fail(e, "step kernel");
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_adam_step(mpbp_plan plan, const mpbp_adam* cfg, int64_t t, float* u, float* chi,
+                           float* alpha, float* chi_log, float* alpha_log, float* state,
+                           const float* grad_u, const float* grad_chi, const float* grad_alpha,
+                           void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!cfg) return fail(MPBP_ERR_INVALID, "cfg is NULL");
+  if (!u || !chi || !alpha || !state) return fail(MPBP_ERR_INVALID, "u, chi, alpha and state are required");
+  if (t > 0 && (!grad_u || !grad_chi || !grad_alpha)) return fail(MPBP_ERR_INVALID, "the gradients are required");
+  if (cfg->log_params != 0 && cfg->log_params != 1) return fail(MPBP_ERR_INVALID, "log_params must be 0 or 1");
+  if (cfg->log_params && (!chi_log || !alpha_log))
+    return fail(MPBP_ERR_INVALID, "chi_log and alpha_log are required with log_params");
+  if (t < 0) return fail(MPBP_ERR_INVALID, "t must be >= 0 (got %lld)", (long long)t);
+  if (t == 0) {
+    const long long nf0 = plan->tied ? plan->tied : plan->nvox;
+    hipStream_t s0 = (hipStream_t)stream;
+    hipError_t e0 = mpbp::launch_fill(state, 2 * (4 * nf0 + plan->M), 0.f, s0);
+    if (e0 == hipSuccess && cfg->log_params) e0 = mpbp::launch_exp(chi, chi_log, nf0, s0);
+    if (e0 == hipSuccess && cfg->log_params) e0 = mpbp::launch_exp(alpha, alpha_log, plan->M, s0);
+    if (e0 != hipSuccess) return hip_fail(e0, "adam initialisation");
+    return MPBP_OK;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(cfg->lr[i]) || cfg->lr[i] < 0.f) return fail(MPBP_ERR_INVALID, "lr[%d] invalid", i);
+  if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) ||
+      !(cfg->eps > 0.f) || !std::isfinite(cfg->eps))
+    return fail(MPBP_ERR_INVALID, "beta1, beta2 must be in [0, 1) and eps > 0");
+  if (cfg->fixed_alpha < -1 || cfg->fixed_alpha >= plan->M)
+    return fail(MPBP_ERR_INVALID, "fixed_alpha %d out of range", cfg->fixed_alpha);
+  const long long nf = plan->tied ? plan->tied : plan->nvox;
+  const float c1 = (float)(1.0 - std::pow((double)cfg->beta1, (double)t));
+  const float c2 = (float)(1.0 - std::pow((double)cfg->beta2, (double)t));
+  if (!(c1 > 0.f) || !(c2 > 0.f)) return fail(MPBP_ERR_INVALID, "bias corrections vanish (beta = 0 and t too small?)");
+  // state: first moments of (u, chi, alpha), then second moments
+  float* m = state;
+  float* v = state + 4 * nf + plan->M;
+  hipStream_t s = (hipStream_t)stream;
+  const int lg = cfg->log_params;
+  hipError_t e = mpbp::launch_adam(u, nullptr, m, v, grad_u, 3 * nf, cfg->lr[0], cfg->beta1, cfg->beta2,
+                                   cfg->eps, c1, c2, 0, 0, -1, s);
+  if (e == hipSuccess)
+    e = mpbp::launch_adam(lg ? chi_log : chi, lg ? chi : nullptr, m + 3 * nf, v + 3 * nf, grad_chi, nf, cfg->lr[1],
+                          cfg->beta1, cfg->beta2, cfg->eps, c1, c2, lg, 1, -1, s);
+  if (e == hipSuccess)
+    e = mpbp::launch_adam(lg ? alpha_log : alpha, lg ? alpha : nullptr, m + 4 * nf, v + 4 * nf, grad_alpha, plan->M,
+                          cfg->lr[2], cfg->beta1, cfg->beta2, cfg->eps, c1, c2, lg, 1, cfg->fixed_alpha, s);
+  if (e != hipSuccess) return hip_fail(e, "adam kernel");
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_norm2(mpbp_plan plan, const float* a, int64_t n, double* out, void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!a || !out || n < 0) return fail(MPBP_ERR_INVALID, "a and out are required and n >= 0");
+  hipError_t e = mpbp::launch_norm2(a, n, plan->d_red, kRedParts, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "norm kernel");
   return MPBP_OK;
 }
 

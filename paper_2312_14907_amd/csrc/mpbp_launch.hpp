@@ -29,6 +29,13 @@ hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, 
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
                            float* grad_alpha, hipStream_t s);
 hipError_t launch_step(float* p, const float* g, long long n, float eta, hipStream_t s);
+hipError_t launch_adam(float* p, float* x, float* m, float* v, const float* g, long long n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, int log_mode, int project,
+                       long long fixed, hipStream_t s);
+hipError_t launch_exp(float* x, const float* xlog, long long n, hipStream_t s);
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t s);
+// out (dev double) = sum of a[i]^2, using part[max_part] as scratch.
+hipError_t launch_norm2(const float* a, long long n, double* part, int max_part, double* out, hipStream_t s);
 hipError_t launch_mark_active(unsigned char* act, long long n_frames, const int* list, int n,
                               hipStream_t s);
 

@@ -1,4 +1,4 @@
-"""The five synthetic strained-membrane workloads.
+"""The synthetic strained-membrane workloads (five, and a one-eighth crop of the fifth).
 
 Each workload is a plain dictionary.  Geometry readings (where the paper is silent):
 
@@ -135,12 +135,23 @@ def _c5():
     }
 
 
+def _c5_crop8():
+    # One eighth of c5_full in volume (32 x 256 x 128) and in frames (32 x 16 raster per
+    # peak), same peaks, probe, detector and raster step: the CPU-timing stand-in of the
+    # full loop.
+    cfg = _c5()
+    cfg.update({"name": "c5_crop8", "index": 6, "ny": 256, "nx": 128})
+    cfg["peaks"] = [_peak(k, 256, (32, 16), (8, 8), 1e5) for k in range(3)]
+    return cfg
+
+
 _BUILDERS = {
     "c1_tiny": _c1,
     "c2_forward": _c2,
     "c3_grad": _c3,
     "c4_batch": _c4,
     "c5_full": _c5,
+    "c5_crop8": _c5_crop8,
 }
 CONFIG_NAMES = tuple(_BUILDERS)
 

@@ -234,3 +234,10 @@ def crop_problem(problem, peak_rows):
         out.scan_n[m, 0] = r1 - r0
         out.scan_origin[m, 0] = problem.scan_origin[m, 0] + r0 * problem.scan_step[m, 0]
     return out
+
+
+def frame_order(n_frames, seed, epochs):
+    """The shuffled frame order of a minibatch reconstruction: one random permutation
+    of all frames per epoch (the shuffle of Algorithm 1), concatenated, int32."""
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.permutation(n_frames) for _ in range(epochs)]).astype(np.int32)

@@ -18,7 +18,7 @@ from oracle import mpbp_oracle as O  # noqa: E402
 
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "mpbp.h")).read()
-    declared = set(re.findall(r"\b(mpbp_[a-z_]+)\s*\(", header))
+    declared = set(re.findall(r"\b(mpbp_[a-z0-9_]+)\s*\(", header))
     assert declared == set(B.EXPORTED)
     lib = ctypes.CDLL(B.LIB_PATH)
     for name in sorted(declared):
