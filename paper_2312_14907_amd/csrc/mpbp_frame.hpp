@@ -176,7 +176,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         for (int g = 0; g < G; ++g) {
           const unsigned a = min((unsigned)(pby[h] - ssy[g]), (unsigned)np);
           const unsigned b = min((unsigned)(pbx[h] - ssx[g]), (unsigned)np);
-          w[g] = Wb[g * sw + (int)(a * np1 + b)];
+          w[g] = Wb[g * sw + (int)(__umul24(a, (unsigned)np1) + b)];
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[h] = cadd(acc[h], w[g]);
@@ -305,24 +305,28 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
 #pragma unroll
           for (int b = 0; b < RQ; ++b) v[b] = {re[b], ex[b * (RP + 1) + t]};
           DFT<RQ, false>::run(v);
-          float rowl = 0.f;
+          if (mif) {
 #pragma unroll
-          for (int d = 0; d < RQ; ++d) {
-            // X = D Psi.  r = |Psi| - sqrt(y); gradient r X / |X| (0 where |X|^2 is
-            // below the smallest normal float, i.e. Psi = 0 in this precision).
-            const cplx X = v[d];
-            const float s2 = X.x * X.x + X.y * X.y;
-            if (mif) mif[(long long)k * D + t + RP * d] = s2 * invD2;
-            if (has_y) {
-              const bool nzr = s2 >= 1.17549435e-38f;
-              const float rinv = __builtin_amdgcn_rsqf(nzr ? s2 : 1.0f);
-              const float A = nzr ? s2 * rinv * invD : 0.f;
-              const float res = A - __builtin_amdgcn_sqrtf(yv[d]);
-              rowl = fmaf(0.5f * res, res, rowl);
-              v[d] = cscale(X, nzr ? res * rinv : 0.f);
-            }
+            for (int d = 0; d < RQ; ++d)
+              mif[(long long)k * D + t + RP * d] = fmaf(v[d].x, v[d].x, v[d].y * v[d].y) * invD2;
           }
-          lsum += (double)rowl;
+          if (has_y) {
+            float rowl = 0.f;
+#pragma unroll
+            for (int d = 0; d < RQ; ++d) {
+              // X = D Psi.  r = |Psi| - sqrt(y); gradient r X / |X|.  The reciprocal
+              // square root is taken of |X|^2 + FLT_MIN: finite where X = 0 (there the
+              // modulus and the gradient come out exactly 0), absorbed for |X|^2 above
+              // about 1e-31.
+              const cplx X = v[d];
+              const float s2 = fmaf(X.x, X.x, X.y * X.y);
+              const float rinv = __builtin_amdgcn_rsqf(s2 + 1.17549435e-38f);
+              const float res = fmaf(s2 * rinv, invD, -__builtin_amdgcn_sqrtf(yv[d]));
+              rowl = fmaf(res, res, rowl);
+              v[d] = cscale(X, res * rinv);
+            }
+            lsum += 0.5 * (double)rowl;
+          }
         }
         if (A.grad) {
           wave_sync();
