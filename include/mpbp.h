@@ -100,9 +100,12 @@ enum {
   MPBP_OPT_XCD_ORDER = 3,    /* 1 = hand each XCD a contiguous band of frames (default) */
   MPBP_OPT_PROFILE = 4,      /* 1 = record HIP events around every kernel stage on the
                                 call's stream (read with mpbp_stage_times); default 0    */
-  MPBP_OPT_GRAD_BATCH = 5    /* frames whose footprint gradients the back-projection
+  MPBP_OPT_GRAD_BATCH = 5,   /* frames whose footprint gradients the back-projection
                                 kernel reads per step of its frame walk: 1, 2 (default)
                                 or 4; set by mpbp_autotune                               */
+  MPBP_OPT_GRAD_TILE = 6     /* back-projection tile: 16 (16 x 4 voxels, default) or 8
+                                (8 x 8 voxels on a grid aligned with the first peak's
+                                raster); set by mpbp_autotune                            */
 };
 
 /* Kernel stages timed under MPBP_OPT_PROFILE. */
@@ -223,7 +226,7 @@ mpbp_status mpbp_stage_times(mpbp_plan plan, double* ms, int64_t* counts);
 /* Autotuner.  Times every compiled launch variant of the per-frame kernel for each
    detector-size class of the plan (footprint bound, projection slab depth = object
    slices staged per step, XCD-aware frame order) and of the back-projection kernel
-   (frames read per step), on the caller's inputs (layouts as in mpbp_loss_grad; y is
+   (frames read per step, tile shape), on the caller's inputs (layouts as in mpbp_loss_grad; y is
    required), and keeps the fastest for later calls.  Every variant computes the same
    result.  Synchronous: waits for `stream`.  Allocates and frees a gradient scratch
    of 16 * nz * ny * nx bytes.  If the environment variable MPBP_TUNE_CACHE names a
@@ -242,7 +245,7 @@ mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound
                              int xcd_order);
 
 /* The plan's launch parameters as a JSON object: source ("default", "cache",
-   "autotune" or "manual"), grad_batch, per size class {D, key, frames, fy, fx, FB, G,
+   "autotune" or "manual"), grad_batch, grad_tile, per size class {D, key, frames, fy, fx, FB, G,
    xcd, us} and the candidates the last mpbp_autotune timed.  Writes at most `cap`
    bytes (NUL-terminated) to buf (may be NULL) and the size needed, NUL included, to
    *len (may be NULL); MPBP_ERR_INVALID if cap is too small for the text. */

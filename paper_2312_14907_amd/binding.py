@@ -20,6 +20,7 @@ MPBP_OPT_GRAPH = 2
 MPBP_OPT_XCD_ORDER = 3
 MPBP_OPT_PROFILE = 4
 MPBP_OPT_GRAD_BATCH = 5
+MPBP_OPT_GRAD_TILE = 6
 MPBP_Z_TIED = 1
 STAGES = ("object", "frames", "grad", "finalize", "plain")
 

@@ -19,6 +19,7 @@ ARCH = os.environ.get("MPBP_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-fno-signed-zeros",
     "-Wno-unused-command-line-argument",
 ]
 

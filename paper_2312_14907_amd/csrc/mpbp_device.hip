@@ -64,13 +64,15 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
   return s;
 }
 
-// B: frames whose footprint gradients are read per step of the frame walk.
-template <int B>
+// B: frames whose footprint gradients are read per step of the frame walk.  TX: tile
+// width (TX x TY voxels per slice, TX * TY = 64: one wavefront per slice).  The tile
+// grid starts at (tile_oy, tile_ox) <= 0, so that a grid aligned with a raster of step
+// TX x TY gives every voxel of a tile the same covering frames.
+template <int B, int TX>
 __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
+  constexpr int TY = kGradTile / TX;
   extern __shared__ cplx smem[];
   const int np = A.np, nz = A.nz;
-  const int RW = kGradTX + A.maxspan_x;
-  const int RS = (kGradTY + A.maxspan_y) * RW;       // one staged region (complex)
   cplx* Ps = smem;                                   // np * np
   int2* sh = reinterpret_cast<int2*>(Ps + np * np);  // nz
   double* apl = reinterpret_cast<double*>(sh + nz);  // alpha partials
@@ -81,23 +83,19 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   float tgu[3] = {0.f, 0.f, 0.f}, tgc = 0.f;
 
   const int tid = threadIdx.x;
-  const int tx = tid % kGradTX, ty = (tid / kGradTX) % kGradTY, tz = tid / (kGradTX * kGradTY);
+  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / kGradTile;
   // Tiles are handed out so that each XCD (blocks are dispatched round-robin over the
   // 8 XCDs) walks a contiguous band of tile rows: neighbouring tiles read the same
   // frames' footprints, which then stay in that XCD's L2.
   const int tile = frame_block_index(blockIdx.x, gridDim.x, 1);
   if (tile >= A.tiles_x * A.tiles_y) return;
   const int bx = tile % A.tiles_x, by = tile / A.tiles_x;
-  const int x0 = bx * kGradTX, y0 = by * kGradTY;
+  const int x0 = A.tile_ox + bx * TX, y0 = A.tile_oy + by * TY;
   const int x = x0 + tx, y = y0 + ty;
-  const bool inb = x < A.nx && y < A.ny;
+  const bool inb = (unsigned)x < (unsigned)A.nx && (unsigned)y < (unsigned)A.ny;
   const long long nvox = (long long)nz * A.ny * A.nx;
   const unsigned lat = (unsigned)(y * A.nx + x);                 // lateral pixel
   const unsigned fstride = A.tied ? (unsigned)(A.ny * A.nx) : (unsigned)nvox;   // field component stride
-  // this thread's element positions in a staged region (row-major with stride RW)
-  const int e0r = tid / RW, e0c = tid - e0r * RW;
-  const int e1 = tid + kGradThreads;
-  const int e1r = e1 / RW, e1c = e1 - e1r * RW;
   if (tid < kMaxPeaksDev) apl[tid] = 0.0;
 
   for (int zb = 0; zb < nz; zb += kGradZB) {
@@ -109,9 +107,9 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       const PeakDev pk = A.peaks[m];
       // Frames of this peak whose windows meet the tile: a rectangle of the raster.
       const int iy_lo = max(0, -floordiv(-(y0 - np + 1 - pk.oy), pk.sy));
-      const int iy_hi = min(pk.rows - 1, floordiv(y0 + kGradTY - 1 - pk.oy, pk.sy));
+      const int iy_hi = min(pk.rows - 1, floordiv(y0 + TY - 1 - pk.oy, pk.sy));
       const int ix_lo = max(0, -floordiv(-(x0 - np + 1 - pk.ox), pk.sx));
-      const int ix_hi = min(pk.cols - 1, floordiv(x0 + kGradTX - 1 - pk.ox, pk.sx));
+      const int ix_hi = min(pk.cols - 1, floordiv(x0 + TX - 1 - pk.ox, pk.sx));
       const int ncx = ix_hi - ix_lo + 1;
       const int ncand = (iy_hi >= iy_lo && ncx > 0) ? (iy_hi - iy_lo + 1) * ncx : 0;
       __syncthreads();
@@ -239,7 +237,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   __syncthreads();
   if (A.tied) {
     // z-sums: add the kGradTZ slice groups of each lateral pixel in a fixed order
-    const int xy = tid % (kGradTX * kGradTY);
+    const int xy = tid % kGradTile;
     zred[0 * kGradThreads + tid] = tgu[0];
     zred[1 * kGradThreads + tid] = tgu[1];
     zred[2 * kGradThreads + tid] = tgu[2];
@@ -249,7 +247,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       float s[4] = {0.f, 0.f, 0.f, 0.f};
       for (int g = 0; g < kGradTZ; ++g)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) s[c] += zred[c * kGradThreads + g * kGradTX * kGradTY + xy];
+        for (int c = 0; c < 4; ++c) s[c] += zred[c * kGradThreads + g * kGradTile + xy];
       A.grad_u[lat] = s[0];
       A.grad_u[fstride + lat] = s[1];
       A.grad_u[2u * fstride + lat] = s[2];
@@ -431,28 +429,33 @@ bool frame_instance(int D, int FB, int G) { return frames_op(2, D, FB, G, nullpt
 
 static const int kDets[] = {32, 64, 96, 128, 192, 256};
 
+#define MPBP_GRAD_INSTANCES(X) X(1, 16) X(2, 16) X(4, 16) X(1, 8) X(2, 8) X(4, 8)
+
 hipError_t prepare_kernels() {
   hipError_t e = hipSuccess;
   for (int D : kDets)
     for (int FB : {32, 48, 64, D})
       for (int G : kSlabDepths)
         if (e == hipSuccess && frame_instance(D, FB, G)) e = frames_op(1, D, FB, G, nullptr, 0, nullptr);
-  for (int B : kGradBatches)
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(B == 1 ? (const void*)k_grad<1> : B == 2 ? (const void*)k_grad<2> : (const void*)k_grad<4>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+#define MPBP_CASE(b, tx)                                                                        \
+  if (e == hipSuccess)                                                                          \
+    e = hipFuncSetAttribute((const void*)k_grad<b, tx>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            160 * 1024);
+  MPBP_GRAD_INSTANCES(MPBP_CASE)
+#undef MPBP_CASE
   return e;
 }
 
-hipError_t launch_grad(int batch, const GradArgs& a, int lds_bytes, hipStream_t s) {
+hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, hipStream_t s) {
   const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
-  switch (batch) {
-    case 1: k_grad<1><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a); break;
-    case 2: k_grad<2><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a); break;
-    case 4: k_grad<4><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a); break;
-    default: return hipErrorInvalidValue;
+#define MPBP_CASE(b, tx)                                                       \
+  if (batch == b && tile_x == tx) {                                            \
+    k_grad<b, tx><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);        \
+    return hipGetLastError();                                                  \
   }
-  return hipGetLastError();
+  MPBP_GRAD_INSTANCES(MPBP_CASE)
+#undef MPBP_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,

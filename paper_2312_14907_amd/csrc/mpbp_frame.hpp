@@ -13,6 +13,9 @@
 
 namespace mpbp {
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const cplx lds_cplx;   // LDS-addressed complex
+
 // ------------------------------------------------------------------- frame kernel ---
 template <int D> struct ColLen { static constexpr int L = 64; };
 template <> struct ColLen<32> { static constexpr int L = 32; };
@@ -137,23 +140,43 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
 #pragma unroll
       for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
     }
-    int pby[kProjPix], pbx[kProjPix];
+    // Footprint pixel q = (qy, qx) of slice z reads staged element (qy + min s_y -
+    // s_y(z), qx + min s_x - s_x(z)), each coordinate clamped to np (the zero border).
+    // Both coordinates travel as one pair of 16-bit lanes: one packed subtract, one
+    // packed clamp and one dot product (row * (np + 1) * 8 + column * 8 + slice base)
+    // give the byte offset of the element.
+    u16x2 pq[kProjPix];
     cplx acc[kProjPix];
 #pragma unroll
     for (int h = 0; h < kProjPix; ++h) {
       const int p = tid + NT * h;
       const int qy = p / fx;
-      pby[h] = qy + pk.miny;
-      pbx[h] = p - qy * fx + pk.minx;
+      pq[h] = u16x2{(unsigned short)(p - qy * fx + pk.minx), (unsigned short)(qy + pk.miny)};
       acc[h] = {0.f, 0.f};
     }
+    const u16x2 lim = {(unsigned short)np, (unsigned short)np};
+    const u16x2 wts = {(unsigned short)sizeof(cplx), (unsigned short)(np1 * sizeof(cplx))};
+    // LDS byte address of the staging area (the dot product adds it for free)
+    const unsigned wb_lds = (unsigned)(size_t)(const lds_cplx*)Wb;
     for (int z0 = 0; z0 < nz; z0 += G) {
       __syncthreads();
+      if (z0 + G <= nz) {   // uniform: every slice of the group exists
 #pragma unroll
-      for (int g = 0; g < G; ++g)
+        for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int i = 0; i < kProjE; ++i)
-          if (wo[i] >= 0) Wb[g * sw + wo[i]] = (z0 + g < nz) ? cmul(pv[i], on[g][i]) : cplx{0.f, 0.f};
+          for (int i = 0; i < kProjE; ++i) {
+            if ((i + 1) * NT <= np2)   // uniform: every lane holds a probe pixel
+              Wb[g * sw + wo[i]] = cmul(pv[i], on[g][i]);
+            else if (wo[i] >= 0)
+              Wb[g * sw + wo[i]] = cmul(pv[i], on[g][i]);
+          }
+      } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int i = 0; i < kProjE; ++i)
+            if (wo[i] >= 0) Wb[g * sw + wo[i]] = (z0 + g < nz) ? cmul(pv[i], on[g][i]) : cplx{0.f, 0.f};
+      }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int z = z0 + G + g;
@@ -161,12 +184,11 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
 #pragma unroll
         for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
       }
-      int ssy[G], ssx[G];
+      u16x2 ssh[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int z = z0 + g < nz ? z0 + g : 0;
-        ssy[g] = shz[2 * z];
-        ssx[g] = shz[2 * z + 1];
+        ssh[g] = u16x2{(unsigned short)shz[2 * z + 1], (unsigned short)shz[2 * z]};
       }
       __syncthreads();
 #pragma unroll
@@ -174,9 +196,10 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         cplx w[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          const unsigned a = min((unsigned)(pby[h] - ssy[g]), (unsigned)np);
-          const unsigned b = min((unsigned)(pbx[h] - ssx[g]), (unsigned)np);
-          w[g] = Wb[g * sw + (int)(__umul24(a, (unsigned)np1) + b)];
+          const u16x2 d = __builtin_elementwise_min(pq[h] - ssh[g], lim);
+          const unsigned a = __builtin_amdgcn_udot2(d, wts, wb_lds + (unsigned)(g * sw * sizeof(cplx)), false);
+          const lds_cplx* q = (const lds_cplx*)(size_t)a;
+          w[g] = cplx{q->x, q->y};
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[h] = cadd(acc[h], w[g]);

@@ -92,13 +92,17 @@ struct mpbp_plan_t {
   std::vector<SizeClass> classes;      // full batch: frames of one detector size, in `order`
   std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch
   int grad_batch = mpbp::kDefaultGradBatch;
+  int grad_tile = mpbp::kDefaultGradTileX;
   double grad_tuned_us = 0.0;
   std::string tune_source = "default";
   std::string tune_report;             // candidates timed by the last mpbp_autotune
   int lds_fwd = 0, lds_grad_frame = 0, lds_grad = 0;
   int maxspan_y = 0, maxspan_x = 0;
   int max_cand = 0;
-  int tiles_x = 0, tiles_y = 0;
+  // gradient tile grids, per compiled tile width: origin (<= 0) and tile counts
+  struct GradTiling { int tx, ox, oy, nx, ny; };
+  std::vector<GradTiling> tilings;
+  int max_tiles = 0;
   long long slots_cplx = 0;
   // options
   int path = 0, graph = 1, xcd = 1;
@@ -289,19 +293,32 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   }
   p->ylen = p->y_off[p->M];
   p->slots_cplx = slot;
-  if ((mpbp::kGradTY + p->maxspan_y) * (mpbp::kGradTX + p->maxspan_x) > 2 * mpbp::kGradThreads)
-    return fail(MPBP_ERR_UNSUPPORTED, "shear spans %d x %d exceed the gradient kernel's staging tile",
-                p->maxspan_y, p->maxspan_x);
   p->max_cand = 0;
-  for (const auto& d : p->pdev) {
-    const int cy = std::min(d.rows, (mpbp::kGradTY + np - 2) / d.sy + 2);
-    const int cx = std::min(d.cols, (mpbp::kGradTX + np - 2) / d.sx + 2);
-    p->max_cand = std::max(p->max_cand, cy * cx);
+  p->tilings.clear();
+  p->max_tiles = 0;
+  for (int tx : mpbp::kGradTileXs) {
+    const int ty = mpbp::kGradTile / tx;
+    for (const auto& d : p->pdev) {
+      const int cy = std::min(d.rows, (ty + np - 2) / d.sy + 2);
+      const int cx = std::min(d.cols, (tx + np - 2) / d.sx + 2);
+      p->max_cand = std::max(p->max_cand, cy * cx);
+    }
+    // The 8 x 8 grid is aligned with the first peak's raster (tile edges on its frame
+    // edges), so that with an 8-voxel step every voxel of a tile has the same frames;
+    // the 16 x 4 grid starts at the object's corner.
+    mpbp_plan_t::GradTiling t{tx, 0, 0, 0, 0};
+    if (tx == 8) {
+      const int rx = ((p->pdev[0].ox % tx) + tx) % tx, ry = ((p->pdev[0].oy % ty) + ty) % ty;
+      t.ox = rx ? rx - tx : 0;
+      t.oy = ry ? ry - ty : 0;
+    }
+    t.nx = (p->nx - t.ox + tx - 1) / tx;
+    t.ny = (p->ny - t.oy + ty - 1) / ty;
+    p->tilings.push_back(t);
+    p->max_tiles = std::max(p->max_tiles, t.nx * t.ny);
   }
   p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0);
   if (p->lds_grad > kMaxLds) return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", p->lds_grad);
-  p->tiles_x = (p->nx + mpbp::kGradTX - 1) / mpbp::kGradTX;
-  p->tiles_y = (p->ny + mpbp::kGradTY - 1) / mpbp::kGradTY;
   // Full-batch processing order: larger windows first (they cost most), each peak's
   // frames in raster order.
   std::vector<int> pk(p->M);
@@ -364,7 +381,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_obj, (size_t)p->M * p->nvox * 2);
   ALLOC(p->d_slots, (size_t)p->slots_cplx * 2);
   ALLOC(p->d_floss, p->F);
-  ALLOC(p->d_apart, (size_t)p->tiles_x * p->tiles_y * p->M);
+  ALLOC(p->d_apart, (size_t)p->max_tiles * p->M);
   ALLOC(p->d_red, kRedParts);
   ALLOC(p->d_tw, p->tw.size());
 #undef ALLOC
@@ -528,6 +545,12 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   return a;
 }
 
+const mpbp_plan_t::GradTiling& grad_tiling(mpbp_plan p) {
+  for (const auto& t : p->tilings)
+    if (t.tx == p->grad_tile) return t;
+  return p->tilings.front();
+}
+
 mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const float* alpha,
                          const float* probe, bool subset, float* grad_u, float* grad_chi) {
   mpbp::GradArgs g{};
@@ -539,7 +562,9 @@ mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const fl
   g.peaks = p->d_peaks;
   g.n_peaks = p->M;
   g.nz = p->nz; g.ny = p->ny; g.nx = p->nx; g.np = p->np;
-  g.tiles_x = p->tiles_x; g.tiles_y = p->tiles_y;
+  const auto& tl = grad_tiling(p);
+  g.tiles_x = tl.nx; g.tiles_y = tl.ny;
+  g.tile_ox = tl.ox; g.tile_oy = tl.oy;
   g.maxspan_y = p->maxspan_y; g.maxspan_x = p->maxspan_x;
   g.max_cand = p->max_cand;
   g.tied = p->tied != 0;
@@ -590,7 +615,7 @@ hipError_t enqueue_loss_grad(mpbp_plan p, const float* u, const float* chi, cons
   const mpbp::GradArgs g = grad_args(p, u, chi, alpha, probe, subset, grad_u, grad_chi);
   {
     StageTimer t(p, MPBP_STAGE_GRAD, s);
-    e = mpbp::launch_grad(p->grad_batch, g, p->lds_grad, s);
+    e = mpbp::launch_grad(p->grad_batch, p->grad_tile, g, p->lds_grad, s);
   }
   if (e != hipSuccess) return *what = "gradient kernel", e;
   return hipSuccess;
@@ -742,10 +767,12 @@ void load_tuning(mpbp_plan_t* p) {
   }
   const std::string gk = grad_key(p, arch);
   for (const auto& e : entries) {
-    int b = 0;
+    int b = 0, tx = 0;
     double us = 0.0;
-    if (e.first == gk && std::sscanf(e.second.c_str(), "batch=%d us=%lf", &b, &us) == 2 && (b == 1 || b == 2 || b == 4)) {
+    if (e.first == gk && std::sscanf(e.second.c_str(), "batch=%d tile=%d us=%lf", &b, &tx, &us) == 3 &&
+        (b == 1 || b == 2 || b == 4) && (tx == 16 || tx == 8)) {
       p->grad_batch = b;
+      p->grad_tile = tx;
       p->grad_tuned_us = us;
       used = true;
     }
@@ -772,7 +799,7 @@ void save_tuning(const mpbp_plan_t* p) {
     snprintf(buf, sizeof(buf), "FB=%d G=%d xcd=%d us=%.2f", c.FB, c.G, c.xcd, c.tuned_us);
     put(frames_key(p, c, arch), buf);
   }
-  snprintf(buf, sizeof(buf), "batch=%d us=%.2f", p->grad_batch, p->grad_tuned_us);
+  snprintf(buf, sizeof(buf), "batch=%d tile=%d us=%.2f", p->grad_batch, p->grad_tile, p->grad_tuned_us);
   put(grad_key(p, arch), buf);
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
@@ -907,7 +934,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
   const int* list = frames ? plan->d_list : plan->d_order;
   const int* out_list = frames ? plan->d_list : nullptr;
   hipError_t e;
-  int n_part = plan->tiles_x * plan->tiles_y;
+  int n_part = grad_tiling(plan).nx * grad_tiling(plan).ny;
   const double* apart = plan->d_apart;
   if (plan->path == 1) {
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
@@ -1060,6 +1087,15 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
         clear_graphs(plan);
       }
       return MPBP_OK;
+    case MPBP_OPT_GRAD_TILE:
+      if (value != 16 && value != 8) return fail(MPBP_ERR_INVALID, "grad tile must be 16 or 8");
+      plan->grad_tile = (int)value;
+      plan->tune_source = "manual";
+      if (plan->device >= 0) {
+        (void)hipSetDevice(plan->device);
+        clear_graphs(plan);
+      }
+      return MPBP_OK;
     default:
       return fail(MPBP_ERR_INVALID, "unknown option %d", option);
   }
@@ -1073,6 +1109,7 @@ mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value) {
     case MPBP_OPT_XCD_ORDER: *value = plan->xcd; return MPBP_OK;
     case MPBP_OPT_PROFILE: *value = plan->profile; return MPBP_OK;
     case MPBP_OPT_GRAD_BATCH: *value = plan->grad_batch; return MPBP_OK;
+    case MPBP_OPT_GRAD_TILE: *value = plan->grad_tile; return MPBP_OK;
     default: return fail(MPBP_ERR_INVALID, "unknown option %d", option);
   }
 }
@@ -1164,21 +1201,27 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
   }
   if (e == hipSuccess) {
     // the gradient kernel, on the footprint gradients the frame launches left in the slots
-    const mpbp::GradArgs g = grad_args(plan, u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * nf);
     double best = 1e300;
-    int bb = plan->grad_batch;
-    for (int B : mpbp::kGradBatches) {
-      if (e != hipSuccess) break;
-      double us = 0.0;
-      e = time_us([&]() { return mpbp::launch_grad(B, g, plan->lds_grad, s); }, 3, &us);
-      snprintf(buf, sizeof(buf), "%s{\"grad_batch\": %d, \"us\": %.2f}", rep.size() > 1 ? ", " : "", B, us);
-      rep += buf;
-      if (e == hipSuccess && us < best) {
-        best = us;
-        bb = B;
+    int bb = plan->grad_batch, bt = plan->grad_tile;
+    for (int TX : mpbp::kGradTileXs) {
+      plan->grad_tile = TX;
+      const mpbp::GradArgs g = grad_args(plan, u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * nf);
+      for (int B : mpbp::kGradBatches) {
+        if (e != hipSuccess) break;
+        double us = 0.0;
+        e = time_us([&]() { return mpbp::launch_grad(B, TX, g, plan->lds_grad, s); }, 3, &us);
+        snprintf(buf, sizeof(buf), "%s{\"grad_batch\": %d, \"grad_tile\": %d, \"us\": %.2f}",
+                 rep.size() > 1 ? ", " : "", B, TX, us);
+        rep += buf;
+        if (e == hipSuccess && us < best) {
+          best = us;
+          bb = B;
+          bt = TX;
+        }
       }
     }
     plan->grad_batch = bb;
+    plan->grad_tile = bt;
     plan->grad_tuned_us = best;
   }
   cleanup();
@@ -1214,7 +1257,8 @@ mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound
 mpbp_status mpbp_tuning(mpbp_plan plan, char* buf, int64_t cap, int64_t* len) {
   if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
   std::string out = "{\"source\": \"" + plan->tune_source + "\", \"grad_batch\": " +
-                    std::to_string(plan->grad_batch) + ", \"classes\": [";
+                    std::to_string(plan->grad_batch) + ", \"grad_tile\": " + std::to_string(plan->grad_tile) +
+                    ", \"classes\": [";
   char tmp[256];
   for (size_t i = 0; i < plan->classes.size(); ++i) {
     const auto& c = plan->classes[i];

@@ -58,6 +58,7 @@ struct GradArgs {
   int n_peaks;
   int nz, ny, nx, np;
   int tiles_x, tiles_y;
+  int tile_ox, tile_oy;      // origin of the tile grid (<= 0)
   int maxspan_y, maxspan_x;  // largest shear span over peaks
   int max_cand;              // largest number of frames of one peak meeting one tile
   int tied;                  // 1: u, chi and their gradients per lateral pixel (z-sums)
@@ -71,8 +72,10 @@ constexpr int kSlabDepths[] = {2, 4};   // compiled projection slab depths (slic
 constexpr int kDefaultSlab = 4;
 constexpr int kProjE = 4;     // probe pixels staged per lane (probe_n^2 <= 4 * 256)
 constexpr int kProjPix = 8;   // footprint pixels per lane (fy * fx <= 8 * 256)
-constexpr int kGradTX = 16, kGradTY = 4, kGradTZ = 8;  // 512 threads
-constexpr int kGradThreads = kGradTX * kGradTY * kGradTZ;
+constexpr int kGradTile = 64, kGradTZ = 8;              // 64 voxels of a slice x 8 slice groups
+constexpr int kGradThreads = kGradTile * kGradTZ;        // 512 threads
+constexpr int kGradTileXs[] = {16, 8};                   // compiled tile widths (16 x 4, 8 x 8)
+constexpr int kDefaultGradTileX = 16;
 constexpr int kGradZB = 32;                             // z per pass of the grad kernel
 constexpr int kGradZPer = kGradZB / kGradTZ;            // z per thread per pass
 constexpr int kGradBatches[] = {1, 2, 4};               // compiled frame-walk batch sizes

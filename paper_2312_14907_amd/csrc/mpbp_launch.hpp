@@ -23,8 +23,9 @@ hipError_t launch_object(const float* u, const float* chi, const float* alpha, c
 // slices staged per projection step.
 hipError_t launch_frames(int D, int FB, int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
 int frame_bound(int D, int footprint);
-// Gradient kernel reading `batch` frames per step of its frame walk (1, 2 or 4).
-hipError_t launch_grad(int batch, const GradArgs& a, int lds_bytes, hipStream_t s);
+// Gradient kernel reading `batch` frames per step of its frame walk (1, 2 or 4), over
+// tiles `tile_x` voxels wide (16: 16 x 4, 8: 8 x 8).
+hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, hipStream_t s);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
                            float* grad_alpha, hipStream_t s);

@@ -151,6 +151,12 @@ def test_launch_parameter_api_on_host_plan():
         assert plan.mpbp_get_option(B.MPBP_OPT_GRAD_BATCH) == v
     with pytest.raises(B.MPBPError):
         plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, 3)
+    assert plan.mpbp_tuning()["grad_tile"] == 16
+    for v in (8, 16):
+        plan.mpbp_set_option(B.MPBP_OPT_GRAD_TILE, v)
+        assert plan.mpbp_get_option(B.MPBP_OPT_GRAD_TILE) == v
+    with pytest.raises(B.MPBPError):
+        plan.mpbp_set_option(B.MPBP_OPT_GRAD_TILE, 4)
     with pytest.raises(B.MPBPError) as e:     # autotuning needs a device plan
         z = np.zeros(1, np.float32)
         plan.mpbp_autotune(z, z, z, z, z, stream=0)
