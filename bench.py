@@ -46,12 +46,13 @@ def parse():
 
 
 def frame_kernel_work(prob, tab_shear):
-    """Algorithmic HBM bytes and nominal FLOPs of the per-frame kernel for all frames.
+    """Algorithmic HBM bytes and nominal FLOPs of the per-frame transform kernel
+    (k_frames) for all frames.
 
     Bytes per frame: the measured intensities, 4 D^2 (read once).  FLOPs per frame
     (5 N log2 N per complex N-point transform): forward and adjoint transforms of the
-    F_x footprint columns and of all D rows, 12 per detector pixel for the modulus
-    residual, 8 per complex multiply-add of the sheared projection (Np^2 Nz).
+    F_x footprint columns and of all D rows, and 12 per detector pixel for the modulus
+    residual.  (The sheared projection, 8 Np^2 Nz per frame, runs in k_project.)
     """
     import math
     import numpy as np
@@ -62,7 +63,7 @@ def frame_kernel_work(prob, tab_shear):
         span_x = int(tab_shear[m, :, 1].max() - tab_shear[m, :, 1].min())
         fx = prob.probe_n + span_x
         fft = 5.0 * d * math.log2(d)
-        per = 2 * fx * fft + 2 * d * fft + 12.0 * d * d + 8.0 * prob.probe_n ** 2 * prob.nz
+        per = 2 * fx * fft + 2 * d * fft + 12.0 * d * d
         nbytes += nfr * 4.0 * d * d
         flops += nfr * per
     return nbytes, flops
@@ -150,11 +151,13 @@ def cpu_baseline(prob, f, y_dev, n_frames):
         def __getitem__(self, sl):
             return self.t[sl].cpu().numpy()
 
+    from threadpoolctl import threadpool_limits
     u = (f["u"] + f["delta"]).astype(np.float32)
     frames = list(range(n_frames))
-    t0 = time.perf_counter()
-    O.loss_grad(u, f["chi"], f["alpha"], f["probe"], DeviceY(y_dev), prob, frames=frames)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):      # one core: the figure is per host core
+        t0 = time.perf_counter()
+        O.loss_grad(u, f["chi"], f["alpha"], f["probe"], DeviceY(y_dev), prob, frames=frames)
+        dt = time.perf_counter() - t0
     return n_frames / dt, dt
 
 
@@ -198,10 +201,12 @@ def run_loop(args, torch):
         rng = np.random.default_rng(ccfg["seed"])
         cy = np.concatenate([speckle_counts(rng, int(cprob.det[m]), int(cprob.scan_n[m].prod()), 1e5).ravel()
                              for m in range(cprob.n_peaks)])
-        t1 = time.perf_counter()
-        _, cl, _ = O.line_search_descent(np.zeros_like(cf["u"]), cf["chi"], cf["alpha"], cf["probe"], cy, cprob,
-                                         iterations=1)
-        cdt = time.perf_counter() - t1
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            _, cl, _ = O.line_search_descent(np.zeros_like(cf["u"]), cf["chi"], cf["alpha"], cf["probe"], cy,
+                                             cprob, iterations=1)
+            cdt = time.perf_counter() - t1
         out["cpu_baseline"] = {"kind": "oracle", "cores": 1, "workload": crop, "frames": cprob.n_frames(),
                                "seconds_per_iteration": round(cdt, 2),
                                "note": "one iteration of the same loop (one loss+gradient evaluation and the "

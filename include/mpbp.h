@@ -111,11 +111,12 @@ enum {
 /* Kernel stages timed under MPBP_OPT_PROFILE. */
 enum {
   MPBP_STAGE_OBJECT = 0,     /* per-peak object build, eq. (1)/(3)                        */
-  MPBP_STAGE_FRAMES = 1,     /* per-frame forward model, residual and adjoint, eq. (2)-(4)*/
+  MPBP_STAGE_FRAMES = 1,     /* per-frame transforms, residual and adjoint, eq. (2)-(4)  */
   MPBP_STAGE_GRAD = 2,       /* back-projection gather and chain rule                     */
   MPBP_STAGE_FINALIZE = 3,   /* FP64 reductions                                           */
   MPBP_STAGE_PLAIN = 4,      /* the whole plain path (MPBP_OPT_PATH = 1)                 */
-  MPBP_NUM_STAGES = 5
+  MPBP_STAGE_PROJECT = 5,    /* per-frame probe product and sheared projection, eq. (2)  */
+  MPBP_NUM_STAGES = 6
 };
 
 /* Validate `problem`, build the integer tables (scan offsets, shear offsets, ragged y
@@ -239,7 +240,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi,
 
 /* Select a frame-kernel variant by hand for size class `size_class` (the order of
    the "classes" list of mpbp_tuning): compiled footprint bound (>= the class's
-   smallest, see mpbp_tuning "key"), slab depth (2 or 4) and XCD order (0 or 1).
+   smallest, see mpbp_tuning "key"), slab depth (4 or 8) and XCD order (0 or 1).
    MPBP_ERR_UNSUPPORTED if that variant is not compiled or does not fit in LDS. */
 mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound, int slab,
                              int xcd_order);

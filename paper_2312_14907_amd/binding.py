@@ -22,7 +22,7 @@ MPBP_OPT_PROFILE = 4
 MPBP_OPT_GRAD_BATCH = 5
 MPBP_OPT_GRAD_TILE = 6
 MPBP_Z_TIED = 1
-STAGES = ("object", "frames", "grad", "finalize", "plain")
+STAGES = ("object", "frames", "grad", "finalize", "plain", "project")
 
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
             "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",

@@ -18,6 +18,7 @@
 
 #include "mpbp_dft.hpp"
 #include "mpbp_frame.hpp"
+#include "mpbp_project.hpp"
 #include "mpbp_kernels.hpp"
 #include "mpbp_launch.hpp"
 
@@ -402,30 +403,43 @@ int frame_bound(int D, int f) {
 }
 
 // One translation unit per detector size instantiates the frame kernel (mpbp_frames_<D>.hip).
-hipError_t frames_d32(int op, int fb, int g, const FrameArgs* a, int lds_bytes, hipStream_t s);
-hipError_t frames_d64(int op, int fb, int g, const FrameArgs* a, int lds_bytes, hipStream_t s);
-hipError_t frames_d96(int op, int fb, int g, const FrameArgs* a, int lds_bytes, hipStream_t s);
-hipError_t frames_d128(int op, int fb, int g, const FrameArgs* a, int lds_bytes, hipStream_t s);
-hipError_t frames_d192(int op, int fb, int g, const FrameArgs* a, int lds_bytes, hipStream_t s);
-hipError_t frames_d256(int op, int fb, int g, const FrameArgs* a, int lds_bytes, hipStream_t s);
+hipError_t frames_d32(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
+hipError_t frames_d64(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
+hipError_t frames_d96(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
+hipError_t frames_d128(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
+hipError_t frames_d192(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
+hipError_t frames_d256(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
 
-static hipError_t frames_op(int op, int D, int FB, int G, const FrameArgs* a, int lds_bytes, hipStream_t s) {
+static hipError_t frames_op(int op, int D, int FB, const FrameArgs* a, int lds_bytes, hipStream_t s) {
   switch (D) {
-    case 32: return frames_d32(op, FB, G, a, lds_bytes, s);
-    case 64: return frames_d64(op, FB, G, a, lds_bytes, s);
-    case 96: return frames_d96(op, FB, G, a, lds_bytes, s);
-    case 128: return frames_d128(op, FB, G, a, lds_bytes, s);
-    case 192: return frames_d192(op, FB, G, a, lds_bytes, s);
-    case 256: return frames_d256(op, FB, G, a, lds_bytes, s);
+    case 32: return frames_d32(op, FB, a, lds_bytes, s);
+    case 64: return frames_d64(op, FB, a, lds_bytes, s);
+    case 96: return frames_d96(op, FB, a, lds_bytes, s);
+    case 128: return frames_d128(op, FB, a, lds_bytes, s);
+    case 192: return frames_d192(op, FB, a, lds_bytes, s);
+    case 256: return frames_d256(op, FB, a, lds_bytes, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_frames(int D, int FB, int G, const FrameArgs& a, int lds_bytes, hipStream_t s) {
-  return frames_op(0, D, FB, G, &a, lds_bytes, s);
+hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s) {
+  return frames_op(0, D, FB, &a, lds_bytes, s);
 }
 
-bool frame_instance(int D, int FB, int G) { return frames_op(2, D, FB, G, nullptr, 0, nullptr) == hipSuccess; }
+bool frame_instance(int D, int FB) { return frames_op(2, D, FB, nullptr, 0, nullptr) == hipSuccess; }
+
+hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s) {
+  const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
+  if (grid == 0) return hipSuccess;
+  switch (G) {
+    case 4: k_project<4><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
+    case 8: k_project<8><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int project_lds_bytes(int np, int G) { return G * (np + 1) * (np + 1) * (int)sizeof(cplx); }
 
 static const int kDets[] = {32, 64, 96, 128, 192, 256};
 
@@ -435,8 +449,11 @@ hipError_t prepare_kernels() {
   hipError_t e = hipSuccess;
   for (int D : kDets)
     for (int FB : {32, 48, 64, D})
-      for (int G : kSlabDepths)
-        if (e == hipSuccess && frame_instance(D, FB, G)) e = frames_op(1, D, FB, G, nullptr, 0, nullptr);
+      if (e == hipSuccess && frame_instance(D, FB)) e = frames_op(1, D, FB, nullptr, 0, nullptr);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_project<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_project<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 #define MPBP_CASE(b, tx)                                                                        \
   if (e == hipSuccess)                                                                          \
     e = hipFuncSetAttribute((const void*)k_grad<b, tx>, hipFuncAttributeMaxDynamicSharedMemorySize, \
@@ -511,26 +528,25 @@ hipError_t launch_mark_active(unsigned char* act, long long n_frames, const int*
 namespace mpbp {
 
 template <int D>
-static int lds_for(int fy, int fx, int fxp, int np, int nz, bool grad, int G) {
+static int lds_for(int fy, int fx, int fxp, bool grad) {
   using RC = LineCfg<D>;
   constexpr int L = ColLen<D>::L;
   constexpr int RLINES = kFrameThreads / RC::TPL;
   constexpr int EXL = RC::Q * (RC::P + 1);
-  const long long exch_min = (long long)G * (np + 1) * (np + 1) - ((long long)L * fxp + L / 8);
-  const long long exch = (RLINES * EXL + 1) / 2 > exch_min ? (RLINES * EXL + 1) / 2 : exch_min;
+  const long long exch = (RLINES * EXL + 1) / 2;
   const long long cpx = D + L + (long long)(D / L) * fy + (long long)fy * fx +
                         (grad ? (long long)fy * fx : 0) + (long long)L * fxp + L / 8 + exch;
-  return (int)(cpx * 8 + (long long)nz * 8);
+  return (int)(cpx * 8);
 }
 
-int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad, int G) {
+int frame_lds_bytes(int D, int fy, int fx, int fxp, bool grad) {
   switch (D) {
-    case 32: return lds_for<32>(fy, fx, fxp, np, nz, grad, G);
-    case 64: return lds_for<64>(fy, fx, fxp, np, nz, grad, G);
-    case 96: return lds_for<96>(fy, fx, fxp, np, nz, grad, G);
-    case 128: return lds_for<128>(fy, fx, fxp, np, nz, grad, G);
-    case 192: return lds_for<192>(fy, fx, fxp, np, nz, grad, G);
-    case 256: return lds_for<256>(fy, fx, fxp, np, nz, grad, G);
+    case 32: return lds_for<32>(fy, fx, fxp, grad);
+    case 64: return lds_for<64>(fy, fx, fxp, grad);
+    case 96: return lds_for<96>(fy, fx, fxp, grad);
+    case 128: return lds_for<128>(fy, fx, fxp, grad);
+    case 192: return lds_for<192>(fy, fx, fxp, grad);
+    case 256: return lds_for<256>(fy, fx, fxp, grad);
     default: return -1;
   }
 }

@@ -35,7 +35,7 @@ __device__ __forceinline__ int frame_block_index(int b, int n, int xcd) {
 // the same ramp, which the inverse transform undoes.  With the footprint at the origin,
 // only the first ceil(FB / Q) inputs of each lane are nonzero and only those outputs are
 // needed, so the compiler drops the rest of the first and last DFT stages.
-template <int D, int FB, int G>
+template <int D, int FB>
 __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
   using RC = LineCfg<D>;
   constexpr int RP = RC::P, RQ = RC::Q, RT = RC::TPL;
@@ -58,13 +58,10 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   constexpr int NAC = (FB + CQ - 1) / CQ < CP ? (FB + CQ - 1) / CQ : CP;  // live column inputs
 
   const int tid = threadIdx.x;
-  const int np = A.np, nz = A.nz;
   const int fy = pk.fy, fx = pk.fx, fxp = pk.fxp;
   // chunk row k starts at k * fxp + k / 8: the skew spreads the column pass's lanes
   // (8 rows apart) over the LDS banks
   auto TRI = [fxp](int k) { return k * fxp + (k >> 3); };
-  const int m = A.peak_of[fid];
-  const int py = A.scan[2 * fid], px = A.scan[2 * fid + 1];
   const int j = fid - pk.frame_base;
 
   // LDS layout (complex units):
@@ -74,8 +71,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   //   psi  [fy][fx] exit wave on the footprint
   //   gacc [fy][fx] footprint gradient
   //   Tr   [L][fxp] chunk of the column-transformed footprint, row k at k*fxp + k/8
-  //   exch          per-line exchange buffers (with Tr: staged slices during the projection)
-  //   sh   [nz]     shear offsets
+  //   exch          per-line exchange buffers
   cplx* tw2 = sm;
   cplx* twc = tw2 + D;
   cplx* ftw = twc + L;
@@ -83,132 +79,17 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   cplx* gacc = psi + fy * fx;
   cplx* Tr = gacc + (A.grad ? fy * fx : 0);
   cplx* exch = Tr + L * fxp + L / 8;
-  // the exchange area also holds (with the chunk buffer before it) G staged slices
-  const int exch_min = G * (np + 1) * (np + 1) - (L * fxp + L / 8);
-  const int exch_sz = (RLINES * EXL + 1) / 2 > exch_min ? (RLINES * EXL + 1) / 2 : exch_min;
-  int2* sh = reinterpret_cast<int2*>(exch + exch_sz);
 
   {
     const cplx* tsrc = reinterpret_cast<const cplx*>(A.tw) + pk.tw_off;
     for (int k = tid; k < D + L + R * fy; k += NT) tw2[k] = tsrc[k];
   }
-  const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
-  for (int z = tid; z < nz; z += NT) {
-    const int* s = A.shear + 2 * (m * nz + z);
-    sh[z] = make_int2(s[0], s[1]);
-  }
+
+  // ---- the exit wave on the footprint, left in the frame's slot by k_project ----
+  cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
+  for (int p = tid; p < fy * fx; p += NT) psi[p] = slot[p];
   if (A.grad)
     for (int k = tid; k < fy * fx; k += NT) gacc[k] = {0.f, 0.f};
-  __syncthreads();
-
-  // ---- eq. (2): R diag(P) S O -> exit wave on the footprint (gather over slices) ----
-  cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
-  const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * A.ny * A.nx;
-  // The illuminated slices W_z = P * O[z, window] are staged G at a time in the
-  // chunk / exchange area (idle during the projection), the next group's object values
-  // already in flight in registers; each lane then gathers its footprint pixels
-  //   psi[q] += W_z[q + min shear - s(z)]   (zero outside the probe support).
-  // A staged slice is (np + 1) x (np + 1) with a zero last row and column: offsets
-  // outside the support are clamped onto them, so the gather has no tests or branches.
-  {
-    const int np1 = np + 1;
-    const int sw = np1 * np1;
-    const int np2 = np * np;
-    cplx* Wb = Tr;
-    const int* shz = A.shear + 2 * m * nz;   // uniform: scalar loads
-    for (int k = tid; k < G * (2 * np + 1); k += NT) {
-      const int g = k / (2 * np + 1), e = k - g * (2 * np + 1);
-      Wb[g * sw + (e <= np ? np * np1 + e : (e - np - 1) * np1 + np)] = {0.f, 0.f};
-    }
-    cplx pv[kProjE];
-    int off[kProjE], wo[kProjE];
-#pragma unroll
-    for (int i = 0; i < kProjE; ++i) {
-      const int e = tid + NT * i;
-      const int a = e / np, b = e - (e / np) * np;
-      const int oy = py + a, ox = px + b;
-      const bool ok = e < np2 && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
-      pv[i] = ok ? probe[e < np2 ? e : 0] : cplx{0.f, 0.f};
-      off[i] = ok ? oy * A.nx + ox : 0;
-      wo[i] = e < np2 ? a * np1 + b : -1;
-    }
-    const long long plane = (long long)A.ny * A.nx;
-    cplx on[G][kProjE];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const cplx* Oz = O + (long long)(g < nz ? g : 0) * plane;
-#pragma unroll
-      for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
-    }
-    // Footprint pixel q = (qy, qx) of slice z reads staged element (qy + min s_y -
-    // s_y(z), qx + min s_x - s_x(z)), each coordinate clamped to np (the zero border).
-    // Both coordinates travel as one pair of 16-bit lanes: one packed subtract, one
-    // packed clamp and one dot product (row * (np + 1) * 8 + column * 8 + slice base)
-    // give the byte offset of the element.
-    u16x2 pq[kProjPix];
-    cplx acc[kProjPix];
-#pragma unroll
-    for (int h = 0; h < kProjPix; ++h) {
-      const int p = tid + NT * h;
-      const int qy = p / fx;
-      pq[h] = u16x2{(unsigned short)(p - qy * fx + pk.minx), (unsigned short)(qy + pk.miny)};
-      acc[h] = {0.f, 0.f};
-    }
-    const u16x2 lim = {(unsigned short)np, (unsigned short)np};
-    const u16x2 wts = {(unsigned short)sizeof(cplx), (unsigned short)(np1 * sizeof(cplx))};
-    // LDS byte address of the staging area (the dot product adds it for free)
-    const unsigned wb_lds = (unsigned)(size_t)(const lds_cplx*)Wb;
-    for (int z0 = 0; z0 < nz; z0 += G) {
-      __syncthreads();
-      if (z0 + G <= nz) {   // uniform: every slice of the group exists
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-          for (int i = 0; i < kProjE; ++i) {
-            if ((i + 1) * NT <= np2)   // uniform: every lane holds a probe pixel
-              Wb[g * sw + wo[i]] = cmul(pv[i], on[g][i]);
-            else if (wo[i] >= 0)
-              Wb[g * sw + wo[i]] = cmul(pv[i], on[g][i]);
-          }
-      } else {
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-          for (int i = 0; i < kProjE; ++i)
-            if (wo[i] >= 0) Wb[g * sw + wo[i]] = (z0 + g < nz) ? cmul(pv[i], on[g][i]) : cplx{0.f, 0.f};
-      }
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int z = z0 + G + g;
-        const cplx* Oz = O + (long long)(z < nz ? z : 0) * plane;
-#pragma unroll
-        for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
-      }
-      u16x2 ssh[G];
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int z = z0 + g < nz ? z0 + g : 0;
-        ssh[g] = u16x2{(unsigned short)shz[2 * z + 1], (unsigned short)shz[2 * z]};
-      }
-      __syncthreads();
-#pragma unroll
-      for (int h = 0; h < kProjPix; ++h) {
-        cplx w[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const u16x2 d = __builtin_elementwise_min(pq[h] - ssh[g], lim);
-          const unsigned a = __builtin_amdgcn_udot2(d, wts, wb_lds + (unsigned)(g * sw * sizeof(cplx)), false);
-          const lds_cplx* q = (const lds_cplx*)(size_t)a;
-          w[g] = cplx{q->x, q->y};
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[h] = cadd(acc[h], w[g]);
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < kProjPix; ++h)
-      if (tid + NT * h < fy * fx) psi[tid + NT * h] = acc[h];
-  }
   __syncthreads();
 
   const bool has_y = A.y != nullptr;
@@ -454,47 +335,46 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   }
 }
 
-// One instance per detector size D, footprint bound FB and projection slab depth G
-// (slices staged per step); the frames of a size class form one launch.
-template <int D, int FB, int G>
+// One instance per detector size D and footprint bound FB; the frames of a size class
+// form one launch.
+template <int D, int FB>
 __global__ __launch_bounds__(kFrameThreads) void k_frames(FrameArgs A) {
   extern __shared__ cplx smem[];
   const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
   if (idx >= A.n_list) return;
   const int fid = A.list[idx];
   const PeakDev pk = A.peaks[A.peak_of[fid]];
-  frame_body<D, FB, G>(A, pk, fid, smem);
+  frame_body<D, FB>(A, pk, fid, smem);
 }
 
 // Launch / prepare one instance.  op 0: launch over a.n_list frames; op 1: allow the
 // instance the full LDS of a CU on the current device; op 2: report that the instance
 // exists (hipSuccess).
-template <int D, int FB, int G>
+template <int D, int FB>
 hipError_t frame_instance_op(int op, const FrameArgs* a, int lds_bytes, hipStream_t s) {
   if (op == 1)
-    return hipFuncSetAttribute((const void*)k_frames<D, FB, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    return hipFuncSetAttribute((const void*)k_frames<D, FB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                160 * 1024);
   if (op == 2) return hipSuccess;
   const unsigned grid = a->xcd ? (unsigned)(((a->n_list + 7) / 8) * 8) : (unsigned)a->n_list;
   if (grid == 0) return hipSuccess;
-  k_frames<D, FB, G><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(*a);
+  k_frames<D, FB><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(*a);
   return hipGetLastError();
 }
 
-// Dispatch over the compiled footprint bounds FBs... and slab depths kSlabDepths.
+// Dispatch over the compiled footprint bounds FBs...
 template <int D, int... FBs>
-hipError_t frame_dispatch(int op, int fb, int g, const FrameArgs* a, int lds_bytes, hipStream_t s) {
+hipError_t frame_dispatch(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s) {
   hipError_t e = hipErrorInvalidValue;
   bool done = false;
-  auto one = [&](auto fb_, auto g_) {
-    constexpr int F = decltype(fb_)::value, GG = decltype(g_)::value;
-    if (!done && fb == F && g == GG) {
-      e = frame_instance_op<D, F, GG>(op, a, lds_bytes, s);
+  auto one = [&](auto fb_) {
+    constexpr int F = decltype(fb_)::value;
+    if (!done && fb == F) {
+      e = frame_instance_op<D, F>(op, a, lds_bytes, s);
       done = true;
     }
   };
-  (one(std::integral_constant<int, FBs>{}, std::integral_constant<int, 2>{}), ...);
-  (one(std::integral_constant<int, FBs>{}, std::integral_constant<int, 4>{}), ...);
+  (one(std::integral_constant<int, FBs>{}), ...);
   return e;
 }
 

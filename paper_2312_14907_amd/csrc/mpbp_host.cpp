@@ -85,8 +85,8 @@ struct mpbp_plan_t {
   struct SizeClass {
     int D, key, begin, count;
     int fy, fx;                        // largest footprint over the class's peaks
-    int FB, G, xcd;
-    int lds_fwd[5], lds_grad[5];       // dynamic LDS per slab depth (index G)
+    int FB, G, xcd;                    // G: slab depth of the projection kernel
+    int lds_fwd, lds_grad;             // dynamic LDS of the frame kernel
     double tuned_us;                   // autotuned launch time (0: not tuned)
   };
   std::vector<SizeClass> classes;      // full batch: frames of one detector size, in `order`
@@ -97,6 +97,7 @@ struct mpbp_plan_t {
   std::string tune_source = "default";
   std::string tune_report;             // candidates timed by the last mpbp_autotune
   int lds_fwd = 0, lds_grad_frame = 0, lds_grad = 0;
+  int lds_project[9] = {0};        // projection kernel, per slab depth
   int maxspan_y = 0, maxspan_x = 0;
   int max_cand = 0;
   // gradient tile grids, per compiled tile width: origin (<= 0) and tile counts
@@ -272,12 +273,11 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     d.gx = (float)k.g[0]; d.gy = (float)k.g[1]; d.gz = (float)k.g[2];
     d.tw_off = (long long)(p->tw.size() / 2);
     mpbp::frame_twiddles(d.D, d.fy, p->tw);
-    d.lds_bytes = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, true, mpbp::kDefaultSlab);
+    d.lds_bytes = mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, true);
     if (d.lds_bytes > kMaxLds)
       return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d needs %d B of LDS", m, d.fy, d.fx, d.lds_bytes);
     p->lds_grad_frame = std::max(p->lds_grad_frame, d.lds_bytes);
-    p->lds_fwd = std::max(p->lds_fwd, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false,
-                                                            mpbp::kDefaultSlab));
+    p->lds_fwd = std::max(p->lds_fwd, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, false));
     p->maxspan_y = std::max(p->maxspan_y, d.spany);
     p->maxspan_x = std::max(p->maxspan_x, d.spanx);
     slot += (long long)d.nfr * d.fy * d.fx;
@@ -318,6 +318,9 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     p->max_tiles = std::max(p->max_tiles, t.nx * t.ny);
   }
   p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0);
+  for (int G : mpbp::kSlabDepths) p->lds_project[G] = mpbp::project_lds_bytes(np, G);
+  if (p->lds_project[mpbp::kDefaultSlab] > kMaxLds)
+    return fail(MPBP_ERR_UNSUPPORTED, "projection needs %d B of LDS", p->lds_project[mpbp::kDefaultSlab]);
   if (p->lds_grad > kMaxLds) return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", p->lds_grad);
   // Full-batch processing order: larger windows first (they cost most), each peak's
   // frames in raster order.
@@ -349,10 +352,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     c.count += d.nfr;
     c.fy = std::max(c.fy, d.fy);
     c.fx = std::max(c.fx, d.fx);
-    for (int G : mpbp::kSlabDepths) {
-      c.lds_fwd[G] = std::max(c.lds_fwd[G], mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, false, G));
-      c.lds_grad[G] = std::max(c.lds_grad[G], mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, np, p->nz, true, G));
-    }
+    c.lds_fwd = std::max(c.lds_fwd, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, false));
+    c.lds_grad = std::max(c.lds_grad, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, true));
     for (int j = 0; j < d.nfr; ++j) p->order.push_back(d.frame_base + j);
   }
   return MPBP_OK;
@@ -494,27 +495,49 @@ struct StageTimer {
 // `branch` (graph capture), the classes after the first run on fork streams joined back
 // into `s`, so the captured graph holds them as parallel nodes: the classes write
 // disjoint slots and frame losses.
+// Each class runs the projection kernel (exit waves into the frames' slots), then the
+// frame kernel.  Direct launches run every class's projection first, then every class's
+// frame kernel, each group under its stage timer.
 hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset, bool grad, hipStream_t s,
                           bool branch = false) {
   const auto& cls = subset ? p->sub_classes : p->classes;
   const int* list = subset ? p->d_list_sorted : p->d_order;
-  hipError_t e = hipSuccess;
-  if (branch) e = hipEventRecord(p->fork_ev, s);
-  size_t k = 0;
-  bool first = true;
-  for (const auto& c : cls) {
-    if (c.count == 0) continue;
+  auto class_args = [&](const mpbp_plan_t::SizeClass& c) {
     mpbp::FrameArgs a = base;
     a.list = list + c.begin;
     a.n_list = c.count;
     a.xcd = c.xcd;
+    return a;
+  };
+  hipError_t e = hipSuccess;
+  if (!branch) {
+    {
+      StageTimer t(p, MPBP_STAGE_PROJECT, s);
+      for (const auto& c : cls)
+        if (c.count && e == hipSuccess) e = mpbp::launch_project(c.G, class_args(c), p->lds_project[c.G], s);
+    }
+    {
+      StageTimer t(p, MPBP_STAGE_FRAMES, s);
+      for (const auto& c : cls)
+        if (c.count && e == hipSuccess)
+          e = mpbp::launch_frames(c.D, c.FB, class_args(c), grad ? c.lds_grad : c.lds_fwd, s);
+    }
+    return e;
+  }
+  e = hipEventRecord(p->fork_ev, s);
+  size_t k = 0;
+  bool first = true;
+  for (const auto& c : cls) {
+    if (c.count == 0) continue;
+    const mpbp::FrameArgs a = class_args(c);
     hipStream_t t = s;
-    if (branch && !first) {
+    if (!first) {
       t = p->forks[k];
       if (e == hipSuccess) e = hipStreamWaitEvent(t, p->fork_ev, 0);
     }
-    if (e == hipSuccess) e = mpbp::launch_frames(c.D, c.FB, c.G, a, grad ? c.lds_grad[c.G] : c.lds_fwd[c.G], t);
-    if (branch && !first) {
+    if (e == hipSuccess) e = mpbp::launch_project(c.G, a, p->lds_project[c.G], t);
+    if (e == hipSuccess) e = mpbp::launch_frames(c.D, c.FB, a, grad ? c.lds_grad : c.lds_fwd, t);
+    if (!first) {
       if (e == hipSuccess) e = hipEventRecord(p->joins[k], t);
       if (e == hipSuccess) e = hipStreamWaitEvent(s, p->joins[k], 0);
       ++k;
@@ -586,10 +609,7 @@ hipError_t enqueue_forward(mpbp_plan p, const float* u, const float* chi, const 
   if (e != hipSuccess) return *what = "object kernel", e;
   mpbp::FrameArgs a = frame_args(p, y, list, n, model_intensity, 0);
   a.probe = probe;
-  {
-    StageTimer t(p, MPBP_STAGE_FRAMES, s);
-    e = enqueue_frames(p, a, subset, false, s, branch);
-  }
+  e = enqueue_frames(p, a, subset, false, s, branch);
   if (e != hipSuccess) return *what = "frame kernel", e;
   return hipSuccess;
 }
@@ -607,10 +627,7 @@ hipError_t enqueue_loss_grad(mpbp_plan p, const float* u, const float* chi, cons
   if (e != hipSuccess) return *what = "object kernel", e;
   mpbp::FrameArgs a = frame_args(p, y, list, n, nullptr, 1);
   a.probe = probe;
-  {
-    StageTimer t(p, MPBP_STAGE_FRAMES, s);
-    e = enqueue_frames(p, a, subset, true, s, branch);
-  }
+  e = enqueue_frames(p, a, subset, true, s, branch);
   if (e != hipSuccess) return *what = "frame kernel", e;
   const mpbp::GradArgs g = grad_args(p, u, chi, alpha, probe, subset, grad_u, grad_chi);
   {
@@ -696,15 +713,15 @@ std::vector<int> class_bounds(const mpbp_plan_t::SizeClass& c) {
   for (int fb : {32, 48, 64, c.D})
     if (fb >= c.key && std::find(out.begin(), out.end(), fb) == out.end()) {
       bool any = false;
-      for (int G : mpbp::kSlabDepths) any = any || mpbp::frame_instance(c.D, fb, G);
+      any = mpbp::frame_instance(c.D, fb);
       if (any) out.push_back(fb);
     }
   return out;
 }
 
-bool variant_ok(const mpbp_plan_t::SizeClass& c, int fb, int G) {
-  return fb >= c.key && G >= 0 && G < 5 && mpbp::frame_instance(c.D, fb, G) && c.lds_grad[G] > 0 &&
-         c.lds_grad[G] <= kMaxLds && c.lds_fwd[G] <= kMaxLds;
+bool variant_ok(const mpbp_plan_t* p, const mpbp_plan_t::SizeClass& c, int fb, int G) {
+  return fb >= c.key && (G == 4 || G == 8) && mpbp::frame_instance(c.D, fb) && c.lds_grad > 0 &&
+         c.lds_grad <= kMaxLds && c.lds_fwd <= kMaxLds && p->lds_project[G] <= kMaxLds;
 }
 
 std::string device_arch(int device) {
@@ -759,7 +776,7 @@ void load_tuning(mpbp_plan_t* p) {
       int fb = 0, G = 0, xcd = 0;
       double us = 0.0;
       if (e.first == k && std::sscanf(e.second.c_str(), "FB=%d G=%d xcd=%d us=%lf", &fb, &G, &xcd, &us) == 4 &&
-          variant_ok(c, fb, G) && (xcd == 0 || xcd == 1)) {
+          variant_ok(p, c, fb, G) && (xcd == 0 || xcd == 1)) {
         c.FB = fb; c.G = G; c.xcd = xcd; c.tuned_us = us;
         used = true;
       }
@@ -1183,12 +1200,15 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
     for (int fb : class_bounds(c))
       for (int G : mpbp::kSlabDepths)
         for (int xcd = 0; xcd < 2 && e == hipSuccess; ++xcd) {
-          if (!variant_ok(c, fb, G)) continue;
+          if (!variant_ok(plan, c, fb, G)) continue;
           mpbp::FrameArgs a = frame_args(plan, y, plan->d_order + c.begin, c.count, nullptr, 1);
           a.probe = (const float*)probe;
           a.xcd = xcd;
           double us = 0.0;
-          e = time_us([&]() { return mpbp::launch_frames(c.D, fb, G, a, c.lds_grad[G], s); }, 3, &us);
+          e = time_us([&]() {
+                hipError_t r = mpbp::launch_project(G, a, plan->lds_project[G], s);
+                return r == hipSuccess ? mpbp::launch_frames(c.D, fb, a, c.lds_grad, s) : r;
+              }, 3, &us);
           snprintf(buf, sizeof(buf), "%s{\"class\": %zu, \"FB\": %d, \"G\": %d, \"xcd\": %d, \"us\": %.2f}",
                    rep.size() > 1 ? ", " : "", ci, fb, G, xcd, us);
           rep += buf;
@@ -1239,7 +1259,7 @@ mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound
     return fail(MPBP_ERR_INVALID, "size class %d out of range [0, %zu)", size_class, plan->classes.size());
   auto& c = plan->classes[size_class];
   if (xcd_order != 0 && xcd_order != 1) return fail(MPBP_ERR_INVALID, "xcd_order must be 0 or 1");
-  if (!variant_ok(c, footprint_bound, slab))
+  if (!variant_ok(plan, c, footprint_bound, slab))
     return fail(MPBP_ERR_UNSUPPORTED, "no compiled frame kernel for D=%d with footprint bound %d >= %d and slab %d",
                 c.D, footprint_bound, c.key, slab);
   c.FB = footprint_bound;

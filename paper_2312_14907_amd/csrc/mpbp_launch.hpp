@@ -11,17 +11,20 @@ namespace mpbp {
 // Allow the frame and gradient kernels the full 160 KB of LDS on the current device.
 // Called once per plan, before any launch (and before any graph capture).
 hipError_t prepare_kernels();
-// True if the frame kernel is compiled for detector size D, footprint bound FB and
-// projection slab depth G.
-bool frame_instance(int D, int FB, int G);
+// True if the frame kernel is compiled for detector size D and footprint bound FB.
+bool frame_instance(int D, int FB);
 
 // tied = ny * nx for fields given per lateral pixel (the z-tied parameterisation), else 0.
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
                          int n_peaks, long long nvox, long long tied, float* obj, hipStream_t s);
 // Frames of one detector size D whose footprints fit FB x FB (a.list holds only such
-// frames; frame_bound(D, largest footprint side) is the smallest such FB), with G object
-// slices staged per projection step.
-hipError_t launch_frames(int D, int FB, int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
+// frames; frame_bound(D, largest footprint side) is the smallest such FB).  Reads each
+// frame's exit wave from its slot (written by launch_project).
+hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s);
+// Exit waves of the listed frames into their slots, G object slices staged per step
+// (G = 4 or 8); lds_bytes from project_lds_bytes.
+hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
+int project_lds_bytes(int np, int G);
 int frame_bound(int D, int footprint);
 // Gradient kernel reading `batch` frames per step of its frame walk (1, 2 or 4), over
 // tiles `tile_x` voxels wide (16: 16 x 4, 8: 8 x 8).
@@ -40,9 +43,8 @@ hipError_t launch_norm2(const float* a, long long n, double* part, int max_part,
 hipError_t launch_mark_active(unsigned char* act, long long n_frames, const int* list, int n,
                               hipStream_t s);
 
-// Dynamic LDS of the frame kernel for one peak and slab depth G (bytes); must match
-// frame_body's layout.
-int frame_lds_bytes(int D, int fy, int fx, int fxp, int np, int nz, bool grad, int G);
+// Dynamic LDS of the frame kernel for one peak (bytes); must match frame_body's layout.
+int frame_lds_bytes(int D, int fy, int fx, int fxp, bool grad);
 // Append the frame kernel's twiddle tables of one peak (complex64 as float pairs):
 // row twiddles [D], column twiddles [L], residue-fold twiddles [R][fy] (footprint at
 // the window origin).

@@ -79,7 +79,7 @@ def test_every_variant_matches_default(c4):
     n = 0
     for k, c in enumerate(classes):
         for fb in sorted({48, 64, c["D"], 32} - {x for x in (32, 48, 64) if x < c["key"]}):
-            for g in (2, 4):
+            for g in (4, 8):
                 for xcd in (0, 1):
                     try:
                         plan.mpbp_set_variant(k, fb, g, xcd)
@@ -124,13 +124,14 @@ def test_autotune_and_cache(c4, tmp_path):
         for k, c in enumerate(t["classes"]):
             cand = [x for x in t["candidates"] if x.get("class") == k]
             assert cand, f"class {k} not timed"
-            best = min(cand, key=lambda x: x["us"])
-            assert (c["FB"], c["G"], c["xcd"]) == (best["FB"], best["G"], best["xcd"])
-            assert c["us"] == pytest.approx(best["us"], abs=0.01)
+            best = min(x["us"] for x in cand)       # (the report rounds to 0.01 us)
+            chosen = [x for x in cand if (x["FB"], x["G"], x["xcd"]) == (c["FB"], c["G"], c["xcd"])]
+            assert chosen and chosen[0]["us"] <= best + 0.01
+            assert c["us"] == pytest.approx(best, abs=0.01)
         gb = [x for x in t["candidates"] if "grad_batch" in x]
         assert sorted((x["grad_batch"], x["grad_tile"]) for x in gb) == [(b, tx) for b in (1, 2, 4) for tx in (8, 16)]
-        fastest = min(gb, key=lambda x: x["us"])
-        assert (t["grad_batch"], t["grad_tile"]) == (fastest["grad_batch"], fastest["grad_tile"])
+        chosen = [x for x in gb if (x["grad_batch"], x["grad_tile"]) == (t["grad_batch"], t["grad_tile"])]
+        assert chosen and chosen[0]["us"] <= min(x["us"] for x in gb) + 0.01
         _close(_run(plan, args), ref, "autotuned")
         lines = cache.read_text().splitlines()
         assert len(lines) == len(t["classes"]) + 1 and all(" | " in ln for ln in lines)

@@ -135,13 +135,13 @@ def test_launch_parameter_api_on_host_plan():
         assert c["FB"] == c["key"] and c["G"] == 4 and c["xcd"] == 1
         assert max(c["fy"], c["fx"]) <= c["key"]
     k = next(i for i, c in enumerate(t["classes"]) if c["D"] == 256)
-    plan.mpbp_set_variant(k, 256, 2, 0)
+    plan.mpbp_set_variant(k, 256, 8, 0)
     c = plan.mpbp_tuning()["classes"][k]
-    assert (c["FB"], c["G"], c["xcd"]) == (256, 2, 0)
+    assert (c["FB"], c["G"], c["xcd"]) == (256, 8, 0)
     assert plan.mpbp_tuning()["source"] == "manual"
     for args, status in (((len(t["classes"]), 48, 4, 1), 1),   # class out of range
                          ((k, 32, 4, 1), 6),                  # bound below the footprint
-                         ((k, 48, 3, 1), 6),                  # slab depth not compiled
+                         ((k, 48, 2, 1), 6),                  # slab depth not compiled
                          ((k, 48, 4, 2), 1)):                 # bad xcd flag
         with pytest.raises(B.MPBPError) as e:
             plan.mpbp_set_variant(*args)
