@@ -240,7 +240,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi,
 
 /* Select a frame-kernel variant by hand for size class `size_class` (the order of
    the "classes" list of mpbp_tuning): compiled footprint bound (>= the class's
-   smallest, see mpbp_tuning "key"), slab depth (4 or 8) and XCD order (0 or 1).
+   smallest, see mpbp_tuning "key"), slab depth (2, 4 or 8) and XCD order (0 or 1).
    MPBP_ERR_UNSUPPORTED if that variant is not compiled or does not fit in LDS. */
 mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound, int slab,
                              int xcd_order);

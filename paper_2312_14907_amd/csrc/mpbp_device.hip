@@ -432,6 +432,7 @@ hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t 
   const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
   switch (G) {
+    case 2: k_project<2><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
     case 4: k_project<4><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
     case 8: k_project<8><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
     default: return hipErrorInvalidValue;
@@ -439,7 +440,7 @@ hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t 
   return hipGetLastError();
 }
 
-int project_lds_bytes(int np, int G) { return G * (np + 1) * (np + 1) * (int)sizeof(cplx); }
+int project_lds_bytes(int np, int G) { return G * (np + 1) * (np + 1) * (int)sizeof(cplx) + G * 4; }
 
 static const int kDets[] = {32, 64, 96, 128, 192, 256};
 
@@ -450,6 +451,8 @@ hipError_t prepare_kernels() {
   for (int D : kDets)
     for (int FB : {32, 48, 64, D})
       if (e == hipSuccess && frame_instance(D, FB)) e = frames_op(1, D, FB, nullptr, 0, nullptr);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_project<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_project<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e == hipSuccess)

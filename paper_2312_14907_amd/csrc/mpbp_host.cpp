@@ -720,7 +720,7 @@ std::vector<int> class_bounds(const mpbp_plan_t::SizeClass& c) {
 }
 
 bool variant_ok(const mpbp_plan_t* p, const mpbp_plan_t::SizeClass& c, int fb, int G) {
-  return fb >= c.key && (G == 4 || G == 8) && mpbp::frame_instance(c.D, fb) && c.lds_grad > 0 &&
+  return fb >= c.key && (G == 2 || G == 4 || G == 8) && mpbp::frame_instance(c.D, fb) && c.lds_grad > 0 &&
          c.lds_grad <= kMaxLds && c.lds_fwd <= kMaxLds && p->lds_project[G] <= kMaxLds;
 }
 

@@ -68,7 +68,7 @@ struct GradArgs {
 };
 
 constexpr int kFrameThreads = 256;
-constexpr int kSlabDepths[] = {4, 8};   // compiled projection slab depths (slices staged per step)
+constexpr int kSlabDepths[] = {2, 4, 8};   // compiled projection slab depths (slices staged per step)
 constexpr int kDefaultSlab = 4;
 constexpr int kProjE = 4;     // probe pixels staged per lane (probe_n^2 <= 4 * 256)
 constexpr int kProjPix = 8;   // footprint pixels per lane (fy * fx <= 8 * 256)

@@ -24,9 +24,9 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
   cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
   const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * A.ny * A.nx;
-  // The illuminated slices W_z = P * O[z, window] are staged G at a time in LDS, the
-  // next group's object values already in flight in registers; each lane then gathers
-  // its footprint pixels
+  // The illuminated slices W_z = P * O[z, window], summed over runs of slices with equal
+  // shear offset within each group of G slices, are staged in LDS; each lane then
+  // gathers its footprint pixels
   //   psi[q] += W_z[q + min shear - s(z)]   (zero outside the probe support).
   // A staged slice is (np + 1) x (np + 1) with a zero last row and column: offsets
   // outside the support are clamped onto them, so the gather has no tests or branches.
@@ -53,18 +53,26 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
       wo[i] = e < np2 ? a * np1 + b : -1;
     }
     const long long plane = (long long)A.ny * A.nx;
-    cplx on[G][kProjE];
+    // Object values of two groups of G slices are in flight: group k + 2 is requested
+    // while group k is used (the loads are L2 round trips that one group's work does
+    // not cover).
+    auto load_group = [&](cplx (&on)[G][kProjE], int z0) {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const cplx* Oz = O + (long long)(g < nz ? g : 0) * plane;
+      for (int g = 0; g < G; ++g) {
+        const int z = z0 + g < nz ? z0 + g : nz - 1;
+        const cplx* Oz = O + (long long)z * plane;
 #pragma unroll
-      for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
-    }
+        for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
+      }
+    };
+    cplx onA[G][kProjE], onB[G][kProjE];
+    load_group(onA, 0);
+    load_group(onB, G);
     // Footprint pixel q = (qy, qx) of slice z reads staged element (qy + min s_y -
     // s_y(z), qx + min s_x - s_x(z)), each coordinate clamped to np (the zero border).
     // Both coordinates travel as one pair of 16-bit lanes: one packed subtract, one
-    // packed clamp and one dot product (row * (np + 1) * 8 + column * 8 + slice base)
-    // give the byte offset of the element.
+    // packed clamp and one dot product (row * (np + 1) * 8 + column * 8 + slot base)
+    // give the byte address of the element.
     u16x2 pq[kProjPix];
     cplx acc[kProjPix];
 #pragma unroll
@@ -76,54 +84,64 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
     }
     const u16x2 lim = {(unsigned short)np, (unsigned short)np};
     const u16x2 wts = {(unsigned short)sizeof(cplx), (unsigned short)(np1 * sizeof(cplx))};
-    // LDS byte address of the staging area (the dot product adds it for free)
-    const unsigned wb_lds = (unsigned)(size_t)(const lds_cplx*)Wb;
-    for (int z0 = 0; z0 < nz; z0 += G) {
-      __syncthreads();
-      if (z0 + G <= nz) {   // uniform: every slice of the group exists
+    const unsigned wb_lds = (unsigned)(size_t)(const lds_cplx*)Wb;   // LDS byte address of slot 0
+    u16x2* slot_shift = reinterpret_cast<u16x2*>(Wb + G * sw);      // shear of each staged slot
+    auto stage = [&](const cplx (&w)[kProjE], int sl) {
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+      for (int i = 0; i < kProjE; ++i) {
+        if ((i + 1) * NT <= np2)   // uniform: every lane holds a probe pixel
+          Wb[sl * sw + wo[i]] = w[i];
+        else if (wo[i] >= 0)
+          Wb[sl * sw + wo[i]] = w[i];
+      }
+    };
+    // One group: slices with equal shear offset (runs, uniform) are summed in registers
+    // and staged once, then every footprint pixel gathers from the staged slots.
+    auto step = [&](cplx (&on)[G][kProjE], int z0) {
+      __syncthreads();   // the previous group's gather is done with the slots
+      int nsl = 0;
+      int cy = shz[2 * z0], cx = shz[2 * z0 + 1];
+      cplx w[kProjE];
 #pragma unroll
-          for (int i = 0; i < kProjE; ++i) {
-            if ((i + 1) * NT <= np2)   // uniform: every lane holds a probe pixel
-              Wb[g * sw + wo[i]] = cmul(pv[i], on[g][i]);
-            else if (wo[i] >= 0)
-              Wb[g * sw + wo[i]] = cmul(pv[i], on[g][i]);
+      for (int i = 0; i < kProjE; ++i) w[i] = cmul(pv[i], on[0][i]);
+#pragma unroll
+      for (int g = 1; g < G; ++g) {
+        const int z = z0 + g;
+        if (z < nz) {   // uniform
+          const int sy = shz[2 * z], sx = shz[2 * z + 1];
+          if (sy != cy || sx != cx) {   // uniform: a new run
+            stage(w, nsl);
+            if (tid == 0) slot_shift[nsl] = u16x2{(unsigned short)cx, (unsigned short)cy};
+            ++nsl;
+            cy = sy;
+            cx = sx;
+#pragma unroll
+            for (int i = 0; i < kProjE; ++i) w[i] = cmul(pv[i], on[g][i]);
+          } else {
+#pragma unroll
+            for (int i = 0; i < kProjE; ++i) w[i] = cadd(w[i], cmul(pv[i], on[g][i]));
           }
-      } else {
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-          for (int i = 0; i < kProjE; ++i)
-            if (wo[i] >= 0) Wb[g * sw + wo[i]] = (z0 + g < nz) ? cmul(pv[i], on[g][i]) : cplx{0.f, 0.f};
-      }
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int z = z0 + G + g;
-        const cplx* Oz = O + (long long)(z < nz ? z : 0) * plane;
-#pragma unroll
-        for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
-      }
-      u16x2 ssh[G];
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int z = z0 + g < nz ? z0 + g : 0;
-        ssh[g] = u16x2{(unsigned short)shz[2 * z + 1], (unsigned short)shz[2 * z]};
-      }
-      __syncthreads();
-#pragma unroll
-      for (int h = 0; h < kProjPix; ++h) {
-        cplx w[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const u16x2 d = __builtin_elementwise_min(pq[h] - ssh[g], lim);
-          const unsigned a = __builtin_amdgcn_udot2(d, wts, wb_lds + (unsigned)(g * sw * sizeof(cplx)), false);
-          const lds_cplx* q = (const lds_cplx*)(size_t)a;
-          w[g] = cplx{q->x, q->y};
         }
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[h] = cadd(acc[h], w[g]);
       }
+      stage(w, nsl);
+      if (tid == 0) slot_shift[nsl] = u16x2{(unsigned short)cx, (unsigned short)cy};
+      ++nsl;
+      load_group(on, z0 + 2 * G);
+      __syncthreads();
+      for (int k = 0; k < nsl; ++k) {   // uniform trip count
+        const u16x2 sh = slot_shift[k];
+        const unsigned base = wb_lds + (unsigned)(k * sw * sizeof(cplx));
+#pragma unroll
+        for (int h = 0; h < kProjPix; ++h) {
+          const u16x2 d = __builtin_elementwise_min(pq[h] - sh, lim);
+          const lds_cplx* q = (const lds_cplx*)(size_t)__builtin_amdgcn_udot2(d, wts, base, false);
+          acc[h] = cadd(acc[h], cplx{q->x, q->y});
+        }
+      }
+    };
+    for (int z0 = 0; z0 < nz; z0 += 2 * G) {
+      step(onA, z0);
+      if (z0 + G < nz) step(onB, z0 + G);   // uniform
     }
 #pragma unroll
     for (int h = 0; h < kProjPix; ++h)
@@ -132,8 +150,13 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
 
 }
 
+// Occupancy target: the shallower the slab, the less LDS and the fewer registers, the
+// more workgroups per CU.
+template <int G> struct ProjectWaves { static constexpr int value = G <= 2 ? 5 : G <= 4 ? 4 : 2; };
+
 template <int G>
-__global__ __launch_bounds__(kFrameThreads) void k_project(FrameArgs A) {
+__global__ __launch_bounds__(kFrameThreads) __attribute__((amdgpu_waves_per_eu(ProjectWaves<G>::value)))
+void k_project(FrameArgs A) {
   extern __shared__ cplx smem[];
   const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
   if (idx >= A.n_list) return;

@@ -79,7 +79,7 @@ def test_every_variant_matches_default(c4):
     n = 0
     for k, c in enumerate(classes):
         for fb in sorted({48, 64, c["D"], 32} - {x for x in (32, 48, 64) if x < c["key"]}):
-            for g in (4, 8):
+            for g in (2, 4, 8):
                 for xcd in (0, 1):
                     try:
                         plan.mpbp_set_variant(k, fb, g, xcd)

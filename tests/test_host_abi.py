@@ -141,7 +141,7 @@ def test_launch_parameter_api_on_host_plan():
     assert plan.mpbp_tuning()["source"] == "manual"
     for args, status in (((len(t["classes"]), 48, 4, 1), 1),   # class out of range
                          ((k, 32, 4, 1), 6),                  # bound below the footprint
-                         ((k, 48, 2, 1), 6),                  # slab depth not compiled
+                         ((k, 48, 3, 1), 6),                  # slab depth not compiled
                          ((k, 48, 4, 2), 1)):                 # bad xcd flag
         with pytest.raises(B.MPBPError) as e:
             plan.mpbp_set_variant(*args)
