@@ -80,7 +80,7 @@ def step_bytes(prob):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("mpbp_device.hip", "mpbp_dft.hpp", "mpbp_kernels.hpp"):
+    for f in ("mpbp_device.hip", "mpbp_dft.hpp", "mpbp_frame.hpp", "mpbp_kernels.hpp", "mpbp_project.hpp"):
         with open(os.path.join(ROOT, "paper_2312_14907_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

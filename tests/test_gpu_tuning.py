@@ -4,12 +4,12 @@ Every compiled variant of the frame kernel (footprint bound, projection slab dep
 XCD-aware order) and of the back-projection kernel (frames per step) computes the same
 result as the default launch parameters, which the oracle parity tests cover.  The XCD
 order and the frame batch leave every operation as it is, so those results are bitwise
-equal.  The slab depth keeps the order of every sum and a larger footprint bound only
-adds exact zeros, but in another instance the compiler may contract products into FMAs
-in another order, so those results agree to rounding: 1e-5 of each output's largest
-magnitude.  The autotuner
-picks the fastest timed candidate, leaves the results unchanged, and its cache file
-restores the choice in a new plan.
+equal.  The slab depth changes which slices of equal shear are summed before staging, a
+larger footprint bound only adds exact zeros, and in another instance the compiler may
+contract products into FMAs in another order, so those results agree to rounding: 1e-5
+of each output's largest magnitude.  The autotuner picks the fastest projection slab
+depth, then the fastest footprint bound and XCD order, leaves the results unchanged, and
+its cache file restores the choice in a new plan.
 """
 import os
 
@@ -122,7 +122,13 @@ def test_autotune_and_cache(c4, tmp_path):
         t = plan.mpbp_tuning()
         assert t["source"] == "autotune"
         for k, c in enumerate(t["classes"]):
-            cand = [x for x in t["candidates"] if x.get("class") == k]
+            # slab depth: the fastest projection for the chosen XCD order
+            proj = [x for x in t["candidates"] if x.get("class") == k and x.get("kernel") == "project"]
+            assert sorted((x["G"], x["xcd"]) for x in proj) == [(g, x) for g in (2, 4, 8) for x in (0, 1)]
+            at_x = [x for x in proj if x["xcd"] == c["xcd"]]
+            assert [x for x in at_x if x["G"] == c["G"]][0]["us"] <= min(x["us"] for x in at_x) + 0.01
+            # footprint bound and XCD order: the fastest projection + frame kernel pair
+            cand = [x for x in t["candidates"] if x.get("class") == k and "FB" in x]
             assert cand, f"class {k} not timed"
             best = min(x["us"] for x in cand)       # (the report rounds to 0.01 us)
             chosen = [x for x in cand if (x["FB"], x["G"], x["xcd"]) == (c["FB"], c["G"], c["xcd"])]
