@@ -362,13 +362,15 @@ def log_param_grad(x, grad_x):
 
 
 def adam_reconstruct(u, chi_log, alpha_log, probe, y, problem, order, batch, iterations,
-                     lr=(0.01, 0.1, 0.1), fixed_alpha=0, beta1=0.9, beta2=0.999, eps=1e-8):
-    """Algorithm 1 without the unwrap projection (its line 5): minibatches of `batch`
-    consecutive frames of the shuffled frame order `order` (the shuffle is an input),
-    minibatch gradients summed over the frames (eq. (11)), then Adam on u and on the
-    log variables chi~, alpha~ of eq. (8), alpha of peak `fixed_alpha` held fixed (-1:
-    none).  Returns (u, chi_log, alpha_log, losses) with the minibatch loss of every
-    iteration (evaluated before that iteration's update)."""
+                     lr=(0.01, 0.1, 0.1), fixed_alpha=0, beta1=0.9, beta2=0.999, eps=1e-8,
+                     unwrap=False):
+    """Algorithm 1: minibatches of `batch` consecutive frames of the shuffled frame order
+    `order` (the shuffle is an input), minibatch gradients summed over the frames
+    (eq. (11)), then Adam on u and on the log variables chi~, alpha~ of eq. (8), alpha of
+    peak `fixed_alpha` held fixed (-1: none); with unwrap=True every update of u is
+    followed by the unwrap projection Pi_U of eq. (10) (the algorithm's last step; without
+    it, the concurrent-wrapped variant).  Returns (u, chi_log, alpha_log, losses) with the
+    minibatch loss of every iteration (evaluated before that iteration's update)."""
     u = np.array(u, dtype=np.float64)
     cl = np.array(chi_log, dtype=np.float64)
     al = np.array(alpha_log, dtype=np.float64)
@@ -385,6 +387,9 @@ def adam_reconstruct(u, chi_log, alpha_log, probe, y, problem, order, batch, ite
         grads = [r["grad_u"], log_param_grad(chi, r["grad_chi"]), log_param_grad(alpha, r["grad_alpha"])]
         t = it + 1
         u, mom[0], sec[0] = adam_update(u, grads[0], mom[0], sec[0], t, lr[0], beta1, beta2, eps)
+        if unwrap:
+            from oracle.unwrap_oracle import unwrap_projector
+            u = unwrap_projector(u.astype(np.float32), problem.g)
         cl, mom[1], sec[1] = adam_update(cl, grads[1], mom[1], sec[1], t, lr[1], beta1, beta2, eps)
         keep = al[fixed_alpha] if fixed_alpha >= 0 else None
         keep_m = (mom[2][fixed_alpha], sec[2][fixed_alpha]) if fixed_alpha >= 0 else None

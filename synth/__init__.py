@@ -16,6 +16,8 @@ from .inputs import (
     poisson_counts,
     speckle_counts,
     crop_problem,
+    unwrap_field,
+    lattice_jump,
 )
 
 __all__ = [

@@ -241,3 +241,30 @@ def frame_order(n_frames, seed, epochs):
     of all frames per epoch (the shuffle of Algorithm 1), concatenated, int32."""
     rng = np.random.default_rng(seed)
     return np.concatenate([rng.permutation(n_frames) for _ in range(epochs)]).astype(np.int32)
+
+
+def unwrap_field(nz, ny, nx, seed, sigma_nm=0.2, corr=12.0, noise_nm=0.0):
+    """Seeded displacement field for the phase-unwrap tests, float32 [3][nz][ny][nx].
+
+    Each component is a smooth periodic Gaussian random field of standard deviation
+    `sigma_nm` and correlation length `corr` voxels (z-invariant), plus, per slice, a
+    constant offset of 0.05 sigma and white noise of standard deviation `noise_nm`.
+    With sigma = 0.2 nm and corr = 12 the phases G . u of the (111) peaks span several
+    multiples of 2 pi while neighbouring pixels differ by less than pi."""
+    rng = np.random.default_rng(seed)
+    base = np.stack([_grf(rng, ny, nx, sigma_nm, corr) for _ in range(3)])
+    u = np.repeat(base[:, None], nz, axis=1)
+    u += 0.05 * sigma_nm * rng.standard_normal((3, nz, 1, 1))
+    if noise_nm > 0:
+        u += noise_nm * rng.standard_normal(u.shape)
+    return u.astype(np.float32)
+
+
+def lattice_jump(u, y0, y1, x0, x1, cells=1):
+    """Copy of u with `cells` lattice translations a * e_x added on the lateral patch
+    [y0, y1) x [x0, x1) of every slice: for every Bragg vector G_hkl = (2 pi / a)(h, k, l)
+    the phase changes by 2 pi h cells, a multiple of 2 pi (the periodicity artefact the
+    unwrap projector removes)."""
+    v = np.array(u, dtype=np.float32, copy=True)
+    v[0, ..., y0:y1, x0:x1] += np.float32(cells * LATTICE_A_NM)
+    return v
