@@ -56,7 +56,8 @@ typedef enum {
   MPBP_ERR_FOOTPRINT = 3,    /* a sheared probe support leaves its detector window      */
   MPBP_ERR_DEVICE = 4,       /* HIP failure, or a compute call on a host-only plan      */
   MPBP_ERR_NOMEM = 5,        /* device or host allocation failed                        */
-  MPBP_ERR_UNSUPPORTED = 6   /* valid but outside what the kernels implement            */
+  MPBP_ERR_UNSUPPORTED = 6,  /* valid but outside what the kernels implement            */
+  MPBP_ERR_INTERNAL = 7      /* a device-side consistency check failed                  */
 } mpbp_status;
 
 /* One Bragg peak m (sections 2-3; eq. (2) operators S and R). */
@@ -251,6 +252,33 @@ mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound
    bytes (NUL-terminated) to buf (may be NULL) and the size needed, NUL included, to
    *len (may be NULL); MPBP_ERR_INVALID if cap is too small for the text. */
 mpbp_status mpbp_tuning(mpbp_plan plan, char* buf, int64_t cap, int64_t* len);
+
+/* The phase-unwrap projector Pi_U of eq. (10) (section 3.3; the last step of every
+   iteration of Algorithm 1), applied in place:
+     u <- W^{-1}{W{u . H}} . H^T (H H^T)^{-1},
+   H the 3 x n_peaks matrix of Bragg vectors (eq. (9)), W the phase wrap, W^{-1} the 2D
+   phase unwrapping of every map (one per peak and per z-slice; one per peak under
+   MPBP_Z_TIED) by reliability-guided merging (Herraez et al., Appl. Opt. 41, 7437
+   (2002)): pixel reliability 1 / sqrt(H^2 + V^2 + D1^2 + D2^2) from the second
+   differences of the wrapped phase along the row, the column and both diagonals (0 on
+   the map border), edges between 4-neighbours ordered by the summed reliability of
+   their pixels (ties by MurmurHash3's fmix32 of the edge index, horizontal edges
+   i (nx - 1) + j first, then vertical edges ny (nx - 1) + i nx + j), and groups joined
+   from the most reliable edge down.  Every map's free multiple of 2 pi is fixed by
+   rounding (halves up) the mean of its wrap counts rint(G_m . u / 2 pi) minus those of
+   the unwrapped phase, so that a field without phase jumps is left unchanged.  The
+   update is applied as u += 2 pi N . H^+ with the integer maps N below and the
+   Moore-Penrose H^+ (equal to eq. (10) for non-coplanar Bragg vectors; for coplanar
+   ones the component of u that no peak sees is kept).  Wraps, reliabilities and edge
+   keys are computed in float32, each operation rounded in the order written above.
+     u      (dev) float, the layout of mpbp_loss_grad; overwritten with Pi_U(u)
+     wraps  (dev) int32 [n_peaks][nz][ny][nx] ([n_peaks][1][ny][nx] under MPBP_Z_TIED),
+            may be NULL: N, the multiples of 2 pi the projector adds to each phase
+            G_m . u (the unwrapped phase is G_m . u + 2 pi N)
+   The first call allocates a workspace of about 44 bytes per map pixel, kept until
+   mpbp_plan_destroy.  Synchronous: waits for `stream` (it reads back a device-side
+   consistency flag; MPBP_ERR_INTERNAL if a merge step found its tree inconsistent). */
+mpbp_status mpbp_unwrap_project(mpbp_plan plan, float* u, int32_t* wraps, void* stream);
 
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* mpbp_last_error(void);

@@ -10,10 +10,13 @@ __all__ = ["Plan", "MPBPError", "MPBPLoss", "binding", "autograd"]
 
 
 def __getattr__(name):
+    # importlib, not "from . import x": the latter asks this module for the attribute
+    # first and would recurse into __getattr__ before the submodule is loaded
+    import importlib
     if name in ("Plan", "MPBPError", "binding"):
-        from . import binding
+        binding = importlib.import_module(__name__ + ".binding")
         return binding if name == "binding" else getattr(binding, name)
     if name in ("MPBPLoss", "autograd"):
-        from . import autograd
+        autograd = importlib.import_module(__name__ + ".autograd")
         return autograd if name == "autograd" else autograd.MPBPLoss
     raise AttributeError(name)

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libmpbp.so")
 
 MPBP_OK = 0
 STATUS_NAMES = {0: "MPBP_OK", 1: "MPBP_ERR_INVALID", 2: "MPBP_ERR_SHAPE", 3: "MPBP_ERR_FOOTPRINT",
-                4: "MPBP_ERR_DEVICE", 5: "MPBP_ERR_NOMEM", 6: "MPBP_ERR_UNSUPPORTED"}
+                4: "MPBP_ERR_DEVICE", 5: "MPBP_ERR_NOMEM", 6: "MPBP_ERR_UNSUPPORTED", 7: "MPBP_ERR_INTERNAL"}
 MPBP_OPT_PATH = 1
 MPBP_OPT_GRAPH = 2
 MPBP_OPT_XCD_ORDER = 3
@@ -27,7 +27,7 @@ STAGES = ("object", "frames", "grad", "finalize", "plain", "project")
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
             "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",
             "mpbp_get_option", "mpbp_stage_times", "mpbp_autotune", "mpbp_set_variant", "mpbp_tuning",
-            "mpbp_adam_step", "mpbp_norm2", "mpbp_last_error")
+            "mpbp_adam_step", "mpbp_norm2", "mpbp_unwrap_project", "mpbp_last_error")
 
 
 class mpbp_peak(ctypes.Structure):
@@ -90,6 +90,8 @@ def _load():
     lib.mpbp_adam_step.restype = st
     lib.mpbp_norm2.argtypes = [vp, vp, i64, vp, vp]
     lib.mpbp_norm2.restype = st
+    lib.mpbp_unwrap_project.argtypes = [vp, vp, vp, vp]
+    lib.mpbp_unwrap_project.restype = st
     lib.mpbp_last_error.argtypes = []
     lib.mpbp_last_error.restype = ctypes.c_char_p
     return lib
@@ -219,6 +221,17 @@ class Plan:
 
     def mpbp_norm2(self, a, out, n=None, stream=None):
         _check(lib.mpbp_norm2(self.handle, _ptr(a), int(a.numel() if n is None else n), _ptr(out), _stream(stream)))
+
+    def mpbp_unwrap_project(self, u, wraps=None, stream=None):
+        """Pi_U of eq. (10) in place on u (float32, the layout of mpbp_loss_grad); wraps:
+        optional int32 [n_peaks][nz or 1][ny][nx] receiving the 2 pi multiples added."""
+        lat = (1 if self.flags & MPBP_Z_TIED else self.nz) * self.ny * self.nx
+        if u.numel() != 3 * lat or u.element_size() != 4 or not u.is_contiguous():
+            raise ValueError(f"u must be a contiguous float32 tensor of {3 * lat} elements")
+        if wraps is not None and (wraps.numel() != self.n_peaks * lat or wraps.element_size() != 4
+                                  or not wraps.is_contiguous()):
+            raise ValueError(f"wraps must be a contiguous int32 tensor of {self.n_peaks * lat} elements")
+        _check(lib.mpbp_unwrap_project(self.handle, _ptr(u), _ptr(wraps), _stream(stream)))
 
     def mpbp_set_option(self, option, value):
         _check(lib.mpbp_set_option(self.handle, int(option), int(value)))

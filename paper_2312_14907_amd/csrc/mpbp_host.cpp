@@ -17,6 +17,7 @@
 #include "mpbp_kernels.hpp"
 #include "mpbp_launch.hpp"
 #include "mpbp_plain.hpp"
+#include "mpbp_unwrap.hpp"
 
 using mpbp::PeakDev;
 
@@ -135,6 +136,10 @@ struct mpbp_plan_t {
   size_t ev_used = 0;
   double stage_ms[MPBP_NUM_STAGES] = {0};
   int64_t stage_n[MPBP_NUM_STAGES] = {0};
+  // unwrap projector workspace (allocated by the first mpbp_unwrap_project call)
+  mpbp::UnwrapArgs uw{};
+  void* d_uw = nullptr;
+  int* h_uw_err = nullptr;         // pinned copy of the device consistency flag
   // captured full-batch calls (MPBP_OPT_GRAPH)
   std::vector<GraphEntry> graphs;
   uint64_t graph_clock = 0;
@@ -186,6 +191,8 @@ void free_device(mpbp_plan_t* p) {
   if (p->h_list) (void)hipHostFree(p->h_list);
   if (p->staged) (void)hipEventDestroy(p->staged);
   mpbp::plain_free(&p->plain);
+  (void)hipFree(p->d_uw);
+  if (p->h_uw_err) (void)hipHostFree(p->h_uw_err);
 }
 
 // Build tables and per-peak constants on the host; validate the problem.
@@ -826,6 +833,118 @@ void save_tuning(const mpbp_plan_t* p) {
   (void)std::rename(tmp.c_str(), path);
 }
 
+
+// ---- the unwrap projector (eqs. (9)-(10)) ----
+
+// Moore-Penrose inverse H^+ (M x 3) of H (3 x M, column m = G_m), in double:
+// H^+ = H^T (H H^T)^+, with the pseudo-inverse of the symmetric 3 x 3 matrix H H^T from
+// its eigen-decomposition by cyclic Jacobi rotations; eigenvalues below 1e-12 of the
+// largest count as zero (coplanar Bragg vectors: the component no peak sees is kept).
+void bragg_pinv(const std::vector<mpbp_peak>& pk, double hp[][3]) {
+  double A[3][3] = {{0}}, V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (const auto& p : pk)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) A[a][b] += p.g[a] * p.g[b];
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= 1e-32 * dia) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (A[p][q] == 0.0) continue;
+        // rotation in the (p, q) plane that zeroes A[p][q]
+        const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 3; ++k) {          // A <- A J
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {          // A <- J^T A
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; ++k) {          // V <- V J
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  double lmax = 0.0;
+  for (int k = 0; k < 3; ++k) lmax = std::max(lmax, std::fabs(A[k][k]));
+  double Ai[3][3] = {{0}};
+  for (int k = 0; k < 3; ++k) {
+    if (!(A[k][k] > 1e-12 * lmax)) continue;
+    const double il = 1.0 / A[k][k];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Ai[a][b] += il * V[a][k] * V[b][k];
+  }
+  for (size_t m = 0; m < pk.size(); ++m)
+    for (int c = 0; c < 3; ++c) {
+      double v = 0.0;
+      for (int a = 0; a < 3; ++a) v += pk[m].g[a] * Ai[a][c];
+      hp[m][c] = v;
+    }
+}
+
+// Allocate the projector's workspace on first use.
+mpbp_status ensure_unwrap(mpbp_plan_t* p) {
+  if (p->d_uw) return MPBP_OK;
+  mpbp::UnwrapArgs& A = p->uw;
+  A = mpbp::UnwrapArgs{};
+  A.M = p->M;
+  A.S = p->tied ? 1 : p->nz;
+  A.ny = p->ny;
+  A.nx = p->nx;
+  A.np = (long long)p->ny * p->nx;
+  A.nmaps = (long long)A.M * A.S;
+  A.npix = A.nmaps * A.np;
+  A.rounds = mpbp::unwrap_rounds(A.np);
+  if (2 * A.np >= (1LL << 31)) return fail(MPBP_ERR_SHAPE, "unwrap: ny * nx too large (%lld)", A.np);
+  double hp[kMaxPeaks][3];
+  bragg_pinv(p->peaks, hp);
+  for (int m = 0; m < A.M; ++m)
+    for (int c = 0; c < 3; ++c) {
+      A.g[m][c] = (float)p->peaks[m].g[c];
+      A.coef[m][c] = (float)(2.0 * M_PI * hp[m][c]);
+    }
+  // one allocation: 8-byte arrays first
+  const long long n = A.npix;
+  size_t bytes = 0;
+  auto take = [&](size_t b) { size_t o = bytes; bytes += (b + 255) & ~(size_t)255; return o; };
+  const size_t o_best = take(8 * n), o_sums = take(8 * A.nmaps), o_psi = take(4 * n), o_q = take(4 * n),
+               o_rel = take(4 * n), o_par = take(4 * n), o_pot = take(4 * n), o_hk = take(4 * n),
+               o_hpot = take(4 * n), o_hooks = take(4 * (size_t)A.rounds), o_err = take(4);
+  hipError_t e = hipMalloc(&p->d_uw, bytes);
+  if (e != hipSuccess) {
+    p->d_uw = nullptr;
+    return fail(MPBP_ERR_NOMEM, "unwrap workspace (%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  e = hipHostMalloc((void**)&p->h_uw_err, sizeof(int), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(p->d_uw);
+    p->d_uw = nullptr;
+    p->h_uw_err = nullptr;
+    return fail(MPBP_ERR_NOMEM, "unwrap status word: %s", hipGetErrorString(e));
+  }
+  char* b = (char*)p->d_uw;
+  A.best = (unsigned long long*)(b + o_best);
+  A.sums = (long long*)(b + o_sums);
+  A.psi = (float*)(b + o_psi);
+  A.q = (int*)(b + o_q);
+  A.rel = (float*)(b + o_rel);
+  A.par = (int*)(b + o_par);
+  A.pot = (int*)(b + o_pot);
+  A.hk = (int*)(b + o_hk);
+  A.hpot = (int*)(b + o_hpot);
+  A.hooks = (int*)(b + o_hooks);
+  A.err = (int*)(b + o_err);
+  return MPBP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1055,6 +1174,22 @@ mpbp_status mpbp_adam_step(mpbp_plan plan, const mpbp_adam* cfg, int64_t t, floa
     e = mpbp::launch_adam(lg ? alpha_log : alpha, lg ? alpha : nullptr, m + 4 * nf, v + 4 * nf, grad_alpha, plan->M,
                           cfg->lr[2], cfg->beta1, cfg->beta2, cfg->eps, c1, c2, lg, 1, cfg->fixed_alpha, s);
   if (e != hipSuccess) return hip_fail(e, "adam kernel");
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_unwrap_project(mpbp_plan plan, float* u, int32_t* wraps, void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!u) return fail(MPBP_ERR_INVALID, "u is required");
+  st = ensure_unwrap(plan);
+  if (st != MPBP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = mpbp::launch_unwrap(u, wraps, plan->uw, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(plan->h_uw_err, plan->uw.err, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "unwrap projector");
+  if (*plan->h_uw_err != 0)
+    return fail(MPBP_ERR_INTERNAL, "unwrap projector: merge consistency check %d failed", *plan->h_uw_err);
   return MPBP_OK;
 }
 

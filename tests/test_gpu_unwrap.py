@@ -1,0 +1,120 @@
+"""GPU parity of the unwrap projector Pi_U (eq. (10), section 3.3) against the oracle.
+
+The integer maps N (the multiples of 2 pi added to every phase G_m . u) must be
+bit-exact: both sides take every decision (wrap, reliability, edge order, edge wrap
+counts, global offset) in the same float32 steps and exact integers, and the maximum
+spanning tree of a total edge order is unique.  The projected field is compared to the
+oracle's literal eq. (10) in float64 to 2e-6 nm (the float32 rounding of the wrapped
+phase, ~1e-5 rad, over |G| ~ 31 rad/nm, plus float32 rounding of u).
+
+Cases: c1_tiny (per-slice maps, 8 slices) with a lattice-translation artefact and noise;
+ragged maps (37 x 45, 33 x 61); the z-tied parameterisation; a quantised field whose
+phases are multiples of pi/4 (many equal reliabilities, so the tie order decides the
+tree, and phase steps above pi, so the tree decides the result); a smooth field (left
+bitwise unchanged); two calls in a row on one plan; the full c5_full lateral grid
+(512 x 512, three peaks) in the z-tied parameterisation.
+"""
+import numpy as np
+import pytest
+
+from oracle import unwrap_oracle as U
+from synth import get_config, lattice_jump, make_problem, unwrap_field
+from synth.inputs import LATTICE_A_NM
+from tests.gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+B = pytest.importorskip("paper_2312_14907_amd.binding")
+
+ATOL_NM = 2e-6
+
+
+def _problem(name, ny=None, nx=None):
+    cfg = get_config(name)
+    if ny:
+        cfg["ny"], cfg["nx"] = ny, nx
+    return make_problem(cfg)
+
+
+def _gpu(plan, u):
+    du = dev(u)
+    wraps = torch.zeros((plan.n_peaks,) + tuple(u.shape[1:]), dtype=torch.int32, device="cuda:0")
+    plan.mpbp_unwrap_project(du, wraps)
+    torch.cuda.synchronize()
+    return host(du), host(wraps)
+
+
+def _check(plan, prob, u, what):
+    say(f"unwrap {what}: maps {prob.n_peaks} x {u.shape[1]} of {u.shape[2]} x {u.shape[3]}")
+    got_u, got_w = _gpu(plan, u)
+    ref_u, ref_w = U.unwrap_projector(u, prob.g, return_wraps=True)
+    np.testing.assert_array_equal(got_w, ref_w, err_msg=what)
+    np.testing.assert_allclose(got_u, ref_u, atol=ATOL_NM, rtol=0, err_msg=what)
+    return got_u, got_w
+
+
+def test_c1_slices_lattice_jump_and_noise():
+    prob = _problem("c1_tiny")
+    plan = B.Plan(prob, 0)
+    u = unwrap_field(prob.nz, prob.ny, prob.nx, seed=21, noise_nm=0.03)
+    u = lattice_jump(u, 4, 14, 6, 20, cells=1)
+    _, w = _check(plan, prob, u, "c1_tiny + jump + noise")
+    assert w.any()
+
+
+@pytest.mark.parametrize("ny, nx", [(37, 45), (33, 61)])
+def test_ragged_maps(ny, nx):
+    prob = _problem("c1_tiny", ny, nx)
+    plan = B.Plan(prob, 0)
+    u = unwrap_field(prob.nz, ny, nx, seed=ny + nx, noise_nm=0.05)
+    u = lattice_jump(u, 3, ny // 2, nx // 3, nx - 2, cells=2)
+    _check(plan, prob, u, f"ragged {ny} x {nx}")
+
+
+def test_z_tied():
+    prob = _problem("c1_tiny", 48, 40)
+    plan = B.Plan(prob, 0, flags=B.MPBP_Z_TIED)
+    u = unwrap_field(1, 48, 40, seed=23, noise_nm=0.04)
+    _check(plan, prob, lattice_jump(u, 10, 30, 5, 25, cells=1), "z-tied 48 x 40")
+
+
+def test_quantised_phases_tie_order_decides():
+    prob = _problem("c1_tiny")
+    plan = B.Plan(prob, 0)
+    rng = np.random.default_rng(24)
+    # a random 4 x 4 tile of the levels 0, 3, 6 (phases h k pi / 4) repeated over each
+    # slice: every reliability recurs many times, and steps of 6 pi / 4 wrap (residues)
+    k = np.zeros((prob.nz, prob.ny, prob.nx), dtype=np.int64)
+    ii, jj = np.meshgrid(np.arange(prob.ny), np.arange(prob.nx), indexing="ij")
+    for z in range(prob.nz):
+        tile = 3 * rng.integers(0, 3, (4, 4))
+        k[z] = tile[ii % 4, jj % 4]
+    u = np.zeros((3, prob.nz, prob.ny, prob.nx), dtype=np.float32)
+    u[0] = (k * (LATTICE_A_NM / 8.0)).astype(np.float32)
+    rel = U.reliability(U.wrap(U.phase_maps(u, prob.g))[0][0, 0])
+    assert len(np.unique(rel[1:-1, 1:-1])) <= 16            # ties everywhere
+    _check(plan, prob, u, "quantised phases")
+
+
+def test_smooth_field_unchanged_bitwise_and_repeat_calls():
+    prob = _problem("c1_tiny")
+    plan = B.Plan(prob, 0)
+    u = unwrap_field(prob.nz, prob.ny, prob.nx, seed=25)
+    got_u, got_w = _gpu(plan, u)
+    assert not got_w.any()
+    np.testing.assert_array_equal(got_u, u)
+    # the same plan again, on another field (workspace reused)
+    v = lattice_jump(unwrap_field(prob.nz, prob.ny, prob.nx, seed=26, noise_nm=0.02), 2, 9, 2, 30)
+    _check(plan, prob, v, "second call")
+
+
+def test_c5_lateral_grid_full_size():
+    prob = _problem("c5_full")
+    plan = B.Plan(prob, 0, flags=B.MPBP_Z_TIED)
+    u = unwrap_field(1, prob.ny, prob.nx, seed=27, noise_nm=0.03)
+    u = lattice_jump(u, 100, 300, 50, 260, cells=1)
+    _, w = _check(plan, prob, u, "c5_full lateral grid, z-tied")
+    assert (w != 0).mean() > 0.1

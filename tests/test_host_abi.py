@@ -166,3 +166,19 @@ def test_launch_parameter_api_on_host_plan():
     small = ctypes.create_string_buffer(8)
     assert B.lib.mpbp_tuning(plan.handle, small, 8, ctypes.byref(n)) == 1
     assert len(small.value) == 7
+
+
+def test_package_lazy_attributes():
+    # the package resolves its submodules on first attribute access (regression: the
+    # lookup once recursed into itself before the submodule was loaded)
+    import importlib
+    import paper_2312_14907_amd as P
+    P = importlib.reload(P)
+    assert P.Plan is B.Plan and P.binding is B and P.MPBPError is B.MPBPError
+
+
+def test_unwrap_needs_a_device_plan():
+    plan = B.Plan(make_problem(get_config("c1_tiny")), device=-1)
+    with pytest.raises(B.MPBPError) as e:
+        B._check(B.lib.mpbp_unwrap_project(plan.handle, None, None, None))
+    assert e.value.status == 4
