@@ -161,6 +161,50 @@ def cpu_baseline(prob, f, y_dev, n_frames):
     return n_frames / dt, dt
 
 
+def unwrap_inputs(prob, nz):
+    """Seeded displacement field on the workload's grid for the unwrap projector: a
+    smooth strain field with noise and one lattice-translation artefact on a patch."""
+    from synth import lattice_jump, unwrap_field
+    u = unwrap_field(nz, prob.ny, prob.nx, seed=5, noise_nm=0.03)
+    return lattice_jump(u, prob.ny // 5, 3 * prob.ny // 5, prob.nx // 10, prob.nx // 2)
+
+
+def time_unwrap(prob, torch, calls):
+    """ms per mpbp_unwrap_project call on the workload's lateral grid, z-tied (one map per
+    peak, the paper's 2D unwrapping) and per slice (one map per peak and slice)."""
+    from paper_2312_14907_amd.binding import MPBP_Z_TIED, Plan
+    out = {}
+    for name, flags, nz in (("tied", MPBP_Z_TIED, 1), ("slices", 0, prob.nz)):
+        plan = Plan(prob, 0, flags=flags)
+        u0 = torch.from_numpy(unwrap_inputs(prob, nz)).to("cuda:0")
+        u = u0.clone()
+        plan.mpbp_unwrap_project(u)            # workspace allocation, warm-up
+        ts = []
+        for _ in range(calls):
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.mpbp_unwrap_project(u)        # synchronous
+            ts.append(time.perf_counter() - t0)
+        ms = 1e3 * sorted(ts)[len(ts) // 2]
+        px = prob.n_peaks * nz * prob.ny * prob.nx
+        out[name] = {"maps": prob.n_peaks * nz, "map": [prob.ny, prob.nx], "ms_per_call": round(ms, 3),
+                     "map_pixels_per_s": round(px / ms * 1e3, 1)}
+        plan.close()
+    return out
+
+
+def cpu_unwrap(prob):
+    """The unwrap oracle on the z-tied maps of the workload (one per peak), seconds."""
+    from threadpoolctl import threadpool_limits
+    from oracle import unwrap_oracle as U
+    u = unwrap_inputs(prob, 1)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        U.unwrap_projector(u, prob.g)
+        return time.perf_counter() - t0
+
+
 def run_loop(args, torch):
     """Full-batch descent on u from u = 0 (chi and alpha at the truth) with an Armijo
     line search; the loss curve and the time per iteration, beside the oracle's time per
@@ -320,6 +364,9 @@ def main():
                         "speedup_fused_vs_plain": round((nfr / pdt and value / (nfr / pdt)), 2),
                         "loss_rel_diff": abs(ploss - loss) / abs(loss)}
 
+    # the unwrap projector of eq. (10), the last step of Algorithm 1 (not part of `value`)
+    out["unwrap"] = time_unwrap(prob, torch, 10)
+
     if not args.no_cpu_baseline:
         n = args.cpu_frames or (1024 if prob.n_frames() >= 1024 else prob.n_frames())
         rate, cdt = cpu_baseline(prob, f, args_t[4], n)
@@ -328,6 +375,9 @@ def main():
             "sample": f"FP64 oracle loss+gradient over the first {n} frames (a minibatch of "
                       f"{args.workload}), including its whole-volume object build and chain "
                       f"rule: {cdt:.1f} s"}
+        usec = cpu_unwrap(prob)
+        out["cpu_baseline"]["unwrap_tied_s_per_call"] = round(usec, 3)
+        out["unwrap"]["tied"]["speedup_vs_oracle"] = round(usec / (out["unwrap"]["tied"]["ms_per_call"] / 1e3), 1)
     print(json.dumps(out), flush=True)
 
 

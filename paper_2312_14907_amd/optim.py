@@ -5,9 +5,11 @@ Adam update, eq. (8) exponentials, sums of squares, gradient steps) runs in the
 library's kernels; the loops choose frames and step sizes.  Device buffers are torch
 CUDA tensors.
 
-  adam_reconstruct      Algorithm 1 without its phase-unwrap projection: shuffled
-                        minibatches, minibatch gradients (eq. (11)), Adam on u and the
-                        log variables chi~ = log chi, alpha~ = log alpha (eq. (8)).
+  adam_reconstruct      Algorithm 1: shuffled minibatches, minibatch gradients
+                        (eq. (11)), Adam on u and the log variables chi~ = log chi,
+                        alpha~ = log alpha (eq. (8)), and with unwrap=True the
+                        phase-unwrap projection Pi_U of eq. (10) after every update
+                        (without it: the concurrent-wrapped variant).
   line_search_descent   full-batch gradient descent on u with a backtracking (Armijo)
                         step-size search.
 """
@@ -19,7 +21,7 @@ import torch
 
 
 def adam_reconstruct(plan, probe, y, u, chi_log, alpha_log, order, batch=50, iterations=None,
-                     lr=(0.01, 0.1, 0.1), fixed_alpha=0, beta1=0.9, beta2=0.999, eps=1e-8):
+                     lr=(0.01, 0.1, 0.1), fixed_alpha=0, beta1=0.9, beta2=0.999, eps=1e-8, unwrap=False):
     """Run `iterations` minibatch iterations (default: one pass over `order`).
 
     u, chi_log, alpha_log: device float32 tensors updated in place (u in the layout of
@@ -44,6 +46,8 @@ def adam_reconstruct(plan, probe, y, u, chi_log, alpha_log, order, batch=50, ite
         frames = order[start:start + batch]
         plan.mpbp_loss_grad(u, chi, alpha, probe, y, gu, gc, ga, frames=frames, loss=hist[it:it + 1])
         plan.mpbp_adam_step(cfg, it + 1, u, chi, alpha, chi_log, alpha_log, state, gu, gc, ga)
+        if unwrap:
+            plan.mpbp_unwrap_project(u)
     torch.cuda.synchronize(dev)
     return chi, alpha, hist[:n_iter].cpu().numpy()
 

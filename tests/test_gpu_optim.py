@@ -2,9 +2,9 @@
 
 * mpbp_adam_step against the oracle's Adam update and eq. (8) chain rule, elementwise,
   over several steps, in both parameterisations and with a fixed reference alpha;
-* Algorithm 1 (without its unwrap projection) on c1_tiny with the same shuffled frame
-  order on both sides: per-iteration minibatch losses, and the oracle's objective at
-  the two final fields;
+* Algorithm 1 on c1_tiny with the same shuffled frame order on both sides, without and
+  with its unwrap projection (eq. (10)): per-iteration minibatch losses, the oracle's
+  objective at the two final fields, and the removal of a lattice-translation artefact;
 * the Armijo line-search loop on c1_tiny: losses and accepted steps of the first
   iterations, and a monotone decrease.
 Adam scales every step to the learning rate, so a gradient element whose sign is
@@ -16,7 +16,7 @@ import pytest
 
 from oracle import mpbp_oracle as O
 from synth import get_config, make_fields, make_problem
-from synth.inputs import frame_order
+from synth.inputs import LATTICE_A_NM as LATTICE, frame_order
 from tests.conftest import ragged
 from tests.gpu_util import dev, host, say
 
@@ -119,6 +119,31 @@ def test_algorithm1_c1_matches_oracle(c1):
     f_start = O.loss(u0, chi0, np.exp(al0), f["probe"], y, prob)[0]
     assert f_gpu == pytest.approx(f_ora, rel=1e-3)
     assert f_gpu < f_start
+
+
+def test_algorithm1_with_unwrap_c1_matches_oracle(c1):
+    # Algorithm 1 with its last step, the unwrap projection Pi_U of eq. (10), starting
+    # from a field with a lattice-translation artefact on a patch
+    from synth import lattice_jump
+    cfg, prob, f, y = c1
+    say("Algorithm 1 with the unwrap projection, c1_tiny")
+    plan = B.Plan(prob, 0)
+    order = frame_order(prob.n_frames(), cfg["seed"], epochs=3)
+    u0 = lattice_jump((f["u"] + f["delta"]).astype(np.float32), 6, 20, 4, 18, cells=1)
+    chi0 = np.maximum(f["chi"], 1e-3).astype(np.float32)
+    cl0 = np.log(chi0).astype(np.float32)
+    al0 = (np.log(f["alpha"]) + 0.1).astype(np.float32)
+    lr, batch, iters = (0.002, 0.02, 0.02), 25, 6
+    du, dcl, dal = dev(u0), dev(cl0), dev(al0)
+    _, _, losses = optim.adam_reconstruct(plan, dev(f["probe"]), dev(y), du, dcl, dal, order, batch=batch,
+                                          iterations=iters, lr=lr, fixed_alpha=0, unwrap=True)
+    ou, ocl, oal, olosses = O.adam_reconstruct(u0, cl0, al0, f["probe"], y, prob, order, batch, iters, lr=lr,
+                                               fixed_alpha=0, unwrap=True)
+    np.testing.assert_allclose(losses, olosses, rtol=1e-3)
+    # the projection removed the artefact: the field is back near the smooth one
+    smooth = (f["u"] + f["delta"]).astype(np.float64)
+    assert np.abs(host(du) - smooth).max() < 0.1 * LATTICE
+    assert np.abs(ou - smooth).max() < 0.1 * LATTICE
 
 
 def test_line_search_c1_matches_oracle(c1):
