@@ -440,7 +440,12 @@ hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t 
   return hipGetLastError();
 }
 
-int project_lds_bytes(int np, int G) { return G * (np + 1) * (np + 1) * (int)sizeof(cplx) + G * 4; }
+// the footprint accumulator: up to kProjPix * kFrameThreads pixels (the plan checks fy * fx)
+int project_lds_bytes(int np, int G) {
+  (void)np;
+  (void)G;
+  return kProjPix * kFrameThreads * (int)sizeof(cplx);
+}
 
 static const int kDets[] = {32, 64, 96, 128, 192, 256};
 

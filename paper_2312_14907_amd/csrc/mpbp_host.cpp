@@ -917,7 +917,7 @@ mpbp_status ensure_unwrap(mpbp_plan_t* p) {
   auto take = [&](size_t b) { size_t o = bytes; bytes += (b + 255) & ~(size_t)255; return o; };
   const size_t o_best = take(8 * n), o_sums = take(8 * A.nmaps), o_psi = take(4 * n), o_q = take(4 * n),
                o_rel = take(4 * n), o_par = take(4 * n), o_pot = take(4 * n), o_hk = take(4 * n),
-               o_hpot = take(4 * n), o_hooks = take(4 * (size_t)A.rounds), o_err = take(4);
+               o_hpot = take(4 * n), o_hooks = take(4 * 64 * (size_t)A.rounds), o_err = take(4);
   hipError_t e = hipMalloc(&p->d_uw, bytes);
   if (e != hipSuccess) {
     p->d_uw = nullptr;

@@ -21,8 +21,8 @@ hipError_t launch_object(const float* u, const float* chi, const float* alpha, c
 // frames; frame_bound(D, largest footprint side) is the smallest such FB).  Reads each
 // frame's exit wave from its slot (written by launch_project).
 hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s);
-// Exit waves of the listed frames into their slots, G object slices staged per step
-// (G = 2, 4 or 8); lds_bytes from project_lds_bytes.
+// Exit waves of the listed frames into their slots, with G object slices in flight per
+// lane (G = 2, 4 or 8); lds_bytes from project_lds_bytes.
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
 int project_lds_bytes(int np, int G);
 int frame_bound(int D, int footprint);

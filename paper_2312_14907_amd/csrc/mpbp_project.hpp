@@ -11,7 +11,14 @@
 
 namespace mpbp {
 
-// G: object slices staged per step (the slab depth).
+// G: object slices in flight per lane (loads issued G slices ahead of their use).
+//
+// eq. (2) R diag(P) S O on the footprint: psi[q] = sum_z (P O_z)[q - s(z) + min s].
+// Consecutive slices with equal shear offset (runs, uniform) are summed in registers;
+// at the end of a run each lane adds its probe pixels of the run's sum into the
+// footprint accumulator in LDS at the run's offset.  Within one run every footprint
+// pixel receives at most one value, so no two lanes collide; a barrier separates runs,
+// which keeps the order of every sum fixed.
 template <int G>
 __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
   constexpr int NT = kFrameThreads;
@@ -24,135 +31,86 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
   cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
   const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * A.ny * A.nx;
-  // The illuminated slices W_z = P * O[z, window], summed over runs of slices with equal
-  // shear offset within each group of G slices, are staged in LDS; each lane then
-  // gathers its footprint pixels
-  //   psi[q] += W_z[q + min shear - s(z)]   (zero outside the probe support).
-  // A staged slice is (np + 1) x (np + 1) with a zero last row and column: offsets
-  // outside the support are clamped onto them, so the gather has no tests or branches.
-  {
-    const int np1 = np + 1;
-    const int sw = np1 * np1;
-    const int np2 = np * np;
-    cplx* Wb = sm;
-    const int* shz = A.shear + 2 * m * nz;   // uniform: scalar loads
-    for (int k = tid; k < G * (2 * np + 1); k += NT) {
-      const int g = k / (2 * np + 1), e = k - g * (2 * np + 1);
-      Wb[g * sw + (e <= np ? np * np1 + e : (e - np - 1) * np1 + np)] = {0.f, 0.f};
-    }
-    cplx pv[kProjE];
-    int off[kProjE], wo[kProjE];
+  const int* shz = A.shear + 2 * m * nz;   // uniform: scalar loads
+  const int np2 = np * np;
+  cplx* acc = sm;                          // [fy][fx] footprint accumulator
+  for (int p = tid; p < fy * fx; p += NT) acc[p] = {0.f, 0.f};
+
+  // lane's probe pixels e = tid + NT i: probe value (0 off the object), object offset,
+  // and footprint offset at zero shear
+  cplx pv[kProjE];
+  unsigned off[kProjE];   // byte offset in a slice: a 32-bit lane offset from a uniform base
+  int fo[kProjE];
+#pragma unroll
+  for (int i = 0; i < kProjE; ++i) {
+    const int e = tid + NT * i;
+    const int a = e / np, b = e - (e / np) * np;
+    const int oy = py + a, ox = px + b;
+    const bool ok = e < np2 && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
+    pv[i] = ok ? probe[e < np2 ? e : 0] : cplx{0.f, 0.f};
+    off[i] = ok ? (unsigned)(oy * A.nx + ox) * (unsigned)sizeof(cplx) : 0u;
+    fo[i] = a * fx + b;
+  }
+  // Object reads: a uniform slice base plus the lane's 32-bit byte offset.  The slice
+  // index passes through readfirstlane, which hides the affine recurrence from the
+  // compiler's strength reduction; otherwise it keeps one 64-bit pointer per load live
+  // across the loop and spills them.
+  const long long plane = (long long)A.ny * A.nx;
+  auto load = [&](cplx (&o)[kProjE], int z) {
+    const int zz = __builtin_amdgcn_readfirstlane(z < nz ? z : nz - 1);
+    const char* Oz = reinterpret_cast<const char*>(O + (long long)zz * plane);
+#pragma unroll
+    for (int i = 0; i < kProjE; ++i) o[i] = *reinterpret_cast<const cplx*>(Oz + off[i]);
+  };
+  // footprint offset of slice z's pixel (0, 0): (s_y - min s_y) fx + (s_x - min s_x)
+  auto shift = [&](int z) { return (shz[2 * z] - pk.miny) * fx + (shz[2 * z + 1] - pk.minx); };
+  cplx w[kProjE];
+  auto flush = [&](int d) {
+    __syncthreads();   // zeroing, or the previous run's additions, are complete
 #pragma unroll
     for (int i = 0; i < kProjE; ++i) {
-      const int e = tid + NT * i;
-      const int a = e / np, b = e - (e / np) * np;
-      const int oy = py + a, ox = px + b;
-      const bool ok = e < np2 && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
-      pv[i] = ok ? probe[e < np2 ? e : 0] : cplx{0.f, 0.f};
-      off[i] = ok ? oy * A.nx + ox : 0;
-      wo[i] = e < np2 ? a * np1 + b : -1;
-    }
-    const long long plane = (long long)A.ny * A.nx;
-    // Object values of two groups of G slices are in flight: group k + 2 is requested
-    // while group k is used (the loads are L2 round trips that one group's work does
-    // not cover).
-    auto load_group = [&](cplx (&on)[G][kProjE], int z0) {
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int z = z0 + g < nz ? z0 + g : nz - 1;
-        const cplx* Oz = O + (long long)z * plane;
-#pragma unroll
-        for (int i = 0; i < kProjE; ++i) on[g][i] = Oz[off[i]];
+      if ((i + 1) * NT <= np2 || tid + NT * i < np2) {   // uniform when every lane has a pixel
+        cplx* q = acc + fo[i] + d;
+        *q = cadd(*q, w[i]);
       }
-    };
-    cplx onA[G][kProjE], onB[G][kProjE];
-    load_group(onA, 0);
-    load_group(onB, G);
-    // Footprint pixel q = (qy, qx) of slice z reads staged element (qy + min s_y -
-    // s_y(z), qx + min s_x - s_x(z)), each coordinate clamped to np (the zero border).
-    // Both coordinates travel as one pair of 16-bit lanes: one packed subtract, one
-    // packed clamp and one dot product (row * (np + 1) * 8 + column * 8 + slot base)
-    // give the byte address of the element.
-    u16x2 pq[kProjPix];
-    cplx acc[kProjPix];
-#pragma unroll
-    for (int h = 0; h < kProjPix; ++h) {
-      const int p = tid + NT * h;
-      const int qy = p / fx;
-      pq[h] = u16x2{(unsigned short)(p - qy * fx + pk.minx), (unsigned short)(qy + pk.miny)};
-      acc[h] = {0.f, 0.f};
     }
-    const u16x2 lim = {(unsigned short)np, (unsigned short)np};
-    const u16x2 wts = {(unsigned short)sizeof(cplx), (unsigned short)(np1 * sizeof(cplx))};
-    const unsigned wb_lds = (unsigned)(size_t)(const lds_cplx*)Wb;   // LDS byte address of slot 0
-    u16x2* slot_shift = reinterpret_cast<u16x2*>(Wb + G * sw);      // shear of each staged slot
-    auto stage = [&](const cplx (&w)[kProjE], int sl) {
+  };
+  cplx buf[G][kProjE];
 #pragma unroll
-      for (int i = 0; i < kProjE; ++i) {
-        if ((i + 1) * NT <= np2)   // uniform: every lane holds a probe pixel
-          Wb[sl * sw + wo[i]] = w[i];
-        else if (wo[i] >= 0)
-          Wb[sl * sw + wo[i]] = w[i];
-      }
-    };
-    // One group: slices with equal shear offset (runs, uniform) are summed in registers
-    // and staged once, then every footprint pixel gathers from the staged slots.
-    auto step = [&](cplx (&on)[G][kProjE], int z0) {
-      __syncthreads();   // the previous group's gather is done with the slots
-      int nsl = 0;
-      int cy = shz[2 * z0], cx = shz[2 * z0 + 1];
-      cplx w[kProjE];
+  for (int g = 0; g < G; ++g) load(buf[g], g);
+  int cur = shift(0);
 #pragma unroll
-      for (int i = 0; i < kProjE; ++i) w[i] = cmul(pv[i], on[0][i]);
+  for (int i = 0; i < kProjE; ++i) w[i] = {0.f, 0.f};
+  for (int z0 = 0; z0 < nz; z0 += G) {
 #pragma unroll
-      for (int g = 1; g < G; ++g) {
-        const int z = z0 + g;
-        if (z < nz) {   // uniform
-          const int sy = shz[2 * z], sx = shz[2 * z + 1];
-          if (sy != cy || sx != cx) {   // uniform: a new run
-            stage(w, nsl);
-            if (tid == 0) slot_shift[nsl] = u16x2{(unsigned short)cx, (unsigned short)cy};
-            ++nsl;
-            cy = sy;
-            cx = sx;
+    for (int g = 0; g < G; ++g) {
+      const int z = z0 + g;
+      if (z < nz) {   // uniform
+        cplx v[kProjE];
 #pragma unroll
-            for (int i = 0; i < kProjE; ++i) w[i] = cmul(pv[i], on[g][i]);
-          } else {
+        for (int i = 0; i < kProjE; ++i) v[i] = cmul(pv[i], buf[g][i]);
+        if (z + G < nz) load(buf[g], z + G);
+        const int d = shift(z);
+        if (d != cur) {   // uniform: a new run
+          flush(cur);
+          cur = d;
 #pragma unroll
-            for (int i = 0; i < kProjE; ++i) w[i] = cadd(w[i], cmul(pv[i], on[g][i]));
-          }
+          for (int i = 0; i < kProjE; ++i) w[i] = v[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < kProjE; ++i) w[i] = cadd(w[i], v[i]);
         }
       }
-      stage(w, nsl);
-      if (tid == 0) slot_shift[nsl] = u16x2{(unsigned short)cx, (unsigned short)cy};
-      ++nsl;
-      load_group(on, z0 + 2 * G);
-      __syncthreads();
-      for (int k = 0; k < nsl; ++k) {   // uniform trip count
-        const u16x2 sh = slot_shift[k];
-        const unsigned base = wb_lds + (unsigned)(k * sw * sizeof(cplx));
-#pragma unroll
-        for (int h = 0; h < kProjPix; ++h) {
-          const u16x2 d = __builtin_elementwise_min(pq[h] - sh, lim);
-          const lds_cplx* q = (const lds_cplx*)(size_t)__builtin_amdgcn_udot2(d, wts, base, false);
-          acc[h] = cadd(acc[h], cplx{q->x, q->y});
-        }
-      }
-    };
-    for (int z0 = 0; z0 < nz; z0 += 2 * G) {
-      step(onA, z0);
-      if (z0 + G < nz) step(onB, z0 + G);   // uniform
     }
-#pragma unroll
-    for (int h = 0; h < kProjPix; ++h)
-      if (tid + NT * h < fy * fx) slot[tid + NT * h] = acc[h];
   }
-
+  flush(cur);
+  __syncthreads();
+  for (int p = tid; p < fy * fx; p += NT) slot[p] = acc[p];
 }
 
-// Occupancy target: the shallower the slab, the less LDS and the fewer registers, the
-// more workgroups per CU.
-template <int G> struct ProjectWaves { static constexpr int value = G <= 2 ? 5 : G <= 4 ? 4 : 2; };
+// Occupancy target: the fewer slices in flight, the fewer registers, the more
+// workgroups per CU.
+template <int G> struct ProjectWaves { static constexpr int value = G <= 2 ? 8 : G <= 4 ? 6 : 4; };
 
 template <int G>
 __global__ __launch_bounds__(kFrameThreads) __attribute__((amdgpu_waves_per_eu(ProjectWaves<G>::value)))

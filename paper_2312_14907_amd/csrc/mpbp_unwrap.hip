@@ -32,6 +32,22 @@ namespace {
 
 constexpr float kTwoPi = 6.28318530717958647692f;
 constexpr int kUwThreads = 256;
+constexpr int kHookSlots = 64;     // per-round "a root hooked" flags, one per block mod 64
+
+// True if round r hooked anything (any of its flag slots set).
+__device__ __forceinline__ bool round_hooked(const int* hooks, int r) {
+  const int* h = hooks + r * kHookSlots;
+  int any = 0;
+#pragma unroll 8
+  for (int k = 0; k < kHookSlots; ++k) any |= h[k];
+  return any != 0;
+}
+
+// atomicMax, skipped when the slot already holds a key at least as large (keys only
+// grow during a launch, so a stale read can only cause an unneeded atomic)
+__device__ __forceinline__ void offer(unsigned long long* slot, unsigned long long k) {
+  if (*(volatile unsigned long long*)slot < k) atomicMax(slot, k);
+}
 
 // MurmurHash3's 32-bit finalizer and its inverse (every step is a bijection): the
 // tie-break of equal edge keys.
@@ -95,7 +111,7 @@ __device__ __forceinline__ void edge_ends(uint32_t e, int ny, int nx, int* p, in
 // ---- phases, wrap, and the union-find state of every map pixel ----
 __global__ __launch_bounds__(kUwThreads) void k_uw_wrap(const float* __restrict__ u, UnwrapArgs A) {
   const long long t = (long long)blockIdx.x * kUwThreads + threadIdx.x;
-  if (t < A.rounds) A.hooks[t] = 0;
+  if (t < (long long)A.rounds * kHookSlots) A.hooks[t] = 0;
   if (t < A.nmaps) A.sums[t] = 0;
   if (t == 0) *A.err = 0;
   const long long lat = (long long)A.S * A.np;   // pixels of one component of u
@@ -143,7 +159,7 @@ __global__ __launch_bounds__(kUwThreads) void k_uw_reliability(UnwrapArgs A) {
 
 // ---- Boruvka round r: every root collects its best outgoing edge ----
 __global__ __launch_bounds__(kUwThreads) void k_uw_best(UnwrapArgs A, int r) {
-  if (r > 0 && A.hooks[r - 1] == 0) return;
+  if (r > 0 && !round_hooked(A.hooks, r - 1)) return;
   const long long x = (long long)blockIdx.x * kUwThreads + threadIdx.x;
   if (x >= A.npix) return;
   const long long g = x / A.np;
@@ -157,8 +173,8 @@ __global__ __launch_bounds__(kUwThreads) void k_uw_best(UnwrapArgs A, int r) {
     if (ry != rx) {
       const uint32_t e = (uint32_t)row * (uint32_t)(A.nx - 1) + (uint32_t)col;
       const unsigned long long k = edge_key(relx + A.rel[x + 1], e);
-      atomicMax(A.best + base + rx, k);
-      atomicMax(A.best + base + ry, k);
+      offer(A.best + base + rx, k);
+      offer(A.best + base + ry, k);
     }
   }
   if (row < A.ny - 1) {
@@ -166,8 +182,8 @@ __global__ __launch_bounds__(kUwThreads) void k_uw_best(UnwrapArgs A, int r) {
     if (ry != rx) {
       const uint32_t e = (uint32_t)A.ny * (uint32_t)(A.nx - 1) + (uint32_t)i;
       const unsigned long long k = edge_key(relx + A.rel[x + A.nx], e);
-      atomicMax(A.best + base + rx, k);
-      atomicMax(A.best + base + ry, k);
+      offer(A.best + base + rx, k);
+      offer(A.best + base + ry, k);
     }
   }
 }
@@ -176,7 +192,7 @@ __global__ __launch_bounds__(kUwThreads) void k_uw_best(UnwrapArgs A, int r) {
 // Two roots that chose the same edge would hook onto each other; the smaller index stays
 // a root.  With a total edge order no other cycle can form.
 __global__ __launch_bounds__(kUwThreads) void k_uw_hook(UnwrapArgs A, int r) {
-  if (r > 0 && A.hooks[r - 1] == 0) return;
+  if (r > 0 && !round_hooked(A.hooks, r - 1)) return;
   const long long x = (long long)blockIdx.x * kUwThreads + threadIdx.x;
   bool hooked = false;
   if (x < A.npix) {
@@ -208,15 +224,13 @@ __global__ __launch_bounds__(kUwThreads) void k_uw_hook(UnwrapArgs A, int r) {
       }
     }
   }
-  // one counter update per wavefront
-  const unsigned long long ballot = __ballot(hooked);
-  if (ballot && (threadIdx.x & 63) == (__ffsll((long long)ballot) - 1))
-    atomicAdd(A.hooks + r, (int)__popcll(ballot));
+  // one flag store per block that hooked, spread over the round's slots
+  if (__syncthreads_or(hooked) && threadIdx.x == 0) A.hooks[r * kHookSlots + (blockIdx.x & (kHookSlots - 1))] = 1;
 }
 
 // ---- Boruvka round r: every pixel walks to its new root, summing the offsets ----
 __global__ __launch_bounds__(kUwThreads) void k_uw_walk(UnwrapArgs A, int r) {
-  if (A.hooks[r] == 0) return;
+  if (!round_hooked(A.hooks, r)) return;
   const long long x = (long long)blockIdx.x * kUwThreads + threadIdx.x;
   if (x >= A.npix) return;
   const long long base = (x / A.np) * A.np;
@@ -307,7 +321,7 @@ int unwrap_rounds(long long np) {
 
 hipError_t launch_unwrap(float* u, int* wraps, const UnwrapArgs& A, hipStream_t s) {
   const long long lat = (long long)A.S * A.np;
-  long long nw = lat > A.rounds ? lat : A.rounds;
+  long long nw = lat > (long long)A.rounds * kHookSlots ? lat : (long long)A.rounds * kHookSlots;
   nw = nw > A.nmaps ? nw : A.nmaps;
   k_uw_wrap<<<blocks_for(nw), kUwThreads, 0, s>>>(u, A);
   k_uw_reliability<<<blocks_for(A.npix), kUwThreads, 0, s>>>(A);

@@ -24,7 +24,7 @@ struct UnwrapArgs {
   int* hk;                     // root hooked onto this round (itself if none)
   int* hpot;                   // wrap count of a hooked root relative to its new parent
   unsigned long long* best;    // best outgoing edge key of a root this round (0: none)
-  int* hooks;                  // [rounds] hooks made per round
+  int* hooks;                  // [rounds][64] flags: a root hooked in this round
   long long* sums;             // [nmaps] sum of (q - pot)
   int* err;                    // 0, or a failed consistency check
 };
