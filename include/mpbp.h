@@ -226,8 +226,8 @@ mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value);
 mpbp_status mpbp_stage_times(mpbp_plan plan, double* ms, int64_t* counts);
 
 /* Autotuner.  Times every compiled launch variant of the per-frame kernel for each
-   detector-size class of the plan (footprint bound, projection slab depth = object
-   slices staged per step, XCD-aware frame order) and of the back-projection kernel
+   detector-size class of the plan (footprint bound, projection depth = object slices
+   each lane of the projection kernel has in flight, XCD-aware frame order) and of the back-projection kernel
    (frames read per step, tile shape), on the caller's inputs (layouts as in mpbp_loss_grad; y is
    required), and keeps the fastest for later calls.  Every variant computes the same
    result.  Synchronous: waits for `stream`.  Allocates and frees a gradient scratch
@@ -241,7 +241,8 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi,
 
 /* Select a frame-kernel variant by hand for size class `size_class` (the order of
    the "classes" list of mpbp_tuning): compiled footprint bound (>= the class's
-   smallest, see mpbp_tuning "key"), slab depth (2, 4 or 8) and XCD order (0 or 1).
+   smallest, see mpbp_tuning "key"), projection depth `slab` (object slices in flight per
+   lane: 2, 4 or 8) and XCD order (0 or 1).
    MPBP_ERR_UNSUPPORTED if that variant is not compiled or does not fit in LDS. */
 mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound, int slab,
                              int xcd_order);

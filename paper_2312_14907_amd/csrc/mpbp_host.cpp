@@ -82,11 +82,11 @@ struct mpbp_plan_t {
   std::vector<int32_t> peak_of;  // [F]
   std::vector<int32_t> order;    // processing order of the full batch
   // Frames of one detector size D and smallest footprint bound `key`, with the launch
-  // parameters in use (compiled footprint bound FB >= key, slab depth G, XCD order).
+  // parameters in use (compiled footprint bound FB >= key, projection depth G, XCD order).
   struct SizeClass {
     int D, key, begin, count;
     int fy, fx;                        // largest footprint over the class's peaks
-    int FB, G, xcd;                    // G: slab depth of the projection kernel
+    int FB, G, xcd;                    // G: object slices in flight per lane of the projection
     int lds_fwd, lds_grad;             // dynamic LDS of the frame kernel
     double tuned_us;                   // autotuned launch time (0: not tuned)
   };
@@ -98,7 +98,7 @@ struct mpbp_plan_t {
   std::string tune_source = "default";
   std::string tune_report;             // candidates timed by the last mpbp_autotune
   int lds_fwd = 0, lds_grad_frame = 0, lds_grad = 0;
-  int lds_project[9] = {0};        // projection kernel, per slab depth
+  int lds_project[9] = {0};        // projection kernel, per projection depth
   int maxspan_y = 0, maxspan_x = 0;
   int max_cand = 0;
   // gradient tile grids, per compiled tile width: origin (<= 0) and tile counts
@@ -1327,7 +1327,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
   e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->tied, plan->d_obj, s);
   std::string rep = "[";
   char buf[160];
-  // The projection and the frame kernel are separate launches: the slab depth G is
+  // The projection and the frame kernel are separate launches: the projection depth G is
   // tuned on the projection alone, then the footprint bound FB on projection (at its
   // best G) plus frame kernel, for each XCD order.  Every candidate is timed in two
   // rounds and keeps its faster round (the first launches of a run are slowed by the
@@ -1428,7 +1428,7 @@ mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound
   auto& c = plan->classes[size_class];
   if (xcd_order != 0 && xcd_order != 1) return fail(MPBP_ERR_INVALID, "xcd_order must be 0 or 1");
   if (!variant_ok(plan, c, footprint_bound, slab))
-    return fail(MPBP_ERR_UNSUPPORTED, "no compiled frame kernel for D=%d with footprint bound %d >= %d and slab %d",
+    return fail(MPBP_ERR_UNSUPPORTED, "no compiled frame kernel for D=%d with footprint bound %d >= %d and projection depth %d",
                 c.D, footprint_bound, c.key, slab);
   c.FB = footprint_bound;
   c.G = slab;

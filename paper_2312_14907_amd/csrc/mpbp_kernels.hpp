@@ -68,9 +68,9 @@ struct GradArgs {
 };
 
 constexpr int kFrameThreads = 256;
-constexpr int kSlabDepths[] = {2, 4, 8};   // compiled projection slab depths (slices staged per step)
+constexpr int kSlabDepths[] = {2, 4, 8};   // compiled projection depths (object slices in flight per lane)
 constexpr int kDefaultSlab = 4;
-constexpr int kProjE = 4;     // probe pixels staged per lane (probe_n^2 <= 4 * 256)
+constexpr int kProjE = 4;     // probe pixels per lane in the projection (probe_n^2 <= 4 * 256)
 constexpr int kProjPix = 8;   // footprint pixels per lane (fy * fx <= 8 * 256)
 constexpr int kGradTile = 64, kGradTZ = 8;              // 64 voxels of a slice x 8 slice groups
 constexpr int kGradThreads = kGradTile * kGradTZ;        // 512 threads

@@ -1,13 +1,13 @@
 """Launch variants and the autotuner.
 
-Every compiled variant of the frame kernel (footprint bound, projection slab depth,
+Every compiled variant of the frame kernel (footprint bound, projection depth,
 XCD-aware order) and of the back-projection kernel (frames per step) computes the same
 result as the default launch parameters, which the oracle parity tests cover.  The XCD
 order and the frame batch leave every operation as it is, so those results are bitwise
-equal.  The slab depth changes which slices of equal shear are summed before staging, a
-larger footprint bound only adds exact zeros, and in another instance the compiler may
-contract products into FMAs in another order, so those results agree to rounding: 1e-5
-of each output's largest magnitude.  The autotuner picks the fastest projection slab
+equal.  The projection depth (object slices in flight) and a larger footprint bound
+keep every sum (the bound only adds exact zeros), but in another instance the compiler
+may contract products into FMAs in another order, so those results agree to rounding:
+1e-5 of each output's largest magnitude.  The autotuner picks the fastest projection
 depth, then the fastest footprint bound and XCD order, leaves the results unchanged, and
 its cache file restores the choice in a new plan.
 """
@@ -122,7 +122,7 @@ def test_autotune_and_cache(c4, tmp_path):
         t = plan.mpbp_tuning()
         assert t["source"] == "autotune"
         for k, c in enumerate(t["classes"]):
-            # slab depth: the fastest projection for the chosen XCD order
+            # projection depth: the fastest projection for the chosen XCD order
             proj = [x for x in t["candidates"] if x.get("class") == k and x.get("kernel") == "project"]
             assert sorted((x["G"], x["xcd"]) for x in proj) == [(g, x) for g in (2, 4, 8) for x in (0, 1)]
             at_x = [x for x in proj if x["xcd"] == c["xcd"]]
