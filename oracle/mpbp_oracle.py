@@ -11,7 +11,8 @@ fields with multi-peak Bragg ptychography"):
 
 * eq. (1) and eq. (3): the per-peak object O_m = alpha_m * chi * exp(i G_m . u), with
   G_m in rad/nm (the paper's 2*pi folded into G) and alpha given for every peak;
-* eq. (2): intensity I_{m,j} = |F R_m diag(P_m) S_{m,j} O_m|^2 with background b = 0.
+* eq. (2): intensity I_{m,j} = |F R_m diag(P_m) S_{m,j} O_m|^2 + b_{m,j}, the background
+  b given per frame and detector pixel in the layout of y (None: b = 0).
   S_{m,j} selects the probe window of scan position j (section 4: raster scan), the
   probe is constant along the incident beam x3 (section 4), and R_m projects the
   illuminated slices along the exit beam: slice z lands s_m(z) pixels over, an integer
@@ -194,13 +195,17 @@ def far_field_adjoint(g):
     return np.fft.ifft2(g, norm="ortho")
 
 
-def amplitude_residual(psi_ff, y):
+def amplitude_residual(psi_ff, y, b=None):
     """Per-frame term of eq. (4) and its gradient with respect to the far field.
 
-    Returns (f_frame, R) with f_frame = 1/2 sum (|Psi| - sqrt(y))^2 and
-    R = (|Psi| - sqrt(y)) * Psi / |Psi| (0 where |Psi| = 0).
+    With the model intensity I = |Psi|^2 + b of eq. (2) (b = 0 when None), returns
+    (f_frame, R) with f_frame = 1/2 sum (sqrt(I) - sqrt(y))^2 and
+    R = (sqrt(I) - sqrt(y)) * Psi / sqrt(I) (0 where I = 0).
     """
-    a = np.abs(psi_ff)
+    if b is None:
+        a = np.abs(psi_ff)
+    else:
+        a = np.sqrt(np.abs(psi_ff) ** 2 + np.asarray(b, dtype=np.float64))
     r = a - np.sqrt(np.asarray(y, dtype=np.float64))
     f = 0.5 * float(np.sum(r * r))
     safe = np.where(a > 0.0, a, 1.0)
@@ -233,8 +238,8 @@ def frame_data(y, tab, problem, fid):
     return np.asarray(y[start:start + det * det], dtype=np.float64).reshape(det, det)
 
 
-def model_intensity(u, chi, alpha, probe, problem, frames=None):
-    """I_{m,j} of eq. (2) (b = 0) for the listed frames: list of D x D float64 arrays."""
+def model_intensity(u, chi, alpha, probe, problem, frames=None, background=None):
+    """I_{m,j} of eq. (2) for the listed frames: list of D x D float64 arrays."""
     tab = tables(problem)
     obj = objects(u, chi, alpha, problem)
     probe = np.asarray(probe, dtype=np.complex128)
@@ -243,11 +248,14 @@ def model_intensity(u, chi, alpha, probe, problem, frames=None):
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
         psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]))
-        out.append(np.abs(far_field(psi)) ** 2)
+        inten = np.abs(far_field(psi)) ** 2
+        if background is not None:
+            inten = inten + frame_data(background, tab, problem, fid)
+        out.append(inten)
     return out
 
 
-def loss(u, chi, alpha, probe, y, problem, frames=None):
+def loss(u, chi, alpha, probe, y, problem, frames=None, background=None):
     """f of eq. (4) over the listed frames (all when None).
 
     Returns (f, per_frame) with per_frame the list of per-frame terms.
@@ -260,12 +268,13 @@ def loss(u, chi, alpha, probe, y, problem, frames=None):
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
         psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]))
-        f, _ = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid))
+        b = None if background is None else frame_data(background, tab, problem, fid)
+        f, _ = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid), b)
         per.append(f)
     return float(sum(per)), per
 
 
-def object_gradient(u, chi, alpha, probe, y, problem, frames=None):
+def object_gradient(u, chi, alpha, probe, y, problem, frames=None, background=None):
     """f and g_O,m = df/dO_m (complex, [M][nz][ny][nx]) summed over the listed frames."""
     tab = tables(problem)
     obj = objects(u, chi, alpha, problem)
@@ -277,13 +286,14 @@ def object_gradient(u, chi, alpha, probe, y, problem, frames=None):
         py, px = (int(v) for v in tab["scan"][fid])
         det = int(problem.det[m])
         psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], det)
-        f, grad_ff = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid))
+        b = None if background is None else frame_data(background, tab, problem, fid)
+        f, grad_ff = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid), b)
         per.append(f)
         back_project(far_field_adjoint(grad_ff), probe[m], py, px, tab["shear"][m], g_obj[m])
     return float(sum(per)), per, g_obj, obj
 
 
-def loss_grad(u, chi, alpha, probe, y, problem, frames=None):
+def loss_grad(u, chi, alpha, probe, y, problem, frames=None, background=None):
     """f and its gradient with respect to u, chi and alpha.
 
     Chain rule through O_m = alpha_m chi exp(i phi_m), phi_m = G_m . u:
@@ -293,7 +303,7 @@ def loss_grad(u, chi, alpha, probe, y, problem, frames=None):
       df/dalpha_m = sum_voxels Re(conj(g_O,m) * chi * exp(i phi_m))
     Returns dict(loss, frame_loss, grad_u [3][nz][ny][nx], grad_chi, grad_alpha [M]).
     """
-    f, per, g_obj, obj = object_gradient(u, chi, alpha, probe, y, problem, frames)
+    f, per, g_obj, obj = object_gradient(u, chi, alpha, probe, y, problem, frames, background)
     u = np.asarray(u, dtype=np.float64)
     chi = np.asarray(chi, dtype=np.float64)
     grad_u = np.zeros(u.shape)
@@ -315,14 +325,14 @@ def loss_grad(u, chi, alpha, probe, y, problem, frames=None):
     }
 
 
-def loss_grad_ztied(u2, chi2, alpha, probe, y, problem, frames=None):
+def loss_grad_ztied(u2, chi2, alpha, probe, y, problem, frames=None, background=None):
     """The membrane parameterisation of section 3 (unknowns per lateral pixel, constant
     along x3): u2 [3][1][ny][nx], chi2 [1][ny][nx] broadcast over z; gradients are the
     z-sums of the per-voxel gradients."""
     nz = problem.nz
     u = np.broadcast_to(np.asarray(u2, dtype=np.float64), (3, nz) + tuple(np.shape(u2)[2:]))
     chi = np.broadcast_to(np.asarray(chi2, dtype=np.float64), (nz,) + tuple(np.shape(chi2)[1:]))
-    r = loss_grad(u, chi, alpha, probe, y, problem, frames)
+    r = loss_grad(u, chi, alpha, probe, y, problem, frames, background)
     r["grad_u"] = r["grad_u"].sum(axis=1, keepdims=True)
     r["grad_chi"] = r["grad_chi"].sum(axis=0, keepdims=True)
     return r

@@ -534,3 +534,64 @@ def test_line_search_descent_invariants():
     assert len(etas) == len(losses) == 8
     assert all(b < a for a, b in zip(losses, losses[1:]))
     assert O.loss(out, chi, alpha, probe, y, prob)[0] < losses[-1]
+
+
+# ---------------------------------------------------------- background (eq. (2)) ---
+
+def _background(prob, seed, scale):
+    rng = np.random.default_rng(seed)
+    n = sum(int(prob.det[m]) ** 2 * int(prob.scan_n[m].prod()) for m in range(prob.n_peaks))
+    return rng.uniform(0.0, scale, n)
+
+
+def test_background_zero_is_no_background():
+    prob = tiny_problem()
+    u, chi, alpha, probe = random_fields(prob, seed=61)
+    rng = np.random.default_rng(62)
+    y = ragged(O.model_intensity(u + rng.normal(0, 0.05, size=u.shape), chi, alpha, probe, prob))
+    a = O.loss_grad(u, chi, alpha, probe, y, prob)
+    b = O.loss_grad(u, chi, alpha, probe, y, prob, background=np.zeros_like(y))
+    for k in ("loss", "grad_u", "grad_chi", "grad_alpha"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_background_closed_form_without_object():
+    # chi = 0: the exit wave vanishes, I = b, f = 1/2 sum (sqrt(b) - sqrt(y))^2 and every
+    # gradient is 0 (the residual's direction Psi / sqrt(I) is 0)
+    prob = tiny_problem()
+    u, chi, alpha, probe = random_fields(prob, seed=63)
+    bg = _background(prob, 64, 3.0)
+    y = np.random.default_rng(65).uniform(0.0, 5.0, bg.size)
+    r = O.loss_grad(u, np.zeros_like(chi), alpha, probe, y, prob, background=bg)
+    assert r["loss"] == pytest.approx(0.5 * np.sum((np.sqrt(bg) - np.sqrt(y)) ** 2), rel=1e-12)
+    assert not r["grad_u"].any() and not r["grad_chi"].any()
+    inten = O.model_intensity(u, np.zeros_like(chi), alpha, probe, prob, background=bg)
+    np.testing.assert_array_equal(np.concatenate([i.ravel() for i in inten]), bg)
+
+
+def test_background_zero_loss_at_truth_and_central_differences():
+    prob = tiny_problem()
+    u, chi, alpha, probe = random_fields(prob, seed=66)
+    rng = np.random.default_rng(67)
+    bg = _background(prob, 68, 2.0)
+    y0 = ragged(O.model_intensity(u, chi, alpha, probe, prob, background=bg))
+    r0 = O.loss_grad(u, chi, alpha, probe, y0, prob, background=bg)
+    assert r0["loss"] < 1e-20 and np.abs(r0["grad_u"]).max() < 1e-9
+    y = ragged(O.model_intensity(u + rng.normal(0, 0.05, size=u.shape), chi * 0.9, alpha, probe, prob,
+                                 background=bg))
+    r = O.loss_grad(u, chi, alpha, probe, y, prob, background=bg)
+    f = lambda uu, cc: O.loss(uu, cc, alpha, probe, y, prob, background=bg)[0]
+    scale_u, scale_c = np.abs(r["grad_u"]).max(), np.abs(r["grad_chi"]).max()
+    for _ in range(8):
+        c = int(rng.integers(3))
+        idx = tuple(int(rng.integers(s)) for s in u.shape[1:])
+        up, um = u.copy(), u.copy()
+        up[(c,) + idx] += 1e-6
+        um[(c,) + idx] -= 1e-6
+        assert (f(up, chi) - f(um, chi)) / 2e-6 == pytest.approx(r["grad_u"][(c,) + idx], abs=1e-6 * scale_u)
+    for _ in range(6):
+        idx = tuple(int(rng.integers(s)) for s in chi.shape)
+        cp, cm = chi.copy(), chi.copy()
+        cp[idx] += 1e-6
+        cm[idx] -= 1e-6
+        assert (f(u, cp) - f(u, cm)) / 2e-6 == pytest.approx(r["grad_chi"][idx], abs=1e-6 * scale_c)
