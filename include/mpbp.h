@@ -254,6 +254,16 @@ mpbp_status mpbp_set_variant(mpbp_plan plan, int size_class, int footprint_bound
    *len (may be NULL); MPBP_ERR_INVALID if cap is too small for the text. */
 mpbp_status mpbp_tuning(mpbp_plan plan, char* buf, int64_t cap, int64_t* len);
 
+/* The background b of eq. (2): the model intensity becomes
+     I_{m,j} = | F R_m diag(P_m) S_{m,j} O_m |^2 + b_{m,j}
+   in mpbp_forward (model_intensity, loss) and mpbp_loss_grad (eq. (4) compares sqrt(I)
+   with sqrt(y); the gradient is (sqrt(I) - sqrt(y)) Psi / sqrt(I) on the far field).
+     b  (dev) float, ragged in the layout of y, b >= 0; NULL (the default) = no background.
+   The plan keeps the pointer (not a copy): the caller keeps the buffer alive and
+   unchanged in size while it is set; its contents may change between calls.  Both paths
+   and the autotuner use it; captured graphs are keyed by it. */
+mpbp_status mpbp_set_background(mpbp_plan plan, const float* b);
+
 /* The phase-unwrap projector Pi_U of eq. (10) (section 3.3; the last step of every
    iteration of Algorithm 1), applied in place:
      u <- W^{-1}{W{u . H}} . H^T (H H^T)^{-1},

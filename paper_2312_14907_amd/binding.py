@@ -27,7 +27,8 @@ STAGES = ("object", "frames", "grad", "finalize", "plain", "project")
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
             "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",
             "mpbp_get_option", "mpbp_stage_times", "mpbp_autotune", "mpbp_set_variant", "mpbp_tuning",
-            "mpbp_adam_step", "mpbp_norm2", "mpbp_unwrap_project", "mpbp_last_error")
+            "mpbp_adam_step", "mpbp_norm2", "mpbp_set_background", "mpbp_unwrap_project",
+            "mpbp_last_error")
 
 
 class mpbp_peak(ctypes.Structure):
@@ -90,6 +91,8 @@ def _load():
     lib.mpbp_adam_step.restype = st
     lib.mpbp_norm2.argtypes = [vp, vp, i64, vp, vp]
     lib.mpbp_norm2.restype = st
+    lib.mpbp_set_background.argtypes = [vp, vp]
+    lib.mpbp_set_background.restype = st
     lib.mpbp_unwrap_project.argtypes = [vp, vp, vp, vp]
     lib.mpbp_unwrap_project.restype = st
     lib.mpbp_last_error.argtypes = []
@@ -221,6 +224,14 @@ class Plan:
 
     def mpbp_norm2(self, a, out, n=None, stream=None):
         _check(lib.mpbp_norm2(self.handle, _ptr(a), int(a.numel() if n is None else n), _ptr(out), _stream(stream)))
+
+    def mpbp_set_background(self, b):
+        """Background b of eq. (2) (device float, ragged like y) for later calls; None clears
+        it.  The plan keeps a reference to the tensor while it is set."""
+        if b is not None and (b.numel() != self.intensity_size or b.element_size() != 4 or not b.is_contiguous()):
+            raise ValueError(f"b must be a contiguous float32 tensor of {self.intensity_size} elements")
+        _check(lib.mpbp_set_background(self.handle, _ptr(b)))
+        self._background = b
 
     def mpbp_unwrap_project(self, u, wraps=None, stream=None):
         """Pi_U of eq. (10) in place on u (float32, the layout of mpbp_loss_grad); wraps:

@@ -35,7 +35,8 @@ __device__ __forceinline__ int frame_block_index(int b, int n, int xcd) {
 // the same ramp, which the inverse transform undoes.  With the footprint at the origin,
 // only the first ceil(FB / Q) inputs of each lane are nonzero and only those outputs are
 // needed, so the compiler drops the rest of the first and last DFT stages.
-template <int D, int FB>
+// BG: the model intensity carries the background b of eq. (2) (A.bg, ragged like y).
+template <int D, int FB, bool BG>
 __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
   using RC = LineCfg<D>;
   constexpr int RP = RC::P, RQ = RC::Q, RT = RC::TPL;
@@ -95,6 +96,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   const bool has_y = A.y != nullptr;
   const float* yf = has_y ? A.y + pk.y_off + (long long)j * D * D : nullptr;
   float* mif = A.mi ? A.mi + pk.y_off + (long long)j * D * D : nullptr;
+  const float* bgf = BG ? A.bg + pk.y_off + (long long)j * D * D : nullptr;
   const float invD = 1.0f / (float)D;
   const float invD2 = invD * invD;
   double lsum = 0.0;
@@ -102,11 +104,18 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   // Intensities are prefetched one row-iteration ahead (across chunk boundaries) so the
   // HBM latency overlaps the transforms of the current rows.
   const int rline = tid / RT, rt = tid % RT;
-  float ynext[RQ];
+  float ynext[RQ], bnext[BG ? RQ : 1];
   if (has_y && rowp(rt)) {
     const float* yr = yf + (long long)(R * rline) * D;
 #pragma unroll
     for (int d = 0; d < RQ; ++d) ynext[d] = __builtin_nontemporal_load(yr + rt + RP * d);
+  }
+  if constexpr (BG) {
+    if (rowp(rt)) {
+      const float* br = bgf + (long long)(R * rline) * D;
+#pragma unroll
+      for (int d = 0; d < RQ; ++d) bnext[d] = __builtin_nontemporal_load(br + rt + RP * d);
+    }
   }
 
   for (int r = 0; r < R; ++r) {
@@ -162,9 +171,13 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
       for (int k0 = 0; k0 < L; k0 += RLINES) {
         const int kp = k0 + line;
         const int k = R * kp + r;
-        float yv[RQ];
+        float yv[RQ], bv[BG ? RQ : 1];
 #pragma unroll
         for (int d = 0; d < RQ; ++d) yv[d] = ynext[d];
+        if constexpr (BG) {
+#pragma unroll
+          for (int d = 0; d < RQ; ++d) bv[d] = bnext[d];
+        }
         {
           const int nk0 = k0 + RLINES < L ? k0 + RLINES : 0;
           const int nr = k0 + RLINES < L ? r : r + 1;
@@ -172,6 +185,13 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
             const float* yr = yf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
             for (int d = 0; d < RQ; ++d) ynext[d] = __builtin_nontemporal_load(yr + t + RP * d);
+          }
+          if constexpr (BG) {
+            if (rowp(t) && nr < R) {
+              const float* br = bgf + (long long)(R * (nk0 + line) + nr) * D;
+#pragma unroll
+              for (int d = 0; d < RQ; ++d) bnext[d] = __builtin_nontemporal_load(br + t + RP * d);
+            }
           }
         }
         cplx v[RV];
@@ -211,23 +231,34 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           DFT<RQ, false>::run(v);
           if (mif) {
 #pragma unroll
-            for (int d = 0; d < RQ; ++d)
-              mif[(long long)k * D + t + RP * d] = fmaf(v[d].x, v[d].x, v[d].y * v[d].y) * invD2;
+            for (int d = 0; d < RQ; ++d) {
+              const float i2 = fmaf(v[d].x, v[d].x, v[d].y * v[d].y) * invD2;
+              mif[(long long)k * D + t + RP * d] = BG ? i2 + bv[BG ? d : 0] : i2;
+            }
           }
           if (has_y) {
             float rowl = 0.f;
 #pragma unroll
             for (int d = 0; d < RQ; ++d) {
-              // X = D Psi.  r = |Psi| - sqrt(y); gradient r X / |X|.  The reciprocal
-              // square root is taken of |X|^2 + FLT_MIN: finite where X = 0 (there the
-              // modulus and the gradient come out exactly 0), absorbed for |X|^2 above
-              // about 1e-31.
               const cplx X = v[d];
               const float s2 = fmaf(X.x, X.x, X.y * X.y);
-              const float rinv = __builtin_amdgcn_rsqf(s2 + 1.17549435e-38f);
-              const float res = fmaf(s2 * rinv, invD, -__builtin_amdgcn_sqrtf(yv[d]));
-              rowl = fmaf(res, res, rowl);
-              v[d] = cscale(X, res * rinv);
+              if constexpr (BG) {
+                // I = |Psi|^2 + b; r = sqrt(I) - sqrt(y); gradient r Psi / sqrt(I), Psi = X / D.
+                const float I = fmaf(s2, invD2, bv[BG ? d : 0]);
+                const float ri = __builtin_amdgcn_rsqf(I + 1.17549435e-38f);
+                const float res = fmaf(I, ri, -__builtin_amdgcn_sqrtf(yv[d]));
+                rowl = fmaf(res, res, rowl);
+                v[d] = cscale(X, res * ri * invD);
+              } else {
+                // X = D Psi.  r = |Psi| - sqrt(y); gradient r X / |X|.  The reciprocal
+                // square root is taken of |X|^2 + FLT_MIN: finite where X = 0 (there the
+                // modulus and the gradient come out exactly 0), absorbed for |X|^2 above
+                // about 1e-31.
+                const float rinv = __builtin_amdgcn_rsqf(s2 + 1.17549435e-38f);
+                const float res = fmaf(s2 * rinv, invD, -__builtin_amdgcn_sqrtf(yv[d]));
+                rowl = fmaf(res, res, rowl);
+                v[d] = cscale(X, res * rinv);
+              }
             }
             lsum += 0.5 * (double)rowl;
           }
@@ -337,28 +368,36 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
 
 // One instance per detector size D and footprint bound FB; the frames of a size class
 // form one launch.
-template <int D, int FB>
+template <int D, int FB, bool BG>
 __global__ __launch_bounds__(kFrameThreads) void k_frames(FrameArgs A) {
   extern __shared__ cplx smem[];
   const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
   if (idx >= A.n_list) return;
   const int fid = A.list[idx];
   const PeakDev pk = A.peaks[A.peak_of[fid]];
-  frame_body<D, FB>(A, pk, fid, smem);
+  frame_body<D, FB, BG>(A, pk, fid, smem);
 }
 
-// Launch / prepare one instance.  op 0: launch over a.n_list frames; op 1: allow the
-// instance the full LDS of a CU on the current device; op 2: report that the instance
-// exists (hipSuccess).
+// Launch / prepare one instance (with and without background).  op 0: launch over
+// a.n_list frames (the background variant when a.bg is set); op 1: allow both variants
+// the full LDS of a CU on the current device; op 2: report that the instance exists.
 template <int D, int FB>
 hipError_t frame_instance_op(int op, const FrameArgs* a, int lds_bytes, hipStream_t s) {
-  if (op == 1)
-    return hipFuncSetAttribute((const void*)k_frames<D, FB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               160 * 1024);
+  if (op == 1) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_frames<D, FB, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_frames<D, FB, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    return e;
+  }
   if (op == 2) return hipSuccess;
   const unsigned grid = a->xcd ? (unsigned)(((a->n_list + 7) / 8) * 8) : (unsigned)a->n_list;
   if (grid == 0) return hipSuccess;
-  k_frames<D, FB><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(*a);
+  if (a->bg)
+    k_frames<D, FB, true><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(*a);
+  else
+    k_frames<D, FB, false><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(*a);
   return hipGetLastError();
 }
 

@@ -124,6 +124,7 @@ struct mpbp_plan_t {
   double* d_apart = nullptr;
   double* d_red = nullptr;         // sum-of-squares partials (kRedParts)
   float* d_tw = nullptr;           // twiddle tables of all peaks
+  const float* d_bg = nullptr;     // caller's background b of eq. (2) (mpbp_set_background)
   std::vector<float> tw;
   int* h_list = nullptr;           // pinned staging of the caller's list
   hipEvent_t staged = nullptr;
@@ -559,6 +560,7 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   mpbp::FrameArgs a{};
   a.obj = p->d_obj;
   a.y = y;
+  a.bg = p->d_bg;
   a.list = list;
   a.n_list = n;
   a.scan = p->d_scan;
@@ -1019,6 +1021,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
   hipError_t e;
   if (plan->path == 1) {
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
+    plan->plain.bg = plan->d_bg;
     e = mpbp::plain_forward(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                             plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                             frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
@@ -1028,7 +1031,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
     GraphKey key;
     key.kind = 0;
     key.xcd = plan->xcd;
-    const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, model_intensity};
+    const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, model_intensity, plan->d_bg};
     std::copy(std::begin(ptrs), std::end(ptrs), key.ptr);
     return run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
       hipError_t le = enqueue_forward(plan, u, chi, alpha, (const float*)probe, y, list, n, false,
@@ -1074,6 +1077,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
   const double* apart = plan->d_apart;
   if (plan->path == 1) {
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
+    plan->plain.bg = plan->d_bg;
     e = mpbp::plain_loss_grad(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                               plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                               frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
@@ -1083,7 +1087,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     GraphKey key;
     key.kind = 1;
     key.xcd = plan->xcd;
-    const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, grad_u, grad_chi, grad_alpha};
+    const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, grad_u, grad_chi, grad_alpha, plan->d_bg};
     std::copy(std::begin(ptrs), std::end(ptrs), key.ptr);
     return run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
       hipError_t le = enqueue_loss_grad(plan, u, chi, alpha, (const float*)probe, y, list, n, false,
@@ -1199,6 +1203,12 @@ mpbp_status mpbp_norm2(mpbp_plan plan, const float* a, int64_t n, double* out, v
   if (!a || !out || n < 0) return fail(MPBP_ERR_INVALID, "a and out are required and n >= 0");
   hipError_t e = mpbp::launch_norm2(a, n, plan->d_red, kRedParts, out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "norm kernel");
+  return MPBP_OK;
+}
+
+mpbp_status mpbp_set_background(mpbp_plan plan, const float* b) {
+  if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
+  plan->d_bg = b;   // graphs are keyed by it
   return MPBP_OK;
 }
 

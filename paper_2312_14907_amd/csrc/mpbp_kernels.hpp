@@ -31,6 +31,7 @@ struct FrameArgs {
   const float* obj;        // complex64 [M][nz][ny][nx] (interleaved)
   const float* probe;      // complex64 [M][np][np]
   const float* y;          // ragged intensities (may be null)
+  const float* bg;         // background b of eq. (2), ragged like y (may be null)
   const int* list;         // global frame ids to process
   int n_list;
   const int* scan;         // [F][2] (py, px)

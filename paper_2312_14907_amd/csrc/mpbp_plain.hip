@@ -83,7 +83,8 @@ __global__ __launch_bounds__(256) void k_pl_fft(float* __restrict__ buf, int D, 
 
 // Modulus residual of eq. (4) on one frame, in place; per-row loss partials.
 __global__ __launch_bounds__(256) void k_pl_residual(float* __restrict__ psi,
-                                                     const float* __restrict__ y, int D,
+                                                     const float* __restrict__ y,
+                                                     const float* __restrict__ bg, int D,
                                                      double* __restrict__ lpart,
                                                      float* __restrict__ mi, int grad) {
   __shared__ double red[256];
@@ -92,7 +93,8 @@ __global__ __launch_bounds__(256) void k_pl_residual(float* __restrict__ psi,
   double s = 0.0;
   for (int c = tid; c < D; c += blockDim.x) {
     cplx* X = reinterpret_cast<cplx*>(psi) + (long long)row * D + c;
-    const float a2 = (X->x * X->x + X->y * X->y) * invD * invD;
+    float a2 = (X->x * X->x + X->y * X->y) * invD * invD;   // model intensity of eq. (2)
+    if (bg) a2 += bg[(long long)row * D + c];
     if (mi) mi[(long long)row * D + c] = a2;
     if (y) {
       const float A = sqrtf(a2);
@@ -262,7 +264,8 @@ static hipError_t plain_frames(PlainWork* w, const PeakDev* hp, const PeakDev* d
     k_pl_project<<<dim3((D * D + 255) / 256), dim3(256), 0, s>>>(obj, probe, dshear, dp, m, py, px, nz, ny, nx, np, w->psi);
     k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, D, 1, 0);
     k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, 1, D, 0);
-    k_pl_residual<<<dim3(D), dim3(256), 0, s>>>(w->psi, y ? y + yo : nullptr, D, w->lpart, mi ? mi + yo : nullptr, grad ? 1 : 0);
+    k_pl_residual<<<dim3(D), dim3(256), 0, s>>>(w->psi, y ? y + yo : nullptr, w->bg ? w->bg + yo : nullptr, D,
+                                                 w->lpart, mi ? mi + yo : nullptr, grad ? 1 : 0);
     if (y) k_pl_sum<<<dim3(1), dim3(64), 0, s>>>(w->lpart, D, floss + fid);
     if (grad) {
       k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, D, 1, 1);

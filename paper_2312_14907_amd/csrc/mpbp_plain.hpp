@@ -18,6 +18,7 @@ struct PlainWork {
   long long gobj_len = 0;
   long long apart_len = 0;
   int dmax = 0;
+  const float* bg = nullptr;   // background b of eq. (2), ragged like y (set by the plan)
 };
 
 void plain_free(PlainWork* w);
