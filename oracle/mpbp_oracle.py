@@ -11,7 +11,8 @@ fields with multi-peak Bragg ptychography"):
 
 * eq. (1) and eq. (3): the per-peak object O_m = alpha_m * chi * exp(i G_m . u), with
   G_m in rad/nm (the paper's 2*pi folded into G) and alpha given for every peak;
-* eq. (2): intensity I_{m,j} = |F R_m diag(P_m) S_{m,j} O_m|^2 + b_{m,j}, the background
+* eq. (2): intensity I_{m,j} = |F R_m diag(P_m) S_{m,j} O_m|^2 + b_{m,j}; P_m is the probe,
+  [M][Np][Np] constant along x3 or a 3D illumination volume [M][nz][Np][Np]; the background
   b given per frame and detector pixel in the layout of y (None: b = 0).
   S_{m,j} selects the probe window of scan position j (section 4: raster scan), the
   probe is constant along the incident beam x3 (section 4), and R_m projects the
@@ -145,14 +146,21 @@ def _support_block(p0, n, size):
     return a0, max(a0, a1)
 
 
+def _probe_slice(probe_m, z):
+    """The probe of slice z: probe_m is [n][n] (constant along x3) or [nz][n][n] (a 3D
+    illumination volume, section 2)."""
+    return probe_m[z] if probe_m.ndim == 3 else probe_m
+
+
 def exit_wave(o_m, probe_m, py, px, shear_m, det):
     """R diag(P) S O for one frame: the D x D exit wave.
 
     For every slice z and probe pixel (a, b) with an in-grid object voxel,
-      psi[a + c + s_y(z), b + c + s_x(z)] += P[a, b] * O[z, py + a, px + b].
+      psi[a + c + s_y(z), b + c + s_x(z)] += P_z[a, b] * O[z, py + a, px + b]
+    (P_z = P for a probe constant along x3).
     """
     nz, ny, nx = o_m.shape
-    n = probe_m.shape[0]
+    n = probe_m.shape[-1]
     c = window_offset(det, n)
     psi = np.zeros((det, det), dtype=np.complex128)
     a0, a1 = _support_block(py, n, ny)
@@ -162,25 +170,25 @@ def exit_wave(o_m, probe_m, py, px, shear_m, det):
     for z in range(nz):
         sy, sx = int(shear_m[z, 0]), int(shear_m[z, 1])
         psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1] += (
-            probe_m[a0:a1, b0:b1] * o_m[z, py + a0:py + a1, px + b0:px + b1])
+            _probe_slice(probe_m, z)[a0:a1, b0:b1] * o_m[z, py + a0:py + a1, px + b0:px + b1])
     return psi
 
 
 def back_project(g_psi, probe_m, py, px, shear_m, g_o_m):
     """Adjoint of exit_wave, accumulated into g_o_m in place:
-      g_O[z, py + a, px + b] += conj(P[a, b]) * g_psi[a + c + s_y(z), b + c + s_x(z)].
+      g_O[z, py + a, px + b] += conj(P_z[a, b]) * g_psi[a + c + s_y(z), b + c + s_x(z)].
     """
     nz, ny, nx = g_o_m.shape
-    n = probe_m.shape[0]
+    n = probe_m.shape[-1]
     det = g_psi.shape[0]
     c = window_offset(det, n)
     a0, a1 = _support_block(py, n, ny)
     b0, b1 = _support_block(px, n, nx)
     if a1 <= a0 or b1 <= b0:
         return
-    pc = np.conj(probe_m[a0:a1, b0:b1])
     for z in range(nz):
         sy, sx = int(shear_m[z, 0]), int(shear_m[z, 1])
+        pc = np.conj(_probe_slice(probe_m, z)[a0:a1, b0:b1])
         g_o_m[z, py + a0:py + a1, px + b0:px + b1] += (
             pc * g_psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1])
 

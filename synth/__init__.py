@@ -18,6 +18,7 @@ from .inputs import (
     crop_problem,
     unwrap_field,
     lattice_jump,
+    incident_probe_3d,
 )
 
 __all__ = [

@@ -268,3 +268,23 @@ def lattice_jump(u, y0, y1, x0, x1, cells=1):
     v = np.array(u, dtype=np.float32, copy=True)
     v[0, ..., y0:y1, x0:x1] += np.float32(cells * LATTICE_A_NM)
     return v
+
+
+def incident_probe_3d(probe2d, nz, t_in):
+    """3D illumination volume [nz][n][n] from a 2D beam profile: the profile is carried
+    unchanged along an inclined incident beam, so the support of slice z is the 2D
+    profile shifted laterally by round((z - nz // 2) * t_in) pixels (t_in = (t_y, t_x),
+    the incident beam's lateral offset per slice).  Pixels shifted out of the n x n
+    window are dropped (section 4 builds its 3D probes this way from a measured profile)."""
+    p = np.asarray(probe2d)
+    n = p.shape[-1]
+    out = np.zeros((nz, n, n), dtype=p.dtype)
+    for z in range(nz):
+        dy = int(np.floor((z - nz // 2) * float(t_in[0]) + 0.5))
+        dx = int(np.floor((z - nz // 2) * float(t_in[1]) + 0.5))
+        ys, yd = (0, dy) if dy >= 0 else (-dy, 0)
+        xs, xd = (0, dx) if dx >= 0 else (-dx, 0)
+        h, w = n - abs(dy), n - abs(dx)
+        if h > 0 and w > 0:
+            out[z, yd:yd + h, xd:xd + w] = p[ys:ys + h, xs:xs + w]
+    return out

@@ -595,3 +595,81 @@ def test_background_zero_loss_at_truth_and_central_differences():
         cp[idx] += 1e-6
         cm[idx] -= 1e-6
         assert (f(u, cp) - f(u, cm)) / 2e-6 == pytest.approx(r["grad_chi"][idx], abs=1e-6 * scale_c)
+
+
+# -------------------------------------------------- 3D illumination (section 2) ---
+
+def _exit_wave_bruteforce_3d(o_m, probe3, py, px, shear_m, det):
+    nz, ny, nx = o_m.shape
+    n = probe3.shape[-1]
+    c = (det - n) // 2
+    psi = np.zeros((det, det), dtype=np.complex128)
+    for z in range(nz):
+        for a in range(n):
+            for b in range(n):
+                yy, xx = py + a, px + b
+                if 0 <= yy < ny and 0 <= xx < nx:
+                    psi[a + c + shear_m[z, 0], b + c + shear_m[z, 1]] += probe3[z, a, b] * o_m[z, yy, xx]
+    return psi
+
+
+def _probe3(prob, seed):
+    rng = np.random.default_rng(seed)
+    s = (prob.n_peaks, prob.nz, prob.probe_n, prob.probe_n)
+    return rng.normal(size=s) + 1j * rng.normal(size=s)
+
+
+def test_3d_probe_projection_bruteforce_and_adjoint():
+    prob = tiny_problem()
+    tab = O.tables(prob)
+    u, chi, alpha, _ = random_fields(prob, seed=81)
+    p3 = _probe3(prob, 82)
+    obj = O.objects(u, chi, alpha, prob)
+    rng = np.random.default_rng(83)
+    for fid in range(prob.n_frames()):
+        m = tab["peak_of_frame"][fid]
+        py, px = tab["scan"][fid]
+        det = int(prob.det[m])
+        got = O.exit_wave(obj[m], p3[m], py, px, tab["shear"][m], det)
+        ref = _exit_wave_bruteforce_3d(obj[m], p3[m], py, px, tab["shear"][m], det)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+        w = rng.normal(size=(det, det)) + 1j * rng.normal(size=(det, det))
+        ahw = np.zeros(obj[m].shape, dtype=np.complex128)
+        O.back_project(w, p3[m], py, px, tab["shear"][m], ahw)
+        assert abs(np.vdot(w, got) - np.vdot(ahw, obj[m])) <= 1e-12 * max(1.0, abs(np.vdot(w, got)))
+
+
+def test_3d_probe_constant_along_x3_is_the_2d_probe():
+    prob = tiny_problem()
+    u, chi, alpha, probe = random_fields(prob, seed=84)
+    p3 = np.repeat(probe[:, None], prob.nz, axis=1)
+    rng = np.random.default_rng(85)
+    y = ragged(O.model_intensity(u + rng.normal(0, 0.05, size=u.shape), chi, alpha, probe, prob))
+    a = O.loss_grad(u, chi, alpha, probe, y, prob)
+    b = O.loss_grad(u, chi, alpha, p3, y, prob)
+    for k in ("loss", "grad_u", "grad_chi", "grad_alpha"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_3d_probe_gradient_matches_central_differences():
+    prob = tiny_problem()
+    u, chi, alpha, _ = random_fields(prob, seed=86)
+    p3 = _probe3(prob, 87) * 0.3
+    rng = np.random.default_rng(88)
+    y = ragged(O.model_intensity(u + rng.normal(0, 0.05, size=u.shape), chi, alpha, p3, prob))
+    r = O.loss_grad(u, chi, alpha, p3, y, prob)
+    f = lambda uu, cc: O.loss(uu, cc, alpha, p3, y, prob)[0]
+    scale_u, scale_c = np.abs(r["grad_u"]).max(), np.abs(r["grad_chi"]).max()
+    for _ in range(8):
+        c = int(rng.integers(3))
+        idx = tuple(int(rng.integers(s)) for s in u.shape[1:])
+        up, um = u.copy(), u.copy()
+        up[(c,) + idx] += 1e-6
+        um[(c,) + idx] -= 1e-6
+        assert (f(up, chi) - f(um, chi)) / 2e-6 == pytest.approx(r["grad_u"][(c,) + idx], abs=1e-6 * scale_u)
+    for _ in range(6):
+        idx = tuple(int(rng.integers(s)) for s in chi.shape)
+        cp, cm = chi.copy(), chi.copy()
+        cp[idx] += 1e-6
+        cm[idx] -= 1e-6
+        assert (f(u, cp) - f(u, cm)) / 2e-6 == pytest.approx(r["grad_chi"][idx], abs=1e-6 * scale_c)
