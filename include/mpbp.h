@@ -26,6 +26,7 @@
  *                 MPBP_Z_TIED)
  *   alpha   (dev) float [n_peaks]             per-peak scale alpha_m > 0
  *   probe   (dev) complex64 [n_peaks][probe_n][probe_n], interleaved (re, im) floats
+ *                 ([n_peaks][nz][probe_n][probe_n] under MPBP_PROBE_3D)
  *   y       (dev) float, ragged: peaks concatenated, peak m holds
  *                 [frames_m][D_m][D_m]; offsets from mpbp_tables (y_off)
  *   frames  (host) int32 [n_frames]: global frame ids (peak-major, raster order within
@@ -75,7 +76,7 @@ typedef struct {
   int32_t probe_n;           /* probe support (square)                                     */
   int32_t n_peaks;
   const mpbp_peak* peaks;    /* (host) [n_peaks]; copied by mpbp_plan_create               */
-  uint32_t flags;            /* 0 or MPBP_Z_TIED                                           */
+  uint32_t flags;            /* 0, or MPBP_Z_TIED and / or MPBP_PROBE_3D                   */
 } mpbp_problem;
 
 /* Problem flags.
@@ -84,6 +85,12 @@ typedef struct {
    [1][ny][nx], both holding for every slice z; grad_u and grad_chi have the same shapes
    and hold the z-sums of the per-voxel gradients. */
 enum { MPBP_Z_TIED = 1 };
+/* MPBP_PROBE_3D: per-peak 3D illumination volumes (section 2: the probe satisfying each
+   Bragg condition is three-dimensional): probe is then (dev) complex64
+   [n_peaks][nz][probe_n][probe_n], the probe of every slice z on the same probe_n x
+   probe_n support of scan position j, and eq. (2) reads diag(P_m) as P_m[z] on slice z.
+   May be combined with MPBP_Z_TIED. */
+enum { MPBP_PROBE_3D = 2 };
 
 /* Options of mpbp_set_option / mpbp_get_option. */
 enum {

@@ -69,7 +69,9 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
 // width (TX x TY voxels per slice, TX * TY = 64: one wavefront per slice).  The tile
 // grid starts at (tile_oy, tile_ox) <= 0, so that a grid aligned with a raster of step
 // TX x TY gives every voxel of a tile the same covering frames.
-template <int B, int TX>
+// P3: the probe varies along z (probe [M][nz][np][np]): conj(P_z) is read per frame and
+// slice from the probe volume (L2-resident) instead of the per-peak probe in LDS.
+template <int B, int TX, bool P3>
 __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   constexpr int TY = kGradTile / TX;
   extern __shared__ cplx smem[];
@@ -114,8 +116,9 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       const int ncx = ix_hi - ix_lo + 1;
       const int ncand = (iy_hi >= iy_lo && ncx > 0) ? (iy_hi - iy_lo + 1) * ncx : 0;
       __syncthreads();
-      const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
-      for (int k = tid; k < np * np; k += kGradThreads) Ps[k] = probe[k];
+      const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * (P3 ? nz : 1) * np * np;
+      if (!P3)
+        for (int k = tid; k < np * np; k += kGradThreads) Ps[k] = probe[k];
       for (int z = tid; z < nz; z += kGradThreads) {
         const int* s = A.shear + 2 * (m * nz + z);
         sh[z] = make_int2(s[0], s[1]);
@@ -164,14 +167,23 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
           }
         }
         if (nb == 0) break;
-        cplx gv[B][kGradZPer], pv[B];
+        cplx gv[B][kGradZPer], pv[B], pz[B][P3 ? kGradZPer : 1];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
           const int a = y - fpy[k], b = x - fpx[k];
           const bool inw = k < nb && inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
           const int ac = inw ? a : 0, bc = inw ? b : 0;
-          const cplx pr = Ps[ac * np + bc];
-          pv[k] = inw ? pr : cplx{0.f, 0.f};
+          if constexpr (P3) {
+#pragma unroll
+            for (int i = 0; i < kGradZPer; ++i) {
+              const int z = zb + tz + kGradTZ * i;
+              const cplx pr = probe[(long long)(z < nz ? z : 0) * np * np + ac * np + bc];
+              pz[k][i] = inw ? pr : cplx{0.f, 0.f};
+            }
+          } else {
+            const cplx pr = Ps[ac * np + bc];
+            pv[k] = inw ? pr : cplx{0.f, 0.f};
+          }
           const cplx* sl = slots + fso[k];
 #pragma unroll
           for (int i = 0; i < kGradZPer; ++i) gv[k][i] = sl[(ac + zsy[i]) * pk.fx + bc + zsx[i]];
@@ -179,7 +191,8 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
 #pragma unroll
         for (int k = 0; k < B; ++k)
 #pragma unroll
-          for (int i = 0; i < kGradZPer; ++i) acc[i] = cadd(acc[i], cmulc(gv[k][i], pv[k]));   // conj(P) g_psi
+          for (int i = 0; i < kGradZPer; ++i)   // conj(P) g_psi
+            acc[i] = cadd(acc[i], cmulc(gv[k][i], P3 ? pz[k][P3 ? i : 0] : pv[k]));
       }
       // chain rule through O_m = alpha_m chi exp(i G_m . u); 32-bit voxel offsets from
       // uniform bases (the plan limits 3 * nvox to 2^32)
@@ -431,12 +444,20 @@ bool frame_instance(int D, int FB) { return frames_op(2, D, FB, nullptr, 0, null
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s) {
   const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
+#define MPBP_PROJ(g)                                                                    \
+  case g:                                                                               \
+    if (a.probe3)                                                                       \
+      k_project<g, true><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);         \
+    else                                                                                \
+      k_project<g, false><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);        \
+    break;
   switch (G) {
-    case 2: k_project<2><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
-    case 4: k_project<4><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
-    case 8: k_project<8><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
+    MPBP_PROJ(2)
+    MPBP_PROJ(4)
+    MPBP_PROJ(8)
     default: return hipErrorInvalidValue;
   }
+#undef MPBP_PROJ
   return hipGetLastError();
 }
 
@@ -456,15 +477,17 @@ hipError_t prepare_kernels() {
   for (int D : kDets)
     for (int FB : {32, 48, 64, D})
       if (e == hipSuccess && frame_instance(D, FB)) e = frames_op(1, D, FB, nullptr, 0, nullptr);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_project<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_project<4>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_project<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  const void* projs[] = {(const void*)k_project<2, false>, (const void*)k_project<4, false>,
+                         (const void*)k_project<8, false>, (const void*)k_project<2, true>,
+                         (const void*)k_project<4, true>, (const void*)k_project<8, true>};
+  for (const void* f : projs)
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 #define MPBP_CASE(b, tx)                                                                        \
   if (e == hipSuccess)                                                                          \
-    e = hipFuncSetAttribute((const void*)k_grad<b, tx>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+    e = hipFuncSetAttribute((const void*)k_grad<b, tx, false>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            160 * 1024);                                                        \
+  if (e == hipSuccess)                                                                          \
+    e = hipFuncSetAttribute((const void*)k_grad<b, tx, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                             160 * 1024);
   MPBP_GRAD_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
@@ -475,7 +498,10 @@ hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, 
   const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
 #define MPBP_CASE(b, tx)                                                       \
   if (batch == b && tile_x == tx) {                                            \
-    k_grad<b, tx><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);        \
+    if (a.probe3)                                                              \
+      k_grad<b, tx, true><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);  \
+    else                                                                       \
+      k_grad<b, tx, false><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a); \
     return hipGetLastError();                                                  \
   }
   MPBP_GRAD_INSTANCES(MPBP_CASE)

@@ -73,6 +73,7 @@ struct mpbp_plan_t {
   int nz = 0, ny = 0, nx = 0, np = 0, M = 0;
   long long nvox = 0;
   long long tied = 0;              // ny * nx under MPBP_Z_TIED, else 0
+  int probe3 = 0;                  // MPBP_PROBE_3D: probe [M][nz][np][np]
   int64_t F = 0, ylen = 0;
   std::vector<mpbp_peak> peaks;
   std::vector<PeakDev> pdev;
@@ -199,8 +200,8 @@ void free_device(mpbp_plan_t* p) {
 // Build tables and per-peak constants on the host; validate the problem.
 mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   if (!pr) return fail(MPBP_ERR_INVALID, "problem is NULL");
-  if (pr->flags & ~(uint32_t)MPBP_Z_TIED)
-    return fail(MPBP_ERR_INVALID, "unknown flags 0x%x (only MPBP_Z_TIED is defined)", pr->flags);
+  if (pr->flags & ~(uint32_t)(MPBP_Z_TIED | MPBP_PROBE_3D))
+    return fail(MPBP_ERR_INVALID, "unknown flags 0x%x (MPBP_Z_TIED and MPBP_PROBE_3D are defined)", pr->flags);
   if (pr->nz < 1 || pr->ny < 1 || pr->nx < 1)
     return fail(MPBP_ERR_SHAPE, "object grid must be positive (nz=%d ny=%d nx=%d)", pr->nz, pr->ny, pr->nx);
   if (pr->probe_n < 1) return fail(MPBP_ERR_SHAPE, "probe_n must be positive (%d)", pr->probe_n);
@@ -217,6 +218,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   p->nz = pr->nz; p->ny = pr->ny; p->nx = pr->nx; p->np = pr->probe_n; p->M = pr->n_peaks;
   p->nvox = nvox;
   p->tied = (pr->flags & MPBP_Z_TIED) ? (long long)pr->ny * pr->nx : 0;
+  p->probe3 = (pr->flags & MPBP_PROBE_3D) ? 1 : 0;
   p->peaks.assign(pr->peaks, pr->peaks + pr->n_peaks);
   p->pdev.assign(p->M, PeakDev{});
   p->shear.assign((size_t)p->M * p->nz * 2, 0);
@@ -574,6 +576,7 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   a.nz = p->nz; a.ny = p->ny; a.nx = p->nx; a.np = p->np;
   a.grad = grad;
   a.xcd = p->xcd;
+  a.probe3 = p->probe3;
   return a;
 }
 
@@ -600,6 +603,7 @@ mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const fl
   g.maxspan_y = p->maxspan_y; g.maxspan_x = p->maxspan_x;
   g.max_cand = p->max_cand;
   g.tied = p->tied != 0;
+  g.probe3 = p->probe3;
   g.grad_u = grad_u; g.grad_chi = grad_chi;
   g.alpha_part = p->d_apart;
   return g;
@@ -1022,6 +1026,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
   if (plan->path == 1) {
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
     plan->plain.bg = plan->d_bg;
+    plan->plain.probe3 = plan->probe3;
     e = mpbp::plain_forward(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                             plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                             frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
@@ -1078,6 +1083,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
   if (plan->path == 1) {
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
     plan->plain.bg = plan->d_bg;
+    plan->plain.probe3 = plan->probe3;
     e = mpbp::plain_loss_grad(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                               plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                               frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,

@@ -45,6 +45,7 @@ struct FrameArgs {
   int nz, ny, nx, np;
   int grad;                // 1: also compute the footprint gradient
   int xcd;                 // XCD-aware block order
+  int probe3;              // 1: probe is [M][nz][np][np] (a 3D illumination volume)
 };
 
 struct GradArgs {
@@ -63,6 +64,7 @@ struct GradArgs {
   int maxspan_y, maxspan_x;  // largest shear span over peaks
   int max_cand;              // largest number of frames of one peak meeting one tile
   int tied;                  // 1: u, chi and their gradients per lateral pixel (z-sums)
+  int probe3;                // 1: probe is [M][nz][np][np] (a 3D illumination volume)
   float* grad_u;
   float* grad_chi;
   double* alpha_part;      // [n_blocks][M]

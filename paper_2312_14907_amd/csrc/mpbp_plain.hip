@@ -18,7 +18,7 @@ __global__ __launch_bounds__(256) void k_pl_project(const float* __restrict__ ob
                                                     const float* __restrict__ probe,
                                                     const int* __restrict__ shear,
                                                     const PeakDev* __restrict__ peaks, int m, int py,
-                                                    int px, int nz, int ny, int nx, int np,
+                                                    int px, int nz, int ny, int nx, int np, int probe3,
                                                     float* __restrict__ psi) {
   const PeakDev pk = peaks[m];
   const int D = pk.D;
@@ -26,9 +26,11 @@ __global__ __launch_bounds__(256) void k_pl_project(const float* __restrict__ ob
   if (p >= D * D) return;
   const int wy = p / D, wx = p - wy * D;
   const cplx* O = reinterpret_cast<const cplx*>(obj) + (long long)m * nz * ny * nx;
-  const cplx* P = reinterpret_cast<const cplx*>(probe) + (long long)m * np * np;
+  const long long pz = probe3 ? (long long)np * np : 0;   // probe slice stride
+  const cplx* P0 = reinterpret_cast<const cplx*>(probe) + (long long)m * (probe3 ? nz : 1) * np * np;
   cplx acc = {0.f, 0.f};
   for (int z = 0; z < nz; ++z) {
+    const cplx* P = P0 + z * pz;
     const int a = wy - pk.c - shear[2 * (m * nz + z)];
     const int b = wx - pk.c - shear[2 * (m * nz + z) + 1];
     if ((unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np) {
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(256) void k_pl_backproject(const float* __restrict_
                                                         const int* __restrict__ shear,
                                                         const PeakDev* __restrict__ peaks, int m,
                                                         int py, int px, int nz, int ny, int nx,
-                                                        int np, float* __restrict__ gobj) {
+                                                        int np, int probe3, float* __restrict__ gobj) {
   const PeakDev pk = peaks[m];
   const int D = pk.D;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(256) void k_pl_backproject(const float* __restrict_
   const int wy = a + pk.c + shear[2 * (m * nz + z)];
   const int wx = b + pk.c + shear[2 * (m * nz + z) + 1];
   const cplx g = reinterpret_cast<const cplx*>(psi)[wy * D + wx];
-  const cplx p = reinterpret_cast<const cplx*>(probe)[(long long)m * np * np + ab];
+  const cplx p = reinterpret_cast<const cplx*>(probe)[((long long)m * (probe3 ? nz : 1) + (probe3 ? z : 0)) * np * np + ab];
   cplx* dst = reinterpret_cast<cplx*>(gobj) + (long long)m * nz * ny * nx + ((long long)z * ny + oy) * nx + ox;
   const float invD = 1.0f / (float)D;
   *dst = cadd(*dst, cscale(cmulc(g, p), invD));
@@ -261,7 +263,8 @@ static hipError_t plain_frames(PlainWork* w, const PeakDev* hp, const PeakDev* d
     const int D = pk.D;
     const int py = hscan[2 * fid], px = hscan[2 * fid + 1];
     const long long yo = pk.y_off + (long long)(fid - pk.frame_base) * D * D;
-    k_pl_project<<<dim3((D * D + 255) / 256), dim3(256), 0, s>>>(obj, probe, dshear, dp, m, py, px, nz, ny, nx, np, w->psi);
+    k_pl_project<<<dim3((D * D + 255) / 256), dim3(256), 0, s>>>(obj, probe, dshear, dp, m, py, px, nz, ny, nx, np,
+                                                                 w->probe3, w->psi);
     k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, D, 1, 0);
     k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, 1, D, 0);
     k_pl_residual<<<dim3(D), dim3(256), 0, s>>>(w->psi, y ? y + yo : nullptr, w->bg ? w->bg + yo : nullptr, D,
@@ -270,7 +273,8 @@ static hipError_t plain_frames(PlainWork* w, const PeakDev* hp, const PeakDev* d
     if (grad) {
       k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, D, 1, 1);
       k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, 1, D, 1);
-      k_pl_backproject<<<dim3((nz * np * np + 255) / 256), dim3(256), 0, s>>>(w->psi, probe, dshear, dp, m, py, px, nz, ny, nx, np, w->gobj);
+      k_pl_backproject<<<dim3((nz * np * np + 255) / 256), dim3(256), 0, s>>>(w->psi, probe, dshear, dp, m, py, px, nz,
+                                                                              ny, nx, np, w->probe3, w->gobj);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -19,6 +19,7 @@ struct PlainWork {
   long long apart_len = 0;
   int dmax = 0;
   const float* bg = nullptr;   // background b of eq. (2), ragged like y (set by the plan)
+  int probe3 = 0;              // 1: probe [M][nz][np][np] (set by the plan)
 };
 
 void plain_free(PlainWork* w);

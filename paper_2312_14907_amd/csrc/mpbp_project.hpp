@@ -19,7 +19,9 @@ namespace mpbp {
 // footprint accumulator in LDS at the run's offset.  Within one run every footprint
 // pixel receives at most one value, so no two lanes collide; a barrier separates runs,
 // which keeps the order of every sum fixed.
-template <int G>
+// P3: the probe varies along z (probe [M][nz][np][np]); P_z O_z is formed per slice
+// before the run sums.
+template <int G, bool P3>
 __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
   constexpr int NT = kFrameThreads;
   const int tid = threadIdx.x;
@@ -28,7 +30,8 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   const int m = A.peak_of[fid];
   const int py = A.scan[2 * fid], px = A.scan[2 * fid + 1];
   const int j = fid - pk.frame_base;
-  const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
+  const long long pstride = P3 ? (long long)np * np : 0;   // probe slice stride
+  const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * (P3 ? nz : 1) * np * np;
   cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
   const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * A.ny * A.nx;
   const int* shz = A.shear + 2 * m * nz;   // uniform: scalar loads
@@ -40,7 +43,8 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   // and footprint offset at zero shear
   cplx pv[kProjE];
   unsigned off[kProjE];   // byte offset in a slice: a 32-bit lane offset from a uniform base
-  int fo[kProjE];
+  int fo[kProjE], pe[kProjE];
+  bool pok[kProjE];
 #pragma unroll
   for (int i = 0; i < kProjE; ++i) {
     const int e = tid + NT * i;
@@ -48,6 +52,8 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
     const int oy = py + a, ox = px + b;
     const bool ok = e < np2 && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
     pv[i] = ok ? probe[e < np2 ? e : 0] : cplx{0.f, 0.f};
+    pe[i] = e < np2 ? e : 0;
+    pok[i] = ok;
     off[i] = ok ? (unsigned)(oy * A.nx + ox) * (unsigned)sizeof(cplx) : 0u;
     fo[i] = a * fx + b;
   }
@@ -56,11 +62,16 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   // compiler's strength reduction; otherwise it keeps one 64-bit pointer per load live
   // across the loop and spills them.
   const long long plane = (long long)A.ny * A.nx;
-  auto load = [&](cplx (&o)[kProjE], int z) {
+  auto load = [&](cplx (&o)[kProjE], cplx (&q)[P3 ? kProjE : 1], int z) {
     const int zz = __builtin_amdgcn_readfirstlane(z < nz ? z : nz - 1);
     const char* Oz = reinterpret_cast<const char*>(O + (long long)zz * plane);
 #pragma unroll
     for (int i = 0; i < kProjE; ++i) o[i] = *reinterpret_cast<const cplx*>(Oz + off[i]);
+    if constexpr (P3) {
+      const cplx* Pz = probe + (long long)zz * pstride;
+#pragma unroll
+      for (int i = 0; i < kProjE; ++i) q[i] = pok[i] ? Pz[pe[i]] : cplx{0.f, 0.f};
+    }
   };
   // footprint offset of slice z's pixel (0, 0): (s_y - min s_y) fx + (s_x - min s_x)
   auto shift = [&](int z) { return (shz[2 * z] - pk.miny) * fx + (shz[2 * z + 1] - pk.minx); };
@@ -75,9 +86,9 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
       }
     }
   };
-  cplx buf[G][kProjE];
+  cplx buf[G][kProjE], pbuf[G][P3 ? kProjE : 1];
 #pragma unroll
-  for (int g = 0; g < G; ++g) load(buf[g], g);
+  for (int g = 0; g < G; ++g) load(buf[g], pbuf[g], g);
   int cur = shift(0);
 #pragma unroll
   for (int i = 0; i < kProjE; ++i) w[i] = {0.f, 0.f};
@@ -88,8 +99,8 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
       if (z < nz) {   // uniform
         cplx v[kProjE];
 #pragma unroll
-        for (int i = 0; i < kProjE; ++i) v[i] = cmul(pv[i], buf[g][i]);
-        if (z + G < nz) load(buf[g], z + G);
+        for (int i = 0; i < kProjE; ++i) v[i] = cmul(P3 ? pbuf[g][P3 ? i : 0] : pv[i], buf[g][i]);
+        if (z + G < nz) load(buf[g], pbuf[g], z + G);
         const int d = shift(z);
         if (d != cur) {   // uniform: a new run
           flush(cur);
@@ -112,7 +123,7 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
 // workgroups per CU.
 template <int G> struct ProjectWaves { static constexpr int value = G <= 2 ? 8 : G <= 4 ? 6 : 4; };
 
-template <int G>
+template <int G, bool P3>
 __global__ __launch_bounds__(kFrameThreads) __attribute__((amdgpu_waves_per_eu(ProjectWaves<G>::value)))
 void k_project(FrameArgs A) {
   extern __shared__ cplx smem[];
@@ -120,7 +131,7 @@ void k_project(FrameArgs A) {
   if (idx >= A.n_list) return;
   const int fid = A.list[idx];
   const PeakDev pk = A.peaks[A.peak_of[fid]];
-  project_body<G>(A, pk, fid, smem);
+  project_body<G, P3>(A, pk, fid, smem);
 }
 
 }  // namespace mpbp
