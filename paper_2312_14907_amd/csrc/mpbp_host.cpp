@@ -333,7 +333,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     return fail(MPBP_ERR_UNSUPPORTED, "projection needs %d B of LDS", p->lds_project[mpbp::kDefaultSlab]);
   if (p->lds_grad > kMaxLds) return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", p->lds_grad);
   // Full-batch processing order: larger windows first (they cost most), each peak's
-  // frames in raster order.
+  // frames in tiles of its raster.
   std::vector<int> pk(p->M);
   for (int m = 0; m < p->M; ++m) pk[m] = m;
   auto fb = [&](int m) {
@@ -364,7 +364,15 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     c.fx = std::max(c.fx, d.fx);
     c.lds_fwd = std::max(c.lds_fwd, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, false));
     c.lds_grad = std::max(c.lds_grad, mpbp::frame_lds_bytes(d.D, d.fy, d.fx, d.fxp, true));
-    for (int j = 0; j < d.nfr; ++j) p->order.push_back(d.frame_base + j);
+    // frames in square tiles of the raster, tiles in row-major order: a run of
+    // consecutive frames reads a compact patch of the object (it stays in the XCD's L2
+    // while its neighbours are projected)
+    constexpr int kOrderTile = 16;
+    for (int ty = 0; ty < d.rows; ty += kOrderTile)
+      for (int tx = 0; tx < d.cols; tx += kOrderTile)
+        for (int iy = ty; iy < std::min(ty + kOrderTile, d.rows); ++iy)
+          for (int ix = tx; ix < std::min(tx + kOrderTile, d.cols); ++ix)
+            p->order.push_back(d.frame_base + iy * d.cols + ix);
   }
   return MPBP_OK;
 }
