@@ -17,7 +17,9 @@ fields with multi-peak Bragg ptychography"):
   S_{m,j} selects the probe window of scan position j (section 4: raster scan), the
   probe is constant along the incident beam x3 (section 4), and R_m projects the
   illuminated slices along the exit beam: slice z lands s_m(z) pixels over, an integer
-  lateral shear, inside a D_m x D_m window centred on the probe support.  F is the
+  lateral shear, inside a D_m x D_m window centred on the probe support (with
+  problem.shear_linear the offset stays fractional and the slice is spread over the four
+  neighbouring integer offsets with bilinear weights: R interpolating, section 2).  F is the
   orthonormal 2D DFT with kernel exp(-2 pi i k.x / D), DC at index 0;
 * eq. (4): f = 1/2 sum_{m,j} || I^{1/2} - y^{1/2} ||^2, summed (not averaged) over the
   listed frames as in the minibatch sums of eq. (11);
@@ -63,6 +65,22 @@ def shear_table(nz, shear):
     return out
 
 
+def shear_table_linear(nz, shear):
+    """Interpolated exit-beam offsets: s(z) = (z - nz//2) * t per axis, split into
+    s0 = floor(s) and the fraction f = s - s0 in [0, 1).  A slice's illuminated object
+    then lands on offsets s0 (weight 1 - f) and s0 + 1 (weight f) along each axis:
+    linear interpolation of the slice sampled at q - s(z)."""
+    zref = nz // 2
+    s0 = np.zeros((nz, 2), dtype=np.int64)
+    fr = np.zeros((nz, 2), dtype=np.float64)
+    for z in range(nz):
+        for a in range(2):
+            v = float(z - zref) * float(shear[a])
+            s0[z, a] = math.floor(v)
+            fr[z, a] = v - s0[z, a]
+    return s0, fr
+
+
 def scan_positions(scan_n, scan_step, scan_origin):
     """Top-left object voxel (py, px) of the probe support for each raster frame."""
     rows, cols = int(scan_n[0]), int(scan_n[1])
@@ -83,7 +101,8 @@ def tables(problem):
 
     Returns dict with
       scan   [F][2] int: (py, px) per global frame (peaks concatenated, raster order)
-      shear  [M][nz][2] int: s_m(z)
+      shear  [M][nz][2] int: s_m(z) (with problem.shear_linear: floor of the offset)
+      shear_frac [M][nz][2] float or None: fractional offsets (problem.shear_linear)
       y_off  [M+1] int: element offset of peak m's intensities in the ragged y array
       peak_of_frame [F] int, local_index [F] int
       offset [M] int: window offset c_m
@@ -92,6 +111,8 @@ def tables(problem):
     m_count = problem.n_peaks
     scans, peak_of, local = [], [], []
     shear = np.zeros((m_count, problem.nz, 2), dtype=np.int64)
+    linear = bool(getattr(problem, "shear_linear", False))
+    frac = np.zeros((m_count, problem.nz, 2)) if linear else None
     y_off = np.zeros(m_count + 1, dtype=np.int64)
     offs = np.zeros(m_count, dtype=np.int64)
     for m in range(m_count):
@@ -100,9 +121,12 @@ def tables(problem):
         if c < 0:
             raise FootprintError(f"peak {m}: probe support {problem.probe_n} > window {det}")
         offs[m] = c
-        shear[m] = shear_table(problem.nz, problem.shear[m])
+        if linear:
+            shear[m], frac[m] = shear_table_linear(problem.nz, problem.shear[m])
+        else:
+            shear[m] = shear_table(problem.nz, problem.shear[m])
         lo = shear[m].min(axis=0)
-        hi = shear[m].max(axis=0)
+        hi = shear[m].max(axis=0) + (1 if linear else 0)
         if (c + lo < 0).any() or (c + problem.probe_n - 1 + hi > det - 1).any():
             raise FootprintError(f"peak {m}: sheared support leaves the {det}x{det} window")
         pos = scan_positions(problem.scan_n[m], problem.scan_step[m], problem.scan_origin[m])
@@ -113,6 +137,7 @@ def tables(problem):
     return {
         "scan": np.concatenate(scans),
         "shear": shear,
+        "shear_frac": frac,
         "y_off": y_off,
         "peak_of_frame": np.concatenate(peak_of),
         "local_index": np.concatenate(local),
@@ -152,12 +177,23 @@ def _probe_slice(probe_m, z):
     return probe_m[z] if probe_m.ndim == 3 else probe_m
 
 
-def exit_wave(o_m, probe_m, py, px, shear_m, det):
+def _taps(frac_m, z):
+    """(dy, dx, weight) of slice z: one tap of weight 1 for rounded offsets, four
+    bilinear taps for interpolated ones."""
+    if frac_m is None:
+        return [(0, 0, 1.0)]
+    fy, fx = float(frac_m[z, 0]), float(frac_m[z, 1])
+    return [(0, 0, (1 - fy) * (1 - fx)), (0, 1, (1 - fy) * fx), (1, 0, fy * (1 - fx)), (1, 1, fy * fx)]
+
+
+def exit_wave(o_m, probe_m, py, px, shear_m, det, frac_m=None):
     """R diag(P) S O for one frame: the D x D exit wave.
 
     For every slice z and probe pixel (a, b) with an in-grid object voxel,
       psi[a + c + s_y(z), b + c + s_x(z)] += P_z[a, b] * O[z, py + a, px + b]
-    (P_z = P for a probe constant along x3).
+    (P_z = P for a probe constant along x3).  With fractional offsets (frac_m), the term
+    goes to the four offsets s(z) + (dy, dx), dy, dx in {0, 1}, with the bilinear weights
+    of the fractions.
     """
     nz, ny, nx = o_m.shape
     n = probe_m.shape[-1]
@@ -168,15 +204,17 @@ def exit_wave(o_m, probe_m, py, px, shear_m, det):
     if a1 <= a0 or b1 <= b0:
         return psi
     for z in range(nz):
-        sy, sx = int(shear_m[z, 0]), int(shear_m[z, 1])
-        psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1] += (
-            _probe_slice(probe_m, z)[a0:a1, b0:b1] * o_m[z, py + a0:py + a1, px + b0:px + b1])
+        w = _probe_slice(probe_m, z)[a0:a1, b0:b1] * o_m[z, py + a0:py + a1, px + b0:px + b1]
+        for dy, dx, wt in _taps(frac_m, z):
+            sy, sx = int(shear_m[z, 0]) + dy, int(shear_m[z, 1]) + dx
+            psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1] += wt * w
     return psi
 
 
-def back_project(g_psi, probe_m, py, px, shear_m, g_o_m):
+def back_project(g_psi, probe_m, py, px, shear_m, g_o_m, frac_m=None):
     """Adjoint of exit_wave, accumulated into g_o_m in place:
-      g_O[z, py + a, px + b] += conj(P_z[a, b]) * g_psi[a + c + s_y(z), b + c + s_x(z)].
+      g_O[z, py + a, px + b] += conj(P_z[a, b]) * g_psi[a + c + s_y(z), b + c + s_x(z)]
+    (with fractional offsets: the bilinearly weighted sum of the four taps).
     """
     nz, ny, nx = g_o_m.shape
     n = probe_m.shape[-1]
@@ -187,10 +225,11 @@ def back_project(g_psi, probe_m, py, px, shear_m, g_o_m):
     if a1 <= a0 or b1 <= b0:
         return
     for z in range(nz):
-        sy, sx = int(shear_m[z, 0]), int(shear_m[z, 1])
         pc = np.conj(_probe_slice(probe_m, z)[a0:a1, b0:b1])
-        g_o_m[z, py + a0:py + a1, px + b0:px + b1] += (
-            pc * g_psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1])
+        for dy, dx, wt in _taps(frac_m, z):
+            sy, sx = int(shear_m[z, 0]) + dy, int(shear_m[z, 1]) + dx
+            g_o_m[z, py + a0:py + a1, px + b0:px + b1] += (
+                wt * pc * g_psi[c + sy + a0:c + sy + a1, c + sx + b0:c + sx + b1])
 
 
 def far_field(psi):
@@ -246,6 +285,10 @@ def frame_data(y, tab, problem, fid):
     return np.asarray(y[start:start + det * det], dtype=np.float64).reshape(det, det)
 
 
+def _frac(tab, m):
+    return None if tab["shear_frac"] is None else tab["shear_frac"][m]
+
+
 def model_intensity(u, chi, alpha, probe, problem, frames=None, background=None):
     """I_{m,j} of eq. (2) for the listed frames: list of D x D float64 arrays."""
     tab = tables(problem)
@@ -255,7 +298,7 @@ def model_intensity(u, chi, alpha, probe, problem, frames=None, background=None)
     for fid in _frame_list(problem, frames):
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
-        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]))
+        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]), _frac(tab, m))
         inten = np.abs(far_field(psi)) ** 2
         if background is not None:
             inten = inten + frame_data(background, tab, problem, fid)
@@ -275,7 +318,7 @@ def loss(u, chi, alpha, probe, y, problem, frames=None, background=None):
     for fid in _frame_list(problem, frames):
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
-        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]))
+        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]), _frac(tab, m))
         b = None if background is None else frame_data(background, tab, problem, fid)
         f, _ = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid), b)
         per.append(f)
@@ -293,11 +336,11 @@ def object_gradient(u, chi, alpha, probe, y, problem, frames=None, background=No
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
         det = int(problem.det[m])
-        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], det)
+        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], det, _frac(tab, m))
         b = None if background is None else frame_data(background, tab, problem, fid)
         f, grad_ff = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid), b)
         per.append(f)
-        back_project(far_field_adjoint(grad_ff), probe[m], py, px, tab["shear"][m], g_obj[m])
+        back_project(far_field_adjoint(grad_ff), probe[m], py, px, tab["shear"][m], g_obj[m], _frac(tab, m))
     return float(sum(per)), per, g_obj, obj
 
 

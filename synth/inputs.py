@@ -36,6 +36,7 @@ class Problem:
     scan_step: np.ndarray
     scan_origin: np.ndarray
     photons: list = field(default_factory=list)
+    shear_linear: bool = False   # exit-beam offsets interpolated linearly (not rounded)
 
     @property
     def n_peaks(self):

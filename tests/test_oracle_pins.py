@@ -673,3 +673,104 @@ def test_3d_probe_gradient_matches_central_differences():
         cp[idx] += 1e-6
         cm[idx] -= 1e-6
         assert (f(u, cp) - f(u, cm)) / 2e-6 == pytest.approx(r["grad_chi"][idx], abs=1e-6 * scale_c)
+
+
+# ------------------------------------------- interpolating exit-beam offsets (R) ---
+
+def _linear(prob):
+    import dataclasses
+    return dataclasses.replace(prob, shear_linear=True)
+
+
+def _exit_wave_tent(o_m, probe_m, py, px, shear_t, det, nz):
+    # bilinear sampling written with the tent kernel of the continuous offset
+    # s(z) = (z - nz//2) t: psi[q] = sum_z sum_e W_z[e] K(q - c - e - s(z)),
+    # K(d) = max(0, 1 - |d_y|) max(0, 1 - |d_x|)
+    ny, nx = o_m.shape[1:]
+    n = probe_m.shape[0]
+    c = (det - n) // 2
+    psi = np.zeros((det, det), dtype=np.complex128)
+    for z in range(nz):
+        s = ((z - nz // 2) * shear_t[0], (z - nz // 2) * shear_t[1])
+        for a in range(n):
+            for b in range(n):
+                yy, xx = py + a, px + b
+                if not (0 <= yy < ny and 0 <= xx < nx):
+                    continue
+                w = probe_m[a, b] * o_m[z, yy, xx]
+                for qy in range(det):
+                    ky = max(0.0, 1.0 - abs(qy - c - a - s[0]))
+                    if ky == 0.0:
+                        continue
+                    for qx in range(det):
+                        kx = max(0.0, 1.0 - abs(qx - c - b - s[1]))
+                        if kx:
+                            psi[qy, qx] += ky * kx * w
+    return psi
+
+
+def test_linear_offsets_match_the_tent_kernel_and_adjoint():
+    prob = _linear(tiny_problem())
+    tab = O.tables(prob)
+    assert (tab["shear_frac"] > 0).any()
+    u, chi, alpha, probe = random_fields(prob, seed=101)
+    obj = O.objects(u, chi, alpha, prob)
+    rng = np.random.default_rng(102)
+    for fid in range(prob.n_frames()):
+        m = tab["peak_of_frame"][fid]
+        py, px = tab["scan"][fid]
+        det = int(prob.det[m])
+        got = O.exit_wave(obj[m], probe[m], py, px, tab["shear"][m], det, tab["shear_frac"][m])
+        ref = _exit_wave_tent(obj[m], probe[m], py, px, prob.shear[m], det, prob.nz)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+        w = rng.normal(size=(det, det)) + 1j * rng.normal(size=(det, det))
+        ahw = np.zeros(obj[m].shape, dtype=np.complex128)
+        O.back_project(w, probe[m], py, px, tab["shear"][m], ahw, tab["shear_frac"][m])
+        assert abs(np.vdot(w, got) - np.vdot(ahw, obj[m])) <= 1e-12 * max(1.0, abs(np.vdot(w, got)))
+
+
+def test_linear_offsets_conserve_each_slice_and_reduce_to_integer_shears():
+    # the bilinear weights of a slice sum to 1: the exit wave's sum is sum_z sum P O_z
+    prob = _linear(tiny_problem())
+    tab = O.tables(prob)
+    u, chi, alpha, probe = random_fields(prob, seed=103)
+    obj = O.objects(u, chi, alpha, prob)
+    py, px = 2, 2                 # support inside the grid
+    det = int(prob.det[0])
+    psi = O.exit_wave(obj[0], probe[0], py, px, tab["shear"][0], det, tab["shear_frac"][0])
+    n = prob.probe_n
+    assert psi.sum() == pytest.approx(np.sum(probe[0][None] * obj[0][:, py:py + n, px:px + n]), rel=1e-12)
+    # integral offsets: the interpolating projection is the rounded one
+    pint = tiny_problem(shears=((1.0, -1.0), (0.0, 1.0)))
+    a = O.loss_grad(u, chi, alpha, probe, _y(pint, u, chi, alpha, probe), pint)
+    b = O.loss_grad(u, chi, alpha, probe, _y(pint, u, chi, alpha, probe), _linear(pint))
+    for k in ("loss", "grad_u", "grad_chi", "grad_alpha"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-13, atol=1e-13 * np.abs(a[k]).max())
+
+
+def _y(prob, u, chi, alpha, probe):
+    rng = np.random.default_rng(104)
+    return ragged(O.model_intensity(u + rng.normal(0, 0.05, size=u.shape), chi, alpha, probe, prob))
+
+
+def test_linear_offsets_gradient_matches_central_differences():
+    prob = _linear(tiny_problem())
+    u, chi, alpha, probe = random_fields(prob, seed=105)
+    y = _y(prob, u, chi, alpha, probe)
+    r = O.loss_grad(u, chi, alpha, probe, y, prob)
+    f = lambda uu, cc: O.loss(uu, cc, alpha, probe, y, prob)[0]
+    rng = np.random.default_rng(106)
+    scale_u, scale_c = np.abs(r["grad_u"]).max(), np.abs(r["grad_chi"]).max()
+    for _ in range(8):
+        c = int(rng.integers(3))
+        idx = tuple(int(rng.integers(s)) for s in u.shape[1:])
+        up, um = u.copy(), u.copy()
+        up[(c,) + idx] += 1e-6
+        um[(c,) + idx] -= 1e-6
+        assert (f(up, chi) - f(um, chi)) / 2e-6 == pytest.approx(r["grad_u"][(c,) + idx], abs=1e-6 * scale_u)
+    for _ in range(6):
+        idx = tuple(int(rng.integers(s)) for s in chi.shape)
+        cp, cm = chi.copy(), chi.copy()
+        cp[idx] += 1e-6
+        cm[idx] -= 1e-6
+        assert (f(u, cp) - f(u, cm)) / 2e-6 == pytest.approx(r["grad_chi"][idx], abs=1e-6 * scale_c)
