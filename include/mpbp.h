@@ -76,7 +76,7 @@ typedef struct {
   int32_t probe_n;           /* probe support (square)                                     */
   int32_t n_peaks;
   const mpbp_peak* peaks;    /* (host) [n_peaks]; copied by mpbp_plan_create               */
-  uint32_t flags;            /* 0, or MPBP_Z_TIED and / or MPBP_PROBE_3D                   */
+  uint32_t flags;            /* 0, or any of MPBP_Z_TIED, MPBP_PROBE_3D, MPBP_SHEAR_LINEAR */
 } mpbp_problem;
 
 /* Problem flags.
@@ -91,6 +91,13 @@ enum { MPBP_Z_TIED = 1 };
    probe_n support of scan position j, and eq. (2) reads diag(P_m) as P_m[z] on slice z.
    May be combined with MPBP_Z_TIED. */
 enum { MPBP_PROBE_3D = 2 };
+/* MPBP_SHEAR_LINEAR: the exit-beam operator R interpolates (section 2: R rotates and
+   interpolates the illuminated object into the detector frame).  Slice z's lateral
+   offset (z - nz/2) * t_m is kept fractional: with s0 = floor and f the fraction per
+   axis, the slice lands on offsets s0 + (dy, dx), dy, dx in {0, 1}, with the bilinear
+   weights (1 - f_y or f_y) (1 - f_x or f_x) (rounded offsets otherwise).  mpbp_tables
+   then reports s0; footprints are one pixel wider per axis. */
+enum { MPBP_SHEAR_LINEAR = 4 };
 
 /* Options of mpbp_set_option / mpbp_get_option. */
 enum {

@@ -23,6 +23,7 @@ MPBP_OPT_GRAD_BATCH = 5
 MPBP_OPT_GRAD_TILE = 6
 MPBP_Z_TIED = 1
 MPBP_PROBE_3D = 2
+MPBP_SHEAR_LINEAR = 4
 STAGES = ("object", "frames", "grad", "finalize", "plain", "project")
 
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",

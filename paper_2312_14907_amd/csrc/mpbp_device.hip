@@ -71,7 +71,9 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
 // TX x TY gives every voxel of a tile the same covering frames.
 // P3: the probe varies along z (probe [M][nz][np][np]): conj(P_z) is read per frame and
 // slice from the probe volume (L2-resident) instead of the per-peak probe in LDS.
-template <int B, int TX, bool P3>
+// LIN: fractional exit-beam offsets (A.shw): a voxel's footprint gradient is the
+// bilinearly weighted sum of four footprint pixels (the adjoint of the projection's taps).
+template <int B, int TX, bool P3, bool LIN>
 __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   constexpr int TY = kGradTile / TX;
   extern __shared__ cplx smem[];
@@ -133,13 +135,22 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       for (int i = 0; i < kGradZPer; ++i) acc[i] = {0.f, 0.f};
       __syncthreads();
 
-      // this lane's slices: shear offsets in registers
+      // this lane's slices: shear offsets (and tap weights) in registers
       int zsy[kGradZPer], zsx[kGradZPer];
+      float zw[kGradZPer][LIN ? 4 : 1];
 #pragma unroll
       for (int i = 0; i < kGradZPer; ++i) {
         const int z = zb + tz + kGradTZ * i;
         zsy[i] = sh[z < nz ? z : 0].x - pk.miny;
         zsx[i] = sh[z < nz ? z : 0].y - pk.minx;
+        if constexpr (LIN) {
+          const int zc = z < nz ? z : 0;
+          const float ry = A.shw[2 * (m * nz + zc)], rx = A.shw[2 * (m * nz + zc) + 1];
+          zw[i][0] = (1.f - ry) * (1.f - rx);
+          zw[i][LIN ? 1 : 0] = (1.f - ry) * rx;
+          zw[i][LIN ? 2 : 0] = ry * (1.f - rx);
+          zw[i][LIN ? 3 : 0] = ry * rx;
+        }
       }
       // Frames of the minibatch, B at a time (uniform walk, scalar results).
       // Each lane reads its footprint-gradient values straight from the frame's slot:
@@ -186,7 +197,16 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
           }
           const cplx* sl = slots + fso[k];
 #pragma unroll
-          for (int i = 0; i < kGradZPer; ++i) gv[k][i] = sl[(ac + zsy[i]) * pk.fx + bc + zsx[i]];
+          for (int i = 0; i < kGradZPer; ++i) {
+            const cplx* q = sl + (ac + zsy[i]) * pk.fx + bc + zsx[i];
+            if constexpr (LIN) {
+              const cplx q00 = q[0], q01 = q[1], q10 = q[pk.fx], q11 = q[pk.fx + 1];
+              gv[k][i] = cadd(cadd(cscale(q00, zw[i][0]), cscale(q01, zw[i][LIN ? 1 : 0])),
+                              cadd(cscale(q10, zw[i][LIN ? 2 : 0]), cscale(q11, zw[i][LIN ? 3 : 0])));
+            } else {
+              gv[k][i] = q[0];
+            }
+          }
         }
 #pragma unroll
         for (int k = 0; k < B; ++k)
@@ -444,12 +464,16 @@ bool frame_instance(int D, int FB) { return frames_op(2, D, FB, nullptr, 0, null
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s) {
   const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
-#define MPBP_PROJ(g)                                                                    \
-  case g:                                                                               \
-    if (a.probe3)                                                                       \
-      k_project<g, true><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);         \
-    else                                                                                \
-      k_project<g, false><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);        \
+#define MPBP_PROJ(g)                                                                          \
+  case g:                                                                                     \
+    if (a.probe3 && a.shw)                                                                    \
+      k_project<g, true, true><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);         \
+    else if (a.probe3)                                                                        \
+      k_project<g, true, false><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);        \
+    else if (a.shw)                                                                           \
+      k_project<g, false, true><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);        \
+    else                                                                                      \
+      k_project<g, false, false><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);       \
     break;
   switch (G) {
     MPBP_PROJ(2)
@@ -472,23 +496,32 @@ static const int kDets[] = {32, 64, 96, 128, 192, 256};
 
 #define MPBP_GRAD_INSTANCES(X) X(1, 16) X(2, 16) X(4, 16) X(1, 8) X(2, 8) X(4, 8)
 
+template <int B, int TX, bool P3, bool LIN>
+static hipError_t grad_set_lds() {
+  return hipFuncSetAttribute((const void*)k_grad<B, TX, P3, LIN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             160 * 1024);
+}
+
 hipError_t prepare_kernels() {
   hipError_t e = hipSuccess;
   for (int D : kDets)
     for (int FB : {32, 48, 64, D})
       if (e == hipSuccess && frame_instance(D, FB)) e = frames_op(1, D, FB, nullptr, 0, nullptr);
-  const void* projs[] = {(const void*)k_project<2, false>, (const void*)k_project<4, false>,
-                         (const void*)k_project<8, false>, (const void*)k_project<2, true>,
-                         (const void*)k_project<4, true>, (const void*)k_project<8, true>};
+  const void* projs[] = {
+      (const void*)k_project<2, false, false>, (const void*)k_project<4, false, false>,
+      (const void*)k_project<8, false, false>, (const void*)k_project<2, true, false>,
+      (const void*)k_project<4, true, false>,  (const void*)k_project<8, true, false>,
+      (const void*)k_project<2, false, true>,  (const void*)k_project<4, false, true>,
+      (const void*)k_project<8, false, true>,  (const void*)k_project<2, true, true>,
+      (const void*)k_project<4, true, true>,   (const void*)k_project<8, true, true>};
   for (const void* f : projs)
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 #define MPBP_CASE(b, tx)                                                                        \
   if (e == hipSuccess)                                                                          \
-    e = hipFuncSetAttribute((const void*)k_grad<b, tx, false>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                            160 * 1024);                                                        \
-  if (e == hipSuccess)                                                                          \
-    e = hipFuncSetAttribute((const void*)k_grad<b, tx, true>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                            160 * 1024);
+    e = grad_set_lds<b, tx, false, false>();                                                    \
+  if (e == hipSuccess) e = grad_set_lds<b, tx, true, false>();                                  \
+  if (e == hipSuccess) e = grad_set_lds<b, tx, false, true>();                                  \
+  if (e == hipSuccess) e = grad_set_lds<b, tx, true, true>();
   MPBP_GRAD_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
   return e;
@@ -498,10 +531,14 @@ hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, 
   const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
 #define MPBP_CASE(b, tx)                                                       \
   if (batch == b && tile_x == tx) {                                            \
-    if (a.probe3)                                                              \
-      k_grad<b, tx, true><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);  \
-    else                                                                       \
-      k_grad<b, tx, false><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a); \
+    if (a.probe3 && a.shw)                                                              \
+      k_grad<b, tx, true, true><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);     \
+    else if (a.probe3)                                                                  \
+      k_grad<b, tx, true, false><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);    \
+    else if (a.shw)                                                                     \
+      k_grad<b, tx, false, true><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);    \
+    else                                                                                \
+      k_grad<b, tx, false, false><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);   \
     return hipGetLastError();                                                  \
   }
   MPBP_GRAD_INSTANCES(MPBP_CASE)

@@ -74,6 +74,8 @@ struct mpbp_plan_t {
   long long nvox = 0;
   long long tied = 0;              // ny * nx under MPBP_Z_TIED, else 0
   int probe3 = 0;                  // MPBP_PROBE_3D: probe [M][nz][np][np]
+  int linear = 0;                  // MPBP_SHEAR_LINEAR: fractional exit-beam offsets
+  std::vector<float> shw;          // [M][nz][2] their fractions (MPBP_SHEAR_LINEAR)
   int64_t F = 0, ylen = 0;
   std::vector<mpbp_peak> peaks;
   std::vector<PeakDev> pdev;
@@ -114,6 +116,7 @@ struct mpbp_plan_t {
   int* d_scan = nullptr;
   int* d_peak_of = nullptr;
   int* d_shear = nullptr;
+  float* d_shw = nullptr;          // [M][nz][2] fractional offsets (MPBP_SHEAR_LINEAR)
   int* d_order = nullptr;          // full-batch processing order
   int* d_list = nullptr;           // caller's list (subset calls)
   int* d_list_sorted = nullptr;    // the caller's list grouped by detector size
@@ -178,6 +181,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_scan);
   (void)hipFree(p->d_peak_of);
   (void)hipFree(p->d_shear);
+  (void)hipFree(p->d_shw);
   (void)hipFree(p->d_order);
   (void)hipFree(p->d_list);
   (void)hipFree(p->d_list_sorted);
@@ -200,8 +204,9 @@ void free_device(mpbp_plan_t* p) {
 // Build tables and per-peak constants on the host; validate the problem.
 mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   if (!pr) return fail(MPBP_ERR_INVALID, "problem is NULL");
-  if (pr->flags & ~(uint32_t)(MPBP_Z_TIED | MPBP_PROBE_3D))
-    return fail(MPBP_ERR_INVALID, "unknown flags 0x%x (MPBP_Z_TIED and MPBP_PROBE_3D are defined)", pr->flags);
+  if (pr->flags & ~(uint32_t)(MPBP_Z_TIED | MPBP_PROBE_3D | MPBP_SHEAR_LINEAR))
+    return fail(MPBP_ERR_INVALID, "unknown flags 0x%x (MPBP_Z_TIED, MPBP_PROBE_3D and MPBP_SHEAR_LINEAR are defined)",
+                pr->flags);
   if (pr->nz < 1 || pr->ny < 1 || pr->nx < 1)
     return fail(MPBP_ERR_SHAPE, "object grid must be positive (nz=%d ny=%d nx=%d)", pr->nz, pr->ny, pr->nx);
   if (pr->probe_n < 1) return fail(MPBP_ERR_SHAPE, "probe_n must be positive (%d)", pr->probe_n);
@@ -219,9 +224,11 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   p->nvox = nvox;
   p->tied = (pr->flags & MPBP_Z_TIED) ? (long long)pr->ny * pr->nx : 0;
   p->probe3 = (pr->flags & MPBP_PROBE_3D) ? 1 : 0;
+  p->linear = (pr->flags & MPBP_SHEAR_LINEAR) ? 1 : 0;
   p->peaks.assign(pr->peaks, pr->peaks + pr->n_peaks);
   p->pdev.assign(p->M, PeakDev{});
   p->shear.assign((size_t)p->M * p->nz * 2, 0);
+  p->shw.assign((size_t)p->M * p->nz * 2, 0.f);
   p->y_off.assign(p->M + 1, 0);
   p->scan.clear();
   p->peak_of.clear();
@@ -245,15 +252,18 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
       return fail(MPBP_ERR_SHAPE, "peak %d: raster step must be positive", m);
     if ((long long)k.scan_n[0] * k.scan_n[1] > (1LL << 24))
       return fail(MPBP_ERR_SHAPE, "peak %d: raster too large", m);
-    // shear offsets s_m(z) = round-half-away((z - nz/2) * t_m)
+    // shear offsets s_m(z) = round-half-away((z - nz/2) * t_m); under MPBP_SHEAR_LINEAR
+    // the floor of (z - nz/2) * t_m and its fraction (the slice also reaches s + 1)
     int lo[2] = {1 << 30, 1 << 30}, hi[2] = {-(1 << 30), -(1 << 30)};
     for (int z = 0; z < p->nz; ++z) {
       for (int c = 0; c < 2; ++c) {
-        double v = std::round((double)(z - zref) * k.shear[c]);
+        const double t = (double)(z - zref) * k.shear[c];
+        const double v = p->linear ? std::floor(t) : std::round(t);
         int s = (int)v;
         p->shear[((size_t)m * p->nz + z) * 2 + c] = s;
+        if (p->linear) p->shw[((size_t)m * p->nz + z) * 2 + c] = (float)(t - v);
         lo[c] = std::min(lo[c], s);
-        hi[c] = std::max(hi[c], s);
+        hi[c] = std::max(hi[c], s + p->linear);
       }
     }
     const int cw = (k.det - np) / 2;
@@ -392,6 +402,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_scan, p->F * 2);
   ALLOC(p->d_peak_of, p->F);
   ALLOC(p->d_shear, (size_t)p->M * p->nz * 2);
+  ALLOC(p->d_shw, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_order, p->F);
   ALLOC(p->d_list, p->F);
   ALLOC(p->d_list_sorted, p->F);
@@ -412,6 +423,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   if (e == hipSuccess) e = hipMemcpy(p->d_scan, p->scan.data(), p->scan.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_peak_of, p->peak_of.data(), p->peak_of.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_shear, p->shear.data(), p->shear.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_shw, p->shw.data(), p->shw.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), p->order.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_tw, p->tw.data(), p->tw.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy tables");
@@ -585,6 +597,7 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   a.grad = grad;
   a.xcd = p->xcd;
   a.probe3 = p->probe3;
+  a.shw = p->linear ? p->d_shw : nullptr;
   return a;
 }
 
@@ -612,6 +625,7 @@ mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const fl
   g.max_cand = p->max_cand;
   g.tied = p->tied != 0;
   g.probe3 = p->probe3;
+  g.shw = p->linear ? p->d_shw : nullptr;
   g.grad_u = grad_u; g.grad_chi = grad_chi;
   g.alpha_part = p->d_apart;
   return g;
@@ -1035,6 +1049,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
     plan->plain.bg = plan->d_bg;
     plan->plain.probe3 = plan->probe3;
+    plan->plain.shw = plan->linear ? plan->d_shw : nullptr;
     e = mpbp::plain_forward(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                             plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                             frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,
@@ -1092,6 +1107,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
     plan->plain.bg = plan->d_bg;
     plan->plain.probe3 = plan->probe3;
+    plan->plain.shw = plan->linear ? plan->d_shw : nullptr;
     e = mpbp::plain_loss_grad(&plan->plain, plan->pdev.data(), plan->d_peaks, plan->M, plan->nz, plan->ny,
                               plan->nx, plan->np, plan->d_shear, plan->scan.data(), plan->peak_of.data(),
                               frames, frames ? n : (int)plan->F, u, chi, alpha, (const float*)probe, y,

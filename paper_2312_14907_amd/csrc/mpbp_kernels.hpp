@@ -46,6 +46,7 @@ struct FrameArgs {
   int grad;                // 1: also compute the footprint gradient
   int xcd;                 // XCD-aware block order
   int probe3;              // 1: probe is [M][nz][np][np] (a 3D illumination volume)
+  const float* shw;        // [M][nz][2] fractional exit-beam offsets (null: rounded offsets)
 };
 
 struct GradArgs {
@@ -65,6 +66,7 @@ struct GradArgs {
   int max_cand;              // largest number of frames of one peak meeting one tile
   int tied;                  // 1: u, chi and their gradients per lateral pixel (z-sums)
   int probe3;                // 1: probe is [M][nz][np][np] (a 3D illumination volume)
+  const float* shw;          // [M][nz][2] fractional exit-beam offsets (null: rounded offsets)
   float* grad_u;
   float* grad_chi;
   double* alpha_part;      // [n_blocks][M]

@@ -19,6 +19,7 @@ __global__ __launch_bounds__(256) void k_pl_project(const float* __restrict__ ob
                                                     const int* __restrict__ shear,
                                                     const PeakDev* __restrict__ peaks, int m, int py,
                                                     int px, int nz, int ny, int nx, int np, int probe3,
+                                                    const float* __restrict__ shw,
                                                     float* __restrict__ psi) {
   const PeakDev pk = peaks[m];
   const int D = pk.D;
@@ -31,12 +32,20 @@ __global__ __launch_bounds__(256) void k_pl_project(const float* __restrict__ ob
   cplx acc = {0.f, 0.f};
   for (int z = 0; z < nz; ++z) {
     const cplx* P = P0 + z * pz;
-    const int a = wy - pk.c - shear[2 * (m * nz + z)];
-    const int b = wx - pk.c - shear[2 * (m * nz + z) + 1];
-    if ((unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np) {
-      const int oy = py + a, ox = px + b;
-      if ((unsigned)oy < (unsigned)ny && (unsigned)ox < (unsigned)nx)
-        acc = cadd(acc, cmul(P[a * np + b], O[((long long)z * ny + oy) * nx + ox]));
+    // taps (dy, dx): one of weight 1 for rounded offsets, four bilinear ones otherwise
+    const float ry = shw ? shw[2 * (m * nz + z)] : 0.f, rx = shw ? shw[2 * (m * nz + z) + 1] : 0.f;
+    for (int tp = 0; tp < (shw ? 4 : 1); ++tp) {
+      const int dy = tp >> 1, dx = tp & 1;
+      const float wt = (dy ? ry : 1.f - ry) * (dx ? rx : 1.f - rx);
+      const int a = wy - pk.c - shear[2 * (m * nz + z)] - dy;
+      const int b = wx - pk.c - shear[2 * (m * nz + z) + 1] - dx;
+      if ((unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np) {
+        const int oy = py + a, ox = px + b;
+        if ((unsigned)oy < (unsigned)ny && (unsigned)ox < (unsigned)nx) {
+          const cplx t = cmul(P[a * np + b], O[((long long)z * ny + oy) * nx + ox]);
+          acc = cadd(acc, shw ? cscale(t, wt) : t);
+        }
+      }
     }
   }
   reinterpret_cast<cplx*>(psi)[p] = acc;
@@ -131,7 +140,8 @@ __global__ __launch_bounds__(256) void k_pl_backproject(const float* __restrict_
                                                         const int* __restrict__ shear,
                                                         const PeakDev* __restrict__ peaks, int m,
                                                         int py, int px, int nz, int ny, int nx,
-                                                        int np, int probe3, float* __restrict__ gobj) {
+                                                        int np, int probe3, const float* __restrict__ shw,
+                                                        float* __restrict__ gobj) {
   const PeakDev pk = peaks[m];
   const int D = pk.D;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,7 +153,13 @@ __global__ __launch_bounds__(256) void k_pl_backproject(const float* __restrict_
   if ((unsigned)oy >= (unsigned)ny || (unsigned)ox >= (unsigned)nx) return;
   const int wy = a + pk.c + shear[2 * (m * nz + z)];
   const int wx = b + pk.c + shear[2 * (m * nz + z) + 1];
-  const cplx g = reinterpret_cast<const cplx*>(psi)[wy * D + wx];
+  const cplx* ps = reinterpret_cast<const cplx*>(psi);
+  cplx g = ps[wy * D + wx];
+  if (shw) {   // the adjoint of the four bilinear taps
+    const float ry = shw[2 * (m * nz + z)], rx = shw[2 * (m * nz + z) + 1];
+    g = cadd(cadd(cscale(g, (1.f - ry) * (1.f - rx)), cscale(ps[wy * D + wx + 1], (1.f - ry) * rx)),
+             cadd(cscale(ps[(wy + 1) * D + wx], ry * (1.f - rx)), cscale(ps[(wy + 1) * D + wx + 1], ry * rx)));
+  }
   const cplx p = reinterpret_cast<const cplx*>(probe)[((long long)m * (probe3 ? nz : 1) + (probe3 ? z : 0)) * np * np + ab];
   cplx* dst = reinterpret_cast<cplx*>(gobj) + (long long)m * nz * ny * nx + ((long long)z * ny + oy) * nx + ox;
   const float invD = 1.0f / (float)D;
@@ -264,7 +280,7 @@ static hipError_t plain_frames(PlainWork* w, const PeakDev* hp, const PeakDev* d
     const int py = hscan[2 * fid], px = hscan[2 * fid + 1];
     const long long yo = pk.y_off + (long long)(fid - pk.frame_base) * D * D;
     k_pl_project<<<dim3((D * D + 255) / 256), dim3(256), 0, s>>>(obj, probe, dshear, dp, m, py, px, nz, ny, nx, np,
-                                                                 w->probe3, w->psi);
+                                                                 w->probe3, w->shw, w->psi);
     k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, D, 1, 0);
     k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, 1, D, 0);
     k_pl_residual<<<dim3(D), dim3(256), 0, s>>>(w->psi, y ? y + yo : nullptr, w->bg ? w->bg + yo : nullptr, D,
@@ -274,7 +290,7 @@ static hipError_t plain_frames(PlainWork* w, const PeakDev* hp, const PeakDev* d
       k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, D, 1, 1);
       k_pl_fft<<<dim3(D), dim3(128), 0, s>>>(w->psi, D, 1, D, 1);
       k_pl_backproject<<<dim3((nz * np * np + 255) / 256), dim3(256), 0, s>>>(w->psi, probe, dshear, dp, m, py, px, nz,
-                                                                              ny, nx, np, w->probe3, w->gobj);
+                                                                              ny, nx, np, w->probe3, w->shw, w->gobj);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -20,6 +20,7 @@ struct PlainWork {
   int dmax = 0;
   const float* bg = nullptr;   // background b of eq. (2), ragged like y (set by the plan)
   int probe3 = 0;              // 1: probe [M][nz][np][np] (set by the plan)
+  const float* shw = nullptr;  // [M][nz][2] fractional exit-beam offsets or null (set by the plan)
 };
 
 void plain_free(PlainWork* w);

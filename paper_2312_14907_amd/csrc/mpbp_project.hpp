@@ -20,8 +20,11 @@ namespace mpbp {
 // pixel receives at most one value, so no two lanes collide; a barrier separates runs,
 // which keeps the order of every sum fixed.
 // P3: the probe varies along z (probe [M][nz][np][np]); P_z O_z is formed per slice
-// before the run sums.
-template <int G, bool P3>
+// before the run sums.  LIN: fractional exit-beam offsets (A.shw): a slice reaches the
+// offsets s0 + (dy, dx), dy, dx in {0, 1}, with bilinear weights; a run (equal s0)
+// keeps four weighted sums, and its additions go out one tap at a time (a barrier
+// between taps: within a tap no two lanes meet).
+template <int G, bool P3, bool LIN>
 __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
   constexpr int NT = kFrameThreads;
   const int tid = threadIdx.x;
@@ -75,15 +78,37 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   };
   // footprint offset of slice z's pixel (0, 0): (s_y - min s_y) fx + (s_x - min s_x)
   auto shift = [&](int z) { return (shz[2 * z] - pk.miny) * fx + (shz[2 * z + 1] - pk.minx); };
-  cplx w[kProjE];
+  constexpr int NW = LIN ? 4 : 1;   // weighted sums per run (taps)
+  cplx w[NW][kProjE];
   auto flush = [&](int d) {
-    __syncthreads();   // zeroing, or the previous run's additions, are complete
 #pragma unroll
-    for (int i = 0; i < kProjE; ++i) {
-      if ((i + 1) * NT <= np2 || tid + NT * i < np2) {   // uniform when every lane has a pixel
-        cplx* q = acc + fo[i] + d;
-        *q = cadd(*q, w[i]);
+    for (int tp = 0; tp < NW; ++tp) {
+      const int to = d + (tp >> 1) * fx + (tp & 1);   // tap (dy, dx) = (tp / 2, tp % 2)
+      __syncthreads();   // zeroing, or the previous additions, are complete
+#pragma unroll
+      for (int i = 0; i < kProjE; ++i) {
+        if ((i + 1) * NT <= np2 || tid + NT * i < np2) {   // uniform when every lane has a pixel
+          cplx* q = acc + fo[i] + to;
+          *q = cadd(*q, w[tp][i]);
+        }
       }
+    }
+  };
+  // add slice z's P O (v) into the run's sums
+  auto accumulate = [&](const cplx (&v)[kProjE], int z, bool first) {
+    if constexpr (LIN) {
+      const float ry = A.shw[2 * (m * nz + z)], rx = A.shw[2 * (m * nz + z) + 1];   // fractions
+      const float wt[4] = {(1.f - ry) * (1.f - rx), (1.f - ry) * rx, ry * (1.f - rx), ry * rx};
+#pragma unroll
+      for (int tp = 0; tp < 4; ++tp)
+#pragma unroll
+        for (int i = 0; i < kProjE; ++i) {
+          const cplx t = cscale(v[i], wt[tp]);
+          w[tp][i] = first ? t : cadd(w[tp][i], t);
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kProjE; ++i) w[0][i] = first ? v[i] : cadd(w[0][i], v[i]);
     }
   };
   cplx buf[G][kProjE], pbuf[G][P3 ? kProjE : 1];
@@ -91,7 +116,9 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   for (int g = 0; g < G; ++g) load(buf[g], pbuf[g], g);
   int cur = shift(0);
 #pragma unroll
-  for (int i = 0; i < kProjE; ++i) w[i] = {0.f, 0.f};
+  for (int tp = 0; tp < NW; ++tp)
+#pragma unroll
+    for (int i = 0; i < kProjE; ++i) w[tp][i] = {0.f, 0.f};
   for (int z0 = 0; z0 < nz; z0 += G) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -105,11 +132,9 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
         if (d != cur) {   // uniform: a new run
           flush(cur);
           cur = d;
-#pragma unroll
-          for (int i = 0; i < kProjE; ++i) w[i] = v[i];
+          accumulate(v, z, true);
         } else {
-#pragma unroll
-          for (int i = 0; i < kProjE; ++i) w[i] = cadd(w[i], v[i]);
+          accumulate(v, z, false);
         }
       }
     }
@@ -121,17 +146,19 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
 
 // Occupancy target: the fewer slices in flight, the fewer registers, the more
 // workgroups per CU.
-template <int G> struct ProjectWaves { static constexpr int value = G <= 2 ? 8 : G <= 4 ? 6 : 4; };
+template <int G, bool LIN> struct ProjectWaves {
+  static constexpr int value = LIN ? (G <= 2 ? 5 : G <= 4 ? 4 : 3) : (G <= 2 ? 8 : G <= 4 ? 6 : 4);
+};
 
-template <int G, bool P3>
-__global__ __launch_bounds__(kFrameThreads) __attribute__((amdgpu_waves_per_eu(ProjectWaves<G>::value)))
+template <int G, bool P3, bool LIN>
+__global__ __launch_bounds__(kFrameThreads) __attribute__((amdgpu_waves_per_eu(ProjectWaves<G, LIN>::value)))
 void k_project(FrameArgs A) {
   extern __shared__ cplx smem[];
   const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
   if (idx >= A.n_list) return;
   const int fid = A.list[idx];
   const PeakDev pk = A.peaks[A.peak_of[fid]];
-  project_body<G, P3>(A, pk, fid, smem);
+  project_body<G, P3, LIN>(A, pk, fid, smem);
 }
 
 }  // namespace mpbp

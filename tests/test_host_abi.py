@@ -74,10 +74,12 @@ def test_descriptor_validation_codes():
     assert _status_of(B.make_problem_struct(good))[0] == 0
     assert _status_of(None)[0] == 1                       # NULL problem
     s = B.make_problem_struct(good)
-    s.flags = 4
+    s.flags = 8
     assert _status_of(s)[0] == 1                          # undefined flag
     s.flags = B.MPBP_Z_TIED
     assert _status_of(s)[0] == 0                          # membrane parameterisation
+    s.flags = B.MPBP_Z_TIED | B.MPBP_PROBE_3D | B.MPBP_SHEAR_LINEAR
+    assert _status_of(s)[0] == 0                          # every defined flag together
     bad = _supported_problem(((0.3, 0.2), (0.1, -0.4)), dets=(32, 48))
     st, msg = _status_of(B.make_problem_struct(bad))
     assert st == 2 and "48" in msg                        # unsupported detector size
@@ -182,3 +184,16 @@ def test_unwrap_needs_a_device_plan():
     with pytest.raises(B.MPBPError) as e:
         B._check(B.lib.mpbp_unwrap_project(plan.handle, None, None, None))
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("name", ["c1_tiny", "c4_batch", "c5_full"])
+def test_linear_offset_tables_against_oracle(name):
+    # MPBP_SHEAR_LINEAR: the floors of the fractional offsets, bit-exact
+    import dataclasses
+    prob = dataclasses.replace(make_problem(get_config(name)), shear_linear=True)
+    plan = B.Plan(prob, device=-1, flags=B.MPBP_SHEAR_LINEAR)
+    scan, shear, y_off = plan.mpbp_tables()
+    tab = O.tables(prob)
+    np.testing.assert_array_equal(shear, tab["shear"])
+    np.testing.assert_array_equal(scan, tab["scan"])
+    assert (tab["shear_frac"] > 0).any()
