@@ -442,6 +442,7 @@ hipError_t frames_d96(int op, int fb, const FrameArgs* a, int lds_bytes, hipStre
 hipError_t frames_d128(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
 hipError_t frames_d192(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
 hipError_t frames_d256(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
+hipError_t frames_d150(int op, int fb, const FrameArgs* a, int lds_bytes, hipStream_t s);
 
 static hipError_t frames_op(int op, int D, int FB, const FrameArgs* a, int lds_bytes, hipStream_t s) {
   switch (D) {
@@ -451,6 +452,7 @@ static hipError_t frames_op(int op, int D, int FB, const FrameArgs* a, int lds_b
     case 128: return frames_d128(op, FB, a, lds_bytes, s);
     case 192: return frames_d192(op, FB, a, lds_bytes, s);
     case 256: return frames_d256(op, FB, a, lds_bytes, s);
+    case 150: return frames_d150(op, FB, a, lds_bytes, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -492,7 +494,7 @@ int project_lds_bytes(int np, int G) {
   return kProjPix * kFrameThreads * (int)sizeof(cplx);
 }
 
-static const int kDets[] = {32, 64, 96, 128, 192, 256};
+static const int kDets[] = {32, 64, 96, 128, 150, 192, 256};
 
 #define MPBP_GRAD_INSTANCES(X) X(1, 16) X(2, 16) X(4, 16) X(1, 8) X(2, 8) X(4, 8)
 
@@ -618,6 +620,7 @@ int frame_lds_bytes(int D, int fy, int fx, int fxp, bool grad) {
     case 128: return lds_for<128>(fy, fx, fxp, grad);
     case 192: return lds_for<192>(fy, fx, fxp, grad);
     case 256: return lds_for<256>(fy, fx, fxp, grad);
+    case 150: return lds_for<150>(fy, fx, fxp, grad);
     default: return -1;
   }
 }
@@ -649,6 +652,7 @@ bool frame_twiddles(int D, int fy, std::vector<float>& out) {
     case 128: twiddles_for<128>(fy, out); return true;
     case 192: twiddles_for<192>(fy, out); return true;
     case 256: twiddles_for<256>(fy, out); return true;
+    case 150: twiddles_for<150>(fy, out); return true;
     default: return false;
   }
 }
@@ -661,6 +665,7 @@ int frame_chunk_len(int D) {
     case 128: return ColLen<128>::L;
     case 192: return ColLen<192>::L;
     case 256: return ColLen<256>::L;
+    case 150: return ColLen<150>::L;
     default: return -1;
   }
 }

@@ -1,7 +1,7 @@
 // mpbp_dft.hpp - register-resident small DFTs and lane-cooperative line FFTs for gfx950.
 //
 // The far-field operator F of eq. (2) is a 2D DFT of the exit wave; every detector
-// size used here factors as D = P * Q with P, Q in {4, 8, 12, 16}.  A line of D points
+// size used here factors as D = P * Q with P, Q in {4, 5, 8, 10, 12, 15, 16}.  A line of D points
 // is transformed by a group of lanes of one wavefront with the four-step
 // decomposition (n = b + Q a, k = c + P d):
 //
@@ -60,6 +60,38 @@ __device__ constexpr double kSin48[48] = {
     -0.8660254037844386, -0.79335334029123572, -0.70710678118654768, -0.60876142900872088,
     -0.50000000000000044, -0.38268343236508956, -0.25881904510252157, -0.13052619222005168};
 
+// cos and sin of 2 pi k / n for any n, in double at compile time: the turn fraction k / n
+// is reduced to a quadrant exactly (integer arithmetic), then Taylor series on [0, pi/2).
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int i = 1; i < 16; ++i) {
+    t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int i = 1; i < 16; ++i) {
+    t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+    s += t;
+  }
+  return s;
+}
+constexpr double cos_turn(long k, long n) {
+  k = ((k % n) + n) % n;
+  const long q = (4 * k) / n, r = 4 * k - q * n;      // quadrant, remainder
+  const double t = (double)r / (double)n * (kPiD / 2.0);
+  return q == 0 ? taylor_cos(t) : q == 1 ? -taylor_sin(t) : q == 2 ? -taylor_cos(t) : taylor_sin(t);
+}
+constexpr double sin_turn(long k, long n) {
+  k = ((k % n) + n) % n;
+  const long q = (4 * k) / n, r = 4 * k - q * n;
+  const double t = (double)r / (double)n * (kPiD / 2.0);
+  return q == 0 ? taylor_sin(t) : q == 1 ? taylor_cos(t) : q == 2 ? -taylor_sin(t) : -taylor_cos(t);
+}
+
 // Multiply by w_N^K = exp(-+2 pi i K / N) (minus for the forward transform), with the
 // multiples of pi/4 done without general multiplies.
 template <int N, int K, bool INV>
@@ -83,11 +115,14 @@ __device__ __forceinline__ cplx twc(cplx a) {
     constexpr float sy0 = (o == 1 || o == 3) ? -1.f : 1.f;   // forward sign of sin
     constexpr float sy = INV ? -sy0 : sy0;
     return {h * (sx * a.x - sy * a.y), h * (sx * a.y + sy * a.x)};
-  } else {
-    static_assert(48 % N == 0, "twiddle table covers divisors of 48");
+  } else if constexpr (48 % N == 0) {
     constexpr int idx = k * (48 / N);
     constexpr float c = (float)kCos48[idx];
     constexpr float s = INV ? (float)kSin48[idx] : -(float)kSin48[idx];
+    return {a.x * c - a.y * s, a.x * s + a.y * c};
+  } else {
+    constexpr float c = (float)cos_turn(k, N);
+    constexpr float s = INV ? (float)sin_turn(k, N) : -(float)sin_turn(k, N);
     return {a.x * c - a.y * s, a.x * s + a.y * c};
   }
 }
@@ -130,6 +165,30 @@ struct DFT<3, INV> {
     x[0] = cadd(x[0], t);
     x[1] = cadd(m, j);
     x[2] = csub(m, j);
+  }
+};
+
+// X_k = sum_n x_n w^{n k}, w = exp(-+2 pi i / 5), from the pair sums x1 + x4, x2 + x3
+// and differences x1 - x4, x2 - x3 (w^4 = conj(w), w^3 = conj(w^2)).
+template <bool INV>
+struct DFT<5, INV> {
+  __device__ __forceinline__ static void run(cplx* x) {
+    constexpr float c1 = (float)cos_turn(1, 5), c2 = (float)cos_turn(2, 5);
+    constexpr float s1 = (float)sin_turn(1, 5), s2 = (float)sin_turn(2, 5);
+    const cplx t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    const cplx t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    const cplx m1 = {x[0].x + c1 * t1.x + c2 * t2.x, x[0].y + c1 * t1.y + c2 * t2.y};
+    const cplx m2 = {x[0].x + c2 * t1.x + c1 * t2.x, x[0].y + c2 * t1.y + c1 * t2.y};
+    const cplx n1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+    const cplx n2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+    // forward: X1 = m1 - i n1, X4 = m1 + i n1, X2 = m2 - i n2, X3 = m2 + i n2
+    const cplx j1 = INV ? cplx{-n1.y, n1.x} : cplx{n1.y, -n1.x};
+    const cplx j2 = INV ? cplx{-n2.y, n2.x} : cplx{n2.y, -n2.x};
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(m1, j1);
+    x[4] = csub(m1, j1);
+    x[2] = cadd(m2, j2);
+    x[3] = csub(m2, j2);
   }
 };
 
@@ -177,6 +236,8 @@ template <bool INV> struct DFT<6, INV>  { __device__ __forceinline__ static void
 template <bool INV> struct DFT<8, INV>  { __device__ __forceinline__ static void run(cplx* x) { dft_pq<4, 2, INV>(x); } };
 template <bool INV> struct DFT<12, INV> { __device__ __forceinline__ static void run(cplx* x) { dft_pq<4, 3, INV>(x); } };
 template <bool INV> struct DFT<16, INV> { __device__ __forceinline__ static void run(cplx* x) { dft_pq<4, 4, INV>(x); } };
+template <bool INV> struct DFT<10, INV> { __device__ __forceinline__ static void run(cplx* x) { dft_pq<5, 2, INV>(x); } };
+template <bool INV> struct DFT<15, INV> { __device__ __forceinline__ static void run(cplx* x) { dft_pq<5, 3, INV>(x); } };
 
 // Line configuration: D = P * Q; TPL lanes per line (power of two >= max(P, Q)).
 template <int D> struct LineCfg;
@@ -186,6 +247,8 @@ template <> struct LineCfg<96>  { static constexpr int P = 12, Q = 8,  TPL = 16;
 template <> struct LineCfg<128> { static constexpr int P = 16, Q = 8,  TPL = 16; };
 template <> struct LineCfg<192> { static constexpr int P = 16, Q = 12, TPL = 16; };
 template <> struct LineCfg<256> { static constexpr int P = 16, Q = 16, TPL = 16; };
+template <> struct LineCfg<50>  { static constexpr int P = 10, Q = 5,  TPL = 16; };
+template <> struct LineCfg<150> { static constexpr int P = 10, Q = 15, TPL = 16; };
 
 // Order LDS traffic between lanes of one wavefront (all lanes of a line live in one
 // wavefront, so no workgroup barrier is needed for the exchange).

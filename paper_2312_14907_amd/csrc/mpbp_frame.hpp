@@ -20,6 +20,7 @@ typedef __attribute__((address_space(3))) const cplx lds_cplx;   // LDS-addresse
 template <int D> struct ColLen { static constexpr int L = 64; };
 template <> struct ColLen<32> { static constexpr int L = 32; };
 template <> struct ColLen<96> { static constexpr int L = 96; };
+template <> struct ColLen<150> { static constexpr int L = 50; };
 
 __device__ __forceinline__ int frame_block_index(int b, int n, int xcd) {
   if (!xcd) return b;
@@ -171,6 +172,8 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
       for (int k0 = 0; k0 < L; k0 += RLINES) {
         const int kp = k0 + line;
         const int k = R * kp + r;
+        // chunk rows beyond L (when L is not a multiple of the lines per pass) have no work
+        const bool lok = (L % RLINES == 0) || kp < L;
         float yv[RQ], bv[BG ? RQ : 1];
 #pragma unroll
         for (int d = 0; d < RQ; ++d) yv[d] = ynext[d];
@@ -181,19 +184,21 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         {
           const int nk0 = k0 + RLINES < L ? k0 + RLINES : 0;
           const int nr = k0 + RLINES < L ? r : r + 1;
-          if (has_y && rowp(t) && nr < R) {
+          const bool nok = (L % RLINES == 0) || nk0 + line < L;
+          if (has_y && rowp(t) && nr < R && nok) {
             const float* yr = yf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
             for (int d = 0; d < RQ; ++d) ynext[d] = __builtin_nontemporal_load(yr + t + RP * d);
           }
           if constexpr (BG) {
-            if (rowp(t) && nr < R) {
+            if (rowp(t) && nr < R && nok) {
               const float* br = bgf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
               for (int d = 0; d < RQ; ++d) bnext[d] = __builtin_nontemporal_load(br + t + RP * d);
             }
           }
         }
+        if (!lok) continue;   // (uniform per line; the line's prefetch above is done)
         cplx v[RV];
         if (rowq(t)) {
 #pragma unroll

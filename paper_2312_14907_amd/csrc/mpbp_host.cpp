@@ -40,7 +40,7 @@ mpbp_status hip_fail(hipError_t e, const char* what) {
 }
 
 bool supported_det(int d) {
-  return d == 32 || d == 64 || d == 96 || d == 128 || d == 192 || d == 256;
+  return d == 32 || d == 64 || d == 96 || d == 128 || d == 150 || d == 192 || d == 256;
 }
 
 constexpr int kMaxPeaks = 16;
@@ -244,7 +244,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
       if (!std::isfinite(k.shear[c]) || std::fabs(k.shear[c]) > 1e6)
         return fail(MPBP_ERR_INVALID, "peak %d: shear not finite", m);
     if (!supported_det(k.det))
-      return fail(MPBP_ERR_SHAPE, "peak %d: detector size %d not in {32,64,96,128,192,256}", m, k.det);
+      return fail(MPBP_ERR_SHAPE, "peak %d: detector size %d not in {32,64,96,128,150,192,256}", m, k.det);
     if (np > k.det) return fail(MPBP_ERR_FOOTPRINT, "peak %d: probe support %d > window %d", m, np, k.det);
     if (k.scan_n[0] < 1 || k.scan_n[1] < 1)
       return fail(MPBP_ERR_SHAPE, "peak %d: raster must be positive (%d x %d)", m, k.scan_n[0], k.scan_n[1]);

@@ -1,8 +1,8 @@
 // mpbp_plain.hip - the plain path: for every listed frame, separate launches for the
 // projection, the two 1D passes of the forward DFT, the modulus residual, the two
 // passes of the inverse DFT and the back-projection, with the D x D exit wave in device
-// memory.  Line transforms are mixed-radix (2, 3) Stockham FFTs in LDS (Govindaraju et
-// al., SC 2008), one workgroup per line.
+// memory.  Line transforms are mixed-radix (2, 3, 5) Stockham FFTs in LDS (Govindaraju
+// et al., SC 2008), one workgroup per line.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,18 +63,20 @@ __global__ __launch_bounds__(256) void k_pl_fft(float* __restrict__ buf, int D, 
   cplx* dst = b;
   int rem = D;
   for (int ns = 1; ns < D;) {
-    const int R = (rem % 3 == 0) ? 3 : 2;
+    const int R = (rem % 5 == 0) ? 5 : (rem % 3 == 0) ? 3 : 2;
     const int nb = D / R;
     for (int j = tid; j < nb; j += blockDim.x) {
       const int k = j % ns;
-      cplx v[3];
+      cplx v[5];
       for (int r = 0; r < R; ++r) {
         cplx x = src[j + r * nb];
         double s, c;
         sincospi((inv ? 2.0 : -2.0) * (double)(k * r) / (double)(ns * R), &s, &c);
         v[r] = cmul(x, cplx{(float)c, (float)s});
       }
-      if (R == 3) {
+      if (R == 5) {
+        if (inv) DFT<5, true>::run(v); else DFT<5, false>::run(v);
+      } else if (R == 3) {
         if (inv) DFT<3, true>::run(v); else DFT<3, false>::run(v);
       } else {
         DFT<2, false>::run(v);

@@ -28,6 +28,23 @@ PEAKS = [
 
 _SEED_BASE = 231214907
 
+# The paper's numerical experiment (section 4, Table 1): a cubic lattice of 0.3905 nm, the
+# in-plane peaks [100], [110], [120], [210] at 9 keV (wavelength 0.1377 nm), a 150 x 150
+# detector, a 9 x 9 raster at a step of 6 pixels, and mean count rates of 83, 65, 52 and
+# 12 photons per detector pixel.  tan(theta) follows from Bragg's law, sin(theta) =
+# wavelength / (2 d), d = a / |hkl|.
+PAPER_LATTICE_NM = 0.3905
+PAPER_WAVELENGTH_NM = 0.1377
+PAPER_PEAKS = [(1, 0, 0), (1, 1, 0), (1, 2, 0), (2, 1, 0)]
+PAPER_COUNTS = [83.0, 65.0, 52.0, 12.0]
+
+
+def _paper_tan_theta(hkl):
+    import math
+    d = PAPER_LATTICE_NM / math.sqrt(sum(h * h for h in hkl))
+    s = PAPER_WAVELENGTH_NM / (2.0 * d)
+    return s / math.sqrt(1.0 - s * s)
+
 
 def _scan_step(n_obj, n_scan, probe_n):
     # Evenly spread raster covering the object: step = (N - Np) // (n - 1).
@@ -145,6 +162,30 @@ def _c5_crop8():
     return cfg
 
 
+def _c6():
+    # The paper-shaped workload: its detector, peaks, raster and count rates; the
+    # probe support (32) and the slab (24 of 32 slices) stay within what the kernels
+    # take, where the paper has a 100 x 100 probe and a 100-voxel window in x3.
+    peaks = []
+    for hkl, counts in zip(PAPER_PEAKS, PAPER_COUNTS):
+        peaks.append({"hkl": hkl, "tan_theta": _paper_tan_theta(hkl), "det": 150, "scan_n": (9, 9),
+                      "scan_step": (6, 6), "photons": counts * 150 * 150})
+    return {
+        "name": "c6_paper",
+        "index": 7,
+        "nz": 32, "ny": 200, "nx": 200,
+        "voxel_nm": 1.0,
+        "lattice_nm": PAPER_LATTICE_NM,
+        "probe_n": 32, "probe_fwhm": 12.0,
+        "slab": 24,
+        "chi_mode": "photons",
+        "grf_sigma": 0.02, "grf_corr": 4.0,
+        "steps": "three",
+        "noise": True,
+        "peaks": peaks,
+    }
+
+
 _BUILDERS = {
     "c1_tiny": _c1,
     "c2_forward": _c2,
@@ -152,6 +193,7 @@ _BUILDERS = {
     "c4_batch": _c4,
     "c5_full": _c5,
     "c5_crop8": _c5_crop8,
+    "c6_paper": _c6,
 }
 CONFIG_NAMES = tuple(_BUILDERS)
 

@@ -49,9 +49,9 @@ class Problem:
         return int(sum(self.frames_per_peak()))
 
 
-def bragg_vector(hkl):
-    """G_hkl = (2*pi/a) * (h, k, l) in rad/nm (cubic lattice)."""
-    return (2.0 * math.pi / LATTICE_A_NM) * np.asarray(hkl, dtype=np.float64)
+def bragg_vector(hkl, a_nm=LATTICE_A_NM):
+    """G_hkl = (2*pi/a) * (h, k, l) in rad/nm (cubic lattice of constant a_nm)."""
+    return (2.0 * math.pi / a_nm) * np.asarray(hkl, dtype=np.float64)
 
 
 def shear_direction(g, tan_theta):
@@ -82,7 +82,7 @@ def make_problem(cfg):
     origin = np.zeros((m, 2), dtype=np.int64)
     photons = []
     for k, pk in enumerate(cfg["peaks"]):
-        g[k] = bragg_vector(pk["hkl"])
+        g[k] = bragg_vector(pk["hkl"], cfg.get("lattice_nm", LATTICE_A_NM))
         shear[k] = shear_direction(g[k], pk["tan_theta"])
         det[k] = pk["det"]
         scan_n[k] = pk["scan_n"]
