@@ -194,6 +194,19 @@ def time_unwrap(prob, torch, calls):
     return out
 
 
+def time_paper_shape(torch, steps=20):
+    """The paper-shaped workload c6_paper (150 x 150 detectors, four in-plane peaks, 9 x 9
+    rasters): loss+gradient steps after autotuning, direct launches and graph replay."""
+    cfg, prob, f, plan, args_t = make_inputs("c6_paper", torch)
+    plan.mpbp_autotune(*args_t)
+    dt, _, _ = time_steps(plan, args_t, steps, 3, torch)
+    nfr = prob.n_frames()
+    t = plan.mpbp_tuning()
+    return {"workload": "c6_paper", "frames": nfr, "detector": 150, "peaks": prob.n_peaks,
+            "ms_per_step": round(1e3 * dt / steps, 4), "value": round(nfr * steps / dt, 1),
+            "unit": "scan-positions/s", "launch": [{k: c[k] for k in ("FB", "G", "xcd")} for c in t["classes"]]}
+
+
 def cpu_unwrap(prob):
     """The unwrap oracle on the z-tied maps of the workload (one per peak), seconds."""
     from threadpoolctl import threadpool_limits
@@ -366,6 +379,8 @@ def main():
 
     # the unwrap projector of eq. (10), the last step of Algorithm 1 (not part of `value`)
     out["unwrap"] = time_unwrap(prob, torch, 10)
+    # the paper-shaped workload (not part of `value`)
+    out["paper_shape"] = time_paper_shape(torch)
 
     if not args.no_cpu_baseline:
         n = args.cpu_frames or (1024 if prob.n_frames() >= 1024 else prob.n_frames())
