@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
         sh[z] = make_int2(s[0], s[1]);
       }
       // minibatch flags of the candidate frames, loaded in parallel
-      for (int c = tid; c < ncand; c += kGradThreads) {
+      for (int c = tid; c < (A.all_active ? 0 : ncand); c += kGradThreads) {
         const int cy = iy_lo + c / ncx, cx = ix_lo + c % ncx;
         actf[c] = A.active[pk.frame_base + cy * pk.cols + cx];
       }
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
           while (nb == k && iy <= iy_hi) {
             const int cy = iy, cx = ix;
             if (++ix > ix_hi) { ix = ix_lo; ++iy; }
-            const int act = __builtin_amdgcn_readfirstlane((int)actf[ci]);
+            const int act = A.all_active ? 1 : __builtin_amdgcn_readfirstlane((int)actf[ci]);
             ++ci;
             if (!act) continue;
             fpy[k] = pk.oy + cy * pk.sy;

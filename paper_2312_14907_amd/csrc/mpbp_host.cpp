@@ -612,6 +612,7 @@ mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const fl
   mpbp::GradArgs g{};
   g.slots = p->d_slots;
   g.active = subset ? p->d_active : p->d_active_all;
+  g.all_active = subset ? 0 : 1;
   g.probe = probe;
   g.u = u; g.chi = chi; g.alpha = alpha;
   g.shear = p->d_shear;

@@ -52,6 +52,7 @@ struct FrameArgs {
 struct GradArgs {
   const float* slots;      // complex64 footprint gradients
   const unsigned char* active;  // [F] 1 if the frame is in the minibatch
+  int all_active;          // 1: every frame is (full batch): the flags are not read
   const float* probe;
   const float* u;
   const float* chi;
