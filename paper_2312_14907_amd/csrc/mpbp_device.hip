@@ -65,6 +65,22 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
   return s;
 }
 
+// The peak record is the same for every lane: read it once and pass each word through
+// readfirstlane, so that the raster walk and the slot bases derived from it live in
+// scalar registers (a plain load from the table leaves them in vector registers, since
+// the compiler cannot prove the table unchanged by the kernel's own stores).
+__device__ __forceinline__ PeakDev uniform_peak(const PeakDev* p) {
+  static_assert(sizeof(PeakDev) % 4 == 0, "PeakDev is read as 32-bit words");
+  constexpr int kWords = sizeof(PeakDev) / 4;
+  int w[kWords];
+  __builtin_memcpy(w, p, sizeof(PeakDev));
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  PeakDev pk;
+  __builtin_memcpy(&pk, w, sizeof(PeakDev));
+  return pk;
+}
+
 // B: frames whose footprint gradients are read per step of the frame walk.  TX: tile
 // width (TX x TY voxels per slice, TX * TY = 64: one wavefront per slice).  The tile
 // grid starts at (tile_oy, tile_ox) <= 0, so that a grid aligned with a raster of step
@@ -109,7 +125,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
     for (int i = 0; i < kGradZPer; ++i) gux[i] = guy[i] = guz[i] = gch[i] = 0.f;
 
     for (int m = 0; m < A.n_peaks; ++m) {
-      const PeakDev pk = A.peaks[m];
+      const PeakDev pk = uniform_peak(A.peaks + m);
       // Frames of this peak whose windows meet the tile: a rectangle of the raster.
       const int iy_lo = max(0, -floordiv(-(y0 - np + 1 - pk.oy), pk.sy));
       const int iy_hi = min(pk.rows - 1, floordiv(y0 + TY - 1 - pk.oy, pk.sy));
@@ -195,10 +211,12 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
             const cplx pr = Ps[ac * np + bc];
             pv[k] = inw ? pr : cplx{0.f, 0.f};
           }
-          const cplx* sl = slots + fso[k];
+          // uniform slot base + 32-bit lane offset (a slot holds fewer than 2^29 values)
+          const char* sl = reinterpret_cast<const char*>(slots + fso[k]);
 #pragma unroll
           for (int i = 0; i < kGradZPer; ++i) {
-            const cplx* q = sl + (ac + zsy[i]) * pk.fx + bc + zsx[i];
+            const unsigned off = (unsigned)((ac + zsy[i]) * pk.fx + bc + zsx[i]) * (unsigned)sizeof(cplx);
+            const cplx* q = reinterpret_cast<const cplx*>(sl + off);
             if constexpr (LIN) {
               const cplx q00 = q[0], q01 = q[1], q10 = q[pk.fx], q11 = q[pk.fx + 1];
               gv[k][i] = cadd(cadd(cscale(q00, zw[i][0]), cscale(q01, zw[i][LIN ? 1 : 0])),
