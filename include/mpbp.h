@@ -6,17 +6,20 @@
  * fields with multi-peak Bragg ptychography", sections 2-3):
  *
  *   eq. (1), eq. (3)  O_m(r)  = alpha_m * chi(r) * exp(i G_m . u(r))   (G_m in rad/nm)
- *   eq. (2)           I_{m,j} = | F R_m diag(P_m) S_{m,j} O_m |^2       (background b = 0)
+ *   eq. (2)           I_{m,j} = | F R_m diag(P_m) S_{m,j} O_m |^2 + b_{m,j}
  *   eq. (4)           f       = 1/2 sum_{m,j} || I_{m,j}^{1/2} - y_{m,j}^{1/2} ||^2
  *   eq. (11)          minibatch: f and its gradient summed over a subset of the frames
  *
  * S_{m,j} places the probe support (probe_n x probe_n) at scan position j of peak m's
- * raster.  The probe is constant along the incident beam x3 (section 4).  R_m projects
- * the illuminated object along the exit beam: slice z is offset laterally by the
- * integer shear s_m(z) = round_half_away((z - nz/2) * t_m), inside a D_m x D_m
- * exit-wave window whose probe support starts at c_m = (D_m - probe_n) / 2.  F is the
+ * raster.  The probe is constant along the incident beam x3 (section 4), or given per
+ * slice under MPBP_PROBE_3D.  R_m projects the illuminated object along the exit beam:
+ * slice z is offset laterally by the integer shear s_m(z) = round_half_away((z - nz/2)
+ * * t_m), or, under MPBP_SHEAR_LINEAR, by the exact offset (z - nz/2) * t_m with
+ * bilinear weights over its four neighbouring pixels; all inside a D_m x D_m exit-wave
+ * window whose probe support starts at c_m = (D_m - probe_n) / 2.  F is the
  * orthonormal 2D DFT, kernel exp(-2 pi i k.x / D), DC at index [0][0] (no shift); the
- * measured intensities y use the same unshifted layout.
+ * measured intensities y and the background b use the same unshifted layout.  b = 0
+ * unless set with mpbp_set_background.
  *
  * Layouts (all row-major, x fastest; "(dev)" = device memory of the plan's GPU,
  * "(host)" = host memory).  The caller owns every buffer it passes.

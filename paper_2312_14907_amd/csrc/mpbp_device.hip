@@ -310,41 +310,65 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
 }
 
 // --------------------------------------------------------------------- finalize ---
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ floss,
-                                                  const int* __restrict__ out_list, int n_out,
-                                                  double* loss, float* frame_loss,
-                                                  const double* __restrict__ apart, int n_part,
-                                                  int n_peaks, float* grad_alpha) {
-  __shared__ double red[256];
+// One workgroup of 1024 lanes.  Each lane reads its values in batches of kFinBatch
+// independent loads (a loop of one load per add would wait a full memory latency per
+// value), adds them in index order, and the lanes' partials are combined in a fixed
+// order: the sums are deterministic.
+constexpr int kFinThreads = 1024;
+constexpr int kFinBatch = 8;
+
+__device__ __forceinline__ double fin_block_sum(double s, double* red) {
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kFinThreads / 64; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const double* __restrict__ floss,
+                                                          const int* __restrict__ out_list, int n_out,
+                                                          double* __restrict__ loss,
+                                                          float* __restrict__ frame_loss,
+                                                          const double* __restrict__ apart, int n_part,
+                                                          int n_peaks, float* __restrict__ grad_alpha) {
+  __shared__ double red[kFinThreads / 64];
   const int tid = threadIdx.x;
   if (loss || frame_loss) {
     double s = 0.0;
-    for (int i = tid; i < n_out; i += 256) {
-      double v = floss[out_list ? out_list[i] : i];
-      s += v;
-      if (frame_loss) frame_loss[i] = (float)v;
+    for (int i0 = 0; i0 < n_out; i0 += kFinBatch * kFinThreads) {
+      double v[kFinBatch];
+#pragma unroll
+      for (int u = 0; u < kFinBatch; ++u) {
+        const int i = i0 + u * kFinThreads + tid;
+        v[u] = i < n_out ? floss[out_list ? out_list[i] : i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kFinBatch; ++u) {
+        const int i = i0 + u * kFinThreads + tid;
+        s += v[u];
+        if (frame_loss && i < n_out) frame_loss[i] = (float)v[u];
+      }
     }
-    red[tid] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0 && loss) *loss = red[0];
-    __syncthreads();
+    const double t = fin_block_sum(s, red);
+    if (tid == 0 && loss) *loss = t;
   }
   if (grad_alpha) {
     for (int m = 0; m < n_peaks; ++m) {
       double s = 0.0;
-      for (int i = tid; i < n_part; i += 256) s += apart[(long long)i * n_peaks + m];
-      red[tid] = s;
-      __syncthreads();
-      for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
+      for (int i0 = 0; i0 < n_part; i0 += kFinBatch * kFinThreads) {
+        double v[kFinBatch];
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u) {
+          const int i = i0 + u * kFinThreads + tid;
+          v[u] = i < n_part ? apart[(long long)i * n_peaks + m] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinBatch; ++u) s += v[u];
       }
-      if (tid == 0) grad_alpha[m] = (float)red[0];
-      __syncthreads();
+      const double t = fin_block_sum(s, red);
+      if (tid == 0) grad_alpha[m] = (float)t;
     }
   }
 }
@@ -569,7 +593,7 @@ hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, 
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
                            float* grad_alpha, hipStream_t s) {
-  k_finalize<<<dim3(1), dim3(256), 0, s>>>(floss, out_list, n_out, loss, frame_loss, apart, n_part, n_peaks, grad_alpha);
+  k_finalize<<<dim3(1), dim3(kFinThreads), 0, s>>>(floss, out_list, n_out, loss, frame_loss, apart, n_part, n_peaks, grad_alpha);
   return hipGetLastError();
 }
 
