@@ -163,6 +163,45 @@ def cpu_baseline(prob, f, y_dev, n_frames):
     return n_frames / dt, dt
 
 
+def cpu_baseline_all_cores(workload, n_frames, total_frames):
+    """The same oracle call in W concurrent CPU-only child processes (W = the host cores
+    this process may use, at most 16), each on its own minibatch of n_frames frames and
+    one thread; set-up happens before a common start, so the wall time from the start to
+    the last finish covers W oracle calls."""
+    import subprocess
+    import tempfile
+    w_count = max(1, min(len(os.sched_getaffinity(0)), 16))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    go = os.path.join(tempfile.mkdtemp(prefix="mpbp_cpu_"), "go")
+    span = max(1, total_frames - n_frames + 1)
+    procs = [subprocess.Popen([sys.executable, "-m", "oracle.time_worker", workload,
+                               str((w * n_frames) % span), str(n_frames), go],
+                              cwd=ROOT, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                              text=True) for w in range(w_count)]
+    try:
+        for p in procs:
+            if p.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle timing worker failed: " + p.stderr.read()[-2000:])
+        t0 = time.perf_counter()
+        open(go, "w").close()
+        outs = [p.communicate(timeout=900) for p in procs]
+        wall = time.perf_counter() - t0
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+    for p, (out, err) in zip(procs, outs):
+        if p.returncode != 0:
+            raise RuntimeError("oracle timing worker failed: " + err[-2000:])
+    calls = [float(o.strip().splitlines()[-1]) for o, _ in outs]
+    return {"value": round(w_count * n_frames / wall, 2), "unit": "scan-positions/s", "cores": w_count,
+            "kind": "oracle",
+            "sample": f"{w_count} concurrent single-thread processes, each the FP64 oracle's "
+                      f"loss+gradient on its own {n_frames}-frame minibatch of {workload}: "
+                      f"{wall:.1f} s wall (calls {min(calls):.1f}-{max(calls):.1f} s)"}
+
+
 def unwrap_inputs(prob, nz):
     """Seeded displacement field on the workload's grid for the unwrap projector: a
     smooth strain field with noise and one lattice-translation artefact on a patch."""
@@ -393,6 +432,7 @@ def main():
             "sample": f"FP64 oracle loss+gradient over the first {n} frames (a minibatch of "
                       f"{args.workload}), including its whole-volume object build and chain "
                       f"rule: {cdt:.1f} s"}
+        out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(args.workload, n, prob.n_frames())
         if "unwrap" in out:
             usec = cpu_unwrap(prob)
             out["cpu_baseline"]["unwrap_tied_s_per_call"] = round(usec, 3)

@@ -1,0 +1,32 @@
+"""The benchmark's CPU-baseline leg on all host cores: CPU-only worker processes run the
+unchanged oracle on their own minibatches behind a common start (c1_tiny, a few frames)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_all_cores_leg_reports_every_worker():
+    r = bench.cpu_baseline_all_cores("c1_tiny", 8, 75)
+    assert r["kind"] == "oracle" and r["unit"] == "scan-positions/s"
+    assert 1 <= r["cores"] <= 16 and r["value"] > 0
+    assert f"{r['cores']} concurrent" in r["sample"]
+
+
+def test_worker_waits_for_the_start_file(tmp_path):
+    go = tmp_path / "go"
+    p = subprocess.Popen([sys.executable, "-m", "oracle.time_worker", "c1_tiny", "10", "5", str(go)],
+                         cwd=ROOT, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    try:
+        assert p.stdout.readline().strip() == "ready"
+        assert p.poll() is None              # still waiting: nothing timed before the start
+        go.write_text("")
+        out, err = p.communicate(timeout=120)
+    finally:
+        if p.poll() is None:
+            p.kill()
+    assert p.returncode == 0, err
+    assert float(out.strip().splitlines()[-1]) > 0
