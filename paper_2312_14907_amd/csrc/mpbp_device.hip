@@ -151,14 +151,22 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       for (int i = 0; i < kGradZPer; ++i) acc[i] = {0.f, 0.f};
       __syncthreads();
 
-      // this lane's slices: shear offsets (and tap weights) in registers
+      // this lane's slices: shear offsets (and tap weights) in registers.  With integer
+      // offsets and one probe for all slices, a slice whose offset equals the previous
+      // slice's reads the same footprint pixel with the same probe value: its sum over
+      // the frames is the previous slice's, so it skips the walk (same[i], uniform per
+      // wavefront: the lanes of one wavefront share their slices).
+      constexpr bool kRuns = !LIN && !P3;
       int zsy[kGradZPer], zsx[kGradZPer];
+      bool same[kGradZPer];
       float zw[kGradZPer][LIN ? 4 : 1];
 #pragma unroll
       for (int i = 0; i < kGradZPer; ++i) {
-        const int z = zb + tz + kGradTZ * i;
+        const int z = zb + tz * kGradZPer + i;
         zsy[i] = sh[z < nz ? z : 0].x - pk.miny;
         zsx[i] = sh[z < nz ? z : 0].y - pk.minx;
+        same[i] = __builtin_amdgcn_readfirstlane(
+                      (int)(kRuns && i > 0 && z < nz && zsy[i] == zsy[i - 1] && zsx[i] == zsx[i - 1])) != 0;
         if constexpr (LIN) {
           const int zc = z < nz ? z : 0;
           const float ry = A.shw[2 * (m * nz + zc)], rx = A.shw[2 * (m * nz + zc) + 1];
@@ -203,7 +211,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
           if constexpr (P3) {
 #pragma unroll
             for (int i = 0; i < kGradZPer; ++i) {
-              const int z = zb + tz + kGradTZ * i;
+              const int z = zb + tz * kGradZPer + i;
               const cplx pr = probe[(long long)(z < nz ? z : 0) * np * np + ac * np + bc];
               pz[k][i] = inw ? pr : cplx{0.f, 0.f};
             }
@@ -215,6 +223,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
           const char* sl = reinterpret_cast<const char*>(slots + fso[k]);
 #pragma unroll
           for (int i = 0; i < kGradZPer; ++i) {
+            if (same[i]) continue;
             const unsigned off = (unsigned)((ac + zsy[i]) * pk.fx + bc + zsx[i]) * (unsigned)sizeof(cplx);
             const cplx* q = reinterpret_cast<const cplx*>(sl + off);
             if constexpr (LIN) {
@@ -230,8 +239,11 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
         for (int k = 0; k < B; ++k)
 #pragma unroll
           for (int i = 0; i < kGradZPer; ++i)   // conj(P) g_psi
-            acc[i] = cadd(acc[i], cmulc(gv[k][i], P3 ? pz[k][P3 ? i : 0] : pv[k]));
+            if (!same[i]) acc[i] = cadd(acc[i], cmulc(gv[k][i], P3 ? pz[k][P3 ? i : 0] : pv[k]));
       }
+#pragma unroll
+      for (int i = 1; i < kGradZPer; ++i)
+        if (same[i]) acc[i] = acc[i - 1];
       // chain rule through O_m = alpha_m chi exp(i G_m . u); 32-bit voxel offsets from
       // uniform bases (the plan limits 3 * nvox to 2^32)
       float ap = 0.f;
@@ -240,7 +252,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
         const unsigned nv = (unsigned)nvox;
 #pragma unroll
         for (int i = 0; i < kGradZPer; ++i) {
-          const int z = zb + tz + kGradTZ * i;
+          const int z = zb + tz * kGradZPer + i;
           if (z < nz) {
             const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
             const unsigned vf = A.tied ? lat : v;
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       const unsigned nv = (unsigned)nvox;
 #pragma unroll
       for (int i = 0; i < kGradZPer; ++i) {
-        const int z = zb + tz + kGradTZ * i;
+        const int z = zb + tz * kGradZPer + i;
         if (z < nz) {
           const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
           A.grad_u[v] = gux[i];
