@@ -661,8 +661,9 @@ static int lds_for(int fy, int fx, int fxp, bool grad) {
   constexpr int RLINES = kFrameThreads / RC::TPL;
   constexpr int EXL = RC::Q * (RC::P + 1);
   const long long exch = (RLINES * EXL + 1) / 2;
-  const long long cpx = D + L + (long long)(D / L) * fy + (long long)fy * fx +
-                        (grad ? (long long)fy * fx : 0) + (long long)L * fxp + L / 8 + exch;
+  (void)fx;
+  (void)grad;   // the exit wave and its gradient stay in the slots
+  const long long cpx = D + L + (long long)(D / L) * fy + (long long)L * fxp + L / 8 + exch;
   return (int)(cpx * 8);
 }
 

@@ -70,16 +70,15 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   //   tw2  [D]      row twiddles, tw2[c * RQ + t] = w_D^{t c} (lane-contiguous)
   //   twc  [L]      column twiddles, twc[c * CQ + t] = w_L^{t c}
   //   ftw  [R][fy]  residue-fold twiddles w_D^{rr r}
-  //   psi  [fy][fx] exit wave on the footprint
-  //   gacc [fy][fx] footprint gradient
   //   Tr   [L][fxp] chunk of the column-transformed footprint, row k at k*fxp + k/8
   //   exch          per-line exchange buffers
+  // The exit wave and the footprint gradient stay in device memory (the frame's slots;
+  // they are L2-resident while the frame runs): without them the kernel fits three
+  // workgroups per CU instead of two.
   cplx* tw2 = sm;
   cplx* twc = tw2 + D;
   cplx* ftw = twc + L;
-  cplx* psi = ftw + R * fy;
-  cplx* gacc = psi + fy * fx;
-  cplx* Tr = gacc + (A.grad ? fy * fx : 0);
+  cplx* Tr = ftw + R * fy;
   cplx* exch = Tr + L * fxp + L / 8;
 
   {
@@ -87,11 +86,12 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
     for (int k = tid; k < D + L + R * fy; k += NT) tw2[k] = tsrc[k];
   }
 
-  // ---- the exit wave on the footprint, left in the frame's slot by k_project ----
-  cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
-  for (int p = tid; p < fy * fx; p += NT) psi[p] = slot[p];
-  if (A.grad)
-    for (int k = tid; k < fy * fx; k += NT) gacc[k] = {0.f, 0.f};
+  // ---- the exit wave on the footprint, left in the frame's slot by k_project, and the
+  // slot of its gradient (each lane of the adjoint column pass owns the same elements
+  // in every chunk, so its read-modify-writes need no barrier) ----
+  const long long so = pk.slot_off + (long long)j * fy * fx;
+  const cplx* psi = reinterpret_cast<const cplx*>(A.slots) + so;
+  cplx* gacc = A.grad ? reinterpret_cast<cplx*>(A.gslots) + so : nullptr;
   __syncthreads();
 
   const bool has_y = A.y != nullptr;
@@ -324,24 +324,28 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           DFT<CP, true>::run(v);
           if constexpr (FB <= L) {
             cplx gv[NAC], tv[NAC];
+            // chunk 0 starts the sums; the last chunk applies the 1/D of the orthonormal
+            // transforms
+            const float sc = r == R - 1 ? invD : 1.0f;
 #pragma unroll
             for (int a = 0; a < NAC; ++a) {
               const int rr = t + CQ * a;
               const int rc = rr < fy ? rr : 0;
-              gv[a] = gacc[rc * fx + col];
+              gv[a] = r > 0 ? gacc[rc * fx + col] : cplx{0.f, 0.f};
               tv[a] = ftw[r * fy + rc];
             }
 #pragma unroll
             for (int a = 0; a < NAC; ++a) {
               const int rr = t + CQ * a;
-              if (rr < fy) gacc[rr * fx + col] = cadd(gv[a], cmulc(v[a], tv[a]));
+              if (rr < fy) gacc[rr * fx + col] = cscale(cadd(gv[a], cmulc(v[a], tv[a])), sc);
             }
           } else {
 #pragma unroll
             for (int a = 0; a < NAC; ++a) {
               for (int rr = t + CQ * a; rr < fy; rr += L) {
                 cplx* g = gacc + rr * fx + col;
-                *g = cadd(*g, cmulc(v[a], ftw[r * fy + rr]));
+                const cplx prev = r > 0 ? *g : cplx{0.f, 0.f};
+                *g = cscale(cadd(prev, cmulc(v[a], ftw[r * fy + rr])), r == R - 1 ? invD : 1.0f);
               }
             }
           }
@@ -352,9 +356,6 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
     }
   }
 
-  if (A.grad) {
-    for (int p = tid; p < fy * fx; p += NT) slot[p] = cscale(gacc[p], invD);
-  }
 
   if (has_y) {
     // workgroup sum of the per-lane losses (fixed order)

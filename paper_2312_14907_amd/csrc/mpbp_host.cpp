@@ -123,7 +123,8 @@ struct mpbp_plan_t {
   unsigned char* d_active = nullptr;     // per-frame minibatch mask (subset calls)
   unsigned char* d_active_all = nullptr; // all ones
   float* d_obj = nullptr;
-  float* d_slots = nullptr;
+  float* d_slots = nullptr;        // exit waves (k_project -> k_frames)
+  float* d_gslots = nullptr;       // footprint gradients (k_frames -> k_grad)
   double* d_floss = nullptr;
   double* d_apart = nullptr;
   double* d_red = nullptr;         // sum-of-squares partials (kRedParts)
@@ -189,6 +190,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_active_all);
   (void)hipFree(p->d_obj);
   (void)hipFree(p->d_slots);
+  (void)hipFree(p->d_gslots);
   (void)hipFree(p->d_floss);
   (void)hipFree(p->d_apart);
   (void)hipFree(p->d_red);
@@ -410,6 +412,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_active_all, p->F);
   ALLOC(p->d_obj, (size_t)p->M * p->nvox * 2);
   ALLOC(p->d_slots, (size_t)p->slots_cplx * 2);
+  ALLOC(p->d_gslots, (size_t)p->slots_cplx * 2);
   ALLOC(p->d_floss, p->F);
   ALLOC(p->d_apart, (size_t)p->max_tiles * p->M);
   ALLOC(p->d_red, kRedParts);
@@ -590,6 +593,7 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   a.peaks = p->d_peaks;
   a.shear = p->d_shear;
   a.slots = p->d_slots;
+  a.gslots = p->d_gslots;
   a.floss = p->d_floss;
   a.tw = p->d_tw;
   a.mi = mi;
@@ -610,7 +614,7 @@ const mpbp_plan_t::GradTiling& grad_tiling(mpbp_plan p) {
 mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const float* alpha,
                          const float* probe, bool subset, float* grad_u, float* grad_chi) {
   mpbp::GradArgs g{};
-  g.slots = p->d_slots;
+  g.slots = p->d_gslots;
   g.active = subset ? p->d_active : p->d_active_all;
   g.all_active = subset ? 0 : 1;
   g.probe = probe;
