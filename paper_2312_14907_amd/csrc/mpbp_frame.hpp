@@ -105,7 +105,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   // Intensities are prefetched one row-iteration ahead (across chunk boundaries) so the
   // HBM latency overlaps the transforms of the current rows.
   const int rline = tid / RT, rt = tid % RT;
-  float ynext[RQ], bnext[BG ? RQ : 1];
+  float ynext[RQ], bnext[BG ? RQ : 1], yalt[RQ], balt[BG ? RQ : 1];
   if (has_y && rowp(rt)) {
     const float* yr = yf + (long long)(R * rline) * D;
 #pragma unroll
@@ -169,18 +169,14 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
     {
       const int line = tid / RT, t = tid % RT;
       float* ex = reinterpret_cast<float*>(exch) + line * EXL;
-      for (int k0 = 0; k0 < L; k0 += RLINES) {
+      // One row iteration: the intensities (and background) of its rows are in yv (bv);
+      // those of the next iteration are prefetched into ynx (bnx).
+      auto row_iter = [&](int k0, const float (&yv)[RQ], float (&ynx)[RQ], const float (&bv)[BG ? RQ : 1],
+                          float (&bnx)[BG ? RQ : 1]) __attribute__((always_inline)) {
         const int kp = k0 + line;
         const int k = R * kp + r;
         // chunk rows beyond L (when L is not a multiple of the lines per pass) have no work
         const bool lok = (L % RLINES == 0) || kp < L;
-        float yv[RQ], bv[BG ? RQ : 1];
-#pragma unroll
-        for (int d = 0; d < RQ; ++d) yv[d] = ynext[d];
-        if constexpr (BG) {
-#pragma unroll
-          for (int d = 0; d < RQ; ++d) bv[d] = bnext[d];
-        }
         {
           const int nk0 = k0 + RLINES < L ? k0 + RLINES : 0;
           const int nr = k0 + RLINES < L ? r : r + 1;
@@ -188,17 +184,17 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           if (has_y && rowp(t) && nr < R && nok) {
             const float* yr = yf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
-            for (int d = 0; d < RQ; ++d) ynext[d] = __builtin_nontemporal_load(yr + t + RP * d);
+            for (int d = 0; d < RQ; ++d) ynx[d] = __builtin_nontemporal_load(yr + t + RP * d);
           }
           if constexpr (BG) {
             if (rowp(t) && nr < R && nok) {
               const float* br = bgf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
-              for (int d = 0; d < RQ; ++d) bnext[d] = __builtin_nontemporal_load(br + t + RP * d);
+              for (int d = 0; d < RQ; ++d) bnx[d] = __builtin_nontemporal_load(br + t + RP * d);
             }
           }
         }
-        if (!lok) continue;   // (uniform per line; the line's prefetch above is done)
+        if (!lok) return;   // (uniform per line; the line's prefetch above is done)
         cplx v[RV];
         if (rowq(t)) {
 #pragma unroll
@@ -299,6 +295,26 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           }
         }
         wave_sync();
+            };
+      // With an even number of iterations per chunk the two buffers trade places and no
+      // copies are needed; otherwise the prefetched values are copied once per iteration.
+      constexpr int NIT = (L + RLINES - 1) / RLINES;
+      if constexpr (NIT % 2 == 0) {
+        for (int k0 = 0; k0 < L; k0 += 2 * RLINES) {
+          row_iter(k0, ynext, yalt, bnext, balt);
+          row_iter(k0 + RLINES, yalt, ynext, balt, bnext);
+        }
+      } else {
+        for (int k0 = 0; k0 < L; k0 += RLINES) {
+          float yv[RQ], bv[BG ? RQ : 1];
+#pragma unroll
+          for (int d = 0; d < RQ; ++d) yv[d] = ynext[d];
+          if constexpr (BG) {
+#pragma unroll
+            for (int d = 0; d < RQ; ++d) bv[d] = bnext[d];
+          }
+          row_iter(k0, yv, ynext, bv, bnext);
+        }
       }
     }
     __syncthreads();
