@@ -148,7 +148,8 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           }
           DFT<CP, false>::run(v);
 #pragma unroll
-          for (int c = 0; c < CP; ++c) Tr[TRI(c + CP * t) + col] = cmul(v[c], twc[c * CQ + t]);
+          for (int c = 0; c < CP; ++c)   // twiddle w^0 = 1 for c = 0
+            Tr[TRI(c + CP * t) + col] = c == 0 ? v[0] : cmul(v[c], twc[c * CQ + t]);
         }
         wave_sync();
         if (on && colp(t)) {
@@ -210,7 +211,7 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           DFT<RP, false>::run(v);
 #pragma unroll
           for (int c = 0; c < RP; ++c) {
-            v[c] = cmul(v[c], tw2[c * RQ + t]);
+            if (c > 0) v[c] = cmul(v[c], tw2[c * RQ + t]);   // w^0 = 1
             ex[t * (RP + 1) + c] = v[c].x;
           }
         }
@@ -285,7 +286,10 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           wave_sync();
           if (rowq(t)) {
 #pragma unroll
-            for (int c = 0; c < RP; ++c) v[c] = cmulc(cplx{rex[c], ex[t * (RP + 1) + c]}, tw2[c * RQ + t]);
+            for (int c = 0; c < RP; ++c) {
+              const cplx x = {rex[c], ex[t * (RP + 1) + c]};
+              v[c] = c == 0 ? x : cmulc(x, tw2[c * RQ + t]);
+            }
             DFT<RP, true>::run(v);
 #pragma unroll
             for (int a = 0; a < NAR; ++a) {
@@ -336,7 +340,10 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         wave_sync();
         if (on && colq(t)) {
 #pragma unroll
-          for (int c = 0; c < CP; ++c) v[c] = cmulc(Tr[TRI(c + CP * t) + col], twc[c * CQ + t]);
+          for (int c = 0; c < CP; ++c) {
+            const cplx x = Tr[TRI(c + CP * t) + col];
+            v[c] = c == 0 ? x : cmulc(x, twc[c * CQ + t]);
+          }
           DFT<CP, true>::run(v);
           if constexpr (FB <= L) {
             cplx gv[NAC], tv[NAC];
