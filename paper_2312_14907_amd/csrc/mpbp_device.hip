@@ -65,6 +65,13 @@ __device__ __forceinline__ float block_sum_f(float v, float* red) {
   return s;
 }
 
+// acc + a conj(b) with the two fused multiply-adds per component written out, so that
+// every instance of the gradient kernel rounds the frame sums the same way (left to the
+// compiler, the contraction into FMAs differs between instances).
+__device__ __forceinline__ cplx cmulc_acc(cplx acc, cplx a, cplx b) {
+  return {fmaf(a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(a.y, b.x, fmaf(-a.x, b.y, acc.y))};
+}
+
 // The peak record is the same for every lane: read it once and pass each word through
 // readfirstlane, so that the raster walk and the slot bases derived from it live in
 // scalar registers (a plain load from the table leaves them in vector registers, since
@@ -180,66 +187,100 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       // Each lane reads its footprint-gradient values straight from the frame's slot:
       // a wavefront covers a 4 x 16 voxel patch at one slice, so its reads are rows.
       const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
-      int iy = iy_lo, ix = ix_lo, ci = 0;
-      while (iy <= iy_hi) {
-        int nb = 0;
-        int fpy[B], fpx[B];
-        long long fso[B];
+      // one batch of nb (<= B) frames: window origins (fpy, fpx) and slot offsets fso
+      auto batch = [&](int nb, const int (&fpy)[B], const int (&fpx)[B], const long long (&fso)[B])
+                       __attribute__((always_inline)) {
+          cplx gv[B][kGradZPer], pv[B], pz[B][P3 ? kGradZPer : 1];
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-          fpy[k] = fpx[k] = 0;
-          fso[k] = 0;
-          while (nb == k && iy <= iy_hi) {
-            const int cy = iy, cx = ix;
-            if (++ix > ix_hi) { ix = ix_lo; ++iy; }
-            const int act = A.all_active ? 1 : __builtin_amdgcn_readfirstlane((int)actf[ci]);
-            ++ci;
-            if (!act) continue;
-            fpy[k] = pk.oy + cy * pk.sy;
-            fpx[k] = pk.ox + cx * pk.sx;
-            fso[k] = pk.slot_off + (long long)(cy * pk.cols + cx) * pk.fy * pk.fx;
-            nb = k + 1;
-          }
-        }
-        if (nb == 0) break;
-        cplx gv[B][kGradZPer], pv[B], pz[B][P3 ? kGradZPer : 1];
+          for (int k = 0; k < B; ++k) {
+            const int a = y - fpy[k], b = x - fpx[k];
+            const bool inw = k < nb && inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
+            const int ac = inw ? a : 0, bc = inw ? b : 0;
+            if constexpr (P3) {
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-          const int a = y - fpy[k], b = x - fpx[k];
-          const bool inw = k < nb && inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
-          const int ac = inw ? a : 0, bc = inw ? b : 0;
-          if constexpr (P3) {
+              for (int i = 0; i < kGradZPer; ++i) {
+                const int z = zb + tz * kGradZPer + i;
+                const cplx pr = probe[(long long)(z < nz ? z : 0) * np * np + ac * np + bc];
+                pz[k][i] = inw ? pr : cplx{0.f, 0.f};
+              }
+            } else {
+              const cplx pr = Ps[ac * np + bc];
+              pv[k] = inw ? pr : cplx{0.f, 0.f};
+            }
+            // uniform slot base + 32-bit lane offset (a slot holds fewer than 2^29 values)
+            const char* sl = reinterpret_cast<const char*>(slots + fso[k]);
 #pragma unroll
             for (int i = 0; i < kGradZPer; ++i) {
-              const int z = zb + tz * kGradZPer + i;
-              const cplx pr = probe[(long long)(z < nz ? z : 0) * np * np + ac * np + bc];
-              pz[k][i] = inw ? pr : cplx{0.f, 0.f};
+              if (same[i]) continue;
+              const unsigned off = (unsigned)((ac + zsy[i]) * pk.fx + bc + zsx[i]) * (unsigned)sizeof(cplx);
+              const cplx* q = reinterpret_cast<const cplx*>(sl + off);
+              if constexpr (LIN) {
+                const cplx q00 = q[0], q01 = q[1], q10 = q[pk.fx], q11 = q[pk.fx + 1];
+                gv[k][i] = cadd(cadd(cscale(q00, zw[i][0]), cscale(q01, zw[i][LIN ? 1 : 0])),
+                                cadd(cscale(q10, zw[i][LIN ? 2 : 0]), cscale(q11, zw[i][LIN ? 3 : 0])));
+              } else {
+                gv[k][i] = q[0];
+              }
             }
-          } else {
-            const cplx pr = Ps[ac * np + bc];
-            pv[k] = inw ? pr : cplx{0.f, 0.f};
           }
-          // uniform slot base + 32-bit lane offset (a slot holds fewer than 2^29 values)
-          const char* sl = reinterpret_cast<const char*>(slots + fso[k]);
 #pragma unroll
-          for (int i = 0; i < kGradZPer; ++i) {
-            if (same[i]) continue;
-            const unsigned off = (unsigned)((ac + zsy[i]) * pk.fx + bc + zsx[i]) * (unsigned)sizeof(cplx);
-            const cplx* q = reinterpret_cast<const cplx*>(sl + off);
-            if constexpr (LIN) {
-              const cplx q00 = q[0], q01 = q[1], q10 = q[pk.fx], q11 = q[pk.fx + 1];
-              gv[k][i] = cadd(cadd(cscale(q00, zw[i][0]), cscale(q01, zw[i][LIN ? 1 : 0])),
-                              cadd(cscale(q10, zw[i][LIN ? 2 : 0]), cscale(q11, zw[i][LIN ? 3 : 0])));
-            } else {
-              gv[k][i] = q[0];
+          for (int k = 0; k < B; ++k)
+#pragma unroll
+            for (int i = 0; i < kGradZPer; ++i)   // conj(P) g_psi
+              if (!same[i]) acc[i] = cmulc_acc(acc[i], gv[k][i], P3 ? pz[k][P3 ? i : 0] : pv[k]);
+      };
+      if (A.all_active) {
+        // full batch: every covering frame, row by row, B consecutive columns per batch;
+        // window origins and slot offsets advance by additions (scalar registers)
+        const long long fyfx = (long long)pk.fy * pk.fx;
+        int wy = pk.oy + iy_lo * pk.sy;
+        long long srow = pk.slot_off + (long long)(iy_lo * pk.cols + ix_lo) * fyfx;
+        for (int cy = iy_lo; cy <= iy_hi; ++cy) {
+          int wx = pk.ox + ix_lo * pk.sx;
+          long long so = srow;
+          for (int cx = ix_lo; cx <= ix_hi; cx += B) {
+            const int nb = min(B, ix_hi - cx + 1);
+            int fpy[B], fpx[B];
+            long long fso[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) {   // past the row's end: the batch's first slot
+              fpy[k] = wy;
+              fpx[k] = wx + k * pk.sx;
+              fso[k] = k < nb ? so + k * fyfx : so;
             }
+            batch(nb, fpy, fpx, fso);
+            wx += B * pk.sx;
+            so += B * fyfx;
           }
+          wy += pk.sy;
+          srow += (long long)pk.cols * fyfx;
         }
+      } else {
+        // minibatch: skip the frames whose flag is clear
+        int iy = iy_lo, ix = ix_lo, ci = 0;
+        while (ix_lo <= ix_hi && iy <= iy_hi) {
+          int nb = 0;
+          int fpy[B], fpx[B];
+          long long fso[B];
 #pragma unroll
-        for (int k = 0; k < B; ++k)
-#pragma unroll
-          for (int i = 0; i < kGradZPer; ++i)   // conj(P) g_psi
-            if (!same[i]) acc[i] = cadd(acc[i], cmulc(gv[k][i], P3 ? pz[k][P3 ? i : 0] : pv[k]));
+          for (int k = 0; k < B; ++k) {
+            fpy[k] = fpx[k] = 0;
+            fso[k] = 0;
+            while (nb == k && iy <= iy_hi) {
+              const int cy = iy, cx = ix;
+              if (++ix > ix_hi) { ix = ix_lo; ++iy; }
+              const int act = __builtin_amdgcn_readfirstlane((int)actf[ci]);
+              ++ci;
+              if (!act) continue;
+              fpy[k] = pk.oy + cy * pk.sy;
+              fpx[k] = pk.ox + cx * pk.sx;
+              fso[k] = pk.slot_off + (long long)(cy * pk.cols + cx) * pk.fy * pk.fx;
+              nb = k + 1;
+            }
+          }
+          if (nb == 0) break;
+          batch(nb, fpy, fpx, fso);
+        }
       }
 #pragma unroll
       for (int i = 1; i < kGradZPer; ++i)
