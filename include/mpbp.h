@@ -142,7 +142,12 @@ enum {
    device = -1 makes a host-only plan: tables and validation only; compute calls then
    return MPBP_ERR_DEVICE.  Errors: MPBP_ERR_INVALID (null pointers, unknown flags),
    MPBP_ERR_SHAPE (non-positive sizes, D outside the supported set), MPBP_ERR_FOOTPRINT,
-   MPBP_ERR_DEVICE, MPBP_ERR_NOMEM.  On success *out owns the plan. */
+   MPBP_ERR_DEVICE, MPBP_ERR_NOMEM.  On success *out owns the plan.
+   The device workspace holds the per-peak objects (8 n_peaks nz ny nx bytes), two
+   footprint slots per frame (its exit wave and that wave's gradient, 8 F_y F_x bytes
+   each, F = probe_n plus the peak's shear span per axis), the per-frame losses and the
+   per-tile alpha partials: about 0.57 GB for 3 peaks, 32 x 512 x 512 voxels and 12288
+   frames with 43 x 43 footprints. */
 mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan* out);
 
 /* Release the plan and its device workspace (waits for the plan's work to finish).
