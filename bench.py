@@ -321,7 +321,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+              "sharding over several GPUs (bands of scan rows with a halo reduction of the gradient) is designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2312_14907_amd.binding import MPBP_OPT_PATH, MPBP_OPT_PROFILE
