@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# FP32 vector peak without packed-FP32 instructions (disabled in this build):
+# FP32 vector peak without packed-FP32 instructions (the device code is compiled without them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "loss+gradient scan-positions/s at stated tol; batched-fused vs plain, % HBM peak"
@@ -320,7 +320,7 @@ def get_config_named(name):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (got --gpus {args.gpus}); "
               "sharding over several GPUs (bands of scan rows with a halo reduction of the gradient) is designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
