@@ -59,6 +59,13 @@ class MPBPError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2312_14907_amd.build`")
+    # torch first: its HIP runtime is then the one the library binds to.  Loaded the other
+    # way round, the process holds the system runtime and torch's build of it side by
+    # side, and neither sees the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, i32p, st = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int
     lib.mpbp_plan_create.argtypes = [ctypes.POINTER(mpbp_problem), ctypes.c_int, ctypes.POINTER(vp)]
