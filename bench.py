@@ -71,6 +71,26 @@ def frame_kernel_work(prob, tab_shear):
     return nbytes, flops
 
 
+def measured_copy_gbps(torch, mib=1024, reps=10):
+    """Bandwidth of a plain device-to-device copy of `mib` MiB (bytes read + written per
+    second, median of `reps`): the HBM rate a streaming kernel reaches on this GPU."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    return 2 * n * 4 / sorted(ts)[len(ts) // 2] / 1e9
+
+
 def step_bytes(prob):
     """Algorithmic HBM bytes of one loss+gradient step: y once, plus 32 B per voxel
     (read u and chi, write their gradients), plus the probe."""
@@ -343,6 +363,7 @@ def main():
     if not args.no_autotune:
         plan.mpbp_autotune(*args_t)
     tuning = plan.mpbp_tuning()
+    copy_gbps = measured_copy_gbps(torch)
     plan.mpbp_set_option(MPBP_OPT_PROFILE, 1)
     dt, stages, loss = time_steps(plan, args_t, args.steps, args.warmup, torch)
     nfr = prob.n_frames()
@@ -394,6 +415,8 @@ def main():
             "algorithmic_bytes": step_bytes(prob),
             "achieved_GBps": round(step_bytes(prob) / (dt / args.steps) / 1e9, 1),
             "frac": round(step_bytes(prob) / (dt / args.steps) / 1e9 / HBM_PEAK_GBPS, 4),
+            "measured_copy_GBps": round(copy_gbps, 1),
+            "frac_of_measured_copy": round(step_bytes(prob) / (dt / args.steps) / 1e9 / copy_gbps, 4),
         },
         "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
         "loss": loss,
