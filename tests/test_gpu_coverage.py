@@ -57,3 +57,24 @@ def test_uncovered_voxels(wide, path, subset):
     assert_grad_close(got["grad_chi"], ref["grad_chi"], "grad_chi")
     assert_grad_close(got["grad_alpha"], ref["grad_alpha"], "grad_alpha")
     plan.close()
+
+
+def test_minibatch_of_every_frame_equals_full_batch():
+    """All frames listed as a minibatch (staged lists, the flagged walk of the gradient
+    kernel) against the full-batch call (the unflagged walk): the same sums in the same
+    order, so bitwise equal (c4_batch: six detector-size classes)."""
+    cfg = get_config("c4_batch")
+    prob = make_problem(cfg)
+    f = make_fields(cfg, prob)
+    from tests.gpu_util import speckle_y
+    y = speckle_y(prob, cfg["seed"])
+    u = (f["u"] + f["delta"]).astype(np.float32)
+    plan = B.Plan(prob, 0)
+    say("minibatch of every frame vs full batch, c4_batch")
+    full = gpu_loss_grad(plan, u, f["chi"], f["alpha"], f["probe"], y)
+    every = gpu_loss_grad(plan, u, f["chi"], f["alpha"], f["probe"], y, frames=list(range(prob.n_frames())))
+    for k in ("grad_u", "grad_chi", "frame_loss"):
+        np.testing.assert_array_equal(every[k], full[k], err_msg=k)
+    np.testing.assert_allclose(every["grad_alpha"], full["grad_alpha"], rtol=1e-6)
+    assert abs(every["loss"] - full["loss"]) <= 1e-12 * abs(full["loss"])
+    plan.close()
