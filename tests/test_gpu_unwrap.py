@@ -118,3 +118,19 @@ def test_c5_lateral_grid_full_size():
     u = lattice_jump(u, 100, 300, 50, 260, cells=1)
     _, w = _check(plan, prob, u, "c5_full lateral grid, z-tied")
     assert (w != 0).mean() > 0.1
+
+
+def test_single_peak_rank_one():
+    # one Bragg vector: H is 3 x 1 (rank 1), so the projector moves u only along G
+    cfg = dict(get_config("c1_tiny"))
+    cfg["peaks"] = [cfg["peaks"][0]]
+    prob = make_problem(cfg)
+    plan = B.Plan(prob, 0)
+    u = unwrap_field(prob.nz, prob.ny, prob.nx, seed=25, noise_nm=0.04)
+    bad = lattice_jump(u, 6, 20, 4, 22, cells=1)
+    got_u, got_w = _check(plan, prob, bad, "one peak (rank-1 H)")
+    assert got_w.any()
+    g = np.asarray(prob.g[0], dtype=np.float64)
+    g /= np.linalg.norm(g)
+    d = (got_u.astype(np.float64) - bad.astype(np.float64)).reshape(3, -1)
+    assert np.abs(d - np.outer(g, g @ d)).max() <= 1e-5
