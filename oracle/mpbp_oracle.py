@@ -422,26 +422,46 @@ def log_param_grad(x, grad_x):
     return np.asarray(x, dtype=np.float64) * np.asarray(grad_x, dtype=np.float64)
 
 
+def minibatch(order, n_frames, batch, it):
+    """Frames of iteration `it` of Algorithm 1 (section 3.3).
+
+    Each pass over the data starts from a fresh shuffle of the JD = n_frames patterns
+    and runs JD/b minibatches (integer division: every minibatch holds b patterns, and
+    the JD mod b patterns left at the end of a shuffle wait for a later shuffle).
+    `order` holds the shuffles, concatenated (its length a multiple of JD; the passes
+    wrap around them).  Iteration it is minibatch t = it mod (JD/b) of pass
+    e = it div (JD/b): entries [t b, (t + 1) b) of shuffle e.
+    """
+    order = np.asarray(order)
+    if batch < 1 or batch > n_frames:
+        raise ValueError(f"minibatch size {batch} outside [1, {n_frames}]")
+    if len(order) == 0 or len(order) % n_frames:
+        raise ValueError("order must hold whole shuffles of the frames")
+    per_pass = n_frames // batch
+    shuffles = len(order) // n_frames
+    e, t = divmod(int(it), per_pass)
+    perm = order[(e % shuffles) * n_frames:(e % shuffles + 1) * n_frames]
+    return [int(f) for f in perm[t * batch:(t + 1) * batch]]
+
+
 def adam_reconstruct(u, chi_log, alpha_log, probe, y, problem, order, batch, iterations,
                      lr=(0.01, 0.1, 0.1), fixed_alpha=0, beta1=0.9, beta2=0.999, eps=1e-8,
                      unwrap=False):
-    """Algorithm 1: minibatches of `batch` consecutive frames of the shuffled frame order
-    `order` (the shuffle is an input), minibatch gradients summed over the frames
-    (eq. (11)), then Adam on u and on the log variables chi~, alpha~ of eq. (8), alpha of
-    peak `fixed_alpha` held fixed (-1: none); with unwrap=True every update of u is
-    followed by the unwrap projection Pi_U of eq. (10) (the algorithm's last step; without
-    it, the concurrent-wrapped variant).  Returns (u, chi_log, alpha_log, losses) with the
+    """Algorithm 1: the minibatches of `minibatch` (JD/b per shuffle of the frames; the
+    shuffles are an input), minibatch gradients summed over the frames (eq. (11)), then
+    Adam on u and on the log variables chi~, alpha~ of eq. (8), alpha of peak
+    `fixed_alpha` held fixed (-1: none); with unwrap=True every update of u is followed
+    by the unwrap projection Pi_U of eq. (10) (the algorithm's last step; without it, the
+    concurrent-wrapped variant).  Returns (u, chi_log, alpha_log, losses) with the
     minibatch loss of every iteration (evaluated before that iteration's update)."""
     u = np.array(u, dtype=np.float64)
     cl = np.array(chi_log, dtype=np.float64)
     al = np.array(alpha_log, dtype=np.float64)
     mom = [np.zeros_like(u), np.zeros_like(cl), np.zeros_like(al)]
     sec = [np.zeros_like(u), np.zeros_like(cl), np.zeros_like(al)]
-    order = np.asarray(order)
     losses = []
     for it in range(iterations):
-        start = (it * batch) % len(order)
-        frames = [int(f) for f in order[start:start + batch]]
+        frames = minibatch(order, problem.n_frames(), batch, it)
         chi, alpha = np.exp(cl), np.exp(al)
         r = loss_grad(u, chi, alpha, probe, y, problem, frames)
         losses.append(r["loss"])
@@ -462,12 +482,14 @@ def adam_reconstruct(u, chi_log, alpha_log, probe, y, problem, order, batch, ite
 
 
 def line_search_descent(u, chi, alpha, probe, y, problem, iterations, step0=0.01, c=1e-4,
-                        shrink=0.5, grow=2.0, max_backtracks=30):
+                        shrink=0.5, grow=2.0, max_backtracks=30, trials=None):
     """Full-batch gradient descent on u (chi, alpha held) with a backtracking (Armijo)
     step-size search: from u, try u - eta g with eta grown by `grow` from the previous
     accepted step (first: step0 over the RMS of g) and shrunk by `shrink` until
     f(u - eta g) <= f(u) - c eta |g|^2.  Returns (u, losses, etas): the loss before each
-    iteration and the accepted step sizes; stops early when no step is accepted."""
+    iteration and the accepted step sizes; stops early when no step is accepted.  With
+    a list `trials`, each iteration appends the (eta, f(u - eta g)) pairs it tried, in
+    order."""
     u = np.array(u, dtype=np.float64)
     losses, etas = [], []
     eta = None
@@ -479,9 +501,13 @@ def line_search_descent(u, chi, alpha, probe, y, problem, iterations, step0=0.01
         if n2 == 0.0:
             break
         eta = step0 / math.sqrt(n2 / g.size) if eta is None else eta * grow
+        tried = []
+        if trials is not None:
+            trials.append(tried)
         for _ in range(max_backtracks):
             trial = u - eta * g
             f1, _ = loss(trial, chi, alpha, probe, y, problem)
+            tried.append((eta, f1))
             if f1 <= f0 - c * eta * n2:
                 u = trial
                 etas.append(eta)

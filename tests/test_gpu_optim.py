@@ -104,7 +104,9 @@ def test_algorithm1_c1_matches_oracle(c1):
     chi0 = np.maximum(f["chi"], 1e-3).astype(np.float32)
     cl0 = np.log(chi0).astype(np.float32)
     al0 = (np.log(f["alpha"]) + 0.1).astype(np.float32)
-    lr, batch, iters = (0.002, 0.02, 0.02), 25, 6
+    # 75 frames, b = 20: three minibatches per shuffle (15 frames left), six iterations
+    # cross into the second shuffle
+    lr, batch, iters = (0.002, 0.02, 0.02), 20, 6
     du, dcl, dal = dev(u0), dev(cl0), dev(al0)
     chi, alpha, losses = optim.adam_reconstruct(plan, dev(f["probe"]), dev(y), du, dcl, dal, order, batch=batch,
                                                 iterations=iters, lr=lr, fixed_alpha=0)
@@ -159,3 +161,18 @@ def test_line_search_c1_matches_oracle(c1):
     np.testing.assert_allclose(out["etas"][:3], oetas[:3], rtol=1e-3)
     assert all(b < a for a, b in zip(out["losses"], out["losses"][1:]))
     assert out["losses"][-1] < 0.5 * out["losses"][0]
+    # the GPU loop's own trials follow the line search's definition
+    c, step0 = 1e-4, 0.01
+    for k, tr in enumerate(out["trials"]):
+        n2, tried = tr["norm2"], tr["tried"]
+        first = tried[0][0]
+        if k == 0:
+            assert first == pytest.approx(step0 / np.sqrt(n2 / u0.size), rel=1e-12)
+        else:
+            assert first == pytest.approx(2.0 * out["etas"][k - 1], rel=1e-15)
+        for (e0, _), (e1, _) in zip(tried, tried[1:]):
+            assert e1 == pytest.approx(0.5 * e0, rel=1e-15)
+        for e, f1 in tried[:-1]:
+            assert f1 > out["losses"][k] - c * e * n2
+        assert tried[-1][0] == out["etas"][k]
+        assert tried[-1][1] <= out["losses"][k] - c * tried[-1][0] * n2
