@@ -40,7 +40,6 @@ def parse():
                    help="instead of the step benchmark: this many iterations of full-batch gradient "
                         "descent on u with an Armijo line search from u = 0, and the oracle's iteration "
                         "time on a one-eighth crop of the workload")
-    p.add_argument("--cpu-frames", type=int, default=0, help="oracle sample size (0 = auto)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="first run a plain elementwise copy (out = -in) of this many MiB, the "
                         "known-size reference for HBM byte counters")
@@ -161,42 +160,96 @@ def time_steps(plan, args_t, steps, warmup, torch):
     return dt, plan.mpbp_stage_times(), float(loss.item())
 
 
-def cpu_baseline(prob, f, y_dev, n_frames):
-    """The FP64 oracle on a minibatch of the workload's frames (single process)."""
+def baseline_band(prob):
+    """The oracle's sample of the workload: one band of 8 scan rows of every peak's
+    raster (all columns), in the middle of the rasters, with only the object rows those
+    frames reach (one eighth of c5_full's 12288 frames)."""
+    r0 = max(0, int(prob.scan_n[:, 0].max()) // 2 - 4)
+    return r0, r0 + 8
+
+
+def cpu_baseline(name, plan, args_t, torch):
+    """The FP64 oracle on the band crop (single process, one thread), and the accuracy
+    of the timed launch configuration on the same frames.
+
+    The band's intensities are replaced on the device by Poisson counts of the oracle's
+    own forward model at the true fields (seeded per frame); the oracle's loss and
+    gradient on the cropped band are timed; the plan, as tuned for the timed steps,
+    then evaluates the same frames as a minibatch, and its loss, frame losses and
+    gradients are compared with the oracle's (loss relative 1e-5; every gradient field
+    ||d||_2 <= 1e-3 ||ref||_2, on the band's object rows; zero elsewhere)."""
     import numpy as np
-    from oracle import mpbp_oracle as O
-
-    class DeviceY:
-        def __init__(self, t):
-            self.t = t
-
-        def __getitem__(self, sl):
-            return self.t[sl].cpu().numpy()
-
     from threadpoolctl import threadpool_limits
+    from oracle import mpbp_oracle as O
+    from synth import band_problem, get_config, make_fields, make_problem
+    cfg = get_config(name)
+    prob = make_problem(cfg)
+    f = make_fields(cfg, prob)
+    r0, r1 = baseline_band(prob)
+    band, lo, hi, gids = band_problem(prob, r0, r1)
+    crop = np.s_[..., lo:hi, :]
+    inten = O.model_intensity(f["u"][crop], f["chi"][crop], f["alpha"], f["probe"], band)
+    ys = [np.random.default_rng([cfg["seed"], g]).poisson(np.clip(i, 0, None)).astype(np.float32) for g, i in
+          zip(gids, inten)]
     u = (f["u"] + f["delta"]).astype(np.float32)
-    frames = list(range(n_frames))
     with threadpool_limits(limits=1):      # one core: the figure is per host core
         t0 = time.perf_counter()
-        O.loss_grad(u, f["chi"], f["alpha"], f["probe"], DeviceY(y_dev), prob, frames=frames)
+        ref = O.loss_grad(u[crop], f["chi"][crop], f["alpha"], f["probe"], np.concatenate([a.ravel() for a in ys]),
+                          band)
         dt = time.perf_counter() - t0
-    return n_frames / dt, dt
+    # the band's counts into the device intensities, then the plan on the band's frames
+    du, dchi, dal, dpr, dy = args_t
+    _, _, y_off = plan.mpbp_tables()
+    fpp = prob.frames_per_peak()
+    first = np.concatenate([[0], np.cumsum(fpp)])
+    for g, a in zip(gids, ys):
+        m = int(np.searchsorted(first, g, side="right") - 1)
+        d = int(prob.det[m])
+        s = int(y_off[m]) + (g - int(first[m])) * d * d
+        dy[s:s + d * d] = torch.from_numpy(a.ravel()).to(dy.device)
+    du.copy_(torch.from_numpy(u))
+    gu, gc, ga = torch.empty_like(du), torch.empty_like(dchi), torch.empty_like(dal)
+    loss = torch.zeros((), dtype=torch.float64, device=du.device)
+    fl = torch.zeros(len(gids), dtype=torch.float32, device=du.device)
+    plan.mpbp_loss_grad(du, dchi, dal, dpr, dy, gu, gc, ga, frames=gids, loss=loss, frame_loss=fl)
+    torch.cuda.synchronize()
+    gu, gc, ga = gu.cpu().numpy(), gc.cpu().numpy(), ga.cpu().numpy().astype(np.float64)
+
+    def rel(a, b):
+        return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+    acc = {"frames": len(gids), "loss_rel": abs(loss.item() - ref["loss"]) / abs(ref["loss"]),
+           "frame_loss_max_rel": float(np.max(np.abs(fl.cpu().numpy() - ref["frame_loss"]) /
+                                              np.abs(ref["frame_loss"]))),
+           "grad_u_rel": max(rel(gu[c][crop], ref["grad_u"][c]) for c in range(3)),
+           "grad_chi_rel": rel(gc[crop], ref["grad_chi"]), "grad_alpha_rel": rel(ga, ref["grad_alpha"]),
+           "outside_band_max_abs": float(max(np.abs(gu[..., :lo, :]).max(initial=0), np.abs(gu[..., hi:, :]).max(initial=0),
+                                             np.abs(gc[..., :lo, :]).max(initial=0), np.abs(gc[..., hi:, :]).max(initial=0)))}
+    acc["tolerance"] = {"loss_rel": 1e-5, "grad_rel": 1e-3}
+    acc["ok"] = bool(acc["loss_rel"] <= 1e-5 and max(acc["grad_u_rel"], acc["grad_chi_rel"], acc["grad_alpha_rel"]) <= 1e-3
+                     and acc["outside_band_max_abs"] == 0.0)
+    sample = (f"FP64 oracle loss+gradient on one band of {name}: raster rows {r0}-{r1 - 1} of each of the "
+              f"{prob.n_peaks} peaks ({len(gids)} frames), object rows {lo}-{hi - 1} ({hi - lo} of {prob.ny}): "
+              f"{dt:.1f} s")
+    return len(gids) / dt, sample, acc
 
 
 def cpu_baseline_all_cores(workload, n_frames, total_frames):
     """The same oracle call in W concurrent CPU-only child processes (W = the host cores
-    this process may use, at most 16), each on its own minibatch of n_frames frames and
-    one thread; set-up happens before a common start, so the wall time from the start to
-    the last finish covers W oracle calls."""
+    this process may use, at most 16), each on its own band of 8 scan rows (with the
+    object rows it reaches) and one thread; set-up happens before a common start, so the
+    wall time from the start to the last finish covers W oracle calls."""
     import subprocess
     import tempfile
+    from synth import get_config, make_problem
+    prob = make_problem(get_config(workload))
+    rows = int(prob.scan_n[:, 0].max())
     w_count = max(1, min(len(os.sched_getaffinity(0)), 16))
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
     go = os.path.join(tempfile.mkdtemp(prefix="mpbp_cpu_"), "go")
-    span = max(1, total_frames - n_frames + 1)
     procs = [subprocess.Popen([sys.executable, "-m", "oracle.time_worker", workload,
-                               str((w * n_frames) % span), str(n_frames), go],
+                               str((8 * w) % max(rows - 7, 1)), "8", go],
                               cwd=ROOT, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
                               text=True) for w in range(w_count)]
     try:
@@ -214,11 +267,14 @@ def cpu_baseline_all_cores(workload, n_frames, total_frames):
     for p, (out, err) in zip(procs, outs):
         if p.returncode != 0:
             raise RuntimeError("oracle timing worker failed: " + err[-2000:])
-    calls = [float(o.strip().splitlines()[-1]) for o, _ in outs]
-    return {"value": round(w_count * n_frames / wall, 2), "unit": "scan-positions/s", "cores": w_count,
+    lines = [o.strip().splitlines()[-1].split() for o, _ in outs]
+    frames = sum(int(a) for a, _ in lines)
+    calls = [float(b) for _, b in lines]
+    return {"value": round(frames / wall, 2), "unit": "scan-positions/s", "cores": w_count,
             "kind": "oracle",
             "sample": f"{w_count} concurrent single-thread processes, each the FP64 oracle's "
-                      f"loss+gradient on its own {n_frames}-frame minibatch of {workload}: "
+                      f"loss+gradient on its own band of 8 scan rows of every peak of {workload} "
+                      f"({frames // w_count} frames, with the object rows they reach): "
                       f"{wall:.1f} s wall (calls {min(calls):.1f}-{max(calls):.1f} s)"}
 
 
@@ -448,19 +504,20 @@ def main():
         out["paper_shape"] = time_paper_shape(torch)
 
     if not args.no_cpu_baseline:
-        n = args.cpu_frames or (1024 if prob.n_frames() >= 1024 else prob.n_frames())
-        rate, cdt = cpu_baseline(prob, f, args_t[4], n)
-        out["cpu_baseline"] = {
-            "value": round(rate, 2), "unit": "scan-positions/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle loss+gradient over the first {n} frames (a minibatch of "
-                      f"{args.workload}), including its whole-volume object build and chain "
-                      f"rule: {cdt:.1f} s"}
-        out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(args.workload, n, prob.n_frames())
+        rate, sample, acc = cpu_baseline(args.workload, plan, args_t, torch)
+        out["cpu_baseline"] = {"value": round(rate, 2), "unit": "scan-positions/s", "cores": 1, "kind": "oracle",
+                               "sample": sample}
+        out["accuracy"] = acc
+        out["cpu_baseline"]["all_cores"] = cpu_baseline_all_cores(args.workload, 0, prob.n_frames())
         if "unwrap" in out:
             usec = cpu_unwrap(prob)
             out["cpu_baseline"]["unwrap_tied_s_per_call"] = round(usec, 3)
             out["unwrap"]["tied"]["speedup_vs_oracle"] = round(usec / (out["unwrap"]["tied"]["ms_per_call"] / 1e3), 1)
     print(json.dumps(out), flush=True)
+    if "accuracy" in out and not out["accuracy"]["ok"]:
+        print("bench.py: the timed launch configuration is outside the stated tolerance against the oracle",
+              file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

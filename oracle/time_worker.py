@@ -3,14 +3,15 @@
 TEST INFRASTRUCTURE.  Only the benchmark's CPU-baseline leg runs this module, as a
 CPU-only child process (it imports neither torch nor the GPU library).  It times one
 call of the FP64 oracle's loss and gradient (`mpbp_oracle.loss_grad`, unchanged) on a
-minibatch of a workload's frames, as the single-core baseline does; several copies
-released together give the oracle's throughput on all host cores.
+band of a workload's scan rows with the object rows they reach (synth.band_problem), as
+the single-core baseline does; several copies released together give the oracle's
+throughput on all host cores.
 
-Usage: python -m oracle.time_worker WORKLOAD FIRST COUNT GO_FILE
+Usage: python -m oracle.time_worker WORKLOAD ROW0 ROWS GO_FILE
 
-The worker builds the workload's problem and fields, and seeded synthetic counts for
-its frames (the oracle's cost does not depend on their values), prints "ready", waits
-until GO_FILE exists, then prints the seconds the oracle call took.
+The worker builds the band's problem and fields, and seeded synthetic counts for its
+frames (the oracle's cost does not depend on their values), prints "ready", waits until
+GO_FILE exists, then prints the band's frame count and the seconds the oracle call took.
 """
 import os
 import sys
@@ -19,7 +20,7 @@ import time
 import numpy as np
 
 from oracle import mpbp_oracle as O
-from synth import get_config, make_fields, make_problem
+from synth import band_problem, get_config, make_fields, make_problem
 
 
 class FrameCounts:
@@ -40,20 +41,22 @@ class FrameCounts:
 
 
 def main():
-    workload, first, count, go = sys.argv[1], int(sys.argv[2]), int(sys.argv[3]), sys.argv[4]
+    workload, row0, rows, go = sys.argv[1], int(sys.argv[2]), int(sys.argv[3]), sys.argv[4]
     cfg = get_config(workload)
     prob = make_problem(cfg)
     f = make_fields(cfg, prob)
-    u = (f["u"] + f["delta"]).astype(np.float32)
-    frames = list(range(first, first + count))
-    tab = O.tables(prob)
-    y = FrameCounts(_frame_table(prob, tab), frames, cfg["seed"])
+    band, lo, hi, _ = band_problem(prob, row0, row0 + rows)
+    crop = np.s_[..., lo:hi, :]
+    u = (f["u"] + f["delta"]).astype(np.float32)[crop]
+    frames = list(range(band.n_frames()))
+    tab = O.tables(band)
+    y = FrameCounts(_frame_table(band, tab), frames, cfg["seed"])
     print("ready", flush=True)
     while not os.path.exists(go):
         time.sleep(0.002)
     t0 = time.perf_counter()
-    O.loss_grad(u, f["chi"], f["alpha"], f["probe"], y, prob, frames=frames)
-    print(f"{time.perf_counter() - t0:.6f}", flush=True)
+    O.loss_grad(u, f["chi"][crop], f["alpha"], f["probe"], y, band)
+    print(f"{len(frames)} {time.perf_counter() - t0:.6f}", flush=True)
 
 
 def _frame_table(prob, tab):

@@ -122,12 +122,45 @@ def _check(status):
 
 
 def _ptr(t):
-    """Device (or host) address of a tensor / array, or None."""
+    """Device address of a tensor, or None."""
     if t is None:
         return None
-    if isinstance(t, np.ndarray):
-        return t.ctypes.data
     return t.data_ptr()
+
+
+_DTYPES = {"f32": ("float32", 4), "f64": ("float64", 8), "c64": ("complex64", 8)}
+
+
+def _dev_bufs(device, *specs):
+    """Validate the device buffers of one compute call and return their addresses.
+
+    Each spec is (tensor, name, kind, numel[, flags]) with flags a string of "o"
+    (optional: None allowed) and "+" (at least numel elements).  A buffer must be a
+    contiguous torch tensor of dtype `kind` and `numel` elements, on the plan's GPU.
+    The library reads and writes these addresses from its kernels and cannot check
+    them itself.  Every buffer's type, dtype, layout and size are checked before any
+    buffer's device, so the first error names the argument that is wrong."""
+    import torch
+    for t, name, kind, numel, *fl in specs:
+        fl = fl[0] if fl else ""
+        if t is None:
+            if "o" in fl:
+                continue
+            raise ValueError(f"{name} is required")
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name} must be a torch CUDA tensor (got {type(t).__name__})")
+        dt, _ = _DTYPES[kind]
+        if t.dtype != getattr(torch, dt):
+            raise ValueError(f"{name} must be {dt} (got {t.dtype})")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        n = t.numel()
+        if (n < numel) if "+" in fl else (n != numel):
+            raise ValueError(f"{name} must hold {'at least ' if '+' in fl else ''}{numel} elements (got {n})")
+    for t, name, *_ in specs:
+        if t is not None and (not t.is_cuda or t.device.index != device):
+            raise ValueError(f"{name} must be on cuda:{device} (got {t.device})")
+    return tuple(None if t is None else t.data_ptr() for t, *_ in specs)
 
 
 def _stream(stream):
@@ -174,6 +207,23 @@ class Plan:
         self.n_peaks = int(np.asarray(problem.g).shape[0])
         self.n_frames = int(lib.mpbp_num_frames(h))
         self.intensity_size = int(lib.mpbp_intensity_size(h))
+        # element counts of the device buffers
+        self.field_size = (1 if self.flags & MPBP_Z_TIED else self.nz) * self.ny * self.nx
+        self.probe_size = self.n_peaks * (self.nz if self.flags & MPBP_PROBE_3D else 1) * self.probe_n ** 2
+
+    def _input_specs(self, u, chi, alpha, probe, y, y_required=True):
+        return ((u, "u", "f32", 3 * self.field_size), (chi, "chi", "f32", self.field_size),
+                (alpha, "alpha", "f32", self.n_peaks), (probe, "probe", "c64", self.probe_size),
+                (y, "y", "f32", self.intensity_size, "" if y_required else "o"))
+
+    def _grad_specs(self, grad_u, grad_chi, grad_alpha, flags=""):
+        return ((grad_u, "grad_u", "f32", 3 * self.field_size, flags),
+                (grad_chi, "grad_chi", "f32", self.field_size, flags),
+                (grad_alpha, "grad_alpha", "f32", self.n_peaks, flags))
+
+    @staticmethod
+    def _output_specs(n, loss, frame_loss):
+        return ((loss, "loss", "f64", 1, "o"), (frame_loss, "frame_loss", "f32", max(n, 1), "o+"))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -203,23 +253,30 @@ class Plan:
     def mpbp_forward(self, u, chi, alpha, probe, y=None, frames=None, loss=None, frame_loss=None,
                      model_intensity=None, stream=None):
         fp, n, keep = self._frames(frames)
-        _check(lib.mpbp_forward(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(probe), _ptr(y),
-                                fp, n, _ptr(loss), _ptr(frame_loss), _ptr(model_intensity),
-                                _stream(stream)))
+        n_out = self.n_frames if frames is None else n
+        pu, pc, pa, pp, py, pl, pf, pm = _dev_bufs(
+            self.device, *self._input_specs(u, chi, alpha, probe, y, loss is not None or frame_loss is not None),
+            *self._output_specs(n_out, loss, frame_loss),
+            (model_intensity, "model_intensity", "f32", self.intensity_size, "o"))
+        _check(lib.mpbp_forward(self.handle, pu, pc, pa, pp, py, fp, n, pl, pf, pm, _stream(stream)))
         del keep
 
     def mpbp_loss_grad(self, u, chi, alpha, probe, y, grad_u, grad_chi, grad_alpha, frames=None,
                        loss=None, frame_loss=None, stream=None):
         fp, n, keep = self._frames(frames)
-        _check(lib.mpbp_loss_grad(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(probe), _ptr(y),
-                                  fp, n, _ptr(loss), _ptr(frame_loss), _ptr(grad_u), _ptr(grad_chi),
-                                  _ptr(grad_alpha), _stream(stream)))
+        n_out = self.n_frames if frames is None else n
+        pu, pc, pa, pp, py, pl, pf, gu, gc, ga = _dev_bufs(
+            self.device, *self._input_specs(u, chi, alpha, probe, y), *self._output_specs(n_out, loss, frame_loss),
+            *self._grad_specs(grad_u, grad_chi, grad_alpha))
+        _check(lib.mpbp_loss_grad(self.handle, pu, pc, pa, pp, py, fp, n, pl, pf, gu, gc, ga, _stream(stream)))
         del keep
 
     def mpbp_step(self, u, chi, alpha, grad_u, grad_chi, grad_alpha, eta, stream=None):
         e = (ctypes.c_float * 3)(*[float(v) for v in eta])
-        _check(lib.mpbp_step(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(grad_u),
-                             _ptr(grad_chi), _ptr(grad_alpha), e, _stream(stream)))
+        pu, pc, pa, gu, gc, ga = _dev_bufs(
+            self.device, (u, "u", "f32", 3 * self.field_size), (chi, "chi", "f32", self.field_size),
+            (alpha, "alpha", "f32", self.n_peaks), *self._grad_specs(grad_u, grad_chi, grad_alpha))
+        _check(lib.mpbp_step(self.handle, pu, pc, pa, gu, gc, ga, e, _stream(stream)))
 
     def mpbp_adam_step(self, cfg, t, u, chi, alpha, chi_log, alpha_log, state, grad_u, grad_chi, grad_alpha,
                        stream=None):
@@ -227,31 +284,39 @@ class Plan:
         c = mpbp_adam((ctypes.c_float * 3)(*[float(v) for v in cfg["lr"]]), float(cfg.get("beta1", 0.9)),
                       float(cfg.get("beta2", 0.999)), float(cfg.get("eps", 1e-8)), int(cfg.get("log_params", 1)),
                       int(cfg.get("fixed_alpha", -1)))
-        _check(lib.mpbp_adam_step(self.handle, ctypes.byref(c), int(t), _ptr(u), _ptr(chi), _ptr(alpha),
-                                  _ptr(chi_log), _ptr(alpha_log), _ptr(state), _ptr(grad_u), _ptr(grad_chi),
-                                  _ptr(grad_alpha), _stream(stream)))
+        nf, lf = self.field_size, "" if c.log_params else "o"
+        pu, pc, pa, pcl, pal, ps, gu, gc, ga = _dev_bufs(
+            self.device, (u, "u", "f32", 3 * nf), (chi, "chi", "f32", nf), (alpha, "alpha", "f32", self.n_peaks),
+            (chi_log, "chi_log", "f32", nf, lf), (alpha_log, "alpha_log", "f32", self.n_peaks, lf),
+            (state, "state", "f32", 2 * (4 * nf + self.n_peaks)),
+            *self._grad_specs(grad_u, grad_chi, grad_alpha, "o" if int(t) == 0 else ""))
+        _check(lib.mpbp_adam_step(self.handle, ctypes.byref(c), int(t), pu, pc, pa, pcl, pal, ps, gu, gc, ga,
+                                  _stream(stream)))
 
     def mpbp_norm2(self, a, out, n=None, stream=None):
-        _check(lib.mpbp_norm2(self.handle, _ptr(a), int(a.numel() if n is None else n), _ptr(out), _stream(stream)))
+        n = int(a.numel() if n is None else n)
+        pa, po = _dev_bufs(self.device, (a, "a", "f32", n, "+"), (out, "out", "f64", 1))
+        _check(lib.mpbp_norm2(self.handle, pa, n, po, _stream(stream)))
 
     def mpbp_set_background(self, b):
         """Background b of eq. (2) (device float, ragged like y) for later calls; None clears
         it.  The plan keeps a reference to the tensor while it is set."""
-        if b is not None and (b.numel() != self.intensity_size or b.element_size() != 4 or not b.is_contiguous()):
-            raise ValueError(f"b must be a contiguous float32 tensor of {self.intensity_size} elements")
-        _check(lib.mpbp_set_background(self.handle, _ptr(b)))
+        (pb,) = _dev_bufs(self.device, (b, "b", "f32", self.intensity_size, "o"))
+        _check(lib.mpbp_set_background(self.handle, pb))
         self._background = b
 
     def mpbp_unwrap_project(self, u, wraps=None, stream=None):
         """Pi_U of eq. (10) in place on u (float32, the layout of mpbp_loss_grad); wraps:
         optional int32 [n_peaks][nz or 1][ny][nx] receiving the 2 pi multiples added."""
-        lat = (1 if self.flags & MPBP_Z_TIED else self.nz) * self.ny * self.nx
-        if u.numel() != 3 * lat or u.element_size() != 4 or not u.is_contiguous():
-            raise ValueError(f"u must be a contiguous float32 tensor of {3 * lat} elements")
-        if wraps is not None and (wraps.numel() != self.n_peaks * lat or wraps.element_size() != 4
-                                  or not wraps.is_contiguous()):
-            raise ValueError(f"wraps must be a contiguous int32 tensor of {self.n_peaks * lat} elements")
-        _check(lib.mpbp_unwrap_project(self.handle, _ptr(u), _ptr(wraps), _stream(stream)))
+        import torch
+        lat = self.field_size
+        (pu,) = _dev_bufs(self.device, (u, "u", "f32", 3 * lat))
+        if wraps is not None and (not isinstance(wraps, torch.Tensor) or wraps.dtype != torch.int32
+                                  or not wraps.is_cuda or wraps.device.index != self.device
+                                  or wraps.numel() != self.n_peaks * lat or not wraps.is_contiguous()):
+            raise ValueError(f"wraps must be a contiguous int32 tensor of {self.n_peaks * lat} elements "
+                             f"on cuda:{self.device}")
+        _check(lib.mpbp_unwrap_project(self.handle, pu, _ptr(wraps), _stream(stream)))
 
     def mpbp_set_option(self, option, value):
         _check(lib.mpbp_set_option(self.handle, int(option), int(value)))
@@ -264,8 +329,8 @@ class Plan:
         return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(STAGES)}
 
     def mpbp_autotune(self, u, chi, alpha, probe, y, stream=None):
-        _check(lib.mpbp_autotune(self.handle, _ptr(u), _ptr(chi), _ptr(alpha), _ptr(probe), _ptr(y),
-                                 _stream(stream)))
+        pu, pc, pa, pp, py = _dev_bufs(self.device, *self._input_specs(u, chi, alpha, probe, y))
+        _check(lib.mpbp_autotune(self.handle, pu, pc, pa, pp, py, _stream(stream)))
 
     def mpbp_set_variant(self, size_class, footprint_bound, slab, xcd_order):
         _check(lib.mpbp_set_variant(self.handle, int(size_class), int(footprint_bound), int(slab),

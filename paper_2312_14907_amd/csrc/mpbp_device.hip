@@ -39,7 +39,8 @@ __global__ __launch_bounds__(256) void k_object(const float* __restrict__ u,
   float ux = u[vi], uy = u[us + vi], uz = u[2 * us + vi];
   float ch = chi[vi];
   for (int m = 0; m < n_peaks; ++m) {
-    float phi = peaks[m].gx * ux + peaks[m].gy * uy + peaks[m].gz * uz;
+    // G . u with explicit FMAs: the gradient kernel forms the same phase bit for bit
+    float phi = fmaf(peaks[m].gz, uz, fmaf(peaks[m].gy, uy, peaks[m].gx * ux));
     float s, c;
     sincosf(phi, &s, &c);
     float a = alpha[m] * ch;
@@ -299,9 +300,9 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
             const unsigned vf = A.tied ? lat : v;
             const float ux = A.u[vf], uy = A.u[fstride + vf], uzv = A.u[2u * fstride + vf];
             const float ch = A.chi[vf];
-            const float phi = pk.gx * ux + pk.gy * uy + pk.gz * uzv;
+            const float phi = fmaf(pk.gz, uzv, fmaf(pk.gy, uy, pk.gx * ux));   // as k_object
             float s, c;
-            __sincosf(phi, &s, &c);
+            sincosf(phi, &s, &c);   // as k_object: the adjoint uses the forward model's O
             const cplx g = acc[i];
             const float re = g.x * c + g.y * s;                 // Re(conj(g) e^{i phi})
             const float dphi = al * ch * (g.y * c - g.x * s);   // Im(g conj(O))

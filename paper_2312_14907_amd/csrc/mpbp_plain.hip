@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_pl_chain(const float* __restrict__ gobj
     double ap = 0.0;
     if (on) {
       const PeakDev pk = peaks[m];
-      const float phi = pk.gx * ux + pk.gy * uy + pk.gz * uz;
+      const float phi = fmaf(pk.gz, uz, fmaf(pk.gy, uy, pk.gx * ux));   // as k_object
       float s, c;
       sincosf(phi, &s, &c);
       const float al = alpha[m];

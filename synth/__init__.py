@@ -16,6 +16,7 @@ from .inputs import (
     poisson_counts,
     speckle_counts,
     crop_problem,
+    band_problem,
     unwrap_field,
     lattice_jump,
     incident_probe_3d,
@@ -31,4 +32,5 @@ __all__ = [
     "poisson_counts",
     "speckle_counts",
     "crop_problem",
+    "band_problem",
 ]

@@ -237,6 +237,43 @@ def crop_problem(problem, peak_rows):
     return out
 
 
+def band_problem(problem, row0, row1):
+    """One band of scan rows, with the object rows it touches.
+
+    Keeps the raster rows [row0, row1) of every peak (clipped to each raster) and crops
+    the object to the rows [lo, hi) that those frames' probe supports reach (clipped to
+    the grid), shifting the raster origins by -lo.  Returns (band, lo, hi, frames) with
+    `frames` the global frame ids of `problem` that the band's frames are, in the band's
+    own frame order (peak-major, raster order), so that band frame k is problem frame
+    frames[k].  Geometry only: nothing of the forward model is evaluated.
+    """
+    rows = []
+    lo, hi = problem.ny, 0
+    for m in range(problem.n_peaks):
+        r0 = max(0, min(int(row0), int(problem.scan_n[m, 0])))
+        r1 = max(r0, min(int(row1), int(problem.scan_n[m, 0])))
+        rows.append((r0, r1))
+        if r1 > r0:
+            top = int(problem.scan_origin[m, 0]) + r0 * int(problem.scan_step[m, 0])
+            bottom = int(problem.scan_origin[m, 0]) + (r1 - 1) * int(problem.scan_step[m, 0]) + problem.probe_n
+            lo, hi = min(lo, max(top, 0)), max(hi, min(bottom, problem.ny))
+    if hi <= lo:
+        lo, hi = 0, 1
+    band = Problem(problem.name + f"_rows{row0}-{row1}", problem.nz, hi - lo, problem.nx, problem.probe_n,
+                   problem.g.copy(), problem.shear.copy(), problem.det.copy(), problem.scan_n.copy(),
+                   problem.scan_step.copy(), problem.scan_origin.copy(), list(problem.photons),
+                   problem.shear_linear)
+    frames = []
+    base = 0
+    for m, (r0, r1) in enumerate(rows):
+        cols = int(problem.scan_n[m, 1])
+        band.scan_n[m, 0] = r1 - r0
+        band.scan_origin[m, 0] = int(problem.scan_origin[m, 0]) + r0 * int(problem.scan_step[m, 0]) - lo
+        frames += [base + iy * cols + ix for iy in range(r0, r1) for ix in range(cols)]
+        base += int(problem.scan_n[m, 0]) * cols
+    return band, lo, hi, frames
+
+
 def frame_order(n_frames, seed, epochs):
     """The shuffled frame order of a minibatch reconstruction: one random permutation
     of all frames per epoch (the shuffle of Algorithm 1), concatenated, int32."""

@@ -1,5 +1,5 @@
 """The benchmark's CPU-baseline leg on all host cores: CPU-only worker processes run the
-unchanged oracle on their own minibatches behind a common start (c1_tiny, a few frames)."""
+unchanged oracle on their own bands of scan rows behind a common start (c1_tiny)."""
 import os
 import subprocess
 import sys
@@ -18,7 +18,7 @@ def test_all_cores_leg_reports_every_worker():
 
 def test_worker_waits_for_the_start_file(tmp_path):
     go = tmp_path / "go"
-    p = subprocess.Popen([sys.executable, "-m", "oracle.time_worker", "c1_tiny", "10", "5", str(go)],
+    p = subprocess.Popen([sys.executable, "-m", "oracle.time_worker", "c1_tiny", "1", "2", str(go)],
                          cwd=ROOT, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
     try:
         assert p.stdout.readline().strip() == "ready"
@@ -29,4 +29,5 @@ def test_worker_waits_for_the_start_file(tmp_path):
         if p.poll() is None:
             p.kill()
     assert p.returncode == 0, err
-    assert float(out.strip().splitlines()[-1]) > 0
+    frames, seconds = out.strip().splitlines()[-1].split()
+    assert int(frames) == 3 * 2 * 5 and float(seconds) > 0     # 2 raster rows of 5 frames, 3 peaks

@@ -107,9 +107,10 @@ def test_descriptor_validation_codes():
 
 def test_host_only_plan_refuses_compute_and_options():
     plan = B.Plan(_supported_problem(((0.3, 0.2), (0.1, -0.4))), device=-1)
-    with pytest.raises(B.MPBPError) as e:
-        plan.mpbp_forward(np.zeros(1, np.float32), np.zeros(1, np.float32), np.zeros(1, np.float32),
-                          np.zeros(1, np.float32), stream=0)
+    z = np.zeros(1, np.float32)
+    with pytest.raises(B.MPBPError) as e:      # the library's own refusal (no device)
+        B._check(B.lib.mpbp_forward(plan.handle, z.ctypes.data, z.ctypes.data, z.ctypes.data, z.ctypes.data,
+                                    None, None, 0, None, None, None, None))
     assert e.value.status == 4
     with pytest.raises(B.MPBPError) as e:
         plan.mpbp_set_option(99, 0)
@@ -161,7 +162,7 @@ def test_launch_parameter_api_on_host_plan():
         plan.mpbp_set_option(B.MPBP_OPT_GRAD_TILE, 4)
     with pytest.raises(B.MPBPError) as e:     # autotuning needs a device plan
         z = np.zeros(1, np.float32)
-        plan.mpbp_autotune(z, z, z, z, z, stream=0)
+        B._check(B.lib.mpbp_autotune(plan.handle, *(5 * [z.ctypes.data]), None))
     assert e.value.status == 4
     n = ctypes.c_int64()
     assert B.lib.mpbp_tuning(plan.handle, None, 0, ctypes.byref(n)) == 0 and n.value > 2
