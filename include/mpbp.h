@@ -195,6 +195,32 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi,
                            float* grad_u, float* grad_chi, float* grad_alpha,
                            void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): mpbp_loss_grad with its per-call
+   workspace (the per-peak objects, the exit-wave and gradient footprint slots, the
+   per-frame losses and the alpha partials) in a fixed device array of the library
+   instead of the plan's workspace.  The array holds MPBP_STATIC_SCRATCH_BYTES (64 MiB)
+   on every GPU the library creates a plan on; it is set up by mpbp_plan_create and kept
+   until the process ends.  This call allocates nothing (no hipMalloc, hipFree or other
+   allocating call, host or device).
+   Arguments, layouts, ownership and results are those of mpbp_loss_grad, and the
+   results are bitwise equal to it (the same kernels with the plan's launch parameters;
+   always the batched fused path, launched directly: no graph capture, no stage timing).
+   Errors: those of mpbp_loss_grad, and MPBP_ERR_UNSUPPORTED (with the bytes needed in
+   mpbp_last_error) when the plan's workspace exceeds the array; 8 n_peaks nz ny nx bytes
+   of objects plus 16 bytes per footprint pixel of every frame dominate it (about 23 MB
+   for 3 peaks, 16 x 128 x 128 voxels and 768 frames of 37 x 37).
+   Every such call on one GPU uses the same array and leaves its contents there (every
+   region is written before it is read within a call): calls that overlap in time on one
+   GPU, on any streams or plans, race and must be serialised by the caller. */
+#define MPBP_STATIC_SCRATCH_BYTES (64ull << 20)
+mpbp_status mpbp_loss_grad_static(mpbp_plan plan, const float* u, const float* chi,
+                                  const float* alpha, const void* probe, const float* y,
+                                  const int32_t* frames, int64_t n_frames,
+                                  double* loss, float* frame_loss,
+                                  float* grad_u, float* grad_chi, float* grad_alpha,
+                                  void* stream);
+
 /* Plain gradient step in place, p <- p - eta_p * g_p, for (u, chi, alpha) with
    eta = (eta_u, eta_chi, eta_alpha) (host float[3]); the update of Algorithm 1 without
    Adam's moments.  All six device pointers are required. */

@@ -30,7 +30,7 @@ EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_in
             "mpbp_tables", "mpbp_forward", "mpbp_loss_grad", "mpbp_step", "mpbp_set_option",
             "mpbp_get_option", "mpbp_stage_times", "mpbp_autotune", "mpbp_set_variant", "mpbp_tuning",
             "mpbp_adam_step", "mpbp_norm2", "mpbp_set_background", "mpbp_unwrap_project",
-            "mpbp_last_error")
+            "mpbp_last_error", "mpbp_loss_grad_static")
 
 
 class mpbp_peak(ctypes.Structure):
@@ -82,6 +82,8 @@ def _load():
     lib.mpbp_forward.restype = st
     lib.mpbp_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, i32p, i64, vp, vp, vp, vp, vp, vp]
     lib.mpbp_loss_grad.restype = st
+    lib.mpbp_loss_grad_static.argtypes = [vp, vp, vp, vp, vp, vp, i32p, i64, vp, vp, vp, vp, vp, vp]
+    lib.mpbp_loss_grad_static.restype = st
     lib.mpbp_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_float), vp]
     lib.mpbp_step.restype = st
     lib.mpbp_set_option.argtypes = [vp, ctypes.c_int, i64]
@@ -269,6 +271,18 @@ class Plan:
             self.device, *self._input_specs(u, chi, alpha, probe, y), *self._output_specs(n_out, loss, frame_loss),
             *self._grad_specs(grad_u, grad_chi, grad_alpha))
         _check(lib.mpbp_loss_grad(self.handle, pu, pc, pa, pp, py, fp, n, pl, pf, gu, gc, ga, _stream(stream)))
+        del keep
+
+    def mpbp_loss_grad_static(self, u, chi, alpha, probe, y, grad_u, grad_chi, grad_alpha, frames=None,
+                              loss=None, frame_loss=None, stream=None):
+        """mpbp_loss_grad with the library's fixed device workspace (allocates nothing)."""
+        fp, n, keep = self._frames(frames)
+        n_out = self.n_frames if frames is None else n
+        pu, pc, pa, pp, py, pl, pf, gu, gc, ga = _dev_bufs(
+            self.device, *self._input_specs(u, chi, alpha, probe, y), *self._output_specs(n_out, loss, frame_loss),
+            *self._grad_specs(grad_u, grad_chi, grad_alpha))
+        _check(lib.mpbp_loss_grad_static(self.handle, pu, pc, pa, pp, py, fp, n, pl, pf, gu, gc, ga,
+                                         _stream(stream)))
         del keep
 
     def mpbp_step(self, u, chi, alpha, grad_u, grad_chi, grad_alpha, eta, stream=None):

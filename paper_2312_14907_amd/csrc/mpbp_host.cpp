@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -66,6 +67,39 @@ struct GraphEntry {
   uint64_t used = 0;
 };
 
+// The fixed device workspace of mpbp_loss_grad_static (callers that cannot allocate).
+// One copy per GPU, at its own address on each: host code never uses the array's name
+// as an address, only the pointer hipGetSymbolAddress returns with that device current.
+constexpr size_t kStaticScratchBytes = size_t(MPBP_STATIC_SCRATCH_BYTES);
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxScratchDevices] = {};   // per device, set once at plan creation
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Look up this device's copy of the array (the device must be current).  Called by
+// mpbp_plan_create for device plans, once per device.
+mpbp_status scratch_setup(int device) {
+  if (device >= kMaxScratchDevices) return MPBP_OK;   // the static variant then reports it
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return MPBP_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+  g_scratch[device] = ptr;
+  return MPBP_OK;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
+}
+
 }  // namespace
 
 struct mpbp_plan_t {
@@ -94,7 +128,8 @@ struct mpbp_plan_t {
     double tuned_us;                   // autotuned launch time (0: not tuned)
   };
   std::vector<SizeClass> classes;      // full batch: frames of one detector size, in `order`
-  std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch
+  std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch (capacity reserved)
+  std::vector<unsigned char> seen;     // [F] duplicate check of a staged list (sized once)
   int grad_batch = mpbp::kDefaultGradBatch;
   int grad_tile = mpbp::kDefaultGradTileX;
   double grad_tuned_us = 0.0;
@@ -386,6 +421,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
           for (int ix = tx; ix < std::min(tx + kOrderTile, d.cols); ++ix)
             p->order.push_back(d.frame_base + iy * d.cols + ix);
   }
+  p->seen.assign(p->F, 0);
+  p->sub_classes.reserve(p->classes.size());
   return MPBP_OK;
 }
 
@@ -446,12 +483,13 @@ mpbp_status stage_frames(mpbp_plan_t* p, const int32_t* frames, int64_t n, hipSt
     return MPBP_OK;
   }
   if (n < 0 || n > p->F) return fail(MPBP_ERR_INVALID, "n_frames %lld out of range [0, %lld]", (long long)n, (long long)p->F);
-  std::vector<unsigned char> seen(p->F, 0);
+  // (no allocation here: the flags and the class list were sized at plan creation)
+  std::fill(p->seen.begin(), p->seen.end(), (unsigned char)0);
   for (int64_t i = 0; i < n; ++i) {
     int f = frames[i];
     if (f < 0 || f >= p->F) return fail(MPBP_ERR_INVALID, "frame id %d out of range", f);
-    if (seen[f]) return fail(MPBP_ERR_INVALID, "duplicate frame id %d", f);
-    seen[f] = 1;
+    if (p->seen[f]) return fail(MPBP_ERR_INVALID, "duplicate frame id %d", f);
+    p->seen[f] = 1;
   }
   hipError_t e;
   if (p->staged_pending) {
@@ -505,8 +543,8 @@ struct StageTimer {
   int stage;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
-  StageTimer(mpbp_plan_t* p_, int stage_, hipStream_t s_) : p(p_), stage(stage_), s(s_) {
-    if (!p->profile) return;
+  StageTimer(mpbp_plan_t* p_, int stage_, hipStream_t s_, bool on = true) : p(p_), stage(stage_), s(s_) {
+    if (!p->profile || !on) return;
     while (p->ev_pool.size() < p->ev_used + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return;
@@ -532,7 +570,7 @@ struct StageTimer {
 // frame kernel.  Direct launches run every class's projection first, then every class's
 // frame kernel, each group under its stage timer.
 hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset, bool grad, hipStream_t s,
-                          bool branch = false) {
+                          bool branch = false, bool timed = true) {
   const auto& cls = subset ? p->sub_classes : p->classes;
   const int* list = subset ? p->d_list_sorted : p->d_order;
   auto class_args = [&](const mpbp_plan_t::SizeClass& c) {
@@ -545,12 +583,12 @@ hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset,
   hipError_t e = hipSuccess;
   if (!branch) {
     {
-      StageTimer t(p, MPBP_STAGE_PROJECT, s);
+      StageTimer t(p, MPBP_STAGE_PROJECT, s, timed);
       for (const auto& c : cls)
         if (c.count && e == hipSuccess) e = mpbp::launch_project(c.G, class_args(c), p->lds_project[c.G], s);
     }
     {
-      StageTimer t(p, MPBP_STAGE_FRAMES, s);
+      StageTimer t(p, MPBP_STAGE_FRAMES, s, timed);
       for (const auto& c : cls)
         if (c.count && e == hipSuccess)
           e = mpbp::launch_frames(c.D, c.FB, class_args(c), grad ? c.lds_grad : c.lds_fwd, s);
@@ -581,9 +619,23 @@ hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset,
   return e;
 }
 
-mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, float* mi, int grad) {
+// The per-call device workspace of the fused path: per-peak objects, exit-wave and
+// gradient footprint slots, per-frame losses, per-tile alpha partials.  Normally the
+// plan's own buffers; mpbp_loss_grad_static carves it from the library's fixed array.
+struct Work {
+  float* obj;
+  float* slots;
+  float* gslots;
+  double* floss;
+  double* apart;
+};
+
+Work plan_work(mpbp_plan p) { return {p->d_obj, p->d_slots, p->d_gslots, p->d_floss, p->d_apart}; }
+
+mpbp::FrameArgs frame_args(mpbp_plan p, const Work& w, const float* y, const int* list, int n, float* mi,
+                           int grad) {
   mpbp::FrameArgs a{};
-  a.obj = p->d_obj;
+  a.obj = w.obj;
   a.y = y;
   a.bg = p->d_bg;
   a.list = list;
@@ -592,9 +644,9 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const float* y, const int* list, int n, 
   a.peak_of = p->d_peak_of;
   a.peaks = p->d_peaks;
   a.shear = p->d_shear;
-  a.slots = p->d_slots;
-  a.gslots = p->d_gslots;
-  a.floss = p->d_floss;
+  a.slots = w.slots;
+  a.gslots = w.gslots;
+  a.floss = w.floss;
   a.tw = p->d_tw;
   a.mi = mi;
   a.nz = p->nz; a.ny = p->ny; a.nx = p->nx; a.np = p->np;
@@ -611,10 +663,10 @@ const mpbp_plan_t::GradTiling& grad_tiling(mpbp_plan p) {
   return p->tilings.front();
 }
 
-mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const float* alpha,
+mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float* chi, const float* alpha,
                          const float* probe, bool subset, float* grad_u, float* grad_chi) {
   mpbp::GradArgs g{};
-  g.slots = p->d_gslots;
+  g.slots = w.gslots;
   g.active = subset ? p->d_active : p->d_active_all;
   g.all_active = subset ? 0 : 1;
   g.probe = probe;
@@ -632,7 +684,7 @@ mpbp::GradArgs grad_args(mpbp_plan p, const float* u, const float* chi, const fl
   g.probe3 = p->probe3;
   g.shw = p->linear ? p->d_shw : nullptr;
   g.grad_u = grad_u; g.grad_chi = grad_chi;
-  g.alpha_part = p->d_apart;
+  g.alpha_part = w.apart;
   return g;
 }
 
@@ -642,12 +694,13 @@ hipError_t enqueue_forward(mpbp_plan p, const float* u, const float* chi, const 
                            const float* probe, const float* y, const int* list, int n, bool subset,
                            float* model_intensity, hipStream_t s, bool branch, const char** what) {
   hipError_t e;
+  const Work w = plan_work(p);
   {
     StageTimer t(p, MPBP_STAGE_OBJECT, s);
-    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, p->d_obj, s);
+    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, w.obj, s);
   }
   if (e != hipSuccess) return *what = "object kernel", e;
-  mpbp::FrameArgs a = frame_args(p, y, list, n, model_intensity, 0);
+  mpbp::FrameArgs a = frame_args(p, w, y, list, n, model_intensity, 0);
   a.probe = probe;
   e = enqueue_frames(p, a, subset, false, s, branch);
   if (e != hipSuccess) return *what = "frame kernel", e;
@@ -655,23 +708,23 @@ hipError_t enqueue_forward(mpbp_plan p, const float* u, const float* chi, const 
 }
 
 // The batched fused path's launches of one mpbp_loss_grad call, finalize excluded.
-hipError_t enqueue_loss_grad(mpbp_plan p, const float* u, const float* chi, const float* alpha,
+hipError_t enqueue_loss_grad(mpbp_plan p, const Work& w, const float* u, const float* chi, const float* alpha,
                              const float* probe, const float* y, const int* list, int n, bool subset,
                              float* grad_u, float* grad_chi, hipStream_t s, bool branch,
-                             const char** what) {
+                             const char** what, bool timed = true) {
   hipError_t e;
   {
-    StageTimer t(p, MPBP_STAGE_OBJECT, s);
-    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, p->d_obj, s);
+    StageTimer t(p, MPBP_STAGE_OBJECT, s, timed);
+    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, w.obj, s);
   }
   if (e != hipSuccess) return *what = "object kernel", e;
-  mpbp::FrameArgs a = frame_args(p, y, list, n, nullptr, 1);
+  mpbp::FrameArgs a = frame_args(p, w, y, list, n, nullptr, 1);
   a.probe = probe;
-  e = enqueue_frames(p, a, subset, true, s, branch);
+  e = enqueue_frames(p, a, subset, true, s, branch, timed);
   if (e != hipSuccess) return *what = "frame kernel", e;
-  const mpbp::GradArgs g = grad_args(p, u, chi, alpha, probe, subset, grad_u, grad_chi);
+  const mpbp::GradArgs g = grad_args(p, w, u, chi, alpha, probe, subset, grad_u, grad_chi);
   {
-    StageTimer t(p, MPBP_STAGE_GRAD, s);
+    StageTimer t(p, MPBP_STAGE_GRAD, s, timed);
     e = mpbp::launch_grad(p->grad_batch, p->grad_tile, g, p->lds_grad, s);
   }
   if (e != hipSuccess) return *what = "gradient kernel", e;
@@ -1008,6 +1061,14 @@ mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan*
       g_err = msg;
       return st;
     }
+    st = scratch_setup(device);
+    if (st != MPBP_OK) {
+      std::string msg = g_err;
+      free_device(p);
+      delete p;
+      g_err = msg;
+      return st;
+    }
     load_tuning(p);
   } else if (device != -1) {
     delete p;
@@ -1125,8 +1186,8 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, grad_u, grad_chi, grad_alpha, plan->d_bg};
     std::copy(std::begin(ptrs), std::end(ptrs), key.ptr);
     return run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
-      hipError_t le = enqueue_loss_grad(plan, u, chi, alpha, (const float*)probe, y, list, n, false,
-                                        grad_u, grad_chi, cs, true, what);
+      hipError_t le = enqueue_loss_grad(plan, plan_work(plan), u, chi, alpha, (const float*)probe, y, list, n,
+                                        false, grad_u, grad_chi, cs, true, what);
       if (le == hipSuccess) {
         le = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, apart, n_part, plan->M,
                                    grad_alpha, cs);
@@ -1136,8 +1197,8 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     });
   } else {
     const char* what = "";
-    e = enqueue_loss_grad(plan, u, chi, alpha, (const float*)probe, y, list, n, frames != nullptr, grad_u,
-                          grad_chi, s, false, &what);
+    e = enqueue_loss_grad(plan, plan_work(plan), u, chi, alpha, (const float*)probe, y, list, n,
+                          frames != nullptr, grad_u, grad_chi, s, false, &what);
     if (e != hipSuccess) return hip_fail(e, what);
   }
   {
@@ -1145,6 +1206,59 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     e = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, apart, n_part, plan->M,
                               grad_alpha, s);
   }
+  if (e != hipSuccess) return hip_fail(e, "finalize kernel");
+  return MPBP_OK;
+}
+
+// Layout of the fused path's workspace in the fixed array: objects, exit-wave slots,
+// gradient slots, frame losses, alpha partials, each starting on a 256-byte boundary.
+// Returns the bytes needed.
+static size_t static_work(mpbp_plan p, char* base, Work* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return q;
+  };
+  Work t;
+  t.obj = (float*)take(sizeof(float) * 2 * (size_t)p->M * (size_t)p->nvox);
+  t.slots = (float*)take(sizeof(float) * 2 * (size_t)p->slots_cplx);
+  t.gslots = (float*)take(sizeof(float) * 2 * (size_t)p->slots_cplx);
+  t.floss = (double*)take(sizeof(double) * (size_t)p->F);
+  t.apart = (double*)take(sizeof(double) * (size_t)p->max_tiles * p->M);
+  if (w) *w = t;
+  return off;
+}
+
+mpbp_status mpbp_loss_grad_static(mpbp_plan plan, const float* u, const float* chi, const float* alpha,
+                                  const void* probe, const float* y, const int32_t* frames, int64_t n_frames,
+                                  double* loss, float* frame_loss, float* grad_u, float* grad_chi,
+                                  float* grad_alpha, void* stream) {
+  mpbp_status st = check_plan(plan);
+  if (st != MPBP_OK) return st;
+  if (!u || !chi || !alpha || !probe || !y)
+    return fail(MPBP_ERR_INVALID, "u, chi, alpha, probe and y are required");
+  if (!grad_u || !grad_chi || !grad_alpha) return fail(MPBP_ERR_INVALID, "grad_u, grad_chi and grad_alpha are required");
+  const size_t need = static_work(plan, nullptr, nullptr);
+  if (need > kStaticScratchBytes)
+    return fail(MPBP_ERR_UNSUPPORTED, "the workload needs %zu bytes of workspace; the static workspace holds %zu",
+                need, kStaticScratchBytes);
+  char* base = (char*)scratch_of(plan->device);
+  if (!base) return fail(MPBP_ERR_DEVICE, "no static workspace on device %d", plan->device);
+  Work w;
+  static_work(plan, base, &w);
+  hipStream_t s = (hipStream_t)stream;
+  int n = 0;
+  st = stage_frames(plan, frames, n_frames, s, true, &n);
+  if (st != MPBP_OK) return st;
+  const int* list = frames ? plan->d_list : plan->d_order;
+  const int* out_list = frames ? plan->d_list : nullptr;
+  const char* what = "";
+  hipError_t e = enqueue_loss_grad(plan, w, u, chi, alpha, (const float*)probe, y, list, n, frames != nullptr,
+                                   grad_u, grad_chi, s, false, &what, false);
+  if (e != hipSuccess) return hip_fail(e, what);
+  const int n_part = grad_tiling(plan).nx * grad_tiling(plan).ny;
+  e = mpbp::launch_finalize(w.floss, out_list, n, loss, frame_loss, w.apart, n_part, plan->M, grad_alpha, s);
   if (e != hipSuccess) return hip_fail(e, "finalize kernel");
   return MPBP_OK;
 }
@@ -1380,7 +1494,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
   for (size_t ci = 0; ci < plan->classes.size() && e == hipSuccess; ++ci) {
     auto& c = plan->classes[ci];
     if (c.count == 0) continue;
-    mpbp::FrameArgs a = frame_args(plan, y, plan->d_order + c.begin, c.count, nullptr, 1);
+    mpbp::FrameArgs a = frame_args(plan, plan_work(plan), y, plan->d_order + c.begin, c.count, nullptr, 1);
     a.probe = (const float*)probe;
     auto run_pf = [&](int G, int fb, int xcd) {
       a.xcd = xcd;
@@ -1434,7 +1548,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
     int bb = plan->grad_batch, bt = plan->grad_tile;
     for (int TX : mpbp::kGradTileXs) {
       plan->grad_tile = TX;
-      const mpbp::GradArgs g = grad_args(plan, u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * nf);
+      const mpbp::GradArgs g = grad_args(plan, plan_work(plan), u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * nf);
       for (int B : mpbp::kGradBatches) {
         if (e != hipSuccess) break;
         double us = 1e300;
