@@ -118,12 +118,19 @@ enum {
   MPBP_OPT_XCD_ORDER = 3,    /* 1 = hand each XCD a contiguous band of frames (default) */
   MPBP_OPT_PROFILE = 4,      /* 1 = record HIP events around every kernel stage on the
                                 call's stream (read with mpbp_stage_times); default 0    */
-  MPBP_OPT_GRAD_BATCH = 5,   /* frames whose footprint gradients the back-projection
-                                kernel reads per step of its frame walk: 1, 2 (default)
-                                or 4; set by mpbp_autotune                               */
-  MPBP_OPT_GRAD_TILE = 6     /* back-projection tile: 16 (16 x 4 voxels, default) or 8
+  MPBP_OPT_GRAD_BATCH = 5,   /* footprint gradients the back-projection kernel reads at
+                                once: 1, 2, 4, 8 (default) or 16; the run gather takes
+                                at least 4, the per-slice walk at most 4; set by
+                                mpbp_autotune                                            */
+  MPBP_OPT_GRAD_TILE = 6,    /* back-projection tile: 16 (16 x 4 voxels, default) or 8
                                 (8 x 8 voxels on a grid aligned with the first peak's
                                 raster); set by mpbp_autotune                            */
+  MPBP_OPT_GRAD_RUNS = 7     /* 1 (default): with one probe for all slices and rounded
+                                offsets, the back-projection sums the frames once per run
+                                of consecutive slices with equal exit-beam offset (those
+                                slices read the same footprint pixels) and applies the
+                                chain rule per slice; 0: it sums them per slice.  Both
+                                give bitwise the same results.                           */
 };
 
 /* Kernel stages timed under MPBP_OPT_PROFILE. */

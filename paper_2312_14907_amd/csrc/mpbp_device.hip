@@ -73,6 +73,24 @@ __device__ __forceinline__ cplx cmulc_acc(cplx acc, cplx a, cplx b) {
   return {fmaf(a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(a.y, b.x, fmaf(-a.x, b.y, acc.y))};
 }
 
+// Chain rule of one voxel and peak through O_m = alpha_m chi exp(i phi), phi = G_m . u,
+// for the frame sum g of conj(P) g_psi: adds G_m Im(g conj(O)) to du, alpha_m Re(conj(g)
+// e^{i phi}) to dchi and chi Re(conj(g) e^{i phi}) to the alpha partial.  Every
+// product and sum is written out, so both gradient kernels round it identically.
+__device__ __forceinline__ void chain_voxel(const PeakDev& pk, cplx g, float ux, float uy, float uz, float ch,
+                                            float al, float& gux, float& guy, float& guz, float& gch, float& ap) {
+  const float phi = fmaf(pk.gz, uz, fmaf(pk.gy, uy, pk.gx * ux));   // as k_object
+  float s, c;
+  sincosf(phi, &s, &c);                                             // as k_object
+  const float re = fmaf(g.y, s, g.x * c);                           // Re(conj(g) e^{i phi})
+  const float dphi = (al * ch) * fmaf(g.y, c, -(g.x * s));          // Im(g conj(O))
+  gux = fmaf(pk.gx, dphi, gux);
+  guy = fmaf(pk.gy, dphi, guy);
+  guz = fmaf(pk.gz, dphi, guz);
+  gch = fmaf(al, re, gch);
+  ap = fmaf(ch, re, ap);
+}
+
 // The peak record is the same for every lane: read it once and pass each word through
 // readfirstlane, so that the raster walk and the slot bases derived from it live in
 // scalar registers (a plain load from the table leaves them in vector registers, since
@@ -299,18 +317,7 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
             const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
             const unsigned vf = A.tied ? lat : v;
             const float ux = A.u[vf], uy = A.u[fstride + vf], uzv = A.u[2u * fstride + vf];
-            const float ch = A.chi[vf];
-            const float phi = fmaf(pk.gz, uzv, fmaf(pk.gy, uy, pk.gx * ux));   // as k_object
-            float s, c;
-            sincosf(phi, &s, &c);   // as k_object: the adjoint uses the forward model's O
-            const cplx g = acc[i];
-            const float re = g.x * c + g.y * s;                 // Re(conj(g) e^{i phi})
-            const float dphi = al * ch * (g.y * c - g.x * s);   // Im(g conj(O))
-            gux[i] += pk.gx * dphi;
-            guy[i] += pk.gy * dphi;
-            guz[i] += pk.gz * dphi;
-            gch[i] += al * re;
-            ap += ch * re;
+            chain_voxel(pk, acc[i], ux, uy, uzv, A.chi[vf], al, gux[i], guy[i], guz[i], gch[i], ap);
           }
         }
       }
@@ -358,6 +365,198 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
       A.grad_u[fstride + lat] = s[1];
       A.grad_u[2u * fstride + lat] = s[2];
       A.grad_chi[lat] = s[3];
+    }
+  }
+  if (tid < A.n_peaks) A.alpha_part[(long long)tile * A.n_peaks + tid] = apl[tid];
+}
+
+// ------------------------------------ gather back-projection over runs of slices ---
+// With one probe for all slices and integer exit-beam offsets (neither MPBP_PROBE_3D nor
+// MPBP_SHEAR_LINEAR), the slices of a run (consecutive slices with equal offset) read
+// the same footprint pixel of every frame with the same probe value: the frame sum
+// sum_f conj(P) g_psi of a (pixel, run) pair serves every slice of the run.  Per peak and
+// pass of kGradZB slices the kernel first gathers these sums, one item per (pixel, run):
+// a wavefront holds the tile's 64 pixels of one run, and each lane issues the loads of
+// B covering frames at once.  The chain rule then runs per voxel on its run's sum, read
+// from LDS.  The frames are summed in raster order with the same fused multiply-adds as
+// k_grad, so both kernels give the same results bit for bit.
+// The covering frames of a peak (those in the minibatch, in raster order) are listed in
+// LDS once per peak: window origin and slot offset.
+struct GradCand {
+  int fpy, fpx;
+  long long so;
+};
+
+template <int B, int TX>
+__global__ __launch_bounds__(kGradThreads, 4) void k_grad_runs(GradArgs A) {
+  constexpr int TY = kGradTile / TX;
+  extern __shared__ cplx smem[];
+  const int np = A.np, nz = A.nz;
+  cplx* Ps = smem;                                                       // np * np
+  cplx* rs = Ps + np * np;                                               // [kGradZB][kGradTile] run sums
+  GradCand* cand = reinterpret_cast<GradCand*>(rs + kGradZB * kGradTile);  // [max_cand]
+  int2* roff = reinterpret_cast<int2*>(cand + A.max_cand);               // [kGradZB] run offsets
+  double* apl = reinterpret_cast<double*>(roff + kGradZB);               // alpha partials
+  float* red = reinterpret_cast<float*>(apl + kMaxPeaksDev);             // block reduction
+  int* zr = reinterpret_cast<int*>(red + 16);                            // [kGradZB] run of a slice
+  int* ncand_s = zr + kGradZB;                                           // listed frames
+  float* zred = reinterpret_cast<float*>(ncand_s + 4);                   // z-tied partial sums
+  float tgu[3] = {0.f, 0.f, 0.f}, tgc = 0.f;
+
+  const int tid = threadIdx.x;
+  const int lane = tid % kGradTile;
+  const int tz = tid / kGradTile;
+  const int tile = frame_block_index(blockIdx.x, gridDim.x, 1);
+  if (tile >= A.tiles_x * A.tiles_y) return;
+  const int bx = tile % A.tiles_x, by = tile / A.tiles_x;
+  const int x0 = A.tile_ox + bx * TX, y0 = A.tile_oy + by * TY;
+  const int x = x0 + lane % TX, y = y0 + lane / TX;
+  const bool inb = (unsigned)x < (unsigned)A.nx && (unsigned)y < (unsigned)A.ny;
+  const long long nvox = (long long)nz * A.ny * A.nx;
+  const unsigned lat = (unsigned)(y * A.nx + x);
+  const unsigned fstride = A.tied ? (unsigned)(A.ny * A.nx) : (unsigned)nvox;
+  if (tid < kMaxPeaksDev) apl[tid] = 0.0;
+
+  for (int zb = 0; zb < nz; zb += kGradZB) {
+    float gux[kGradZPer], guy[kGradZPer], guz[kGradZPer], gch[kGradZPer];
+    float fu[kGradZPer][3], fc[kGradZPer];   // this lane's u and chi, read once per pass
+#pragma unroll
+    for (int i = 0; i < kGradZPer; ++i) {
+      gux[i] = guy[i] = guz[i] = gch[i] = 0.f;
+      const int z = zb + tz * kGradZPer + i;
+      const unsigned v = ((unsigned)(z < nz ? z : 0) * (unsigned)A.ny + (unsigned)(inb ? y : 0)) * (unsigned)A.nx +
+                         (unsigned)(inb ? x : 0);
+      const unsigned vf = A.tied ? (inb ? lat : 0u) : v;
+      fu[i][0] = A.u[vf];
+      fu[i][1] = A.u[fstride + vf];
+      fu[i][2] = A.u[2u * fstride + vf];
+      fc[i] = A.chi[vf];
+    }
+    const int zn = min(kGradZB, nz - zb);   // slices of this pass
+
+    for (int m = 0; m < A.n_peaks; ++m) {
+      const PeakDev pk = uniform_peak(A.peaks + m);
+      const int iy_lo = max(0, -floordiv(-(y0 - np + 1 - pk.oy), pk.sy));
+      const int iy_hi = min(pk.rows - 1, floordiv(y0 + TY - 1 - pk.oy, pk.sy));
+      const int ix_lo = max(0, -floordiv(-(x0 - np + 1 - pk.ox), pk.sx));
+      const int ix_hi = min(pk.cols - 1, floordiv(x0 + TX - 1 - pk.ox, pk.sx));
+      const int ncx = ix_hi - ix_lo + 1;
+      const int ncand = (iy_hi >= iy_lo && ncx > 0) ? (iy_hi - iy_lo + 1) * ncx : 0;
+      const int* zrun = A.zrun + m * nz;
+      const int k0 = zrun[zb];
+      const int nr = zrun[zb + zn - 1] - k0 + 1;   // runs meeting this pass
+      __syncthreads();
+      const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
+      for (int k = tid; k < np * np; k += kGradThreads) Ps[k] = probe[k];
+      for (int k = tid; k < nr; k += kGradThreads) roff[k] = A.roff[m * nz + k0 + k];
+      for (int k = tid; k < zn; k += kGradThreads) zr[k] = zrun[zb + k] - k0;
+      // the frames of the minibatch meeting the tile, in raster order (wavefront 0:
+      // flags, ballot, prefix count)
+      if (tid < 64) {
+        int base = 0;
+        for (int c0 = 0; c0 < ncand; c0 += 64) {
+          const int c = c0 + tid;
+          const int cy = iy_lo + c / (ncx > 0 ? ncx : 1), cx = ix_lo + c % (ncx > 0 ? ncx : 1);
+          const bool act = c < ncand && (A.all_active || A.active[pk.frame_base + cy * pk.cols + cx]);
+          const unsigned long long mask = __ballot(act);
+          const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+          if (act)
+            cand[pos] = {pk.oy + cy * pk.sy, pk.ox + cx * pk.sx,
+                         pk.slot_off + (long long)(cy * pk.cols + cx) * pk.fy * pk.fx};
+          base += __popcll(mask);
+        }
+        if (tid == 0) *ncand_s = base;
+      }
+      __syncthreads();
+      const int nact = __builtin_amdgcn_readfirstlane(*ncand_s);
+
+      // gather: item = (pixel, run); a wavefront takes the 64 pixels of one run
+      const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
+      for (int run = tz; run < nr; run += kGradTZ) {
+        const int2 ro = roff[run];
+        const int roy = __builtin_amdgcn_readfirstlane(ro.x), rox = __builtin_amdgcn_readfirstlane(ro.y);
+        cplx acc = {0.f, 0.f};
+        for (int c0 = 0; c0 < nact; c0 += B) {
+          cplx gv[B], pv[B];
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            const int c = c0 + k < nact ? c0 + k : c0;   // past the list: its first entry
+            const int fpy = __builtin_amdgcn_readfirstlane(cand[c].fpy);
+            const int fpx = __builtin_amdgcn_readfirstlane(cand[c].fpx);
+            const long long so = cand[c].so;
+            const int a = y - fpy, b = x - fpx;
+            const bool inw = inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
+            const int ac = inw ? a : 0, bc = inw ? b : 0;
+            const cplx pr = Ps[ac * np + bc];
+            pv[k] = inw ? pr : cplx{0.f, 0.f};
+            const char* sl = reinterpret_cast<const char*>(slots + so);
+            const unsigned off = (unsigned)((ac + roy) * pk.fx + bc + rox) * (unsigned)sizeof(cplx);
+            gv[k] = *reinterpret_cast<const cplx*>(sl + off);
+          }
+#pragma unroll
+          for (int k = 0; k < B; ++k)
+            if (c0 + k < nact) acc = cmulc_acc(acc, gv[k], pv[k]);   // conj(P) g_psi
+        }
+        rs[run * kGradTile + lane] = acc;
+      }
+      __syncthreads();
+
+      // chain rule through O_m = alpha_m chi exp(i G_m . u) per voxel
+      float ap = 0.f;
+      if (inb) {
+        const float al = A.alpha[m];
+#pragma unroll
+        for (int i = 0; i < kGradZPer; ++i) {
+          const int zl = tz * kGradZPer + i;
+          if (zl < zn) {
+            chain_voxel(pk, rs[zr[zl] * kGradTile + lane], fu[i][0], fu[i][1], fu[i][2], fc[i], al, gux[i],
+                        guy[i], guz[i], gch[i], ap);
+          }
+        }
+      }
+      const float apb = block_sum_f(ap, red);
+      if (tid == 0) apl[m] += (double)apb;
+    }
+    if (inb && A.tied) {
+#pragma unroll
+      for (int i = 0; i < kGradZPer; ++i) {
+        tgu[0] += gux[i];
+        tgu[1] += guy[i];
+        tgu[2] += guz[i];
+        tgc += gch[i];
+      }
+    } else if (inb) {
+      const unsigned nv = (unsigned)nvox;
+#pragma unroll
+      for (int i = 0; i < kGradZPer; ++i) {
+        const int z = zb + tz * kGradZPer + i;
+        if (z < nz) {
+          const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
+          A.grad_u[v] = gux[i];
+          A.grad_u[nv + v] = guy[i];
+          A.grad_u[2u * nv + v] = guz[i];
+          A.grad_chi[v] = gch[i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (A.tied) {
+    zred[0 * kGradThreads + tid] = tgu[0];
+    zred[1 * kGradThreads + tid] = tgu[1];
+    zred[2 * kGradThreads + tid] = tgu[2];
+    zred[3 * kGradThreads + tid] = tgc;
+    __syncthreads();
+    if (tz == 0 && inb) {
+      float sm4[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int g = 0; g < kGradTZ; ++g)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sm4[c] += zred[c * kGradThreads + g * kGradTile + lane];
+      A.grad_u[lat] = sm4[0];
+      A.grad_u[fstride + lat] = sm4[1];
+      A.grad_u[2u * fstride + lat] = sm4[2];
+      A.grad_chi[lat] = sm4[3];
     }
   }
   if (tid < A.n_peaks) A.alpha_part[(long long)tile * A.n_peaks + tid] = apl[tid];
@@ -583,16 +782,18 @@ hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t 
   return hipGetLastError();
 }
 
-// the footprint accumulator: up to kProjPix * kFrameThreads pixels (the plan checks fy * fx)
-int project_lds_bytes(int np, int G) {
+// the footprint accumulator (up to kProjPix * kFrameThreads pixels: the plan checks
+// fy * fx), then the per-slice offset and fraction tables
+int project_lds_bytes(int np, int G, int nz) {
   (void)np;
   (void)G;
-  return kProjPix * kFrameThreads * (int)sizeof(cplx);
+  return kProjPix * kFrameThreads * (int)sizeof(cplx) + ((nz + 3) & ~3) * 4 + nz * 8;
 }
 
 static const int kDets[] = {32, 64, 96, 128, 150, 192, 256};
 
 #define MPBP_GRAD_INSTANCES(X) X(1, 16) X(2, 16) X(4, 16) X(1, 8) X(2, 8) X(4, 8)
+#define MPBP_GRAD_RUN_INSTANCES(X) X(4, 16) X(8, 16) X(16, 16) X(4, 8) X(8, 8) X(16, 8)
 
 template <int B, int TX, bool P3, bool LIN>
 static hipError_t grad_set_lds() {
@@ -622,11 +823,35 @@ hipError_t prepare_kernels() {
   if (e == hipSuccess) e = grad_set_lds<b, tx, true, true>();
   MPBP_GRAD_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
+#define MPBP_CASE(b, tx)                                                                                   \
+  if (e == hipSuccess)                                                                                     \
+    e = hipFuncSetAttribute((const void*)k_grad_runs<b, tx>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                            160 * 1024);
+  MPBP_GRAD_RUN_INSTANCES(MPBP_CASE)
+#undef MPBP_CASE
   return e;
+}
+
+bool grad_uses_runs(const GradArgs& a) { return a.runs && !a.probe3 && !a.shw; }
+
+int grad_effective_batch(int batch, bool runs) {
+  return runs ? std::min(std::max(batch, 4), 16) : std::min(batch, 4);
 }
 
 hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, hipStream_t s) {
   const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
+  if (grad_uses_runs(a)) {
+    const int b = grad_effective_batch(batch, true);
+#define MPBP_CASE(bb, tx)                                                                     \
+    if (b == bb && tile_x == tx) {                                                            \
+      k_grad_runs<bb, tx><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);               \
+      return hipGetLastError();                                                               \
+    }
+    MPBP_GRAD_RUN_INSTANCES(MPBP_CASE)
+#undef MPBP_CASE
+    return hipErrorInvalidValue;
+  }
+  batch = grad_effective_batch(batch, false);
 #define MPBP_CASE(b, tx)                                                       \
   if (batch == b && tile_x == tx) {                                            \
     if (a.probe3 && a.shw)                                                              \
@@ -767,9 +992,12 @@ int frame_chunk_len(int D) {
   }
 }
 
-int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand, bool tied) {
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand, bool tied, bool runs) {
   (void)maxspan_y;
   (void)maxspan_x;
+  if (runs)   // Ps, run sums, frame list, run offsets, alpha partials, reduction, slice runs, count, z-sums
+    return np * np * 8 + kGradZB * kGradTile * 8 + max_cand * (int)sizeof(GradCand) + kGradZB * 8 +
+           kMaxPeaksDev * 8 + 64 + kGradZB * 4 + 16 + (tied ? 4 * kGradThreads * 4 : 0);
   return np * np * 8 + nz * 8 + kMaxPeaksDev * 8 + 64 + ((max_cand + 15) & ~15) +
          (tied ? 4 * kGradThreads * 4 : 0);
 }

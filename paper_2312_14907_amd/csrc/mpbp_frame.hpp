@@ -128,6 +128,17 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         const bool on = col < fx;
         cplx v[CV];
         if (on && colq(t)) {
+          // the live inputs' loads go out together (clamped addresses, masked by a
+          // multiply): as selects, the compiler put each in a branch of its own and
+          // waited for it before issuing the next
+          cplx pin[NAC];
+          if constexpr (FB <= L) {
+#pragma unroll
+            for (int a = 0; a < NAC; ++a) {
+              const int rr = t + CQ * a;
+              pin[a] = psi[(rr < fy ? rr : 0) * fx + col];
+            }
+          }
 #pragma unroll
           for (int a = 0; a < CP; ++a) {
             // footprint rows rr = t + CQ a (mod L)
@@ -135,10 +146,8 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
             if (a < NAC) {
               if constexpr (FB <= L) {
                 const int rr = t + CQ * a;
-                const bool ok = rr < fy;
-                const cplx pv = psi[(ok ? rr : 0) * fx + col];
-                const cplx tv = ftw[r * fy + (ok ? rr : 0)];
-                s = ok ? cmul(pv, tv) : cplx{0.f, 0.f};
+                const cplx tv = ftw[r * fy + (rr < fy ? rr : 0)];
+                s = cscale(cmul(pin[a < NAC ? a : 0], tv), rr < fy ? 1.0f : 0.0f);
               } else {
                 for (int rr = t + CQ * a; rr < fy; rr += L)
                   s = cadd(s, cmul(psi[rr * fx + col], ftw[r * fy + rr]));

@@ -131,6 +131,10 @@ struct mpbp_plan_t {
   std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch (capacity reserved)
   std::vector<unsigned char> seen;     // [F] duplicate check of a staged list (sized once)
   int grad_batch = mpbp::kDefaultGradBatch;
+  int grad_runs = 1;                   // gather per run of equal exit-beam offset where it applies
+  std::vector<int32_t> zrun;           // [M][nz] run of each slice
+  std::vector<int32_t> roff;           // [M][nz][2] footprint offset of run k
+  int lds_grad_runs = 0;
   int grad_tile = mpbp::kDefaultGradTileX;
   double grad_tuned_us = 0.0;
   std::string tune_source = "default";
@@ -151,6 +155,8 @@ struct mpbp_plan_t {
   int* d_scan = nullptr;
   int* d_peak_of = nullptr;
   int* d_shear = nullptr;
+  int* d_zrun = nullptr;           // [M][nz] (the run gather of the gradient kernel)
+  int* d_roff = nullptr;           // [M][nz][2]
   float* d_shw = nullptr;          // [M][nz][2] fractional offsets (MPBP_SHEAR_LINEAR)
   int* d_order = nullptr;          // full-batch processing order
   int* d_list = nullptr;           // caller's list (subset calls)
@@ -217,6 +223,8 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_scan);
   (void)hipFree(p->d_peak_of);
   (void)hipFree(p->d_shear);
+  (void)hipFree(p->d_zrun);
+  (void)hipFree(p->d_roff);
   (void)hipFree(p->d_shw);
   (void)hipFree(p->d_order);
   (void)hipFree(p->d_list);
@@ -266,6 +274,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   p->pdev.assign(p->M, PeakDev{});
   p->shear.assign((size_t)p->M * p->nz * 2, 0);
   p->shw.assign((size_t)p->M * p->nz * 2, 0.f);
+  p->zrun.assign((size_t)p->M * p->nz, 0);
+  p->roff.assign((size_t)p->M * p->nz * 2, 0);
   p->y_off.assign(p->M + 1, 0);
   p->scan.clear();
   p->peak_of.clear();
@@ -316,6 +326,16 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     d.spany = hi[0] - lo[0]; d.spanx = hi[1] - lo[1];
     d.r0 = cw + lo[0]; d.c0 = cw + lo[1];
     d.fy = np + d.spany; d.fx = np + d.spanx;
+    // runs of consecutive slices with equal offsets, and each run's footprint offset
+    for (int z = 0, k = -1; z < p->nz; ++z) {
+      const int* sz = &p->shear[((size_t)m * p->nz + z) * 2];
+      if (z == 0 || sz[0] != sz[-2] || sz[1] != sz[-1]) {
+        ++k;
+        p->roff[((size_t)m * p->nz + k) * 2] = sz[0] - lo[0];
+        p->roff[((size_t)m * p->nz + k) * 2 + 1] = sz[1] - lo[1];
+      }
+      p->zrun[(size_t)m * p->nz + z] = k;
+    }
     if (d.fy * d.fx > mpbp::kProjPix * mpbp::kFrameThreads)
       return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d above %d pixels", m, d.fy, d.fx,
                   mpbp::kProjPix * mpbp::kFrameThreads);
@@ -374,11 +394,13 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     p->tilings.push_back(t);
     p->max_tiles = std::max(p->max_tiles, t.nx * t.ny);
   }
-  p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0);
-  for (int G : mpbp::kSlabDepths) p->lds_project[G] = mpbp::project_lds_bytes(np, G);
+  p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0, false);
+  p->lds_grad_runs = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0, true);
+  for (int G : mpbp::kSlabDepths) p->lds_project[G] = mpbp::project_lds_bytes(np, G, p->nz);
   if (p->lds_project[mpbp::kDefaultSlab] > kMaxLds)
     return fail(MPBP_ERR_UNSUPPORTED, "projection needs %d B of LDS", p->lds_project[mpbp::kDefaultSlab]);
-  if (p->lds_grad > kMaxLds) return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", p->lds_grad);
+  if (p->lds_grad > kMaxLds || p->lds_grad_runs > kMaxLds)
+    return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", std::max(p->lds_grad, p->lds_grad_runs));
   // Full-batch processing order: larger windows first (they cost most), each peak's
   // frames in tiles of its raster.
   std::vector<int> pk(p->M);
@@ -442,6 +464,8 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_peak_of, p->F);
   ALLOC(p->d_shear, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_shw, (size_t)p->M * p->nz * 2);
+  ALLOC(p->d_zrun, (size_t)p->M * p->nz);
+  ALLOC(p->d_roff, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_order, p->F);
   ALLOC(p->d_list, p->F);
   ALLOC(p->d_list_sorted, p->F);
@@ -464,6 +488,8 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   if (e == hipSuccess) e = hipMemcpy(p->d_peak_of, p->peak_of.data(), p->peak_of.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_shear, p->shear.data(), p->shear.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_shw, p->shw.data(), p->shw.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_zrun, p->zrun.data(), p->zrun.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_roff, p->roff.data(), p->roff.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), p->order.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_tw, p->tw.data(), p->tw.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy tables");
@@ -683,6 +709,9 @@ mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float
   g.tied = p->tied != 0;
   g.probe3 = p->probe3;
   g.shw = p->linear ? p->d_shw : nullptr;
+  g.runs = p->grad_runs;
+  g.zrun = p->d_zrun;
+  g.roff = reinterpret_cast<const int2*>(p->d_roff);
   g.grad_u = grad_u; g.grad_chi = grad_chi;
   g.alpha_part = w.apart;
   return g;
@@ -725,7 +754,7 @@ hipError_t enqueue_loss_grad(mpbp_plan p, const Work& w, const float* u, const f
   const mpbp::GradArgs g = grad_args(p, w, u, chi, alpha, probe, subset, grad_u, grad_chi);
   {
     StageTimer t(p, MPBP_STAGE_GRAD, s, timed);
-    e = mpbp::launch_grad(p->grad_batch, p->grad_tile, g, p->lds_grad, s);
+    e = mpbp::launch_grad(p->grad_batch, p->grad_tile, g, mpbp::grad_uses_runs(g) ? p->lds_grad_runs : p->lds_grad, s);
   }
   if (e != hipSuccess) return *what = "gradient kernel", e;
   return hipSuccess;
@@ -880,7 +909,7 @@ void load_tuning(mpbp_plan_t* p) {
     int b = 0, tx = 0;
     double us = 0.0;
     if (e.first == gk && std::sscanf(e.second.c_str(), "batch=%d tile=%d us=%lf", &b, &tx, &us) == 3 &&
-        (b == 1 || b == 2 || b == 4) && (tx == 16 || tx == 8)) {
+        (b == 1 || b == 2 || b == 4 || b == 8 || b == 16) && (tx == 16 || tx == 8)) {
       p->grad_batch = b;
       p->grad_tile = tx;
       p->grad_tuned_us = us;
@@ -1390,9 +1419,18 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
       plan->profile = (int)value;
       return MPBP_OK;
     case MPBP_OPT_GRAD_BATCH:
-      if (value != 1 && value != 2 && value != 4) return fail(MPBP_ERR_INVALID, "grad batch must be 1, 2 or 4");
+      if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+        return fail(MPBP_ERR_INVALID, "grad batch must be 1, 2, 4, 8 or 16");
       plan->grad_batch = (int)value;
       plan->tune_source = "manual";
+      if (plan->device >= 0) {
+        (void)hipSetDevice(plan->device);
+        clear_graphs(plan);
+      }
+      return MPBP_OK;
+    case MPBP_OPT_GRAD_RUNS:
+      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "grad runs must be 0 or 1");
+      plan->grad_runs = (int)value;
       if (plan->device >= 0) {
         (void)hipSetDevice(plan->device);
         clear_graphs(plan);
@@ -1421,6 +1459,7 @@ mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value) {
     case MPBP_OPT_PROFILE: *value = plan->profile; return MPBP_OK;
     case MPBP_OPT_GRAD_BATCH: *value = plan->grad_batch; return MPBP_OK;
     case MPBP_OPT_GRAD_TILE: *value = plan->grad_tile; return MPBP_OK;
+    case MPBP_OPT_GRAD_RUNS: *value = plan->grad_runs; return MPBP_OK;
     default: return fail(MPBP_ERR_INVALID, "unknown option %d", option);
   }
 }
@@ -1549,12 +1588,15 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
     for (int TX : mpbp::kGradTileXs) {
       plan->grad_tile = TX;
       const mpbp::GradArgs g = grad_args(plan, plan_work(plan), u, chi, alpha, (const float*)probe, false, gbuf, gbuf + 3 * nf);
-      for (int B : mpbp::kGradBatches) {
+      const bool runs = mpbp::grad_uses_runs(g);
+      const std::vector<int> batches = runs ? std::vector<int>(std::begin(mpbp::kGradRunBatches), std::end(mpbp::kGradRunBatches))
+                                            : std::vector<int>(std::begin(mpbp::kGradBatches), std::end(mpbp::kGradBatches));
+      for (int B : batches) {
         if (e != hipSuccess) break;
         double us = 1e300;
         for (int round = 0; round < 2 && e == hipSuccess; ++round) {
           double t = 0.0;
-          e = time_us([&]() { return mpbp::launch_grad(B, TX, g, plan->lds_grad, s); }, 3, &t);
+          e = time_us([&]() { return mpbp::launch_grad(B, TX, g, runs ? plan->lds_grad_runs : plan->lds_grad, s); }, 3, &t);
           us = t < us ? t : us;
         }
         snprintf(buf, sizeof(buf), "%s{\"grad_batch\": %d, \"grad_tile\": %d, \"us\": %.2f}",
@@ -1605,6 +1647,7 @@ mpbp_status mpbp_tuning(mpbp_plan plan, char* buf, int64_t cap, int64_t* len) {
   if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
   std::string out = "{\"source\": \"" + plan->tune_source + "\", \"grad_batch\": " +
                     std::to_string(plan->grad_batch) + ", \"grad_tile\": " + std::to_string(plan->grad_tile) +
+                    ", \"grad_runs\": " + std::to_string(plan->grad_runs) +
                     ", \"classes\": [";
   char tmp[256];
   for (size_t i = 0; i < plan->classes.size(); ++i) {

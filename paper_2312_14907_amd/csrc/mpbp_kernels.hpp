@@ -71,6 +71,9 @@ struct GradArgs {
   int tied;                  // 1: u, chi and their gradients per lateral pixel (z-sums)
   int probe3;                // 1: probe is [M][nz][np][np] (a 3D illumination volume)
   const float* shw;          // [M][nz][2] fractional exit-beam offsets (null: rounded offsets)
+  int runs;                  // 1: gather per run of equal offsets (k_grad_runs) where it applies
+  const int* zrun;           // [M][nz] run of each slice (consecutive slices of equal offset)
+  const int2* roff;          // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
   float* grad_u;
   float* grad_chi;
   double* alpha_part;      // [n_blocks][M]
@@ -87,8 +90,9 @@ constexpr int kGradTileXs[] = {16, 8};                   // compiled tile widths
 constexpr int kDefaultGradTileX = 16;
 constexpr int kGradZB = 32;                             // z per pass of the grad kernel
 constexpr int kGradZPer = kGradZB / kGradTZ;            // z per thread per pass
-constexpr int kGradBatches[] = {1, 2, 4};               // compiled frame-walk batch sizes
-constexpr int kDefaultGradBatch = 2;
+constexpr int kGradBatches[] = {1, 2, 4};               // compiled batch sizes of the per-slice walk
+constexpr int kGradRunBatches[] = {4, 8, 16};           // compiled batch sizes of the run gather
+constexpr int kDefaultGradBatch = 8;
 constexpr int kMaxPeaksDev = 16;
 
 }  // namespace mpbp

@@ -24,11 +24,14 @@ hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipSt
 // Exit waves of the listed frames into their slots, with G object slices in flight per
 // lane (G = 2, 4 or 8); lds_bytes from project_lds_bytes.
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
-int project_lds_bytes(int np, int G);
+int project_lds_bytes(int np, int G, int nz);
 int frame_bound(int D, int footprint);
-// Gradient kernel reading `batch` frames per step of its frame walk (1, 2 or 4), over
-// tiles `tile_x` voxels wide (16: 16 x 4, 8: 8 x 8).
+// Gradient kernel reading `batch` frames at once (the run gather, k_grad_runs, where
+// grad_uses_runs(a): batch clamped to [4, 16]; otherwise the per-slice walk, k_grad:
+// batch clamped to at most 4), over tiles `tile_x` voxels wide (16: 16 x 4, 8: 8 x 8).
 hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, hipStream_t s);
+bool grad_uses_runs(const GradArgs& a);
+int grad_effective_batch(int batch, bool runs);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
                            float* grad_alpha, hipStream_t s);
@@ -52,6 +55,6 @@ bool frame_twiddles(int D, int fy, std::vector<float>& out);
 // Rows per residue chunk of the detector (the column-transform length).
 int frame_chunk_len(int D);
 // Dynamic LDS of the gradient kernel (bytes).
-int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand, bool tied);
+int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand, bool tied, bool runs);
 
 }  // namespace mpbp

@@ -11,7 +11,7 @@
 
 namespace mpbp {
 
-// G: object slices in flight per lane (loads issued G slices ahead of their use).
+// G: object slices in flight per lane (the slices are loaded in blocks of G).
 //
 // eq. (2) R diag(P) S O on the footprint: psi[q] = sum_z (P O_z)[q - s(z) + min s].
 // Consecutive slices with equal shear offset (runs, uniform) are summed in registers;
@@ -40,7 +40,17 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   const int* shz = A.shear + 2 * m * nz;   // uniform: scalar loads
   const int np2 = np * np;
   cplx* acc = sm;                          // [fy][fx] footprint accumulator
+  // per-slice footprint offsets (and interpolation fractions) in LDS: the slice loop
+  // then reads nothing from device memory but the object, and the waits for the
+  // object loads issued G slices ahead cover those loads alone
+  int* sho = reinterpret_cast<int*>(acc + kProjPix * kFrameThreads);                 // [nz]
+  float2* shf = reinterpret_cast<float2*>(sho + ((nz + 3) & ~3));                     // [nz] (LIN)
   for (int p = tid; p < fy * fx; p += NT) acc[p] = {0.f, 0.f};
+  for (int z = tid; z < nz; z += NT) {
+    sho[z] = (shz[2 * z] - pk.miny) * fx + (shz[2 * z + 1] - pk.minx);
+    if constexpr (LIN) shf[z] = make_float2(A.shw[2 * (m * nz + z)], A.shw[2 * (m * nz + z) + 1]);
+  }
+  __syncthreads();
 
   // lane's probe pixels e = tid + NT i: probe value (0 off the object), object offset,
   // and footprint offset at zero shear
@@ -77,7 +87,7 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
     }
   };
   // footprint offset of slice z's pixel (0, 0): (s_y - min s_y) fx + (s_x - min s_x)
-  auto shift = [&](int z) { return (shz[2 * z] - pk.miny) * fx + (shz[2 * z + 1] - pk.minx); };
+  auto shift = [&](int z) { return __builtin_amdgcn_readfirstlane(sho[z]); };
   constexpr int NW = LIN ? 4 : 1;   // weighted sums per run (taps)
   cplx w[NW][kProjE];
   auto flush = [&](int d) {
@@ -97,7 +107,8 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   // add slice z's P O (v) into the run's sums
   auto accumulate = [&](const cplx (&v)[kProjE], int z, bool first) {
     if constexpr (LIN) {
-      const float ry = A.shw[2 * (m * nz + z)], rx = A.shw[2 * (m * nz + z) + 1];   // fractions
+      const float2 f = shf[z];
+      const float ry = f.x, rx = f.y;   // fractions
       const float wt[4] = {(1.f - ry) * (1.f - rx), (1.f - ry) * rx, ry * (1.f - rx), ry * rx};
 #pragma unroll
       for (int tp = 0; tp < 4; ++tp)
@@ -111,15 +122,20 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
       for (int i = 0; i < kProjE; ++i) w[0][i] = first ? v[i] : cadd(w[0][i], v[i]);
     }
   };
-  cplx buf[G][kProjE], pbuf[G][P3 ? kProjE : 1];
-#pragma unroll
-  for (int g = 0; g < G; ++g) load(buf[g], pbuf[g], g);
+  // Slices go in blocks of G: all G slices' loads are issued, then consumed in order.
+  // Nothing loaded is carried across the loop's back-edge, so the compiler waits for
+  // exactly the loads each slice uses (with a prefetch carried across iterations it
+  // copied the buffers at the back-edge and waited for every load there); a frame
+  // costs nz / G memory latencies.
   int cur = shift(0);
 #pragma unroll
   for (int tp = 0; tp < NW; ++tp)
 #pragma unroll
     for (int i = 0; i < kProjE; ++i) w[tp][i] = {0.f, 0.f};
   for (int z0 = 0; z0 < nz; z0 += G) {
+    cplx buf[G][kProjE], pbuf[G][P3 ? kProjE : 1];
+#pragma unroll
+    for (int g = 0; g < G; ++g) load(buf[g], pbuf[g], z0 + g);   // clamped past nz
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int z = z0 + g;
@@ -127,7 +143,6 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
         cplx v[kProjE];
 #pragma unroll
         for (int i = 0; i < kProjE; ++i) v[i] = cmul(P3 ? pbuf[g][P3 ? i : 0] : pv[i], buf[g][i]);
-        if (z + G < nz) load(buf[g], pbuf[g], z + G);
         const int d = shift(z);
         if (d != cur) {   // uniform: a new run
           flush(cur);

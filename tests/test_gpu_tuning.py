@@ -95,10 +95,15 @@ def test_every_variant_matches_default(c4):
                     n += 1
         plan.mpbp_set_variant(k, c["key"], 4, 1)
     assert n >= 2 * 2 * len(classes)
-    for b in (1, 4, 2):
-        say(f"gradient kernel batch {b}")
-        plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, b)
-        _equal(_run(plan, args), ref, f"grad batch {b}")
+    # the run gather (default) and the per-slice walk, every batch size: the frames are
+    # summed in the same order with the same fused multiply-adds, so bit for bit equal
+    for runs in (0, 1):
+        plan.mpbp_set_option(B.MPBP_OPT_GRAD_RUNS, runs)
+        for b in (1, 2, 4, 8, 16):
+            say(f"gradient kernel runs={runs} batch {b}")
+            plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, b)
+            _equal(_run(plan, args), ref, f"grad runs={runs} batch {b}")
+    plan.mpbp_set_option(B.MPBP_OPT_GRAD_RUNS, 1)
     for tx in (8, 16):
         # another tile grid sums the alpha partials over other voxel sets
         say(f"gradient kernel tile width {tx}")
@@ -135,7 +140,7 @@ def test_autotune_and_cache(c4, tmp_path):
             assert chosen and chosen[0]["us"] <= best + 0.01
             assert c["us"] == pytest.approx(best, abs=0.01)
         gb = [x for x in t["candidates"] if "grad_batch" in x]
-        assert sorted((x["grad_batch"], x["grad_tile"]) for x in gb) == [(b, tx) for b in (1, 2, 4) for tx in (8, 16)]
+        assert sorted((x["grad_batch"], x["grad_tile"]) for x in gb) == [(b, tx) for b in (4, 8, 16) for tx in (8, 16)]
         chosen = [x for x in gb if (x["grad_batch"], x["grad_tile"]) == (t["grad_batch"], t["grad_tile"])]
         assert chosen and chosen[0]["us"] <= min(x["us"] for x in gb) + 0.01
         _close(_run(plan, args), ref, "autotuned")
