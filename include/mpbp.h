@@ -125,12 +125,16 @@ enum {
   MPBP_OPT_GRAD_TILE = 6,    /* back-projection tile: 16 (16 x 4 voxels, default) or 8
                                 (8 x 8 voxels on a grid aligned with the first peak's
                                 raster); set by mpbp_autotune                            */
-  MPBP_OPT_GRAD_RUNS = 7     /* 1 (default): with one probe for all slices and rounded
-                                offsets, the back-projection sums the frames once per run
-                                of consecutive slices with equal exit-beam offset (those
-                                slices read the same footprint pixels) and applies the
-                                chain rule per slice; 0: it sums them per slice.  Both
-                                give bitwise the same results.                           */
+  MPBP_OPT_RUNS = 7          /* 1 (default): with one probe for all slices and rounded
+                                offsets (neither MPBP_PROBE_3D nor MPBP_SHEAR_LINEAR),
+                                eq. (2)'s sum over slices is grouped into runs of
+                                consecutive slices with equal exit-beam offset: the
+                                objects are summed over each run once per call, every
+                                frame projects the run sums, and the back-projection sums
+                                the frames once per run and applies the chain rule per
+                                slice.  0: both per slice.  The back-projection gives
+                                bitwise the same results either way; the projection
+                                rounds the regrouped sums differently.                   */
 };
 
 /* Kernel stages timed under MPBP_OPT_PROFILE. */

@@ -21,7 +21,7 @@ MPBP_OPT_XCD_ORDER = 3
 MPBP_OPT_PROFILE = 4
 MPBP_OPT_GRAD_BATCH = 5
 MPBP_OPT_GRAD_TILE = 6
-MPBP_OPT_GRAD_RUNS = 7
+MPBP_OPT_RUNS = 7
 MPBP_Z_TIED = 1
 MPBP_PROBE_3D = 2
 MPBP_SHEAR_LINEAR = 4

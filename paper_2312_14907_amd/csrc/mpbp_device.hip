@@ -49,6 +49,49 @@ __global__ __launch_bounds__(256) void k_object(const float* __restrict__ u,
   }
 }
 
+// --------------------------------------------------------- run-summed objects ---
+// With one probe for all slices and rounded exit-beam offsets, eq. (2)'s projection
+// regroups over runs k of consecutive slices with equal offset s_k:
+//   R diag(P) S O = sum_k shift_{s_k}( P . S_k[window] ),  S_k = sum_{z in run k} O_z,
+// and S_k does not depend on the frame.  This kernel forms every S_k of every peak once
+// (in place of the per-slice objects): one lane per lateral pixel walks z, forms
+// O_m(z) = alpha_m chi e^{i G_m . u} (as k_object) and adds it to peak m's running sum,
+// kept in LDS, which is stored at the last slice of each run.  Output: complex64
+// [run_base_m + k][ny][nx].
+__global__ __launch_bounds__(256) void k_runsum(const float* __restrict__ u, const float* __restrict__ chi,
+                                                const float* __restrict__ alpha,
+                                                const PeakDev* __restrict__ peaks, int n_peaks, int nz,
+                                                long long nlat, int tied, const int* __restrict__ zrun,
+                                                float* __restrict__ rsum) {
+  __shared__ float2 acc[kMaxPeaksDev][256];
+  const int tid = threadIdx.x;
+  const long long p = (long long)blockIdx.x * 256 + tid;
+  if (p >= nlat) return;   // (no barriers below: each lane's sums are its own)
+  const long long us = tied ? nlat : (long long)nz * nlat;   // field component stride
+  for (int z = 0; z < nz; ++z) {
+    const long long vi = tied ? p : (long long)z * nlat + p;
+    const float ux = u[vi], uy = u[us + vi], uz = u[2 * us + vi];
+    const float ch = chi[vi];
+    for (int m = 0; m < n_peaks; ++m) {
+      const float gx = peaks[m].gx, gy = peaks[m].gy, gz = peaks[m].gz;
+      const float phi = fmaf(gz, uz, fmaf(gy, uy, gx * ux));   // as k_object
+      float s, c;
+      sincosf(phi, &s, &c);
+      const float a = alpha[m] * ch;
+      const float2 o = make_float2(a * c, a * s);
+      const int* zr = zrun + m * nz;
+      const int k = zr[z];
+      const bool first = z == 0 || zr[z - 1] != k;    // uniform
+      const bool last = z == nz - 1 || zr[z + 1] != k;
+      const float2 cur = first ? o : make_float2(acc[m][tid].x + o.x, acc[m][tid].y + o.y);
+      if (last)
+        reinterpret_cast<float2*>(rsum)[(long long)(peaks[m].run_base + k) * nlat + p] = cur;
+      else
+        acc[m][tid] = cur;
+    }
+  }
+}
+
 // -------------------------------------------- gather back-projection + chain rule ---
 __device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
   int q = a / b;
@@ -723,6 +766,12 @@ hipError_t launch_object(const float* u, const float* chi, const float* alpha, c
   return hipGetLastError();
 }
 
+hipError_t launch_runsum(const float* u, const float* chi, const float* alpha, const PeakDev* peaks, int n_peaks,
+                         int nz, long long nlat, int tied, const int* zrun, float* rsum, hipStream_t s) {
+  k_runsum<<<dim3(nblk(nlat, 256)), dim3(256), 0, s>>>(u, chi, alpha, peaks, n_peaks, nz, nlat, tied, zrun, rsum);
+  return hipGetLastError();
+}
+
 int frame_bound(int D, int f) {
   if (D == 32) return 32;
   if (f <= 48) return 48;
@@ -772,6 +821,15 @@ hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t 
     else                                                                                      \
       k_project<g, false, false><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a);       \
     break;
+  if (a.runs && !a.probe3 && !a.shw) {
+    switch (G) {
+      case 2: k_project_runs<2><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
+      case 4: k_project_runs<4><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
+      case 8: k_project_runs<8><<<dim3(grid), dim3(kFrameThreads), lds_bytes, s>>>(a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (G) {
     MPBP_PROJ(2)
     MPBP_PROJ(4)
@@ -812,7 +870,9 @@ hipError_t prepare_kernels() {
       (const void*)k_project<4, true, false>,  (const void*)k_project<8, true, false>,
       (const void*)k_project<2, false, true>,  (const void*)k_project<4, false, true>,
       (const void*)k_project<8, false, true>,  (const void*)k_project<2, true, true>,
-      (const void*)k_project<4, true, true>,   (const void*)k_project<8, true, true>};
+      (const void*)k_project<4, true, true>,   (const void*)k_project<8, true, true>,
+      (const void*)k_project_runs<2>,          (const void*)k_project_runs<4>,
+      (const void*)k_project_runs<8>};
   for (const void* f : projs)
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 #define MPBP_CASE(b, tx)                                                                        \

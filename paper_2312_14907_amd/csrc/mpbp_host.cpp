@@ -131,10 +131,11 @@ struct mpbp_plan_t {
   std::vector<SizeClass> sub_classes;  // the same for the last staged minibatch (capacity reserved)
   std::vector<unsigned char> seen;     // [F] duplicate check of a staged list (sized once)
   int grad_batch = mpbp::kDefaultGradBatch;
-  int grad_runs = 1;                   // gather per run of equal exit-beam offset where it applies
+  int runs = 1;                        // project and back-project per run of equal exit-beam
+                                       // offset where it applies (one probe, rounded offsets)
   std::vector<int32_t> zrun;           // [M][nz] run of each slice
   std::vector<int32_t> roff;           // [M][nz][2] footprint offset of run k
-  int lds_grad_runs = 0;
+  int lds_runs = 0;
   int grad_tile = mpbp::kDefaultGradTileX;
   double grad_tuned_us = 0.0;
   std::string tune_source = "default";
@@ -283,6 +284,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   const int np = p->np;
   const int zref = p->nz / 2;
   long long slot = 0;
+  int n_runs = 0;
   for (int m = 0; m < p->M; ++m) {
     const mpbp_peak& k = p->peaks[m];
     for (int c = 0; c < 3; ++c)
@@ -335,7 +337,10 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
         p->roff[((size_t)m * p->nz + k) * 2 + 1] = sz[1] - lo[1];
       }
       p->zrun[(size_t)m * p->nz + z] = k;
+      d.nruns = k + 1;
     }
+    d.run_base = n_runs;
+    n_runs += d.nruns;
     if (d.fy * d.fx > mpbp::kProjPix * mpbp::kFrameThreads)
       return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d above %d pixels", m, d.fy, d.fx,
                   mpbp::kProjPix * mpbp::kFrameThreads);
@@ -395,12 +400,12 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     p->max_tiles = std::max(p->max_tiles, t.nx * t.ny);
   }
   p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0, false);
-  p->lds_grad_runs = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0, true);
+  p->lds_runs = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0, true);
   for (int G : mpbp::kSlabDepths) p->lds_project[G] = mpbp::project_lds_bytes(np, G, p->nz);
   if (p->lds_project[mpbp::kDefaultSlab] > kMaxLds)
     return fail(MPBP_ERR_UNSUPPORTED, "projection needs %d B of LDS", p->lds_project[mpbp::kDefaultSlab]);
-  if (p->lds_grad > kMaxLds || p->lds_grad_runs > kMaxLds)
-    return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", std::max(p->lds_grad, p->lds_grad_runs));
+  if (p->lds_grad > kMaxLds || p->lds_runs > kMaxLds)
+    return fail(MPBP_ERR_UNSUPPORTED, "gradient kernel needs %d B of LDS", std::max(p->lds_grad, p->lds_runs));
   // Full-batch processing order: larger windows first (they cost most), each peak's
   // frames in tiles of its raster.
   std::vector<int> pk(p->M);
@@ -658,6 +663,19 @@ struct Work {
 
 Work plan_work(mpbp_plan p) { return {p->d_obj, p->d_slots, p->d_gslots, p->d_floss, p->d_apart}; }
 
+// Projection and back-projection per run of equal exit-beam offset (one probe for all
+// slices, rounded offsets): the objects are then stored as run sums.
+bool uses_runs(mpbp_plan p) { return p->runs && !p->probe3 && !p->linear; }
+
+// The objects of eq. (1)/(3) into the workspace: per slice, or summed over each run.
+hipError_t launch_objects(mpbp_plan p, const Work& w, const float* u, const float* chi, const float* alpha,
+                          hipStream_t s) {
+  if (uses_runs(p))
+    return mpbp::launch_runsum(u, chi, alpha, p->d_peaks, p->M, p->nz, (long long)p->ny * p->nx, p->tied != 0,
+                               p->d_zrun, w.obj, s);
+  return mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, w.obj, s);
+}
+
 mpbp::FrameArgs frame_args(mpbp_plan p, const Work& w, const float* y, const int* list, int n, float* mi,
                            int grad) {
   mpbp::FrameArgs a{};
@@ -680,6 +698,8 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const Work& w, const float* y, const int
   a.xcd = p->xcd;
   a.probe3 = p->probe3;
   a.shw = p->linear ? p->d_shw : nullptr;
+  a.runs = uses_runs(p);
+  a.roff = reinterpret_cast<const int2*>(p->d_roff);
   return a;
 }
 
@@ -709,7 +729,7 @@ mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float
   g.tied = p->tied != 0;
   g.probe3 = p->probe3;
   g.shw = p->linear ? p->d_shw : nullptr;
-  g.runs = p->grad_runs;
+  g.runs = p->runs;
   g.zrun = p->d_zrun;
   g.roff = reinterpret_cast<const int2*>(p->d_roff);
   g.grad_u = grad_u; g.grad_chi = grad_chi;
@@ -726,7 +746,7 @@ hipError_t enqueue_forward(mpbp_plan p, const float* u, const float* chi, const 
   const Work w = plan_work(p);
   {
     StageTimer t(p, MPBP_STAGE_OBJECT, s);
-    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, w.obj, s);
+    e = launch_objects(p, w, u, chi, alpha, s);
   }
   if (e != hipSuccess) return *what = "object kernel", e;
   mpbp::FrameArgs a = frame_args(p, w, y, list, n, model_intensity, 0);
@@ -744,7 +764,7 @@ hipError_t enqueue_loss_grad(mpbp_plan p, const Work& w, const float* u, const f
   hipError_t e;
   {
     StageTimer t(p, MPBP_STAGE_OBJECT, s, timed);
-    e = mpbp::launch_object(u, chi, alpha, p->d_peaks, p->M, p->nvox, p->tied, w.obj, s);
+    e = launch_objects(p, w, u, chi, alpha, s);
   }
   if (e != hipSuccess) return *what = "object kernel", e;
   mpbp::FrameArgs a = frame_args(p, w, y, list, n, nullptr, 1);
@@ -754,7 +774,7 @@ hipError_t enqueue_loss_grad(mpbp_plan p, const Work& w, const float* u, const f
   const mpbp::GradArgs g = grad_args(p, w, u, chi, alpha, probe, subset, grad_u, grad_chi);
   {
     StageTimer t(p, MPBP_STAGE_GRAD, s, timed);
-    e = mpbp::launch_grad(p->grad_batch, p->grad_tile, g, mpbp::grad_uses_runs(g) ? p->lds_grad_runs : p->lds_grad, s);
+    e = mpbp::launch_grad(p->grad_batch, p->grad_tile, g, mpbp::grad_uses_runs(g) ? p->lds_runs : p->lds_grad, s);
   }
   if (e != hipSuccess) return *what = "gradient kernel", e;
   return hipSuccess;
@@ -1428,9 +1448,9 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
         clear_graphs(plan);
       }
       return MPBP_OK;
-    case MPBP_OPT_GRAD_RUNS:
-      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "grad runs must be 0 or 1");
-      plan->grad_runs = (int)value;
+    case MPBP_OPT_RUNS:
+      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "runs must be 0 or 1");
+      plan->runs = (int)value;
       if (plan->device >= 0) {
         (void)hipSetDevice(plan->device);
         clear_graphs(plan);
@@ -1459,7 +1479,7 @@ mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value) {
     case MPBP_OPT_PROFILE: *value = plan->profile; return MPBP_OK;
     case MPBP_OPT_GRAD_BATCH: *value = plan->grad_batch; return MPBP_OK;
     case MPBP_OPT_GRAD_TILE: *value = plan->grad_tile; return MPBP_OK;
-    case MPBP_OPT_GRAD_RUNS: *value = plan->grad_runs; return MPBP_OK;
+    case MPBP_OPT_RUNS: *value = plan->runs; return MPBP_OK;
     default: return fail(MPBP_ERR_INVALID, "unknown option %d", option);
   }
 }
@@ -1522,7 +1542,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
     cleanup();
     return fail(MPBP_ERR_NOMEM, "hipMalloc gradient scratch: %s", hipGetErrorString(e));
   }
-  e = mpbp::launch_object(u, chi, alpha, plan->d_peaks, plan->M, plan->nvox, plan->tied, plan->d_obj, s);
+  e = launch_objects(plan, plan_work(plan), u, chi, alpha, s);
   std::string rep = "[";
   char buf[160];
   // The projection and the frame kernel are separate launches: the projection depth G is
@@ -1596,7 +1616,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
         double us = 1e300;
         for (int round = 0; round < 2 && e == hipSuccess; ++round) {
           double t = 0.0;
-          e = time_us([&]() { return mpbp::launch_grad(B, TX, g, runs ? plan->lds_grad_runs : plan->lds_grad, s); }, 3, &t);
+          e = time_us([&]() { return mpbp::launch_grad(B, TX, g, runs ? plan->lds_runs : plan->lds_grad, s); }, 3, &t);
           us = t < us ? t : us;
         }
         snprintf(buf, sizeof(buf), "%s{\"grad_batch\": %d, \"grad_tile\": %d, \"us\": %.2f}",
@@ -1647,7 +1667,7 @@ mpbp_status mpbp_tuning(mpbp_plan plan, char* buf, int64_t cap, int64_t* len) {
   if (!plan) return fail(MPBP_ERR_INVALID, "plan is NULL");
   std::string out = "{\"source\": \"" + plan->tune_source + "\", \"grad_batch\": " +
                     std::to_string(plan->grad_batch) + ", \"grad_tile\": " + std::to_string(plan->grad_tile) +
-                    ", \"grad_runs\": " + std::to_string(plan->grad_runs) +
+                    ", \"runs\": " + std::to_string(plan->runs) +
                     ", \"classes\": [";
   char tmp[256];
   for (size_t i = 0; i < plan->classes.size(); ++i) {

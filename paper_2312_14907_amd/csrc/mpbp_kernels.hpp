@@ -25,10 +25,13 @@ struct PeakDev {
   float gx, gy, gz; // Bragg vector (rad/nm)
   int lds_bytes;    // dynamic LDS the frame kernel needs for this peak
   long long tw_off; // complex offset of this peak's twiddle tables (D + L + R * fy)
+  int nruns;        // runs of consecutive slices with equal exit-beam offset
+  int run_base;     // index of this peak's first run over all peaks
 };
 
 struct FrameArgs {
-  const float* obj;        // complex64 [M][nz][ny][nx] (interleaved)
+  const float* obj;        // complex64 [M][nz][ny][nx] (interleaved); with runs: the run
+                           // sums [sum of nruns over peaks][ny][nx] (launch_runsum)
   const float* probe;      // complex64 [M][np][np]
   const float* y;          // ragged intensities (may be null)
   const float* bg;         // background b of eq. (2), ragged like y (may be null)
@@ -50,6 +53,8 @@ struct FrameArgs {
   int xcd;                 // XCD-aware block order
   int probe3;              // 1: probe is [M][nz][np][np] (a 3D illumination volume)
   const float* shw;        // [M][nz][2] fractional exit-beam offsets (null: rounded offsets)
+  int runs;                // 1: project from the run sums (one probe, rounded offsets)
+  const int2* roff;        // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
 };
 
 struct GradArgs {

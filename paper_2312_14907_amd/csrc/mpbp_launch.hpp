@@ -17,6 +17,10 @@ bool frame_instance(int D, int FB);
 // tied = ny * nx for fields given per lateral pixel (the z-tied parameterisation), else 0.
 hipError_t launch_object(const float* u, const float* chi, const float* alpha, const PeakDev* peaks,
                          int n_peaks, long long nvox, long long tied, float* obj, hipStream_t s);
+// The run sums S_k = sum over the slices z of run k of O_m(z), for every peak and run:
+// complex64 [sum of nruns][ny][nx] into rsum (zrun: [M][nz] run of each slice).
+hipError_t launch_runsum(const float* u, const float* chi, const float* alpha, const PeakDev* peaks, int n_peaks,
+                         int nz, long long nlat, int tied, const int* zrun, float* rsum, hipStream_t s);
 // Frames of one detector size D whose footprints fit FB x FB (a.list holds only such
 // frames; frame_bound(D, largest footprint side) is the smallest such FB).  Reads each
 // frame's exit wave from its slot (written by launch_project).

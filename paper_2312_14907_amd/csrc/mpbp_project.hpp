@@ -159,6 +159,76 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   for (int p = tid; p < fy * fx; p += NT) slot[p] = acc[p];
 }
 
+// The projection from the run sums (one probe for all slices, rounded offsets):
+//   psi = sum_k shift_{s_k}( P . S_k[window] )
+// with S_k from launch_runsum.  A frame reads its window of each run's sum (about a
+// third of the slices at the workloads' shears), G runs' loads in flight per lane; each
+// run's P . S_k is added into the LDS footprint accumulator at the run's offset (a
+// barrier per run: within one run no two lanes meet).
+template <int G>
+__device__ void project_runs_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx* sm) {
+  constexpr int NT = kFrameThreads;
+  const int tid = threadIdx.x;
+  const int np = A.np, nz = A.nz;
+  const int fy = pk.fy, fx = pk.fx;
+  const int m = A.peak_of[fid];
+  const int py = A.scan[2 * fid], px = A.scan[2 * fid + 1];
+  const int j = fid - pk.frame_base;
+  const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
+  cplx* slot = reinterpret_cast<cplx*>(A.slots) + pk.slot_off + (long long)j * fy * fx;
+  const long long plane = (long long)A.ny * A.nx;
+  const cplx* S = reinterpret_cast<const cplx*>(A.obj) + (long long)pk.run_base * plane;
+  const int np2 = np * np;
+  const int nr = pk.nruns;
+  cplx* acc = sm;                                                     // [fy][fx]
+  int* sho = reinterpret_cast<int*>(acc + kProjPix * kFrameThreads);  // [nruns] footprint offsets
+  for (int p = tid; p < fy * fx; p += NT) acc[p] = {0.f, 0.f};
+  for (int k = tid; k < nr; k += NT) {
+    const int2 ro = A.roff[m * nz + k];
+    sho[k] = ro.x * fx + ro.y;
+  }
+  cplx pv[kProjE];
+  unsigned off[kProjE];
+  int fo[kProjE];
+#pragma unroll
+  for (int i = 0; i < kProjE; ++i) {
+    const int e = tid + NT * i;
+    const int a = e / np, b = e - (e / np) * np;
+    const int oy = py + a, ox = px + b;
+    const bool ok = e < np2 && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
+    pv[i] = ok ? probe[e < np2 ? e : 0] : cplx{0.f, 0.f};
+    off[i] = ok ? (unsigned)(oy * A.nx + ox) * (unsigned)sizeof(cplx) : 0u;
+    fo[i] = a * fx + b;
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < nr; k0 += G) {
+    cplx buf[G][kProjE];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {   // run index clamped past the last run
+      const int k = __builtin_amdgcn_readfirstlane(k0 + g < nr ? k0 + g : nr - 1);
+      const char* Sk = reinterpret_cast<const char*>(S + (long long)k * plane);
+#pragma unroll
+      for (int i = 0; i < kProjE; ++i) buf[g][i] = *reinterpret_cast<const cplx*>(Sk + off[i]);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (k0 + g < nr) {   // uniform
+        const int d = __builtin_amdgcn_readfirstlane(sho[k0 + g]);
+        __syncthreads();   // zeroing, or the previous run's additions, are complete
+#pragma unroll
+        for (int i = 0; i < kProjE; ++i) {
+          if ((i + 1) * NT <= np2 || tid + NT * i < np2) {   // uniform when every lane has a pixel
+            cplx* q = acc + fo[i] + d;
+            *q = cadd(*q, cmul(pv[i], buf[g][i]));
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int p = tid; p < fy * fx; p += NT) slot[p] = acc[p];
+}
+
 // Occupancy target: the fewer slices in flight, the fewer registers, the more
 // workgroups per CU.
 template <int G, bool LIN> struct ProjectWaves {
@@ -174,6 +244,21 @@ void k_project(FrameArgs A) {
   const int fid = A.list[idx];
   const PeakDev pk = A.peaks[A.peak_of[fid]];
   project_body<G, P3, LIN>(A, pk, fid, smem);
+}
+
+}  // namespace mpbp
+
+namespace mpbp {
+
+template <int G>
+__global__ __launch_bounds__(kFrameThreads) __attribute__((amdgpu_waves_per_eu(ProjectWaves<G, false>::value)))
+void k_project_runs(FrameArgs A) {
+  extern __shared__ cplx smem[];
+  const int idx = frame_block_index(blockIdx.x, gridDim.x, A.xcd);
+  if (idx >= A.n_list) return;
+  const int fid = A.list[idx];
+  const PeakDev pk = A.peaks[A.peak_of[fid]];
+  project_runs_body<G>(A, pk, fid, smem);
 }
 
 }  // namespace mpbp

@@ -95,15 +95,22 @@ def test_every_variant_matches_default(c4):
                     n += 1
         plan.mpbp_set_variant(k, c["key"], 4, 1)
     assert n >= 2 * 2 * len(classes)
-    # the run gather (default) and the per-slice walk, every batch size: the frames are
-    # summed in the same order with the same fused multiply-adds, so bit for bit equal
+    # per run of equal exit-beam offset (default) and per slice: the projection rounds the
+    # regrouped sums differently (close), every gradient batch size of one setting sums
+    # the frames in the same order with the same fused multiply-adds (bit for bit)
     for runs in (0, 1):
-        plan.mpbp_set_option(B.MPBP_OPT_GRAD_RUNS, runs)
+        plan.mpbp_set_option(B.MPBP_OPT_RUNS, runs)
+        first = None
         for b in (1, 2, 4, 8, 16):
-            say(f"gradient kernel runs={runs} batch {b}")
+            say(f"runs={runs}, gradient batch {b}")
             plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, b)
-            _equal(_run(plan, args), ref, f"grad runs={runs} batch {b}")
-    plan.mpbp_set_option(B.MPBP_OPT_GRAD_RUNS, 1)
+            got = _run(plan, args)
+            if first is None:
+                first = got
+                _close(got, ref, f"runs={runs}")
+            _equal(got, first, f"runs={runs} batch {b}")
+    plan.mpbp_set_option(B.MPBP_OPT_RUNS, 1)
+    plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, 8)
     for tx in (8, 16):
         # another tile grid sums the alpha partials over other voxel sets
         say(f"gradient kernel tile width {tx}")

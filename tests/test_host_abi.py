@@ -130,7 +130,7 @@ def test_launch_parameter_api_on_host_plan():
     prob = make_problem(get_config("c4_batch"))
     plan = B.Plan(prob, device=-1)
     t = plan.mpbp_tuning()
-    assert t["source"] == "default" and t["grad_batch"] == 8 and t["grad_runs"] == 1 and t["candidates"] == []
+    assert t["source"] == "default" and t["grad_batch"] == 8 and t["runs"] == 1 and t["candidates"] == []
     # one class per (detector size, smallest footprint bound); frames add up
     assert sum(c["frames"] for c in t["classes"]) == plan.n_frames
     assert [c["D"] for c in t["classes"]] == sorted([c["D"] for c in t["classes"]], reverse=True)
@@ -155,11 +155,11 @@ def test_launch_parameter_api_on_host_plan():
     for v in (3, 32):
         with pytest.raises(B.MPBPError):
             plan.mpbp_set_option(B.MPBP_OPT_GRAD_BATCH, v)
-    assert plan.mpbp_get_option(B.MPBP_OPT_GRAD_RUNS) == 1
-    plan.mpbp_set_option(B.MPBP_OPT_GRAD_RUNS, 0)
-    assert plan.mpbp_get_option(B.MPBP_OPT_GRAD_RUNS) == 0
+    assert plan.mpbp_get_option(B.MPBP_OPT_RUNS) == 1
+    plan.mpbp_set_option(B.MPBP_OPT_RUNS, 0)
+    assert plan.mpbp_get_option(B.MPBP_OPT_RUNS) == 0
     with pytest.raises(B.MPBPError):
-        plan.mpbp_set_option(B.MPBP_OPT_GRAD_RUNS, 2)
+        plan.mpbp_set_option(B.MPBP_OPT_RUNS, 2)
     assert plan.mpbp_tuning()["grad_tile"] == 16
     for v in (8, 16):
         plan.mpbp_set_option(B.MPBP_OPT_GRAD_TILE, v)
