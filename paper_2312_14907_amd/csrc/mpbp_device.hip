@@ -413,196 +413,175 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
   if (tid < A.n_peaks) A.alpha_part[(long long)tile * A.n_peaks + tid] = apl[tid];
 }
 
-// ------------------------------------ gather back-projection over runs of slices ---
-// With one probe for all slices and integer exit-beam offsets (neither MPBP_PROBE_3D nor
+// ------------------------------------ back-projection over runs of slices ---
+// With one probe for all slices and rounded exit-beam offsets (neither MPBP_PROBE_3D nor
 // MPBP_SHEAR_LINEAR), the slices of a run (consecutive slices with equal offset) read
 // the same footprint pixel of every frame with the same probe value: the frame sum
-// sum_f conj(P) g_psi of a (pixel, run) pair serves every slice of the run.  Per peak and
-// pass of kGradZB slices the kernel first gathers these sums, one item per (pixel, run):
-// a wavefront holds the tile's 64 pixels of one run, and each lane issues the loads of
-// B covering frames at once.  The chain rule then runs per voxel on its run's sum, read
-// from LDS.  The frames are summed in raster order with the same fused multiply-adds as
-// k_grad, so both kernels give the same results bit for bit.
-// The covering frames of a peak (those in the minibatch, in raster order) are listed in
-// LDS once per peak: window origin and slot offset.
+//   G_{m,k}[y][x] = sum_f conj(P_m[y - py_f][x - px_f]) g_psi,f[y - py_f + o_k][x - px_f + o_k']
+// serves every slice of run k.  Two kernels:
+//   k_bp_gather  one workgroup per (peak, voxel tile): the frames of the minibatch that
+//                meet the tile are listed in LDS (raster order), and each wavefront sums
+//                them for the tile's 64 pixels and one run at a time, B frames' loads in
+//                flight per lane; the sums go to G (the run sums' buffer, which the
+//                forward projection no longer needs).
+//   k_bp_chain   one lane per lateral pixel walks the slices: the chain rule through
+//                O_m = alpha_m chi e^{i G_m . u} on G_{m, run of z}, gradients written per
+//                voxel (z-summed when tied), alpha partials per workgroup.
+// The frames are summed in raster order with the fused multiply-adds of k_grad and the
+// chain rule is k_grad's (chain_voxel, peaks in order): df/du and df/dchi come out
+// bitwise equal to the per-slice walk; the alpha partials group the voxels differently.
 struct GradCand {
   int fpy, fpx;
   long long so;
 };
 
 template <int B, int TX>
-__global__ __launch_bounds__(kGradThreads, 4) void k_grad_runs(GradArgs A) {
+__global__ __launch_bounds__(kBpThreads) void k_bp_gather(GradArgs A) {
   constexpr int TY = kGradTile / TX;
   extern __shared__ cplx smem[];
   const int np = A.np, nz = A.nz;
-  cplx* Ps = smem;                                                       // np * np
-  cplx* rs = Ps + np * np;                                               // [kGradZB][kGradTile] run sums
-  GradCand* cand = reinterpret_cast<GradCand*>(rs + kGradZB * kGradTile);  // [max_cand]
-  int2* roff = reinterpret_cast<int2*>(cand + A.max_cand);               // [kGradZB] run offsets
-  double* apl = reinterpret_cast<double*>(roff + kGradZB);               // alpha partials
-  float* red = reinterpret_cast<float*>(apl + kMaxPeaksDev);             // block reduction
-  int* zr = reinterpret_cast<int*>(red + 16);                            // [kGradZB] run of a slice
-  int* ncand_s = zr + kGradZB;                                           // listed frames
-  float* zred = reinterpret_cast<float*>(ncand_s + 4);                   // z-tied partial sums
-  float tgu[3] = {0.f, 0.f, 0.f}, tgc = 0.f;
-
+  cplx* Ps = smem;                                                     // np * np
+  GradCand* cand = reinterpret_cast<GradCand*>(Ps + np * np);          // [max_cand]
+  int* ncand_s = reinterpret_cast<int*>(cand + A.max_cand);
   const int tid = threadIdx.x;
-  const int lane = tid % kGradTile;
-  const int tz = tid / kGradTile;
-  const int tile = frame_block_index(blockIdx.x, gridDim.x, 1);
-  if (tile >= A.tiles_x * A.tiles_y) return;
+  const int lane = tid % kGradTile, wv = tid / kGradTile;
+  const int ntiles = A.tiles_x * A.tiles_y;
+  // XCD k takes a contiguous range of (peak, tile): neighbouring tiles read the same
+  // frames' footprints, which then stay in that XCD's L2
+  const int bid = frame_block_index(blockIdx.x, gridDim.x, 1);
+  if (bid >= ntiles * A.n_peaks) return;
+  const int m = bid / ntiles, tile = bid % ntiles;
   const int bx = tile % A.tiles_x, by = tile / A.tiles_x;
   const int x0 = A.tile_ox + bx * TX, y0 = A.tile_oy + by * TY;
   const int x = x0 + lane % TX, y = y0 + lane / TX;
   const bool inb = (unsigned)x < (unsigned)A.nx && (unsigned)y < (unsigned)A.ny;
-  const long long nvox = (long long)nz * A.ny * A.nx;
-  const unsigned lat = (unsigned)(y * A.nx + x);
-  const unsigned fstride = A.tied ? (unsigned)(A.ny * A.nx) : (unsigned)nvox;
-  if (tid < kMaxPeaksDev) apl[tid] = 0.0;
-
-  for (int zb = 0; zb < nz; zb += kGradZB) {
-    float gux[kGradZPer], guy[kGradZPer], guz[kGradZPer], gch[kGradZPer];
-    float fu[kGradZPer][3], fc[kGradZPer];   // this lane's u and chi, read once per pass
-#pragma unroll
-    for (int i = 0; i < kGradZPer; ++i) {
-      gux[i] = guy[i] = guz[i] = gch[i] = 0.f;
-      const int z = zb + tz * kGradZPer + i;
-      const unsigned v = ((unsigned)(z < nz ? z : 0) * (unsigned)A.ny + (unsigned)(inb ? y : 0)) * (unsigned)A.nx +
-                         (unsigned)(inb ? x : 0);
-      const unsigned vf = A.tied ? (inb ? lat : 0u) : v;
-      fu[i][0] = A.u[vf];
-      fu[i][1] = A.u[fstride + vf];
-      fu[i][2] = A.u[2u * fstride + vf];
-      fc[i] = A.chi[vf];
+  const PeakDev pk = uniform_peak(A.peaks + m);
+  const int iy_lo = max(0, -floordiv(-(y0 - np + 1 - pk.oy), pk.sy));
+  const int iy_hi = min(pk.rows - 1, floordiv(y0 + TY - 1 - pk.oy, pk.sy));
+  const int ix_lo = max(0, -floordiv(-(x0 - np + 1 - pk.ox), pk.sx));
+  const int ix_hi = min(pk.cols - 1, floordiv(x0 + TX - 1 - pk.ox, pk.sx));
+  const int ncx = ix_hi - ix_lo + 1;
+  const int ncand = (iy_hi >= iy_lo && ncx > 0) ? (iy_hi - iy_lo + 1) * ncx : 0;
+  const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
+  for (int k = tid; k < np * np; k += kBpThreads) Ps[k] = probe[k];
+  // the frames of the minibatch meeting the tile, in raster order (wavefront 0: flags,
+  // ballot, prefix count)
+  if (tid < 64) {
+    int base = 0;
+    for (int c0 = 0; c0 < ncand; c0 += 64) {
+      const int c = c0 + tid;
+      const int cy = iy_lo + c / (ncx > 0 ? ncx : 1), cx = ix_lo + c % (ncx > 0 ? ncx : 1);
+      const bool act = c < ncand && (A.all_active || A.active[pk.frame_base + cy * pk.cols + cx]);
+      const unsigned long long mask = __ballot(act);
+      const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+      if (act)
+        cand[pos] = {pk.oy + cy * pk.sy, pk.ox + cx * pk.sx,
+                     pk.slot_off + (long long)(cy * pk.cols + cx) * pk.fy * pk.fx};
+      base += __popcll(mask);
     }
-    const int zn = min(kGradZB, nz - zb);   // slices of this pass
-
-    for (int m = 0; m < A.n_peaks; ++m) {
-      const PeakDev pk = uniform_peak(A.peaks + m);
-      const int iy_lo = max(0, -floordiv(-(y0 - np + 1 - pk.oy), pk.sy));
-      const int iy_hi = min(pk.rows - 1, floordiv(y0 + TY - 1 - pk.oy, pk.sy));
-      const int ix_lo = max(0, -floordiv(-(x0 - np + 1 - pk.ox), pk.sx));
-      const int ix_hi = min(pk.cols - 1, floordiv(x0 + TX - 1 - pk.ox, pk.sx));
-      const int ncx = ix_hi - ix_lo + 1;
-      const int ncand = (iy_hi >= iy_lo && ncx > 0) ? (iy_hi - iy_lo + 1) * ncx : 0;
-      const int* zrun = A.zrun + m * nz;
-      const int k0 = zrun[zb];
-      const int nr = zrun[zb + zn - 1] - k0 + 1;   // runs meeting this pass
-      __syncthreads();
-      const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * np * np;
-      for (int k = tid; k < np * np; k += kGradThreads) Ps[k] = probe[k];
-      for (int k = tid; k < nr; k += kGradThreads) roff[k] = A.roff[m * nz + k0 + k];
-      for (int k = tid; k < zn; k += kGradThreads) zr[k] = zrun[zb + k] - k0;
-      // the frames of the minibatch meeting the tile, in raster order (wavefront 0:
-      // flags, ballot, prefix count)
-      if (tid < 64) {
-        int base = 0;
-        for (int c0 = 0; c0 < ncand; c0 += 64) {
-          const int c = c0 + tid;
-          const int cy = iy_lo + c / (ncx > 0 ? ncx : 1), cx = ix_lo + c % (ncx > 0 ? ncx : 1);
-          const bool act = c < ncand && (A.all_active || A.active[pk.frame_base + cy * pk.cols + cx]);
-          const unsigned long long mask = __ballot(act);
-          const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-          if (act)
-            cand[pos] = {pk.oy + cy * pk.sy, pk.ox + cx * pk.sx,
-                         pk.slot_off + (long long)(cy * pk.cols + cx) * pk.fy * pk.fx};
-          base += __popcll(mask);
-        }
-        if (tid == 0) *ncand_s = base;
-      }
-      __syncthreads();
-      const int nact = __builtin_amdgcn_readfirstlane(*ncand_s);
-
-      // gather: item = (pixel, run); a wavefront takes the 64 pixels of one run
-      const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
-      for (int run = tz; run < nr; run += kGradTZ) {
-        const int2 ro = roff[run];
-        const int roy = __builtin_amdgcn_readfirstlane(ro.x), rox = __builtin_amdgcn_readfirstlane(ro.y);
-        cplx acc = {0.f, 0.f};
-        for (int c0 = 0; c0 < nact; c0 += B) {
-          cplx gv[B], pv[B];
-#pragma unroll
-          for (int k = 0; k < B; ++k) {
-            const int c = c0 + k < nact ? c0 + k : c0;   // past the list: its first entry
-            const int fpy = __builtin_amdgcn_readfirstlane(cand[c].fpy);
-            const int fpx = __builtin_amdgcn_readfirstlane(cand[c].fpx);
-            const long long so = cand[c].so;
-            const int a = y - fpy, b = x - fpx;
-            const bool inw = inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
-            const int ac = inw ? a : 0, bc = inw ? b : 0;
-            const cplx pr = Ps[ac * np + bc];
-            pv[k] = inw ? pr : cplx{0.f, 0.f};
-            const char* sl = reinterpret_cast<const char*>(slots + so);
-            const unsigned off = (unsigned)((ac + roy) * pk.fx + bc + rox) * (unsigned)sizeof(cplx);
-            gv[k] = *reinterpret_cast<const cplx*>(sl + off);
-          }
-#pragma unroll
-          for (int k = 0; k < B; ++k)
-            if (c0 + k < nact) acc = cmulc_acc(acc, gv[k], pv[k]);   // conj(P) g_psi
-        }
-        rs[run * kGradTile + lane] = acc;
-      }
-      __syncthreads();
-
-      // chain rule through O_m = alpha_m chi exp(i G_m . u) per voxel
-      float ap = 0.f;
-      if (inb) {
-        const float al = A.alpha[m];
-#pragma unroll
-        for (int i = 0; i < kGradZPer; ++i) {
-          const int zl = tz * kGradZPer + i;
-          if (zl < zn) {
-            chain_voxel(pk, rs[zr[zl] * kGradTile + lane], fu[i][0], fu[i][1], fu[i][2], fc[i], al, gux[i],
-                        guy[i], guz[i], gch[i], ap);
-          }
-        }
-      }
-      const float apb = block_sum_f(ap, red);
-      if (tid == 0) apl[m] += (double)apb;
-    }
-    if (inb && A.tied) {
-#pragma unroll
-      for (int i = 0; i < kGradZPer; ++i) {
-        tgu[0] += gux[i];
-        tgu[1] += guy[i];
-        tgu[2] += guz[i];
-        tgc += gch[i];
-      }
-    } else if (inb) {
-      const unsigned nv = (unsigned)nvox;
-#pragma unroll
-      for (int i = 0; i < kGradZPer; ++i) {
-        const int z = zb + tz * kGradZPer + i;
-        if (z < nz) {
-          const unsigned v = ((unsigned)z * (unsigned)A.ny + (unsigned)y) * (unsigned)A.nx + (unsigned)x;
-          A.grad_u[v] = gux[i];
-          A.grad_u[nv + v] = guy[i];
-          A.grad_u[2u * nv + v] = guz[i];
-          A.grad_chi[v] = gch[i];
-        }
-      }
-    }
+    if (tid == 0) *ncand_s = base;
   }
   __syncthreads();
-  if (A.tied) {
-    zred[0 * kGradThreads + tid] = tgu[0];
-    zred[1 * kGradThreads + tid] = tgu[1];
-    zred[2 * kGradThreads + tid] = tgu[2];
-    zred[3 * kGradThreads + tid] = tgc;
-    __syncthreads();
-    if (tz == 0 && inb) {
-      float sm4[4] = {0.f, 0.f, 0.f, 0.f};
-      for (int g = 0; g < kGradTZ; ++g)
+  const int nact = __builtin_amdgcn_readfirstlane(*ncand_s);
+  const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
+  cplx* G = reinterpret_cast<cplx*>(A.rs) + (long long)pk.run_base * A.nlat + (long long)(inb ? y : 0) * A.nx + (inb ? x : 0);
+  for (int run = wv; run < pk.nruns; run += kBpThreads / kGradTile) {
+    const int2 ro = A.roff[m * nz + run];
+    const int roy = __builtin_amdgcn_readfirstlane(ro.x), rox = __builtin_amdgcn_readfirstlane(ro.y);
+    cplx acc = {0.f, 0.f};
+    for (int c0 = 0; c0 < nact; c0 += B) {
+      cplx gv[B], pv[B];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sm4[c] += zred[c * kGradThreads + g * kGradTile + lane];
-      A.grad_u[lat] = sm4[0];
-      A.grad_u[fstride + lat] = sm4[1];
-      A.grad_u[2u * fstride + lat] = sm4[2];
-      A.grad_chi[lat] = sm4[3];
+      for (int k = 0; k < B; ++k) {
+        const int c = c0 + k < nact ? c0 + k : c0;   // past the list: its first entry
+        const int fpy = __builtin_amdgcn_readfirstlane(cand[c].fpy);
+        const int fpx = __builtin_amdgcn_readfirstlane(cand[c].fpx);
+        const long long so = cand[c].so;
+        const int a = y - fpy, b = x - fpx;
+        const bool inw = inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
+        const int ac = inw ? a : 0, bc = inw ? b : 0;
+        const cplx pr = Ps[ac * np + bc];
+        pv[k] = inw ? pr : cplx{0.f, 0.f};
+        const char* sl = reinterpret_cast<const char*>(slots + so);
+        const unsigned off = (unsigned)((ac + roy) * pk.fx + bc + rox) * (unsigned)sizeof(cplx);
+        gv[k] = *reinterpret_cast<const cplx*>(sl + off);
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k)
+        if (c0 + k < nact) acc = cmulc_acc(acc, gv[k], pv[k]);   // conj(P) g_psi
+    }
+    if (inb) G[(long long)run * A.nlat] = acc;
+  }
+}
+
+// One lane per lateral pixel and chunk of kBpZ slices (per lateral pixel and every slice
+// when tied: the z-sum stays in the lane).
+__global__ __launch_bounds__(kBpThreads) void k_bp_chain(GradArgs A) {
+  __shared__ float red[kBpThreads / 64];
+  const int tid = threadIdx.x;
+  const long long t = (long long)blockIdx.x * kBpThreads + tid;
+  const int nz = A.nz;
+  const long long p = A.tied ? t : t % A.nlat;
+  const int z0 = A.tied ? 0 : (int)(t / A.nlat) * kBpZ;
+  const int z1 = A.tied ? nz : min(z0 + kBpZ, nz);
+  const bool on = A.tied ? t < A.nlat : z0 < nz;
+  const long long nvox = (long long)nz * A.nlat;
+  const long long us = A.tied ? A.nlat : nvox;    // field component stride
+  const cplx* G = reinterpret_cast<const cplx*>(A.rs);
+  float ap[kMaxPeaksDev];
+  float tg[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < kMaxPeaksDev; ++m) ap[m] = 0.f;
+  if (on) {
+    for (int z = z0; z < z1; ++z) {
+      const long long vi = A.tied ? p : (long long)z * A.nlat + p;
+      const float ux = A.u[vi], uy = A.u[us + vi], uz = A.u[2 * us + vi], ch = A.chi[vi];
+      float gux = 0.f, guy = 0.f, guz = 0.f, gch = 0.f;
+#pragma unroll
+      for (int m = 0; m < kMaxPeaksDev; ++m) {
+        if (m < A.n_peaks) {   // uniform
+          const PeakDev pk = uniform_peak(A.peaks + m);
+          const int k = A.zrun[m * nz + z];
+          const cplx g = G[(long long)(pk.run_base + k) * A.nlat + p];
+          chain_voxel(pk, g, ux, uy, uz, ch, A.alpha[m], gux, guy, guz, gch, ap[m]);
+        }
+      }
+      if (A.tied) {
+        tg[0] += gux;
+        tg[1] += guy;
+        tg[2] += guz;
+        tg[3] += gch;
+      } else {
+        A.grad_u[vi] = gux;
+        A.grad_u[nvox + vi] = guy;
+        A.grad_u[2 * nvox + vi] = guz;
+        A.grad_chi[vi] = gch;
+      }
+    }
+    if (A.tied) {
+      A.grad_u[p] = tg[0];
+      A.grad_u[A.nlat + p] = tg[1];
+      A.grad_u[2 * A.nlat + p] = tg[2];
+      A.grad_chi[p] = tg[3];
     }
   }
-  if (tid < A.n_peaks) A.alpha_part[(long long)tile * A.n_peaks + tid] = apl[tid];
+  // alpha partials of this workgroup, one sum per peak (fixed order)
+  for (int m = 0; m < A.n_peaks; ++m) {
+    float v = 0.f;
+#pragma unroll
+    for (int q = 0; q < kMaxPeaksDev; ++q)
+      if (q == m) v = ap[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kBpThreads / 64; ++w) t += (double)red[w];
+      A.alpha_part[(long long)blockIdx.x * A.n_peaks + m] = t;
+    }
+  }
 }
 
 // --------------------------------------------------------------------- finalize ---
@@ -885,7 +864,7 @@ hipError_t prepare_kernels() {
 #undef MPBP_CASE
 #define MPBP_CASE(b, tx)                                                                                   \
   if (e == hipSuccess)                                                                                     \
-    e = hipFuncSetAttribute((const void*)k_grad_runs<b, tx>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+    e = hipFuncSetAttribute((const void*)k_bp_gather<b, tx>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
                             160 * 1024);
   MPBP_GRAD_RUN_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
@@ -893,6 +872,11 @@ hipError_t prepare_kernels() {
 }
 
 bool grad_uses_runs(const GradArgs& a) { return a.runs && !a.probe3 && !a.shw; }
+
+int grad_partials(const GradArgs& a) {
+  if (!grad_uses_runs(a)) return a.tiles_x * a.tiles_y;
+  return (int)nblk(a.tied ? a.nlat : a.nlat * ((a.nz + kBpZ - 1) / kBpZ), kBpThreads);
+}
 
 int grad_effective_batch(int batch, bool runs) {
   return runs ? std::min(std::max(batch, 4), 16) : std::min(batch, 4);
@@ -902,14 +886,18 @@ hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, 
   const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
   if (grad_uses_runs(a)) {
     const int b = grad_effective_batch(batch, true);
+    const unsigned ggrid = (unsigned)(((a.tiles_x * a.tiles_y * a.n_peaks + 7) / 8) * 8);
+    hipError_t e = hipErrorInvalidValue;
 #define MPBP_CASE(bb, tx)                                                                     \
     if (b == bb && tile_x == tx) {                                                            \
-      k_grad_runs<bb, tx><<<dim3(grid), dim3(kGradThreads), lds_bytes, s>>>(a);               \
-      return hipGetLastError();                                                               \
+      k_bp_gather<bb, tx><<<dim3(ggrid), dim3(kBpThreads), lds_bytes, s>>>(a);                \
+      e = hipGetLastError();                                                                  \
     }
     MPBP_GRAD_RUN_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
-    return hipErrorInvalidValue;
+    if (e != hipSuccess) return e;
+    k_bp_chain<<<dim3(grad_partials(a)), dim3(kBpThreads), 0, s>>>(a);
+    return hipGetLastError();
   }
   batch = grad_effective_batch(batch, false);
 #define MPBP_CASE(b, tx)                                                       \
@@ -1055,9 +1043,8 @@ int frame_chunk_len(int D) {
 int grad_lds_bytes(int np, int nz, int maxspan_y, int maxspan_x, int max_cand, bool tied, bool runs) {
   (void)maxspan_y;
   (void)maxspan_x;
-  if (runs)   // Ps, run sums, frame list, run offsets, alpha partials, reduction, slice runs, count, z-sums
-    return np * np * 8 + kGradZB * kGradTile * 8 + max_cand * (int)sizeof(GradCand) + kGradZB * 8 +
-           kMaxPeaksDev * 8 + 64 + kGradZB * 4 + 16 + (tied ? 4 * kGradThreads * 4 : 0);
+  if (runs)   // k_bp_gather: the probe, the frame list, its length
+    return np * np * 8 + max_cand * (int)sizeof(GradCand) + 16;
   return np * np * 8 + nz * 8 + kMaxPeaksDev * 8 + 64 + ((max_cand + 15) & ~15) +
          (tied ? 4 * kGradThreads * 4 : 0);
 }

@@ -148,6 +148,7 @@ struct mpbp_plan_t {
   struct GradTiling { int tx, ox, oy, nx, ny; };
   std::vector<GradTiling> tilings;
   int max_tiles = 0;
+  int max_parts = 0;                   // alpha partials: per tile, or per chain-rule workgroup
   long long slots_cplx = 0;
   // options
   int path = 0, graph = 1, xcd = 1;
@@ -449,6 +450,10 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
             p->order.push_back(d.frame_base + iy * d.cols + ix);
   }
   p->seen.assign(p->F, 0);
+  {
+    const long long lanes = (long long)p->ny * p->nx * (p->tied ? 1 : (p->nz + mpbp::kBpZ - 1) / mpbp::kBpZ);
+    p->max_parts = std::max<long long>(p->max_tiles, (lanes + mpbp::kBpThreads - 1) / mpbp::kBpThreads);
+  }
   p->sub_classes.reserve(p->classes.size());
   return MPBP_OK;
 }
@@ -480,7 +485,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_slots, (size_t)p->slots_cplx * 2);
   ALLOC(p->d_gslots, (size_t)p->slots_cplx * 2);
   ALLOC(p->d_floss, p->F);
-  ALLOC(p->d_apart, (size_t)p->max_tiles * p->M);
+  ALLOC(p->d_apart, (size_t)p->max_parts * p->M);
   ALLOC(p->d_red, kRedParts);
   ALLOC(p->d_tw, p->tw.size());
 #undef ALLOC
@@ -709,6 +714,18 @@ const mpbp_plan_t::GradTiling& grad_tiling(mpbp_plan p) {
   return p->tilings.front();
 }
 
+// Alpha partials the gradient launch leaves: one per voxel tile, or one per workgroup of
+// the run chain rule.
+int bp_parts(mpbp_plan p) {
+  const long long lanes = (long long)p->ny * p->nx * (p->tied ? 1 : (p->nz + mpbp::kBpZ - 1) / mpbp::kBpZ);
+  return (int)((lanes + mpbp::kBpThreads - 1) / mpbp::kBpThreads);
+}
+
+int grad_parts(mpbp_plan p) {
+  if (uses_runs(p)) return bp_parts(p);
+  return grad_tiling(p).nx * grad_tiling(p).ny;
+}
+
 mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float* chi, const float* alpha,
                          const float* probe, bool subset, float* grad_u, float* grad_chi) {
   mpbp::GradArgs g{};
@@ -730,6 +747,8 @@ mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float
   g.probe3 = p->probe3;
   g.shw = p->linear ? p->d_shw : nullptr;
   g.runs = p->runs;
+  g.rs = w.obj;          // the run sums' buffer: the forward projection is done with it
+  g.nlat = (long long)p->ny * p->nx;
   g.zrun = p->d_zrun;
   g.roff = reinterpret_cast<const int2*>(p->d_roff);
   g.grad_u = grad_u; g.grad_chi = grad_chi;
@@ -1216,7 +1235,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
   const int* list = frames ? plan->d_list : plan->d_order;
   const int* out_list = frames ? plan->d_list : nullptr;
   hipError_t e;
-  int n_part = grad_tiling(plan).nx * grad_tiling(plan).ny;
+  int n_part = grad_parts(plan);
   const double* apart = plan->d_apart;
   if (plan->path == 1) {
     StageTimer t(plan, MPBP_STAGE_PLAIN, s);
@@ -1274,7 +1293,7 @@ static size_t static_work(mpbp_plan p, char* base, Work* w) {
   t.slots = (float*)take(sizeof(float) * 2 * (size_t)p->slots_cplx);
   t.gslots = (float*)take(sizeof(float) * 2 * (size_t)p->slots_cplx);
   t.floss = (double*)take(sizeof(double) * (size_t)p->F);
-  t.apart = (double*)take(sizeof(double) * (size_t)p->max_tiles * p->M);
+  t.apart = (double*)take(sizeof(double) * (size_t)p->max_parts * p->M);
   if (w) *w = t;
   return off;
 }
@@ -1306,7 +1325,7 @@ mpbp_status mpbp_loss_grad_static(mpbp_plan plan, const float* u, const float* c
   hipError_t e = enqueue_loss_grad(plan, w, u, chi, alpha, (const float*)probe, y, list, n, frames != nullptr,
                                    grad_u, grad_chi, s, false, &what, false);
   if (e != hipSuccess) return hip_fail(e, what);
-  const int n_part = grad_tiling(plan).nx * grad_tiling(plan).ny;
+  const int n_part = grad_parts(plan);
   e = mpbp::launch_finalize(w.floss, out_list, n, loss, frame_loss, w.apart, n_part, plan->M, grad_alpha, s);
   if (e != hipSuccess) return hip_fail(e, "finalize kernel");
   return MPBP_OK;

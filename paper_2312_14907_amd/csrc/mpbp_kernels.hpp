@@ -76,7 +76,10 @@ struct GradArgs {
   int tied;                  // 1: u, chi and their gradients per lateral pixel (z-sums)
   int probe3;                // 1: probe is [M][nz][np][np] (a 3D illumination volume)
   const float* shw;          // [M][nz][2] fractional exit-beam offsets (null: rounded offsets)
-  int runs;                  // 1: gather per run of equal offsets (k_grad_runs) where it applies
+  int runs;                  // 1: back-project per run of equal offsets (k_bp_gather, k_bp_chain)
+                             // where it applies
+  float* rs;                 // complex64 [sum of nruns][ny][nx]: the frame sums per run
+  long long nlat;            // ny * nx
   const int* zrun;           // [M][nz] run of each slice (consecutive slices of equal offset)
   const int2* roff;          // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
   float* grad_u;
@@ -97,6 +100,8 @@ constexpr int kGradZB = 32;                             // z per pass of the gra
 constexpr int kGradZPer = kGradZB / kGradTZ;            // z per thread per pass
 constexpr int kGradBatches[] = {1, 2, 4};               // compiled batch sizes of the per-slice walk
 constexpr int kGradRunBatches[] = {4, 8, 16};           // compiled batch sizes of the run gather
+constexpr int kBpThreads = 256;                         // workgroup of k_bp_gather and k_bp_chain
+constexpr int kBpZ = 4;                                 // slices per lane of k_bp_chain
 constexpr int kDefaultGradBatch = 8;
 constexpr int kMaxPeaksDev = 16;
 

@@ -30,11 +30,15 @@ hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipSt
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
 int project_lds_bytes(int np, int G, int nz);
 int frame_bound(int D, int footprint);
-// Gradient kernel reading `batch` frames at once (the run gather, k_grad_runs, where
+// Back-projection and chain rule reading `batch` frames at once (the run gather
+// k_bp_gather plus k_bp_chain, where
 // grad_uses_runs(a): batch clamped to [4, 16]; otherwise the per-slice walk, k_grad:
 // batch clamped to at most 4), over tiles `tile_x` voxels wide (16: 16 x 4, 8: 8 x 8).
 hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, hipStream_t s);
 bool grad_uses_runs(const GradArgs& a);
+// Number of alpha partials [n][M] the gradient launch writes (per tile, or per workgroup
+// of the run chain rule).
+int grad_partials(const GradArgs& a);
 int grad_effective_batch(int batch, bool runs);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
