@@ -311,17 +311,20 @@ def time_unwrap(prob, torch, calls):
     return out
 
 
-def time_paper_shape(torch, steps=20):
-    """The paper-shaped workload c6_paper (150 x 150 detectors, four in-plane peaks, 9 x 9
-    rasters): loss+gradient steps after autotuning, direct launches and graph replay."""
-    cfg, prob, f, plan, args_t = make_inputs("c6_paper", torch)
+def time_paper_shape(torch, name="c6_paper", steps=20):
+    """A paper-shaped workload (150 x 150 detectors, four in-plane peaks, 9 x 9 rasters; 32
+    slices, or the paper's 100-voxel window with c6_paper100): loss+gradient steps after
+    autotuning."""
+    cfg, prob, f, plan, args_t = make_inputs(name, torch)
     plan.mpbp_autotune(*args_t)
     dt, _, _ = time_steps(plan, args_t, steps, 3, torch)
     nfr = prob.n_frames()
     t = plan.mpbp_tuning()
-    return {"workload": "c6_paper", "frames": nfr, "detector": 150, "peaks": prob.n_peaks,
+    plan.close()
+    return {"workload": name, "frames": nfr, "detector": 150, "peaks": prob.n_peaks, "slices": prob.nz,
             "ms_per_step": round(1e3 * dt / steps, 4), "value": round(nfr * steps / dt, 1),
-            "unit": "scan-positions/s", "launch": [{k: c[k] for k in ("FB", "G", "xcd")} for c in t["classes"]]}
+            "unit": "scan-positions/s",
+            "launch": [{k: c[k] for k in ("fy", "fx", "FB", "G", "xcd")} for c in t["classes"]]}
 
 
 def cpu_unwrap(prob):
@@ -502,6 +505,7 @@ def main():
         # paper-shaped workload (neither is part of `value`)
         out["unwrap"] = time_unwrap(prob, torch, 10)
         out["paper_shape"] = time_paper_shape(torch)
+        out["paper_shape_100_slices"] = time_paper_shape(torch, "c6_paper100")
 
     if not args.no_cpu_baseline:
         rate, sample, acc = cpu_baseline(args.workload, plan, args_t, torch)

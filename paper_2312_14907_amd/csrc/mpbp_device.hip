@@ -819,12 +819,12 @@ hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t 
   return hipGetLastError();
 }
 
-// the footprint accumulator (up to kProjPix * kFrameThreads pixels: the plan checks
-// fy * fx), then the per-slice offset and fraction tables
-int project_lds_bytes(int np, int G, int nz) {
+// the footprint accumulator (acc_pix pixels, a multiple of 4), then the per-slice offset
+// and fraction tables
+int project_lds_bytes(int np, int G, int nz, int acc_pix) {
   (void)np;
   (void)G;
-  return kProjPix * kFrameThreads * (int)sizeof(cplx) + ((nz + 3) & ~3) * 4 + nz * 8;
+  return acc_pix * (int)sizeof(cplx) + ((nz + 3) & ~3) * 4 + nz * 8;
 }
 
 static const int kDets[] = {32, 64, 96, 128, 150, 192, 256};

@@ -149,6 +149,7 @@ struct mpbp_plan_t {
   std::vector<GradTiling> tilings;
   int max_tiles = 0;
   int max_parts = 0;                   // alpha partials: per tile, or per chain-rule workgroup
+  int acc_pix = 0;                     // projection accumulator: largest fy * fx (multiple of 4)
   long long slots_cplx = 0;
   // options
   int path = 0, graph = 1, xcd = 1;
@@ -282,6 +283,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   p->scan.clear();
   p->peak_of.clear();
   p->tw.clear();
+  p->acc_pix = 0;
   const int np = p->np;
   const int zref = p->nz / 2;
   long long slot = 0;
@@ -342,9 +344,10 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     }
     d.run_base = n_runs;
     n_runs += d.nruns;
-    if (d.fy * d.fx > mpbp::kProjPix * mpbp::kFrameThreads)
+    if (d.fy * d.fx > mpbp::kProjMaxPix)
       return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d above %d pixels", m, d.fy, d.fx,
-                  mpbp::kProjPix * mpbp::kFrameThreads);
+                  mpbp::kProjMaxPix);
+    p->acc_pix = std::max(p->acc_pix, (d.fy * d.fx + 3) & ~3);
     d.fxp = d.fx | 1;
     d.rows = k.scan_n[0]; d.cols = k.scan_n[1];
     d.nfr = d.rows * d.cols;
@@ -402,7 +405,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   }
   p->lds_grad = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0, false);
   p->lds_runs = mpbp::grad_lds_bytes(np, p->nz, p->maxspan_y, p->maxspan_x, p->max_cand, p->tied != 0, true);
-  for (int G : mpbp::kSlabDepths) p->lds_project[G] = mpbp::project_lds_bytes(np, G, p->nz);
+  for (int G : mpbp::kSlabDepths) p->lds_project[G] = mpbp::project_lds_bytes(np, G, p->nz, p->acc_pix);
   if (p->lds_project[mpbp::kDefaultSlab] > kMaxLds)
     return fail(MPBP_ERR_UNSUPPORTED, "projection needs %d B of LDS", p->lds_project[mpbp::kDefaultSlab]);
   if (p->lds_grad > kMaxLds || p->lds_runs > kMaxLds)
@@ -704,6 +707,7 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const Work& w, const float* y, const int
   a.probe3 = p->probe3;
   a.shw = p->linear ? p->d_shw : nullptr;
   a.runs = uses_runs(p);
+  a.acc_pix = p->acc_pix;
   a.roff = reinterpret_cast<const int2*>(p->d_roff);
   return a;
 }

@@ -54,6 +54,8 @@ struct FrameArgs {
   int probe3;              // 1: probe is [M][nz][np][np] (a 3D illumination volume)
   const float* shw;        // [M][nz][2] fractional exit-beam offsets (null: rounded offsets)
   int runs;                // 1: project from the run sums (one probe, rounded offsets)
+  int acc_pix;             // LDS footprint accumulator of the projection: the plan's largest
+                           // fy * fx, rounded up to a multiple of 4
   const int2* roff;        // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
 };
 
@@ -91,7 +93,7 @@ constexpr int kFrameThreads = 256;
 constexpr int kSlabDepths[] = {2, 4, 8};   // compiled projection depths (object slices in flight per lane)
 constexpr int kDefaultSlab = 4;
 constexpr int kProjE = 4;     // probe pixels per lane in the projection (probe_n^2 <= 4 * 256)
-constexpr int kProjPix = 8;   // footprint pixels per lane (fy * fx <= 8 * 256)
+constexpr int kProjMaxPix = 16384;   // largest footprint fy * fx of the projection (128 KB of LDS)
 constexpr int kGradTile = 64, kGradTZ = 8;              // 64 voxels of a slice x 8 slice groups
 constexpr int kGradThreads = kGradTile * kGradTZ;        // 512 threads
 constexpr int kGradTileXs[] = {16, 8};                   // compiled tile widths (16 x 4, 8 x 8)

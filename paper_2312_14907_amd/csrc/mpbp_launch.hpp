@@ -28,7 +28,7 @@ hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipSt
 // Exit waves of the listed frames into their slots, with G object slices in flight per
 // lane (G = 2, 4 or 8); lds_bytes from project_lds_bytes.
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
-int project_lds_bytes(int np, int G, int nz);
+int project_lds_bytes(int np, int G, int nz, int acc_pix);
 int frame_bound(int D, int footprint);
 // Back-projection and chain rule reading `batch` frames at once (the run gather
 // k_bp_gather plus k_bp_chain, where

@@ -43,7 +43,7 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
   // per-slice footprint offsets (and interpolation fractions) in LDS: the slice loop
   // then reads nothing from device memory but the object, and the waits for the
   // object loads issued G slices ahead cover those loads alone
-  int* sho = reinterpret_cast<int*>(acc + kProjPix * kFrameThreads);                 // [nz]
+  int* sho = reinterpret_cast<int*>(acc + A.acc_pix);                                 // [nz]
   float2* shf = reinterpret_cast<float2*>(sho + ((nz + 3) & ~3));                     // [nz] (LIN)
   for (int p = tid; p < fy * fx; p += NT) acc[p] = {0.f, 0.f};
   for (int z = tid; z < nz; z += NT) {
@@ -181,7 +181,7 @@ __device__ void project_runs_body(const FrameArgs& A, const PeakDev& pk, int fid
   const int np2 = np * np;
   const int nr = pk.nruns;
   cplx* acc = sm;                                                     // [fy][fx]
-  int* sho = reinterpret_cast<int*>(acc + kProjPix * kFrameThreads);  // [nruns] footprint offsets
+  int* sho = reinterpret_cast<int*>(acc + A.acc_pix);                 // [nruns] footprint offsets
   for (int p = tid; p < fy * fx; p += NT) acc[p] = {0.f, 0.f};
   for (int k = tid; k < nr; k += NT) {
     const int2 ro = A.roff[m * nz + k];

@@ -186,6 +186,14 @@ def _c6():
     }
 
 
+def _c6_100():
+    # The paper-shaped workload with the paper's 100-voxel window along x3 (Table 1) and a
+    # film of its 17-voxel thickness (section 4) centred in it.
+    cfg = _c6()
+    cfg.update({"name": "c6_paper100", "index": 8, "nz": 100, "slab": 17})
+    return cfg
+
+
 _BUILDERS = {
     "c1_tiny": _c1,
     "c2_forward": _c2,
@@ -194,6 +202,7 @@ _BUILDERS = {
     "c5_full": _c5,
     "c5_crop8": _c5_crop8,
     "c6_paper": _c6,
+    "c6_paper100": _c6_100,
 }
 CONFIG_NAMES = tuple(_BUILDERS)
 

@@ -5,7 +5,10 @@ a step of 6 and the paper's count rates (section 4).
 
 Checked: loss, per-frame losses and gradients on both paths, per voxel and in the membrane
 (z-tied) parameterisation, the model intensities, and the unwrap projector on the four
-coplanar peaks (H H^T of rank 2: the component of u no peak sees is kept).
+coplanar peaks (H H^T of rank 2: the component of u no peak sees is kept).  c6_paper100
+takes the paper's 100-voxel window along x3 (Table 1) with a 17-voxel film: its sheared
+footprints reach 70 x 51 pixels, and it is checked whole on both paths, per slice and
+per run of equal offsets, and through Poisson counts.
 """
 import numpy as np
 import pytest
@@ -90,3 +93,31 @@ def test_c6_unwrap_coplanar_peaks(c6):
     np.testing.assert_array_equal(host(wraps), ref_w)
     np.testing.assert_allclose(host(du), ref_u, atol=2e-6, rtol=0)
     np.testing.assert_array_equal(host(du)[2], u[2])       # u_z: no peak sees it
+
+
+@pytest.fixture(scope="module")
+def c6_100():
+    from synth import photon_rng, poisson_counts
+    cfg = get_config("c6_paper100")
+    prob = make_problem(cfg)
+    f = make_fields(cfg, prob)
+    say("c6_paper100: oracle intensities (100 slices)")
+    y = poisson_counts(photon_rng(cfg), ragged(O.model_intensity(f["u"], f["chi"], f["alpha"], f["probe"], prob)))
+    u = (f["u"] + f["delta"]).astype(np.float32)
+    say("c6_paper100: oracle loss and gradient")
+    return prob, f, y, u, O.loss_grad(u, f["chi"], f["alpha"], f["probe"], y, prob)
+
+
+@pytest.mark.parametrize("path,runs", [(0, 1), (0, 0), (1, 1)])
+def test_c6_hundred_slices(c6_100, path, runs):
+    prob, f, y, u, ref = c6_100
+    say(f"c6_paper100 path={path} runs={runs}")
+    plan = B.Plan(prob, 0)
+    t = plan.mpbp_tuning()
+    assert max(max(c["fy"], c["fx"]) for c in t["classes"]) == 70
+    plan.mpbp_set_option(B.MPBP_OPT_PATH, path)
+    plan.mpbp_set_option(B.MPBP_OPT_RUNS, runs)
+    got = gpu_loss_grad(plan, u, f["chi"], f["alpha"], f["probe"], y)
+    np.testing.assert_allclose(got["frame_loss"], ref["frame_loss"], rtol=1e-5, atol=1e-5 * ref["frame_loss"].max())
+    _check(got, ref)
+    plan.close()
