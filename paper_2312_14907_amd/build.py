@@ -31,17 +31,25 @@ def hipcc():
     return p
 
 
-def build(verbose=False, jobs=None):
-    """Compile every source to an object in parallel, then link libmpbp.so."""
+def build(verbose=False, jobs=None, out=None, objdir=None, host_flags=(), rebuild=None):
+    """Compile every source to an object in parallel, then link libmpbp.so.
+
+    out / objdir: another library path and object folder; host_flags: extra flags of the
+    host compilation (each behind -Xarch_host); rebuild: the sources to compile (the
+    others' objects are taken from the default object folder, which must be built)."""
     jobs = jobs or max(1, min(8, os.cpu_count() or 1))
-    objdir = os.path.join(PKG, "_build")
+    objdir = objdir or os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
+    hflags = [x for f in host_flags for x in ("-Xarch_host", f)]
     procs = []
     objs = []
     for src in SOURCES:
+        if rebuild is not None and src not in rebuild:
+            objs.append(os.path.join(PKG, "_build", src + ".o"))
+            continue
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
-        cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
+        cmd = [hipcc(), *FLAGS, *hflags, "-I", os.path.join(ROOT, "include"), "-c",
                os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
@@ -52,15 +60,16 @@ def build(verbose=False, jobs=None):
             _wait(procs.pop(0))
     while procs:
         _wait(procs.pop(0))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-shared", "-o", tmp, *objs]
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), *FLAGS, *hflags, "-shared", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def _wait(item):

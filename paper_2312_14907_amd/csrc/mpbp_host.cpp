@@ -40,6 +40,28 @@ mpbp_status hip_fail(hipError_t e, const char* what) {
   return fail(MPBP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// MPBP_TRACE=1 in the environment: one line per plan choice on stderr (geometry, size
+// classes and their launch parameters, workspace, autotuner and cache choices, graph
+// captures).
+bool trace_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("MPBP_TRACE");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+void trace(const char* fmt, ...) {
+  if (!trace_on()) return;
+  char buf[768];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "mpbp: %s\n", buf);
+  std::fflush(stderr);
+}
+
 bool supported_det(int d) {
   return d == 32 || d == 64 || d == 96 || d == 128 || d == 150 || d == 192 || d == 256;
 }
@@ -865,6 +887,7 @@ mpbp_status run_graph(mpbp_plan p, const GraphKey& key, hipStream_t s, Enqueue&&
     p->graphs.erase(old);
   }
   p->graphs.push_back({key, exec, ++p->graph_clock});
+  trace("plan %p: captured a %s graph (%zu kept)", (void*)p, key.kind ? "loss_grad" : "forward", p->graphs.size());
   e = hipGraphLaunch(exec, s);
   return e == hipSuccess ? MPBP_OK : hip_fail(e, "hipGraphLaunch");
 }
@@ -959,7 +982,10 @@ void load_tuning(mpbp_plan_t* p) {
       used = true;
     }
   }
-  if (used) p->tune_source = "cache";
+  if (used) {
+    p->tune_source = "cache";
+    trace("plan %p: launch parameters from the tuning cache %s", (void*)p, path);
+  }
 }
 
 void save_tuning(const mpbp_plan_t* p) {
@@ -1107,6 +1133,34 @@ mpbp_status ensure_unwrap(mpbp_plan_t* p) {
 
 extern "C" {
 
+// The plan's choices, under MPBP_TRACE.
+static void trace_plan(const mpbp_plan_t* p, const char* when) {
+  if (!trace_on()) return;
+  trace("plan %p (%s): grid %dx%dx%d, probe %d, %d peaks, %lld frames, flags%s%s%s; device %d", (void*)p, when,
+        p->nz, p->ny, p->nx, p->np, p->M, (long long)p->F, p->tied ? " z-tied" : "", p->probe3 ? " probe-3d" : "",
+        p->linear ? " shear-linear" : "", p->device);
+  for (int m = 0; m < p->M; ++m) {
+    const PeakDev& d = p->pdev[m];
+    trace("  peak %d: D %d, footprint %dx%d, %d runs of equal offset over %d slices, raster %dx%d", m, d.D, d.fy,
+          d.fx, d.nruns, p->nz, d.rows, d.cols);
+  }
+  for (size_t k = 0; k < p->classes.size(); ++k) {
+    const auto& c = p->classes[k];
+    trace("  class %zu: D %d, %d frames, footprint bound %d (smallest %d), projection depth %d, xcd order %d%s", k,
+          c.D, c.count, c.FB, c.key, c.G, c.xcd, c.tuned_us > 0 ? " (tuned)" : "");
+  }
+  trace("  path: %s; objects %s; back-projection %s, batch %d, tile %d; tuning source %s",
+        p->path ? "plain" : "batched fused", (p->runs && !p->probe3 && !p->linear) ? "summed per run" : "per slice",
+        (p->runs && !p->probe3 && !p->linear) ? "per run (gather + chain rule)" : "per slice", p->grad_batch,
+        p->grad_tile, p->tune_source.c_str());
+  trace("  LDS bytes: frame kernel %d, projection %d, back-projection %d; projection accumulator %d pixels",
+        p->lds_grad_frame, p->lds_project[mpbp::kDefaultSlab], (p->runs && !p->probe3 && !p->linear) ? p->lds_runs : p->lds_grad,
+        p->acc_pix);
+  if (p->device >= 0)
+    trace("  device workspace: objects %zu B, two footprint slots of %zu B each, %d alpha partials per peak",
+          sizeof(float) * 2 * (size_t)p->M * (size_t)p->nvox, sizeof(float) * 2 * (size_t)p->slots_cplx, p->max_parts);
+}
+
 mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan* out) {
   if (!out) return fail(MPBP_ERR_INVALID, "out is NULL");
   *out = nullptr;
@@ -1147,6 +1201,7 @@ mpbp_status mpbp_plan_create(const mpbp_problem* problem, int device, mpbp_plan*
     return fail(MPBP_ERR_INVALID, "device must be >= 0, or -1 for a host-only plan");
   }
   g_err.clear();
+  trace_plan(p, "created");
   *out = p;
   return MPBP_OK;
 }
@@ -1660,6 +1715,7 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
   if (e != hipSuccess) return hip_fail(e, "autotune");
   plan->tune_report = rep + "]";
   plan->tune_source = "autotune";
+  trace_plan(plan, "autotuned");
   clear_graphs(plan);
   save_tuning(plan);
   return MPBP_OK;
