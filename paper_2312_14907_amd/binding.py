@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libmpbp.so")
+# MPBP_LIBRARY may name another build of the library (the bounds-checked libmpbp_debug.so)
+LIB_PATH = os.environ.get("MPBP_LIBRARY") or os.path.join(_PKG, "libmpbp.so")
 
 MPBP_OK = 0
 STATUS_NAMES = {0: "MPBP_OK", 1: "MPBP_ERR_INVALID", 2: "MPBP_ERR_SHAPE", 3: "MPBP_ERR_FOOTPRINT",

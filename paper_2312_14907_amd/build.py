@@ -31,16 +31,17 @@ def hipcc():
     return p
 
 
-def build(verbose=False, jobs=None, out=None, objdir=None, host_flags=(), rebuild=None):
+def build(verbose=False, jobs=None, out=None, objdir=None, host_flags=(), rebuild=None, defines=()):
     """Compile every source to an object in parallel, then link libmpbp.so.
 
     out / objdir: another library path and object folder; host_flags: extra flags of the
-    host compilation (each behind -Xarch_host); rebuild: the sources to compile (the
-    others' objects are taken from the default object folder, which must be built)."""
+    host compilation (each behind -Xarch_host); defines: preprocessor symbols (host and
+    device); rebuild: the sources to compile (the others' objects are taken from the
+    default object folder, which must be built)."""
     jobs = jobs or max(1, min(8, os.cpu_count() or 1))
     objdir = objdir or os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    hflags = [x for f in host_flags for x in ("-Xarch_host", f)]
+    hflags = [x for f in host_flags for x in ("-Xarch_host", f)] + [f"-D{d}" for d in defines]
     procs = []
     objs = []
     for src in SOURCES:
@@ -83,5 +84,18 @@ def _wait(item):
         sys.stderr.write("\n".join(warn) + "\n")
 
 
+DEBUG_LIB = os.path.join(PKG, "libmpbp_debug.so")
+
+
+def build_debug(verbose=False):
+    """libmpbp_debug.so: the library with the device-side bounds checks of the projection
+    and the back-projection (MPBP_DEBUG); every compute call then waits and reports a check
+    that fired as MPBP_ERR_INTERNAL.  The kernels with checks live in mpbp_device.hip, the
+    status word's reader in mpbp_host.cpp; the other objects are the release build's."""
+    return build(verbose=verbose, out=DEBUG_LIB, objdir=os.path.join(PKG, "_build_debug"),
+                 rebuild=("mpbp_device.hip", "mpbp_host.cpp"), defines=("MPBP_DEBUG",))
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    print(build_debug(verbose="-v" in sys.argv))

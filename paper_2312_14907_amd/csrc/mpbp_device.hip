@@ -275,7 +275,9 @@ __global__ __launch_bounds__(kGradThreads, 4) void k_grad(GradArgs A) {
             for (int i = 0; i < kGradZPer; ++i) {
               if (same[i]) continue;
               const unsigned off = (unsigned)((ac + zsy[i]) * pk.fx + bc + zsx[i]) * (unsigned)sizeof(cplx);
-              const cplx* q = reinterpret_cast<const cplx*>(sl + off);
+              const bool okq = MPBP_CHECK(
+                  A.dbg, off / sizeof(cplx) + (LIN ? pk.fx + 1 : 0) < (unsigned)(pk.fy * pk.fx), kDbgSlot);
+              const cplx* q = reinterpret_cast<const cplx*>(okq ? sl + off : sl);
               if constexpr (LIN) {
                 const cplx q00 = q[0], q01 = q[1], q10 = q[pk.fx], q11 = q[pk.fx + 1];
                 gv[k][i] = cadd(cadd(cscale(q00, zw[i][0]), cscale(q01, zw[i][LIN ? 1 : 0])),
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_gather(GradArgs A) {
       const unsigned long long mask = __ballot(act);
       const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-      if (act)
+      if (act && MPBP_CHECK(A.dbg, pos < A.max_cand, kDbgFrameList))
         cand[pos] = {pk.oy + cy * pk.sy, pk.ox + cx * pk.sx,
                      pk.slot_off + (long long)(cy * pk.cols + cx) * pk.fy * pk.fx};
       base += __popcll(mask);
@@ -483,7 +485,7 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_gather(GradArgs A) {
     if (tid == 0) *ncand_s = base;
   }
   __syncthreads();
-  const int nact = __builtin_amdgcn_readfirstlane(*ncand_s);
+  const int nact = min(__builtin_amdgcn_readfirstlane(*ncand_s), A.max_cand);
   const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
   cplx* G = reinterpret_cast<cplx*>(A.rs) + (long long)pk.run_base * A.nlat + (long long)(inb ? y : 0) * A.nx + (inb ? x : 0);
   for (int run = wv; run < pk.nruns; run += kBpThreads / kGradTile) {
@@ -505,13 +507,14 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_gather(GradArgs A) {
         pv[k] = inw ? pr : cplx{0.f, 0.f};
         const char* sl = reinterpret_cast<const char*>(slots + so);
         const unsigned off = (unsigned)((ac + roy) * pk.fx + bc + rox) * (unsigned)sizeof(cplx);
-        gv[k] = *reinterpret_cast<const cplx*>(sl + off);
+        const bool okg = MPBP_CHECK(A.dbg, off / sizeof(cplx) < (unsigned)(pk.fy * pk.fx), kDbgSlot);
+        gv[k] = *reinterpret_cast<const cplx*>(okg ? sl + off : sl);
       }
 #pragma unroll
       for (int k = 0; k < B; ++k)
         if (c0 + k < nact) acc = cmulc_acc(acc, gv[k], pv[k]);   // conj(P) g_psi
     }
-    if (inb) G[(long long)run * A.nlat] = acc;
+    if (inb && MPBP_CHECK(A.dbg, pk.run_base + run < A.n_runs, kDbgRunSum)) G[(long long)run * A.nlat] = acc;
   }
 }
 
@@ -542,7 +545,8 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_chain(GradArgs A) {
       for (int m = 0; m < kMaxPeaksDev; ++m) {
         if (m < A.n_peaks) {   // uniform
           const PeakDev pk = uniform_peak(A.peaks + m);
-          const int k = A.zrun[m * nz + z];
+          int k = A.zrun[m * nz + z];
+          if (!MPBP_CHECK(A.dbg, k >= 0 && pk.run_base + k < A.n_runs, kDbgRunSum)) k = -pk.run_base;
           const cplx g = G[(long long)(pk.run_base + k) * A.nlat + p];
           chain_voxel(pk, g, ux, uy, uz, ch, A.alpha[m], gux, guy, guz, gch, ap[m]);
         }

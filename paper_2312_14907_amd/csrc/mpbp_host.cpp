@@ -172,6 +172,7 @@ struct mpbp_plan_t {
   int max_tiles = 0;
   int max_parts = 0;                   // alpha partials: per tile, or per chain-rule workgroup
   int acc_pix = 0;                     // projection accumulator: largest fy * fx (multiple of 4)
+  int n_runs = 0;                      // runs over all peaks
   long long slots_cplx = 0;
   // options
   int path = 0, graph = 1, xcd = 1;
@@ -188,6 +189,7 @@ struct mpbp_plan_t {
   int* d_list_sorted = nullptr;    // the caller's list grouped by detector size
   unsigned char* d_active = nullptr;     // per-frame minibatch mask (subset calls)
   unsigned char* d_active_all = nullptr; // all ones
+  unsigned* d_dbg = nullptr;       // status word of the device bounds checks (debug library)
   float* d_obj = nullptr;
   float* d_slots = nullptr;        // exit waves (k_project -> k_frames)
   float* d_gslots = nullptr;       // footprint gradients (k_frames -> k_grad)
@@ -256,6 +258,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_list_sorted);
   (void)hipFree(p->d_active);
   (void)hipFree(p->d_active_all);
+  (void)hipFree(p->d_dbg);
   (void)hipFree(p->d_obj);
   (void)hipFree(p->d_slots);
   (void)hipFree(p->d_gslots);
@@ -366,6 +369,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     }
     d.run_base = n_runs;
     n_runs += d.nruns;
+    p->n_runs = n_runs;
     if (d.fy * d.fx > mpbp::kProjMaxPix)
       return fail(MPBP_ERR_UNSUPPORTED, "peak %d: footprint %dx%d above %d pixels", m, d.fy, d.fx,
                   mpbp::kProjMaxPix);
@@ -506,6 +510,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_list_sorted, p->F);
   ALLOC(p->d_active, p->F);
   ALLOC(p->d_active_all, p->F);
+  ALLOC(p->d_dbg, 1);
   ALLOC(p->d_obj, (size_t)p->M * p->nvox * 2);
   ALLOC(p->d_slots, (size_t)p->slots_cplx * 2);
   ALLOC(p->d_gslots, (size_t)p->slots_cplx * 2);
@@ -528,6 +533,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), p->order.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_tw, p->tw.data(), p->tw.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy tables");
+  if (e == hipSuccess) e = hipMemset(p->d_dbg, 0, sizeof(unsigned));
   std::vector<unsigned char> ones(p->F, 1);
   e = hipMemcpy(p->d_active_all, ones.data(), p->F, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy mask");
@@ -730,6 +736,8 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const Work& w, const float* y, const int
   a.shw = p->linear ? p->d_shw : nullptr;
   a.runs = uses_runs(p);
   a.acc_pix = p->acc_pix;
+  a.n_runs = p->n_runs;
+  a.dbg = p->d_dbg;
   a.roff = reinterpret_cast<const int2*>(p->d_roff);
   return a;
 }
@@ -775,6 +783,8 @@ mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float
   g.runs = p->runs;
   g.rs = w.obj;          // the run sums' buffer: the forward projection is done with it
   g.nlat = (long long)p->ny * p->nx;
+  g.n_runs = p->n_runs;
+  g.dbg = p->d_dbg;
   g.zrun = p->d_zrun;
   g.roff = reinterpret_cast<const int2*>(p->d_roff);
   g.grad_u = grad_u; g.grad_chi = grad_chi;
@@ -1133,6 +1143,28 @@ mpbp_status ensure_unwrap(mpbp_plan_t* p) {
 
 extern "C" {
 
+// The debug library (MPBP_DEBUG) waits for each compute call and reports a device-side
+// bounds check that fired; the release library returns at once.
+static mpbp_status debug_check(mpbp_plan_t* p, hipStream_t s, mpbp_status st) {
+#ifdef MPBP_DEBUG
+  if (st != MPBP_OK) return st;
+  unsigned bits = 0;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(&bits, p->d_dbg, sizeof(bits), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "debug status word");
+  if (bits) {
+    (void)hipMemset(p->d_dbg, 0, sizeof(unsigned));
+    return fail(MPBP_ERR_INTERNAL, "device bounds check failed (bits 0x%x: 1 accumulator, 2 object, 4 slot, "
+                "8 frame list, 16 run sums)", bits);
+  }
+  return MPBP_OK;
+#else
+  (void)p;
+  (void)s;
+  return st;
+#endif
+}
+
 // The plan's choices, under MPBP_TRACE.
 static void trace_plan(const mpbp_plan_t* p, const char* when) {
   if (!trace_on()) return;
@@ -1254,7 +1286,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
     key.xcd = plan->xcd;
     const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, model_intensity, plan->d_bg};
     std::copy(std::begin(ptrs), std::end(ptrs), key.ptr);
-    return run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
+    return debug_check(plan, s, run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
       hipError_t le = enqueue_forward(plan, u, chi, alpha, (const float*)probe, y, list, n, false,
                                       model_intensity, cs, true, what);
       if (le == hipSuccess && (loss || frame_loss)) {
@@ -1263,7 +1295,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
         if (le != hipSuccess) *what = "finalize kernel";
       }
       return le;
-    });
+    }));
   } else {
     const char* what = "";
     e = enqueue_forward(plan, u, chi, alpha, (const float*)probe, y, list, n, frames != nullptr,
@@ -1275,7 +1307,7 @@ mpbp_status mpbp_forward(mpbp_plan plan, const float* u, const float* chi, const
     e = mpbp::launch_finalize(plan->d_floss, out_list, n, loss, frame_loss, nullptr, 0, plan->M, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "finalize kernel");
   }
-  return MPBP_OK;
+  return debug_check(plan, s, MPBP_OK);
 }
 
 mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, const float* alpha,
@@ -1312,7 +1344,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
     key.xcd = plan->xcd;
     const void* ptrs[] = {u, chi, alpha, probe, y, loss, frame_loss, grad_u, grad_chi, grad_alpha, plan->d_bg};
     std::copy(std::begin(ptrs), std::end(ptrs), key.ptr);
-    return run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
+    return debug_check(plan, s, run_graph(plan, key, s, [&](hipStream_t cs, const char** what) {
       hipError_t le = enqueue_loss_grad(plan, plan_work(plan), u, chi, alpha, (const float*)probe, y, list, n,
                                         false, grad_u, grad_chi, cs, true, what);
       if (le == hipSuccess) {
@@ -1321,7 +1353,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
         if (le != hipSuccess) *what = "finalize kernel";
       }
       return le;
-    });
+    }));
   } else {
     const char* what = "";
     e = enqueue_loss_grad(plan, plan_work(plan), u, chi, alpha, (const float*)probe, y, list, n,
@@ -1334,7 +1366,7 @@ mpbp_status mpbp_loss_grad(mpbp_plan plan, const float* u, const float* chi, con
                               grad_alpha, s);
   }
   if (e != hipSuccess) return hip_fail(e, "finalize kernel");
-  return MPBP_OK;
+  return debug_check(plan, s, MPBP_OK);
 }
 
 // Layout of the fused path's workspace in the fixed array: objects, exit-wave slots,
@@ -1387,7 +1419,7 @@ mpbp_status mpbp_loss_grad_static(mpbp_plan plan, const float* u, const float* c
   const int n_part = grad_parts(plan);
   e = mpbp::launch_finalize(w.floss, out_list, n, loss, frame_loss, w.apart, n_part, plan->M, grad_alpha, s);
   if (e != hipSuccess) return hip_fail(e, "finalize kernel");
-  return MPBP_OK;
+  return debug_check(plan, s, MPBP_OK);
 }
 
 mpbp_status mpbp_step(mpbp_plan plan, float* u, float* chi, float* alpha, const float* grad_u,

@@ -4,6 +4,16 @@
 
 namespace mpbp {
 
+// Device-side bounds checks of the projection and the back-projection, compiled in with
+// MPBP_DEBUG (the debug library): an index outside its buffer sets a bit of the plan's
+// status word (*dbg) and the access is skipped; the host reads the word after the call.
+enum { kDbgAccumulator = 1, kDbgObject = 2, kDbgSlot = 4, kDbgFrameList = 8, kDbgRunSum = 16 };
+#ifdef MPBP_DEBUG
+#define MPBP_CHECK(dbg, cond, bit) ((cond) ? true : (atomicOr((dbg), (unsigned)(bit)), false))
+#else
+#define MPBP_CHECK(dbg, cond, bit) true
+#endif
+
 // Per-peak constants, built on the host from the plan's tables.
 struct PeakDev {
   int D;            // detector / exit-wave window
@@ -56,6 +66,8 @@ struct FrameArgs {
   int runs;                // 1: project from the run sums (one probe, rounded offsets)
   int acc_pix;             // LDS footprint accumulator of the projection: the plan's largest
                            // fy * fx, rounded up to a multiple of 4
+  int n_runs;              // runs over all peaks (the run sums' planes)
+  unsigned* dbg;           // status word of the bounds checks (MPBP_DEBUG)
   const int2* roff;        // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
 };
 
@@ -82,6 +94,8 @@ struct GradArgs {
                              // where it applies
   float* rs;                 // complex64 [sum of nruns][ny][nx]: the frame sums per run
   long long nlat;            // ny * nx
+  int n_runs;                // runs over all peaks
+  unsigned* dbg;             // status word of the bounds checks (MPBP_DEBUG)
   const int* zrun;           // [M][nz] run of each slice (consecutive slices of equal offset)
   const int2* roff;          // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
   float* grad_u;

@@ -98,8 +98,10 @@ __device__ void project_body(const FrameArgs& A, const PeakDev& pk, int fid, cpl
 #pragma unroll
       for (int i = 0; i < kProjE; ++i) {
         if ((i + 1) * NT <= np2 || tid + NT * i < np2) {   // uniform when every lane has a pixel
-          cplx* q = acc + fo[i] + to;
-          *q = cadd(*q, w[tp][i]);
+          if (MPBP_CHECK(A.dbg, (unsigned)(fo[i] + to) < (unsigned)(fy * fx), kDbgAccumulator)) {
+            cplx* q = acc + fo[i] + to;
+            *q = cadd(*q, w[tp][i]);
+          }
         }
       }
     }
@@ -205,7 +207,8 @@ __device__ void project_runs_body(const FrameArgs& A, const PeakDev& pk, int fid
     cplx buf[G][kProjE];
 #pragma unroll
     for (int g = 0; g < G; ++g) {   // run index clamped past the last run
-      const int k = __builtin_amdgcn_readfirstlane(k0 + g < nr ? k0 + g : nr - 1);
+      int k = __builtin_amdgcn_readfirstlane(k0 + g < nr ? k0 + g : nr - 1);
+      if (!MPBP_CHECK(A.dbg, k >= 0 && pk.run_base + k < A.n_runs, kDbgRunSum)) k = 0;
       const char* Sk = reinterpret_cast<const char*>(S + (long long)k * plane);
 #pragma unroll
       for (int i = 0; i < kProjE; ++i) buf[g][i] = *reinterpret_cast<const cplx*>(Sk + off[i]);
@@ -218,8 +221,10 @@ __device__ void project_runs_body(const FrameArgs& A, const PeakDev& pk, int fid
 #pragma unroll
         for (int i = 0; i < kProjE; ++i) {
           if ((i + 1) * NT <= np2 || tid + NT * i < np2) {   // uniform when every lane has a pixel
-            cplx* q = acc + fo[i] + d;
-            *q = cadd(*q, cmul(pv[i], buf[g][i]));
+            if (MPBP_CHECK(A.dbg, (unsigned)(fo[i] + d) < (unsigned)(fy * fx), kDbgAccumulator)) {
+              cplx* q = acc + fo[i] + d;
+              *q = cadd(*q, cmul(pv[i], buf[g][i]));
+            }
           }
         }
       }

@@ -1,0 +1,93 @@
+"""Runs every code path of the bounds-checked debug library (libmpbp_debug.so, selected
+with MPBP_LIBRARY) on the GPU: a compute call whose device-side bounds check fires
+returns MPBP_ERR_INTERNAL, which raises here.  Used by tests/test_gpu_debug_checks.py in
+a child process; prints "ok" at the end."""
+import dataclasses
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import torch  # noqa: E402
+
+from oracle import mpbp_oracle as O  # noqa: E402
+from paper_2312_14907_amd import binding as B  # noqa: E402
+from synth import get_config, make_fields, make_problem, photon_rng, poisson_counts  # noqa: E402
+from synth.inputs import incident_probe_3d  # noqa: E402
+from tests.conftest import ragged  # noqa: E402
+
+assert os.path.basename(B.LIB_PATH) == "libmpbp_debug.so", B.LIB_PATH
+
+
+def d(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def run(prob, f, y, flags=0, options=(), frames=None, probe=None, u=None, static=False):
+    plan = B.Plan(prob, 0, flags=flags)
+    for k, v in options:
+        plan.mpbp_set_option(k, v)
+    u = (f["u"] + f["delta"]).astype(np.float32) if u is None else u
+    chi = f["chi"]
+    if flags & B.MPBP_Z_TIED:
+        u, chi = u[:, :1], chi[:1]
+    pr = f["probe"] if probe is None else probe
+    du, dc, da, dp, dy = d(u), d(chi), d(f["alpha"]), d(pr), d(y)
+    gu, gc, ga = torch.empty_like(du), torch.empty_like(dc), torch.empty_like(da)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda:0")
+    call = plan.mpbp_loss_grad_static if static else plan.mpbp_loss_grad
+    call(du, dc, da, dp, dy, gu, gc, ga, frames=frames, loss=loss)
+    mi = torch.zeros(plan.intensity_size, dtype=torch.float32, device="cuda:0")
+    if not static:
+        plan.mpbp_forward(du, dc, da, dp, dy, frames=frames, loss=loss, model_intensity=mi)
+    torch.cuda.synchronize()
+    plan.close()
+    return float(loss.item()), gu.cpu().numpy()
+
+
+def workload(name, noisy=True):
+    cfg = get_config(name)
+    prob = make_problem(cfg)
+    f = make_fields(cfg, prob)
+    inten = ragged(O.model_intensity(f["u"], f["chi"], f["alpha"], f["probe"], prob))
+    y = poisson_counts(photon_rng(cfg), inten) if (noisy and cfg["noise"]) else inten.astype(np.float32)
+    return prob, f, y
+
+
+prob, f, y = workload("c1_tiny")
+lin = dataclasses.replace(prob, shear_linear=True)
+p3 = np.stack([incident_probe_3d(f["probe"][m], prob.nz, (0.2, -0.3)) for m in range(prob.n_peaks)])
+cases = [
+    ("c1 fused", dict()),
+    ("c1 per slice", dict(options=[(B.MPBP_OPT_RUNS, 0)])),
+    ("c1 plain", dict(options=[(B.MPBP_OPT_PATH, 1)])),
+    ("c1 minibatch", dict(frames=list(range(3, 70, 4)))),
+    ("c1 z-tied", dict(flags=B.MPBP_Z_TIED)),
+    ("c1 3d probe", dict(flags=B.MPBP_PROBE_3D, probe=p3)),
+    ("c1 no-alloc", dict(static=True)),
+    ("c1 graph off, batch 16", dict(options=[(B.MPBP_OPT_GRAPH, 0), (B.MPBP_OPT_GRAD_BATCH, 16)])),
+]
+ref = O.loss_grad((f["u"] + f["delta"]).astype(np.float32), f["chi"], f["alpha"], f["probe"], y, prob)
+for name, kw in cases:
+    loss, gu = run(prob, f, y, **kw)
+    print(name, loss, flush=True)
+    if name in ("c1 fused", "c1 per slice", "c1 plain", "c1 no-alloc"):
+        assert abs(loss - ref["loss"]) <= 1e-5 * ref["loss"], (name, loss, ref["loss"])
+        assert np.linalg.norm(gu.reshape(ref["grad_u"].shape) - ref["grad_u"]) <= 1e-3 * np.linalg.norm(ref["grad_u"])
+loss, _ = run(lin, f, y, flags=B.MPBP_SHEAR_LINEAR)
+print("c1 interpolated offsets", loss, flush=True)
+for name in ("c2_forward", "c4_batch", "c6_paper100"):
+    cfg = get_config(name)
+    prob = make_problem(cfg)
+    f = make_fields(cfg, prob)
+    rng = np.random.default_rng(cfg["seed"])
+    y = np.concatenate([rng.poisson(3.0, int(prob.det[m]) ** 2 * int(prob.scan_n[m].prod())).astype(np.float32)
+                        for m in range(prob.n_peaks)])
+    for opts in ([], [(B.MPBP_OPT_RUNS, 0)]):
+        loss, _ = run(prob, f, y, options=opts)
+        print(name, opts, loss, flush=True)
+        assert np.isfinite(loss)
+print("ok", flush=True)
