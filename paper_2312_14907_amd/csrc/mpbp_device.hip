@@ -68,10 +68,23 @@ __global__ __launch_bounds__(256) void k_runsum(const float* __restrict__ u, con
   const long long p = (long long)blockIdx.x * 256 + tid;
   if (p >= nlat) return;   // (no barriers below: each lane's sums are its own)
   const long long us = tied ? nlat : (long long)nz * nlat;   // field component stride
-  for (int z = 0; z < nz; ++z) {
-    const long long vi = tied ? p : (long long)z * nlat + p;
-    const float ux = u[vi], uy = u[us + vi], uz = u[2 * us + vi];
-    const float ch = chi[vi];
+  constexpr int ZB = 4;   // slices whose fields are loaded together
+  for (int z0 = 0; z0 < nz; z0 += ZB) {
+    float fu[ZB][3], fc[ZB];
+#pragma unroll
+    for (int i = 0; i < ZB; ++i) {
+      const long long vi = tied ? p : (long long)min(z0 + i, nz - 1) * nlat + p;
+      fu[i][0] = u[vi];
+      fu[i][1] = u[us + vi];
+      fu[i][2] = u[2 * us + vi];
+      fc[i] = chi[vi];
+    }
+#pragma unroll
+    for (int i = 0; i < ZB; ++i) {
+    const int z = z0 + i;
+    if (z >= nz) break;   // uniform
+    const float ux = fu[i][0], uy = fu[i][1], uz = fu[i][2];
+    const float ch = fc[i];
     for (int m = 0; m < n_peaks; ++m) {
       const float gx = peaks[m].gx, gy = peaks[m].gy, gz = peaks[m].gz;
       const float phi = fmaf(gz, uz, fmaf(gy, uy, gx * ux));   // as k_object
@@ -88,6 +101,7 @@ __global__ __launch_bounds__(256) void k_runsum(const float* __restrict__ u, con
         reinterpret_cast<float2*>(rsum)[(long long)(peaks[m].run_base + k) * nlat + p] = cur;
       else
         acc[m][tid] = cur;
+    }
     }
   }
 }
@@ -536,7 +550,48 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_chain(GradArgs A) {
   float tg[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int m = 0; m < kMaxPeaksDev; ++m) ap[m] = 0.f;
-  if (on) {
+  if (on && !A.tied) {
+    // kBpZ slices: every load is issued before the first store (the compiler cannot move
+    // loads across the gradient stores, which might alias the fields as far as it knows)
+    float fu[kBpZ][3], fc[kBpZ], gu[kBpZ][3], gc[kBpZ];
+#pragma unroll
+    for (int i = 0; i < kBpZ; ++i) {
+      const long long vi = (long long)min(z0 + i, nz - 1) * A.nlat + p;
+      fu[i][0] = A.u[vi];
+      fu[i][1] = A.u[us + vi];
+      fu[i][2] = A.u[2 * us + vi];
+      fc[i] = A.chi[vi];
+      gu[i][0] = gu[i][1] = gu[i][2] = gc[i] = 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxPeaksDev; ++m) {
+      if (m < A.n_peaks) {   // uniform
+        const PeakDev pk = uniform_peak(A.peaks + m);
+        cplx g[kBpZ];
+#pragma unroll
+        for (int i = 0; i < kBpZ; ++i) {
+          int k = A.zrun[m * nz + min(z0 + i, nz - 1)];
+          if (!MPBP_CHECK(A.dbg, k >= 0 && pk.run_base + k < A.n_runs, kDbgRunSum)) k = -pk.run_base;
+          g[i] = G[(long long)(pk.run_base + k) * A.nlat + p];
+        }
+        const float al = A.alpha[m];
+#pragma unroll
+        for (int i = 0; i < kBpZ; ++i)
+          if (z0 + i < z1)
+            chain_voxel(pk, g[i], fu[i][0], fu[i][1], fu[i][2], fc[i], al, gu[i][0], gu[i][1], gu[i][2], gc[i], ap[m]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kBpZ; ++i) {
+      if (z0 + i < z1) {
+        const long long vi = (long long)(z0 + i) * A.nlat + p;
+        A.grad_u[vi] = gu[i][0];
+        A.grad_u[nvox + vi] = gu[i][1];
+        A.grad_u[2 * nvox + vi] = gu[i][2];
+        A.grad_chi[vi] = gc[i];
+      }
+    }
+  } else if (on) {   // z-tied: every slice of the lateral pixel, summed in the lane
     for (int z = z0; z < z1; ++z) {
       const long long vi = A.tied ? p : (long long)z * A.nlat + p;
       const float ux = A.u[vi], uy = A.u[us + vi], uz = A.u[2 * us + vi], ch = A.chi[vi];
