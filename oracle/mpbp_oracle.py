@@ -19,7 +19,9 @@ fields with multi-peak Bragg ptychography"):
   illuminated slices along the exit beam: slice z lands s_m(z) pixels over, an integer
   lateral shear, inside a D_m x D_m window centred on the probe support (with
   problem.shear_linear the offset stays fractional and the slice is spread over the four
-  neighbouring integer offsets with bilinear weights: R interpolating, section 2).  F is the
+  neighbouring integer offsets with bilinear weights: R interpolating, section 2; with
+  problem.lateral_map, R rotates and scales each slice into the peak's detector frame and
+  interpolates it bilinearly onto the exit-wave pixels, see exit_wave_mapped).  F is the
   orthonormal 2D DFT with kernel exp(-2 pi i k.x / D), DC at index 0;
 * eq. (4): f = 1/2 sum_{m,j} || I^{1/2} - y^{1/2} ||^2, summed (not averaged) over the
   listed frames as in the minibatch sums of eq. (11);
@@ -92,6 +94,98 @@ def scan_positions(scan_n, scan_step, scan_origin):
     return out
 
 
+def _lateral_map(problem):
+    lm = getattr(problem, "lateral_map", None)
+    return None if lm is None else np.asarray(lm, dtype=np.float64)
+
+
+def mapped_geometry(problem, m):
+    """R with a detector map (problem.lateral_map[m] = M, 2 x 2): the probe window's
+    lateral point (a, b) of slice z lands on the exit-wave point
+        q = M ((a, b) - n/2) + (c + n/2) + (z - nz//2) t_m
+    (n the probe support, c the window offset of the support, t_m the exit-beam offset per
+    slice, in exit-wave pixels), so the support's centre lands where the unmapped model
+    puts it, and M = identity gives the interpolated-offset model.  Returns (M, M^-1, the
+    centre c + n/2, the offsets (z - nz//2) t_m [nz][2])."""
+    mat = _lateral_map(problem)[m]
+    n = problem.probe_n
+    centre = window_offset(int(problem.det[m]), n) + n / 2.0
+    dz = np.arange(problem.nz, dtype=np.float64) - problem.nz // 2
+    offs = dz[:, None] * np.asarray(problem.shear[m], dtype=np.float64)[None, :]
+    return mat, np.linalg.inv(mat), centre, offs
+
+
+def mapped_extent(problem, m):
+    """Smallest and largest exit-wave pixel (per axis) that a mapped slice can reach: the
+    images of the support's corners widened by one sample (the interpolation's reach)."""
+    mat, _, centre, offs = mapped_geometry(problem, m)
+    n = problem.probe_n
+    corners = np.array([[a, b] for a in (-1.0, float(n)) for b in (-1.0, float(n))]) - n / 2.0
+    pts = (corners @ mat.T)[None, :, :] + centre + offs[:, None, :]
+    return np.floor(pts.min(axis=(0, 1))).astype(np.int64), np.ceil(pts.max(axis=(0, 1))).astype(np.int64)
+
+
+def _mapped_taps(problem, m, z, det):
+    """For every exit-wave pixel q of the D x D window: the pre-image p = M^-1 (q - centre -
+    offset_z) + n/2 in the probe window's coordinates, as the four bilinear taps
+    (floor(p) + (dy, dx)) and their weights.  Returns (iy [4][D][D], ix, w)."""
+    _, minv, centre, offs = mapped_geometry(problem, m)
+    n = problem.probe_n
+    qy, qx = np.meshgrid(np.arange(det, dtype=np.float64), np.arange(det, dtype=np.float64), indexing="ij")
+    ry, rx = qy - centre - offs[z, 0], qx - centre - offs[z, 1]
+    py = minv[0, 0] * ry + minv[0, 1] * rx + n / 2.0
+    px = minv[1, 0] * ry + minv[1, 1] * rx + n / 2.0
+    y0, x0 = np.floor(py), np.floor(px)
+    fy, fx = py - y0, px - x0
+    iy = np.stack([y0, y0, y0 + 1, y0 + 1]).astype(np.int64)
+    ix = np.stack([x0, x0 + 1, x0, x0 + 1]).astype(np.int64)
+    w = np.stack([(1 - fy) * (1 - fx), (1 - fy) * fx, fy * (1 - fx), fy * fx])
+    return iy, ix, w
+
+
+def exit_wave_mapped(o_m, probe_m, py, px, problem, m):
+    """R diag(P) S O for one frame with the detector map of peak m: slice z's illuminated
+    object, sampled on the probe window's n x n grid (zero off the support and off the
+    object grid), is interpolated bilinearly at each exit-wave pixel's pre-image, and the
+    slices are summed (the projection along k_f)."""
+    nz, ny, nx = o_m.shape
+    n = probe_m.shape[-1]
+    det = int(problem.det[m])
+    psi = np.zeros((det, det), dtype=np.complex128)
+    a0, a1 = _support_block(py, n, ny)
+    b0, b1 = _support_block(px, n, nx)
+    if a1 <= a0 or b1 <= b0:
+        return psi
+    for z in range(nz):
+        ill = np.zeros((n, n), dtype=np.complex128)
+        ill[a0:a1, b0:b1] = _probe_slice(probe_m, z)[a0:a1, b0:b1] * o_m[z, py + a0:py + a1, px + b0:px + b1]
+        iy, ix, w = _mapped_taps(problem, m, z, det)
+        inside = (iy >= 0) & (iy < n) & (ix >= 0) & (ix < n)
+        vals = ill[np.clip(iy, 0, n - 1), np.clip(ix, 0, n - 1)]
+        psi += np.sum(np.where(inside, w * vals, 0.0), axis=0)
+    return psi
+
+
+def back_project_mapped(g_psi, probe_m, py, px, problem, m, g_o_m):
+    """Adjoint of exit_wave_mapped, accumulated into g_o_m in place: every exit-wave
+    pixel's gradient goes back to its four taps with the same weights, then
+    g_O[z, py + a, px + b] += conj(P_z[a, b]) (sum over those contributions)."""
+    nz, ny, nx = g_o_m.shape
+    n = probe_m.shape[-1]
+    det = g_psi.shape[0]
+    a0, a1 = _support_block(py, n, ny)
+    b0, b1 = _support_block(px, n, nx)
+    if a1 <= a0 or b1 <= b0:
+        return
+    for z in range(nz):
+        iy, ix, w = _mapped_taps(problem, m, z, det)
+        inside = (iy >= 0) & (iy < n) & (ix >= 0) & (ix < n)
+        acc = np.zeros((n, n), dtype=np.complex128)
+        np.add.at(acc, (iy[inside], ix[inside]), (w * g_psi[None, :, :])[inside])
+        g_o_m[z, py + a0:py + a1, px + b0:px + b1] += (
+            np.conj(_probe_slice(probe_m, z)[a0:a1, b0:b1]) * acc[a0:a1, b0:b1])
+
+
 class FootprintError(ValueError):
     """The sheared probe support of some slice leaves the detector window."""
 
@@ -125,10 +219,15 @@ def tables(problem):
             shear[m], frac[m] = shear_table_linear(problem.nz, problem.shear[m])
         else:
             shear[m] = shear_table(problem.nz, problem.shear[m])
-        lo = shear[m].min(axis=0)
-        hi = shear[m].max(axis=0) + (1 if linear else 0)
-        if (c + lo < 0).any() or (c + problem.probe_n - 1 + hi > det - 1).any():
-            raise FootprintError(f"peak {m}: sheared support leaves the {det}x{det} window")
+        if _lateral_map(problem) is not None:
+            qlo, qhi = mapped_extent(problem, m)
+            if (qlo < 0).any() or (qhi > det - 1).any():
+                raise FootprintError(f"peak {m}: mapped support leaves the {det}x{det} window")
+        else:
+            lo = shear[m].min(axis=0)
+            hi = shear[m].max(axis=0) + (1 if linear else 0)
+            if (c + lo < 0).any() or (c + problem.probe_n - 1 + hi > det - 1).any():
+                raise FootprintError(f"peak {m}: sheared support leaves the {det}x{det} window")
         pos = scan_positions(problem.scan_n[m], problem.scan_step[m], problem.scan_origin[m])
         scans.append(pos)
         peak_of.append(np.full(len(pos), m, dtype=np.int64))
@@ -289,6 +388,19 @@ def _frac(tab, m):
     return None if tab["shear_frac"] is None else tab["shear_frac"][m]
 
 
+def _exit(o_m, probe_m, py, px, tab, problem, m):
+    if _lateral_map(problem) is not None:
+        return exit_wave_mapped(o_m, probe_m, py, px, problem, m)
+    return exit_wave(o_m, probe_m, py, px, tab["shear"][m], int(problem.det[m]), _frac(tab, m))
+
+
+def _back(g_psi, probe_m, py, px, tab, problem, m, g_o_m):
+    if _lateral_map(problem) is not None:
+        back_project_mapped(g_psi, probe_m, py, px, problem, m, g_o_m)
+    else:
+        back_project(g_psi, probe_m, py, px, tab["shear"][m], g_o_m, _frac(tab, m))
+
+
 def model_intensity(u, chi, alpha, probe, problem, frames=None, background=None):
     """I_{m,j} of eq. (2) for the listed frames: list of D x D float64 arrays."""
     tab = tables(problem)
@@ -298,7 +410,7 @@ def model_intensity(u, chi, alpha, probe, problem, frames=None, background=None)
     for fid in _frame_list(problem, frames):
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
-        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]), _frac(tab, m))
+        psi = _exit(obj[m], probe[m], py, px, tab, problem, m)
         inten = np.abs(far_field(psi)) ** 2
         if background is not None:
             inten = inten + frame_data(background, tab, problem, fid)
@@ -318,7 +430,7 @@ def loss(u, chi, alpha, probe, y, problem, frames=None, background=None):
     for fid in _frame_list(problem, frames):
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
-        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], int(problem.det[m]), _frac(tab, m))
+        psi = _exit(obj[m], probe[m], py, px, tab, problem, m)
         b = None if background is None else frame_data(background, tab, problem, fid)
         f, _ = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid), b)
         per.append(f)
@@ -336,11 +448,11 @@ def object_gradient(u, chi, alpha, probe, y, problem, frames=None, background=No
         m = int(tab["peak_of_frame"][fid])
         py, px = (int(v) for v in tab["scan"][fid])
         det = int(problem.det[m])
-        psi = exit_wave(obj[m], probe[m], py, px, tab["shear"][m], det, _frac(tab, m))
+        psi = _exit(obj[m], probe[m], py, px, tab, problem, m)
         b = None if background is None else frame_data(background, tab, problem, fid)
         f, grad_ff = amplitude_residual(far_field(psi), frame_data(y, tab, problem, fid), b)
         per.append(f)
-        back_project(far_field_adjoint(grad_ff), probe[m], py, px, tab["shear"][m], g_obj[m], _frac(tab, m))
+        _back(far_field_adjoint(grad_ff), probe[m], py, px, tab, problem, m, g_obj[m])
     return float(sum(per)), per, g_obj, obj
 
 

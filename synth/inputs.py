@@ -37,6 +37,9 @@ class Problem:
     scan_origin: np.ndarray
     photons: list = field(default_factory=list)
     shear_linear: bool = False   # exit-beam offsets interpolated linearly (not rounded)
+    # per-peak map of the probe window's lateral voxel coordinates to exit-wave pixels
+    # ([M][2][2]: the detector frame's in-plane rotation and pixel size), or None
+    lateral_map: np.ndarray = None
 
     @property
     def n_peaks(self):
@@ -262,7 +265,7 @@ def band_problem(problem, row0, row1):
     band = Problem(problem.name + f"_rows{row0}-{row1}", problem.nz, hi - lo, problem.nx, problem.probe_n,
                    problem.g.copy(), problem.shear.copy(), problem.det.copy(), problem.scan_n.copy(),
                    problem.scan_step.copy(), problem.scan_origin.copy(), list(problem.photons),
-                   problem.shear_linear)
+                   problem.shear_linear, problem.lateral_map)
     frames = []
     base = 0
     for m, (r0, r1) in enumerate(rows):
@@ -272,6 +275,15 @@ def band_problem(problem, row0, row1):
         frames += [base + iy * cols + ix for iy in range(r0, r1) for ix in range(cols)]
         base += int(problem.scan_n[m, 0]) * cols
     return band, lo, hi, frames
+
+
+def detector_map(pixel_ratio, angle):
+    """The 2 x 2 map of one peak's R from the probe window's lateral voxel coordinates
+    (y, x) to its exit-wave pixels: a rotation by `angle` (radians, the detector frame's
+    in-plane orientation about the exit beam) scaled by `pixel_ratio` = voxel pitch /
+    exit-wave pixel pitch (the Nyquist pixel of that peak's detector geometry)."""
+    c, s = math.cos(angle), math.sin(angle)
+    return pixel_ratio * np.array([[c, -s], [s, c]], dtype=np.float64)
 
 
 def frame_order(n_frames, seed, epochs):
