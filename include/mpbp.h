@@ -72,6 +72,9 @@ typedef struct {
   int32_t scan_n[2];         /* raster (rows, cols); local frame j = row * cols + col      */
   int32_t scan_step[2];      /* raster step (rows, cols), voxels                           */
   int32_t scan_origin[2];    /* object voxel of the probe support's top-left, frame 0     */
+  double  map[4];            /* with MPBP_DETECTOR_MAP: the 2 x 2 map M (row-major) of the
+                                probe window's lateral voxel coordinates (y, x) to exit-
+                                wave pixels of this peak's detector frame; ignored otherwise */
 } mpbp_peak;
 
 typedef struct {
@@ -79,7 +82,8 @@ typedef struct {
   int32_t probe_n;           /* probe support (square)                                     */
   int32_t n_peaks;
   const mpbp_peak* peaks;    /* (host) [n_peaks]; copied by mpbp_plan_create               */
-  uint32_t flags;            /* 0, or any of MPBP_Z_TIED, MPBP_PROBE_3D, MPBP_SHEAR_LINEAR */
+  uint32_t flags;            /* 0, or any of MPBP_Z_TIED, MPBP_PROBE_3D, MPBP_SHEAR_LINEAR,
+                                MPBP_DETECTOR_MAP                                          */
 } mpbp_problem;
 
 /* Problem flags.
@@ -101,6 +105,20 @@ enum { MPBP_PROBE_3D = 2 };
    weights (1 - f_y or f_y) (1 - f_x or f_x) (rounded offsets otherwise).  mpbp_tables
    then reports s0; footprints are one pixel wider per axis. */
 enum { MPBP_SHEAR_LINEAR = 4 };
+/* MPBP_DETECTOR_MAP: R rotates and scales each slice into the peak's detector frame and
+   interpolates it there (section 2: the detector frames differ per Bragg peak, and so may
+   the exit-wave pixel size that each detector's sampling dictates).  With M_m = peaks[m].map
+   (invertible), slice z's probe-window point (a, b) lands on the exit-wave point
+     q = M_m ((a, b) - probe_n/2) + (c_m + probe_n/2) + (z - nz/2) t_m
+   (t_m = shear, in exit-wave pixels), and each exit-wave pixel takes the bilinear
+   interpolation of the illuminated slice P_z . O_z (zero off the probe support and the
+   object) at its pre-image; the slices are summed.  M_m = identity gives the model of
+   MPBP_SHEAR_LINEAR.  The footprint is the bounding box of the mapped support widened by
+   one sample; MPBP_ERR_FOOTPRINT if it leaves the window.  May be combined with
+   MPBP_Z_TIED and MPBP_PROBE_3D, not with MPBP_SHEAR_LINEAR; batched fused path only
+   (the plain path returns MPBP_ERR_UNSUPPORTED).  mpbp_tables still reports the rounded
+   offsets. */
+enum { MPBP_DETECTOR_MAP = 8 };
 
 /* Options of mpbp_set_option / mpbp_get_option. */
 enum {

@@ -26,6 +26,7 @@ MPBP_OPT_RUNS = 7
 MPBP_Z_TIED = 1
 MPBP_PROBE_3D = 2
 MPBP_SHEAR_LINEAR = 4
+MPBP_DETECTOR_MAP = 8
 STAGES = ("object", "frames", "grad", "finalize", "plain", "project")
 
 EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_intensity_size",
@@ -38,7 +39,7 @@ EXPORTED = ("mpbp_plan_create", "mpbp_plan_destroy", "mpbp_num_frames", "mpbp_in
 class mpbp_peak(ctypes.Structure):
     _fields_ = [("g", ctypes.c_double * 3), ("shear", ctypes.c_double * 2), ("det", ctypes.c_int32),
                 ("scan_n", ctypes.c_int32 * 2), ("scan_step", ctypes.c_int32 * 2),
-                ("scan_origin", ctypes.c_int32 * 2)]
+                ("scan_origin", ctypes.c_int32 * 2), ("map", ctypes.c_double * 4)]
 
 
 class mpbp_adam(ctypes.Structure):
@@ -189,6 +190,10 @@ def make_problem_struct(problem, flags=0):
             pk.scan_step[c] = int(problem.scan_step[k][c])
             pk.scan_origin[c] = int(problem.scan_origin[k][c])
         pk.det = int(problem.det[k])
+        lm = getattr(problem, "lateral_map", None)
+        mk = np.eye(2) if lm is None else np.asarray(lm[k], dtype=np.float64)
+        for c in range(4):
+            pk.map[c] = float(mk.reshape(4)[c])
     prob = mpbp_problem(int(problem.nz), int(problem.ny), int(problem.nx), int(problem.probe_n), m,
                         ctypes.cast(peaks, ctypes.POINTER(mpbp_peak)), int(flags))
     prob._peaks_keepalive = peaks

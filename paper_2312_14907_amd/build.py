@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmpbp.so")
 SOURCES = ["mpbp_frames_256.hip", "mpbp_frames_192.hip", "mpbp_frames_128.hip", "mpbp_frames_96.hip",
-           "mpbp_frames_64.hip", "mpbp_frames_32.hip", "mpbp_frames_150.hip", "mpbp_device.hip", "mpbp_plain.hip", "mpbp_unwrap.hip", "mpbp_host.cpp"]
+           "mpbp_frames_64.hip", "mpbp_frames_32.hip", "mpbp_frames_150.hip", "mpbp_device.hip", "mpbp_map.hip", "mpbp_plain.hip", "mpbp_unwrap.hip", "mpbp_host.cpp"]
 ARCH = os.environ.get("MPBP_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.

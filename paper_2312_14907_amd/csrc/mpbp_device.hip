@@ -19,6 +19,7 @@
 #include "mpbp_dft.hpp"
 #include "mpbp_frame.hpp"
 #include "mpbp_project.hpp"
+#include "mpbp_chain.hpp"
 #include "mpbp_kernels.hpp"
 #include "mpbp_launch.hpp"
 
@@ -107,63 +108,6 @@ __global__ __launch_bounds__(256) void k_runsum(const float* __restrict__ u, con
 }
 
 // -------------------------------------------- gather back-projection + chain rule ---
-__device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
-  int q = a / b;
-  return (a % b != 0 && a < 0) ? q - 1 : q;
-}
-
-__device__ __forceinline__ float block_sum_f(float v, float* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  float s = 0.f;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-  __syncthreads();
-  return s;
-}
-
-// acc + a conj(b) with the two fused multiply-adds per component written out, so that
-// every instance of the gradient kernel rounds the frame sums the same way (left to the
-// compiler, the contraction into FMAs differs between instances).
-__device__ __forceinline__ cplx cmulc_acc(cplx acc, cplx a, cplx b) {
-  return {fmaf(a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(a.y, b.x, fmaf(-a.x, b.y, acc.y))};
-}
-
-// Chain rule of one voxel and peak through O_m = alpha_m chi exp(i phi), phi = G_m . u,
-// for the frame sum g of conj(P) g_psi: adds G_m Im(g conj(O)) to du, alpha_m Re(conj(g)
-// e^{i phi}) to dchi and chi Re(conj(g) e^{i phi}) to the alpha partial.  Every
-// product and sum is written out, so both gradient kernels round it identically.
-__device__ __forceinline__ void chain_voxel(const PeakDev& pk, cplx g, float ux, float uy, float uz, float ch,
-                                            float al, float& gux, float& guy, float& guz, float& gch, float& ap) {
-  const float phi = fmaf(pk.gz, uz, fmaf(pk.gy, uy, pk.gx * ux));   // as k_object
-  float s, c;
-  sincosf(phi, &s, &c);                                             // as k_object
-  const float re = fmaf(g.y, s, g.x * c);                           // Re(conj(g) e^{i phi})
-  const float dphi = (al * ch) * fmaf(g.y, c, -(g.x * s));          // Im(g conj(O))
-  gux = fmaf(pk.gx, dphi, gux);
-  guy = fmaf(pk.gy, dphi, guy);
-  guz = fmaf(pk.gz, dphi, guz);
-  gch = fmaf(al, re, gch);
-  ap = fmaf(ch, re, ap);
-}
-
-// The peak record is the same for every lane: read it once and pass each word through
-// readfirstlane, so that the raster walk and the slot bases derived from it live in
-// scalar registers (a plain load from the table leaves them in vector registers, since
-// the compiler cannot prove the table unchanged by the kernel's own stores).
-__device__ __forceinline__ PeakDev uniform_peak(const PeakDev* p) {
-  static_assert(sizeof(PeakDev) % 4 == 0, "PeakDev is read as 32-bit words");
-  constexpr int kWords = sizeof(PeakDev) / 4;
-  int w[kWords];
-  __builtin_memcpy(w, p, sizeof(PeakDev));
-#pragma unroll
-  for (int i = 0; i < kWords; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
-  PeakDev pk;
-  __builtin_memcpy(&pk, w, sizeof(PeakDev));
-  return pk;
-}
-
 // B: frames whose footprint gradients are read per step of the frame walk.  TX: tile
 // width (TX x TY voxels per slice, TX * TY = 64: one wavefront per slice).  The tile
 // grid starts at (tile_oy, tile_ox) <= 0, so that a grid aligned with a raster of step
@@ -846,6 +790,7 @@ hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipSt
 bool frame_instance(int D, int FB) { return frames_op(2, D, FB, nullptr, 0, nullptr) == hipSuccess; }
 
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s) {
+  if (a.mapz) return launch_project_map(a, s);
   const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
 #define MPBP_PROJ(g)                                                                          \
@@ -930,9 +875,10 @@ hipError_t prepare_kernels() {
   return e;
 }
 
-bool grad_uses_runs(const GradArgs& a) { return a.runs && !a.probe3 && !a.shw; }
+bool grad_uses_runs(const GradArgs& a) { return a.runs && !a.probe3 && !a.shw && !a.mapz; }
 
 int grad_partials(const GradArgs& a) {
+  if (a.mapz) return grad_map_partials(a);
   if (!grad_uses_runs(a)) return a.tiles_x * a.tiles_y;
   return (int)nblk(a.tied ? a.nlat : a.nlat * ((a.nz + kBpZ - 1) / kBpZ), kBpThreads);
 }
@@ -942,6 +888,7 @@ int grad_effective_batch(int batch, bool runs) {
 }
 
 hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, hipStream_t s) {
+  if (a.mapz) return launch_grad_map(a, s);
   const unsigned grid = (unsigned)(((a.tiles_x * a.tiles_y + 7) / 8) * 8);
   if (grad_uses_runs(a)) {
     const int b = grad_effective_batch(batch, true);

@@ -132,6 +132,8 @@ struct mpbp_plan_t {
   int probe3 = 0;                  // MPBP_PROBE_3D: probe [M][nz][np][np]
   int linear = 0;                  // MPBP_SHEAR_LINEAR: fractional exit-beam offsets
   std::vector<float> shw;          // [M][nz][2] their fractions (MPBP_SHEAR_LINEAR)
+  int mapped = 0;                  // MPBP_DETECTOR_MAP: R interpolates in each detector frame
+  std::vector<float> mapz;         // [M][nz][2] window centre of slice z, footprint coordinates
   int64_t F = 0, ylen = 0;
   std::vector<mpbp_peak> peaks;
   std::vector<PeakDev> pdev;
@@ -184,6 +186,7 @@ struct mpbp_plan_t {
   int* d_zrun = nullptr;           // [M][nz] (the run gather of the gradient kernel)
   int* d_roff = nullptr;           // [M][nz][2]
   float* d_shw = nullptr;          // [M][nz][2] fractional offsets (MPBP_SHEAR_LINEAR)
+  float* d_mapz = nullptr;         // [M][nz][2] (MPBP_DETECTOR_MAP)
   int* d_order = nullptr;          // full-batch processing order
   int* d_list = nullptr;           // caller's list (subset calls)
   int* d_list_sorted = nullptr;    // the caller's list grouped by detector size
@@ -253,6 +256,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_zrun);
   (void)hipFree(p->d_roff);
   (void)hipFree(p->d_shw);
+  (void)hipFree(p->d_mapz);
   (void)hipFree(p->d_order);
   (void)hipFree(p->d_list);
   (void)hipFree(p->d_list_sorted);
@@ -274,12 +278,67 @@ void free_device(mpbp_plan_t* p) {
   if (p->h_uw_err) (void)hipHostFree(p->h_uw_err);
 }
 
+// MPBP_DETECTOR_MAP: the peak's map M and its inverse, the footprint (the bounding box,
+// over the slices, of the images of the support's corners (-1, -1) .. (n, n) taken
+// relative to the window centre c + n/2, moved by the slice offset (z - nz/2) t, and
+// rounded outwards: the interpolation reaches one sample beyond the support), and each
+// slice's window centre in footprint coordinates (mapz [nz][2]).
+mpbp_status map_footprint(const mpbp_peak& k, int m, int np, int nz, int zref, PeakDev& d, float* mapz) {
+  const double* M = k.map;
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(M[i]) || std::fabs(M[i]) > 1e3)
+      return fail(MPBP_ERR_INVALID, "peak %d: detector map not finite or above 1e3", m);
+  const double det = M[0] * M[3] - M[1] * M[2];
+  if (!(std::fabs(det) > 1e-6)) return fail(MPBP_ERR_INVALID, "peak %d: detector map is singular", m);
+  const double inv[4] = {M[3] / det, -M[1] / det, -M[2] / det, M[0] / det};
+  const double centre = (double)((k.det - np) / 2) + 0.5 * np;
+  double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+  for (int z = 0; z < nz; ++z) {
+    const double oy = (double)(z - zref) * k.shear[0], ox = (double)(z - zref) * k.shear[1];
+    for (double ca : {-1.0, (double)np})
+      for (double cb : {-1.0, (double)np}) {
+        const double ya = ca - 0.5 * np, yb = cb - 0.5 * np;
+        const double q[2] = {M[0] * ya + M[1] * yb + centre + oy, M[2] * ya + M[3] * yb + centre + ox};
+        for (int c = 0; c < 2; ++c) {
+          lo[c] = std::min(lo[c], q[c]);
+          hi[c] = std::max(hi[c], q[c]);
+        }
+      }
+  }
+  const double qlo[2] = {std::floor(lo[0]), std::floor(lo[1])}, qhi[2] = {std::ceil(hi[0]), std::ceil(hi[1])};
+  for (int c = 0; c < 2; ++c)
+    if (qlo[c] < 0 || qhi[c] > k.det - 1)
+      return fail(MPBP_ERR_FOOTPRINT, "peak %d: mapped support leaves the %dx%d window", m, k.det, k.det);
+  d.r0 = (int)qlo[0];
+  d.c0 = (int)qlo[1];
+  d.fy = (int)(qhi[0] - qlo[0]) + 1;
+  d.fx = (int)(qhi[1] - qlo[1]) + 1;
+  d.spany = std::max(0, d.fy - np);
+  d.spanx = std::max(0, d.fx - np);
+  for (int i = 0; i < 4; ++i) {
+    d.mm[i] = (float)M[i];
+    d.mi[i] = (float)inv[i];
+  }
+  // whole pixels within one sample of a point (per axis, plus one for float rounding)
+  d.ncy = (int)std::floor(2.0 * (std::fabs(M[0]) + std::fabs(M[1]))) + 3;
+  d.ncx = (int)std::floor(2.0 * (std::fabs(M[2]) + std::fabs(M[3]))) + 3;
+  for (int z = 0; z < nz; ++z) {
+    mapz[2 * z] = (float)(centre + (double)(z - zref) * k.shear[0] - d.r0);
+    mapz[2 * z + 1] = (float)(centre + (double)(z - zref) * k.shear[1] - d.c0);
+  }
+  return MPBP_OK;
+}
+
 // Build tables and per-peak constants on the host; validate the problem.
 mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   if (!pr) return fail(MPBP_ERR_INVALID, "problem is NULL");
-  if (pr->flags & ~(uint32_t)(MPBP_Z_TIED | MPBP_PROBE_3D | MPBP_SHEAR_LINEAR))
-    return fail(MPBP_ERR_INVALID, "unknown flags 0x%x (MPBP_Z_TIED, MPBP_PROBE_3D and MPBP_SHEAR_LINEAR are defined)",
+  if (pr->flags & ~(uint32_t)(MPBP_Z_TIED | MPBP_PROBE_3D | MPBP_SHEAR_LINEAR | MPBP_DETECTOR_MAP))
+    return fail(MPBP_ERR_INVALID,
+                "unknown flags 0x%x (MPBP_Z_TIED, MPBP_PROBE_3D, MPBP_SHEAR_LINEAR and MPBP_DETECTOR_MAP are defined)",
                 pr->flags);
+  if ((pr->flags & MPBP_DETECTOR_MAP) && (pr->flags & MPBP_SHEAR_LINEAR))
+    return fail(MPBP_ERR_INVALID, "MPBP_DETECTOR_MAP already interpolates the exit-beam offsets: "
+                "MPBP_SHEAR_LINEAR does not apply");
   if (pr->nz < 1 || pr->ny < 1 || pr->nx < 1)
     return fail(MPBP_ERR_SHAPE, "object grid must be positive (nz=%d ny=%d nx=%d)", pr->nz, pr->ny, pr->nx);
   if (pr->probe_n < 1) return fail(MPBP_ERR_SHAPE, "probe_n must be positive (%d)", pr->probe_n);
@@ -298,6 +357,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   p->tied = (pr->flags & MPBP_Z_TIED) ? (long long)pr->ny * pr->nx : 0;
   p->probe3 = (pr->flags & MPBP_PROBE_3D) ? 1 : 0;
   p->linear = (pr->flags & MPBP_SHEAR_LINEAR) ? 1 : 0;
+  p->mapped = (pr->flags & MPBP_DETECTOR_MAP) ? 1 : 0;
+  p->mapz.assign((size_t)pr->n_peaks * pr->nz * 2, 0.f);
   p->peaks.assign(pr->peaks, pr->peaks + pr->n_peaks);
   p->pdev.assign(p->M, PeakDev{});
   p->shear.assign((size_t)p->M * p->nz * 2, 0);
@@ -344,7 +405,7 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
       }
     }
     const int cw = (k.det - np) / 2;
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2 && !p->mapped; ++c)
       if (cw + lo[c] < 0 || cw + np - 1 + hi[c] > k.det - 1)
         return fail(MPBP_ERR_FOOTPRINT, "peak %d: sheared support leaves the %dx%d window", m, k.det, k.det);
     PeakDev& d = p->pdev[m];
@@ -356,6 +417,10 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
     d.spany = hi[0] - lo[0]; d.spanx = hi[1] - lo[1];
     d.r0 = cw + lo[0]; d.c0 = cw + lo[1];
     d.fy = np + d.spany; d.fx = np + d.spanx;
+    if (p->mapped) {
+      const mpbp_status st = map_footprint(k, m, np, p->nz, zref, d, &p->mapz[(size_t)m * p->nz * 2]);
+      if (st != MPBP_OK) return st;
+    }
     // runs of consecutive slices with equal offsets, and each run's footprint offset
     for (int z = 0, k = -1; z < p->nz; ++z) {
       const int* sz = &p->shear[((size_t)m * p->nz + z) * 2];
@@ -482,6 +547,10 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   {
     const long long lanes = (long long)p->ny * p->nx * (p->tied ? 1 : (p->nz + mpbp::kBpZ - 1) / mpbp::kBpZ);
     p->max_parts = std::max<long long>(p->max_tiles, (lanes + mpbp::kBpThreads - 1) / mpbp::kBpThreads);
+    if (p->mapped) {   // the detector-map back-projection: one partial per workgroup of voxels
+      const long long tasks = p->tied ? (long long)p->ny * p->nx : p->nvox;
+      p->max_parts = std::max<long long>(p->max_parts, (tasks + mpbp::kMapThreads - 1) / mpbp::kMapThreads);
+    }
   }
   p->sub_classes.reserve(p->classes.size());
   return MPBP_OK;
@@ -503,6 +572,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_peak_of, p->F);
   ALLOC(p->d_shear, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_shw, (size_t)p->M * p->nz * 2);
+  ALLOC(p->d_mapz, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_zrun, (size_t)p->M * p->nz);
   ALLOC(p->d_roff, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_order, p->F);
@@ -528,6 +598,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   if (e == hipSuccess) e = hipMemcpy(p->d_peak_of, p->peak_of.data(), p->peak_of.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_shear, p->shear.data(), p->shear.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_shw, p->shw.data(), p->shw.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_mapz, p->mapz.data(), p->mapz.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_zrun, p->zrun.data(), p->zrun.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_roff, p->roff.data(), p->roff.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), p->order.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -701,7 +772,7 @@ Work plan_work(mpbp_plan p) { return {p->d_obj, p->d_slots, p->d_gslots, p->d_fl
 
 // Projection and back-projection per run of equal exit-beam offset (one probe for all
 // slices, rounded offsets): the objects are then stored as run sums.
-bool uses_runs(mpbp_plan p) { return p->runs && !p->probe3 && !p->linear; }
+bool uses_runs(mpbp_plan p) { return p->runs && !p->probe3 && !p->linear && !p->mapped; }
 
 // The objects of eq. (1)/(3) into the workspace: per slice, or summed over each run.
 hipError_t launch_objects(mpbp_plan p, const Work& w, const float* u, const float* chi, const float* alpha,
@@ -739,6 +810,7 @@ mpbp::FrameArgs frame_args(mpbp_plan p, const Work& w, const float* y, const int
   a.n_runs = p->n_runs;
   a.dbg = p->d_dbg;
   a.roff = reinterpret_cast<const int2*>(p->d_roff);
+  a.mapz = p->mapped ? reinterpret_cast<const float2*>(p->d_mapz) : nullptr;
   return a;
 }
 
@@ -756,6 +828,10 @@ int bp_parts(mpbp_plan p) {
 }
 
 int grad_parts(mpbp_plan p) {
+  if (p->mapped) {
+    const long long tasks = p->tied ? (long long)p->ny * p->nx : p->nvox;
+    return (int)((tasks + mpbp::kMapThreads - 1) / mpbp::kMapThreads);
+  }
   if (uses_runs(p)) return bp_parts(p);
   return grad_tiling(p).nx * grad_tiling(p).ny;
 }
@@ -787,6 +863,7 @@ mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float
   g.dbg = p->d_dbg;
   g.zrun = p->d_zrun;
   g.roff = reinterpret_cast<const int2*>(p->d_roff);
+  g.mapz = p->mapped ? reinterpret_cast<const float2*>(p->d_mapz) : nullptr;
   g.grad_u = grad_u; g.grad_chi = grad_chi;
   g.alpha_part = w.apart;
   return g;
@@ -1168,13 +1245,16 @@ static mpbp_status debug_check(mpbp_plan_t* p, hipStream_t s, mpbp_status st) {
 // The plan's choices, under MPBP_TRACE.
 static void trace_plan(const mpbp_plan_t* p, const char* when) {
   if (!trace_on()) return;
-  trace("plan %p (%s): grid %dx%dx%d, probe %d, %d peaks, %lld frames, flags%s%s%s; device %d", (void*)p, when,
+  trace("plan %p (%s): grid %dx%dx%d, probe %d, %d peaks, %lld frames, flags%s%s%s%s; device %d", (void*)p, when,
         p->nz, p->ny, p->nx, p->np, p->M, (long long)p->F, p->tied ? " z-tied" : "", p->probe3 ? " probe-3d" : "",
-        p->linear ? " shear-linear" : "", p->device);
+        p->linear ? " shear-linear" : "", p->mapped ? " detector-map" : "", p->device);
   for (int m = 0; m < p->M; ++m) {
     const PeakDev& d = p->pdev[m];
-    trace("  peak %d: D %d, footprint %dx%d, %d runs of equal offset over %d slices, raster %dx%d", m, d.D, d.fy,
-          d.fx, d.nruns, p->nz, d.rows, d.cols);
+    trace("  peak %d: D %d, footprint %dx%d at (%d, %d), %d runs of equal offset over %d slices, raster %dx%d", m,
+          d.D, d.fy, d.fx, d.r0, d.c0, d.nruns, p->nz, d.rows, d.cols);
+    if (p->mapped)
+      trace("    detector map [%g %g; %g %g], %dx%d pixels within one sample", d.mm[0], d.mm[1], d.mm[2], d.mm[3],
+            d.ncy, d.ncx);
   }
   for (size_t k = 0; k < p->classes.size(); ++k) {
     const auto& c = p->classes[k];
@@ -1182,11 +1262,11 @@ static void trace_plan(const mpbp_plan_t* p, const char* when) {
           c.D, c.count, c.FB, c.key, c.G, c.xcd, c.tuned_us > 0 ? " (tuned)" : "");
   }
   trace("  path: %s; objects %s; back-projection %s, batch %d, tile %d; tuning source %s",
-        p->path ? "plain" : "batched fused", (p->runs && !p->probe3 && !p->linear) ? "summed per run" : "per slice",
-        (p->runs && !p->probe3 && !p->linear) ? "per run (gather + chain rule)" : "per slice", p->grad_batch,
+        p->path ? "plain" : "batched fused", (p->runs && !p->probe3 && !p->linear && !p->mapped) ? "summed per run" : "per slice",
+        (p->runs && !p->probe3 && !p->linear && !p->mapped) ? "per run (gather + chain rule)" : "per slice", p->grad_batch,
         p->grad_tile, p->tune_source.c_str());
   trace("  LDS bytes: frame kernel %d, projection %d, back-projection %d; projection accumulator %d pixels",
-        p->lds_grad_frame, p->lds_project[mpbp::kDefaultSlab], (p->runs && !p->probe3 && !p->linear) ? p->lds_runs : p->lds_grad,
+        p->lds_grad_frame, p->lds_project[mpbp::kDefaultSlab], (p->runs && !p->probe3 && !p->linear && !p->mapped) ? p->lds_runs : p->lds_grad,
         p->acc_pix);
   if (p->device >= 0)
     trace("  device workspace: objects %zu B, two footprint slots of %zu B each, %d alpha partials per peak",
@@ -1525,6 +1605,8 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
   switch (option) {
     case MPBP_OPT_PATH:
       if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "path must be 0 or 1");
+      if (value == 1 && plan->mapped)
+        return fail(MPBP_ERR_UNSUPPORTED, "the plain path has no detector-map projection (MPBP_DETECTOR_MAP)");
       plan->path = (int)value;
       return MPBP_OK;
     case MPBP_OPT_GRAPH:

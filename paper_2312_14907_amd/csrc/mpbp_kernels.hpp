@@ -37,6 +37,11 @@ struct PeakDev {
   long long tw_off; // complex offset of this peak's twiddle tables (D + L + R * fy)
   int nruns;        // runs of consecutive slices with equal exit-beam offset
   int run_base;     // index of this peak's first run over all peaks
+  // MPBP_DETECTOR_MAP: the 2 x 2 map M of probe-window coordinates to exit-wave pixels
+  // (row-major), its inverse, and the extent of the exit-wave pixels that one sample
+  // reaches (ncy x ncx pixels: the image of a 2 x 2 sample square, rounded outwards)
+  float mm[4], mi[4];
+  int ncy, ncx;
 };
 
 struct FrameArgs {
@@ -69,6 +74,8 @@ struct FrameArgs {
   int n_runs;              // runs over all peaks (the run sums' planes)
   unsigned* dbg;           // status word of the bounds checks (MPBP_DEBUG)
   const int2* roff;        // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
+  const float2* mapz;      // MPBP_DETECTOR_MAP: [M][nz] exit-wave point of the probe window's
+                           // centre for slice z, in footprint coordinates (null: no map)
 };
 
 struct GradArgs {
@@ -98,6 +105,7 @@ struct GradArgs {
   unsigned* dbg;             // status word of the bounds checks (MPBP_DEBUG)
   const int* zrun;           // [M][nz] run of each slice (consecutive slices of equal offset)
   const int2* roff;          // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
+  const float2* mapz;        // MPBP_DETECTOR_MAP: as FrameArgs::mapz (null: no map)
   float* grad_u;
   float* grad_chi;
   double* alpha_part;      // [n_blocks][M]
@@ -120,5 +128,6 @@ constexpr int kBpThreads = 256;                         // workgroup of k_bp_gat
 constexpr int kBpZ = 4;                                 // slices per lane of k_bp_chain
 constexpr int kDefaultGradBatch = 8;
 constexpr int kMaxPeaksDev = 16;
+constexpr int kMapThreads = 256;                        // workgroup of the detector-map kernels
 
 }  // namespace mpbp

@@ -26,7 +26,8 @@ hipError_t launch_runsum(const float* u, const float* chi, const float* alpha, c
 // frame's exit wave from its slot (written by launch_project).
 hipError_t launch_frames(int D, int FB, const FrameArgs& a, int lds_bytes, hipStream_t s);
 // Exit waves of the listed frames into their slots, with G object slices in flight per
-// lane (G = 2, 4 or 8); lds_bytes from project_lds_bytes.
+// lane (G = 2, 4 or 8); lds_bytes from project_lds_bytes.  With a detector map
+// (a.mapz), launch_project_map runs instead and G and lds_bytes are not used.
 hipError_t launch_project(int G, const FrameArgs& a, int lds_bytes, hipStream_t s);
 int project_lds_bytes(int np, int G, int nz, int acc_pix);
 int frame_bound(int D, int footprint);
@@ -40,6 +41,12 @@ bool grad_uses_runs(const GradArgs& a);
 // of the run chain rule).
 int grad_partials(const GradArgs& a);
 int grad_effective_batch(int batch, bool runs);
+// R with a detector-frame map (MPBP_DETECTOR_MAP, a.mapz set): the interpolating
+// projection and its adjoint back-projection (mpbp_map.hip); launch_project and
+// launch_grad dispatch to them.
+hipError_t launch_project_map(const FrameArgs& a, hipStream_t s);
+hipError_t launch_grad_map(const GradArgs& a, hipStream_t s);
+int grad_map_partials(const GradArgs& a);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
                            float* grad_alpha, hipStream_t s);

@@ -2,6 +2,7 @@
 integer tables bit-exactly as the oracle does, and rejects bad descriptors with the
 documented status codes.  No compute call runs here (no GPU)."""
 import ctypes
+import math
 import os
 import re
 
@@ -74,8 +75,12 @@ def test_descriptor_validation_codes():
     assert _status_of(B.make_problem_struct(good))[0] == 0
     assert _status_of(None)[0] == 1                       # NULL problem
     s = B.make_problem_struct(good)
-    s.flags = 8
+    s.flags = 16
     assert _status_of(s)[0] == 1                          # undefined flag
+    s.flags = B.MPBP_DETECTOR_MAP | B.MPBP_SHEAR_LINEAR
+    assert _status_of(s)[0] == 1                          # the map includes the interpolated offsets
+    s.flags = B.MPBP_DETECTOR_MAP | B.MPBP_Z_TIED | B.MPBP_PROBE_3D
+    assert _status_of(s)[0] == 0                          # identity maps
     s.flags = B.MPBP_Z_TIED
     assert _status_of(s)[0] == 0                          # membrane parameterisation
     s.flags = B.MPBP_Z_TIED | B.MPBP_PROBE_3D | B.MPBP_SHEAR_LINEAR
@@ -204,3 +209,62 @@ def test_linear_offset_tables_against_oracle(name):
     np.testing.assert_array_equal(shear, tab["shear"])
     np.testing.assert_array_equal(scan, tab["scan"])
     assert (tab["shear_frac"] > 0).any()
+
+
+def test_detector_map_window_check_matches_the_oracle():
+    """MPBP_DETECTOR_MAP: the host's footprint check (the mapped support's bounding box,
+    widened by one sample, inside the window) agrees with the oracle's on a sweep of maps
+    near the window's edge; a singular map is an invalid descriptor."""
+    import dataclasses
+    from synth.inputs import detector_map
+    rng = np.random.default_rng(301)
+    base = _supported_problem(((0.3, 0.2), (0.1, -0.4)))
+    agree = {True: 0, False: 0}
+    for _ in range(60):
+        maps = np.stack([detector_map(rng.uniform(0.5, 3.0), rng.uniform(-math.pi, math.pi)) for _ in range(2)])
+        prob = dataclasses.replace(base, lateral_map=maps)
+        try:
+            O.tables(prob)
+            fits = True
+        except O.FootprintError:
+            fits = False
+        st, msg = _status_of(B.make_problem_struct(prob, B.MPBP_DETECTOR_MAP))
+        assert st == (0 if fits else 3), (st, msg, maps)
+        agree[fits] += 1
+    assert agree[True] >= 5 and agree[False] >= 5
+    prob = dataclasses.replace(base, lateral_map=np.stack([np.eye(2), [[1.0, 2.0], [0.5, 1.0]]]))
+    assert _status_of(B.make_problem_struct(prob, B.MPBP_DETECTOR_MAP))[0] == 1
+
+
+def test_detector_map_footprint_matches_the_oracle():
+    """The footprint the host derives for each peak (origin and size, read from the trace)
+    is the oracle's mapped extent."""
+    import subprocess
+    import sys
+    snippet = """
+import dataclasses, math
+import numpy as np
+from synth import get_config, make_problem
+from synth.inputs import detector_map
+from paper_2312_14907_amd.binding import Plan, MPBP_DETECTOR_MAP
+base = make_problem(get_config("c2_forward"))
+maps = np.stack([detector_map(r, a) for r, a in [(1.2, 0.4), (0.9, 2.5), (1.05, -0.7)]])
+Plan(dataclasses.replace(base, lateral_map=maps), device=-1, flags=MPBP_DETECTOR_MAP).close()
+"""
+    env = dict(os.environ, MPBP_TRACE="1", HIP_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, "-c", snippet], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    got = [tuple(int(v) for v in m.groups())
+           for m in re.finditer(r"footprint (\d+)x(\d+) at \((\d+), (\d+)\)", r.stderr)]
+    import dataclasses
+    from synth.inputs import detector_map
+    base = make_problem(get_config("c2_forward"))
+    prob = dataclasses.replace(base, lateral_map=np.stack(
+        [detector_map(a, b) for a, b in [(1.2, 0.4), (0.9, 2.5), (1.05, -0.7)]]))
+    want = []
+    for m in range(prob.n_peaks):
+        lo, hi = O.mapped_extent(prob, m)
+        want.append((int(hi[0] - lo[0] + 1), int(hi[1] - lo[1] + 1), int(lo[0]), int(lo[1])))
+    assert got == want, r.stderr
+    assert "detector-map" in r.stderr
