@@ -65,6 +65,13 @@ def test_tiny_workload_tables_by_hand():
     np.testing.assert_array_equal(tab["offset"], [8, 8, 8])
 
 
+def test_raster_with_unequal_steps_by_hand():
+    # Raster scan (section 4): frame (iy, ix) at origin + (iy step_y, ix step_x), raster
+    # order; a 2 x 3 raster with steps (3, 5) from (-1, 2), written out.
+    got = O.scan_positions((2, 3), (3, 5), (-1, 2))
+    np.testing.assert_array_equal(got, [[-1, 2], [-1, 7], [-1, 12], [2, 2], [2, 7], [2, 12]])
+
+
 def test_large_workload_geometry_readings():
     # Raster origins / steps and footprint spans of the larger workloads, worked out by
     # hand from the centring rule (N - ((n-1) step + Np)) // 2.

@@ -65,6 +65,17 @@ def test_reliability_is_wrap_invariant():
     np.testing.assert_allclose(U.reliability(psi2), U.reliability(psi), rtol=1e-4)
 
 
+def test_edge_reliability_is_the_sum_of_its_pixels():
+    # The method's edge reliability is the sum of the two pixels' reliabilities; on a 2 x 2
+    # map the edges are (0,1), (2,3) (rows) then (0,2), (1,3) (columns).
+    R = np.array([[0.1, 5.0], [2.0, 2.0]], dtype=np.float32)
+    p, q = U.edge_list(2, 2)
+    np.testing.assert_array_equal(p, [0, 2, 0, 1])
+    np.testing.assert_array_equal(q, [1, 3, 2, 3])
+    np.testing.assert_allclose(U.edge_keys(R, p, q), [5.1, 4.0, 2.1, 7.0], rtol=1e-6)
+    np.testing.assert_array_equal(U.edge_order(U.edge_keys(R, p, q)), [3, 0, 1, 2])
+
+
 def test_fmix32_bijective_and_order_total():
     h = U.fmix32(np.arange(1 << 16))
     assert len(np.unique(h)) == 1 << 16 and int(U.fmix32(0)) == 0
