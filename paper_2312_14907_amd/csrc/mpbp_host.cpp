@@ -556,6 +556,8 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
   return MPBP_OK;
 }
 
+mpbp_status ensure_capture_streams(mpbp_plan p);
+
 mpbp_status alloc_device(mpbp_plan_t* p) {
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -610,7 +612,8 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy mask");
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-  return MPBP_OK;
+  // the fork streams of concurrent size classes (direct launches and graph captures)
+  return ensure_capture_streams(p);
 }
 
 // Validate and stage a caller's frame list; returns the number of listed frames.
@@ -706,7 +709,8 @@ struct StageTimer {
 // disjoint slots and frame losses.
 // Each class runs the projection kernel (exit waves into the frames' slots), then the
 // frame kernel.  Direct launches run every class's projection first, then every class's
-// frame kernel, each group under its stage timer.
+// frame kernel, each group under its stage timer (the classes of a group side by side on
+// the fork streams, which the plan creates with its device buffers).
 hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset, bool grad, hipStream_t s,
                           bool branch = false, bool timed = true) {
   const auto& cls = subset ? p->sub_classes : p->classes;
@@ -720,17 +724,42 @@ hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset,
   };
   hipError_t e = hipSuccess;
   if (!branch) {
-    {
-      StageTimer t(p, MPBP_STAGE_PROJECT, s, timed);
-      for (const auto& c : cls)
-        if (c.count && e == hipSuccess) e = mpbp::launch_project(c.G, class_args(c), p->lds_project[c.G], s);
-    }
-    {
-      StageTimer t(p, MPBP_STAGE_FRAMES, s, timed);
-      for (const auto& c : cls)
-        if (c.count && e == hipSuccess)
-          e = mpbp::launch_frames(c.D, c.FB, class_args(c), grad ? c.lds_grad : c.lds_fwd, s);
-    }
+    // Direct launches: every class's projection, then every class's frame kernel.  With
+    // more than one class, the classes of each stage run concurrently on the plan's fork
+    // streams, joined back into `s` before the next stage (the GPU then fills one
+    // class's last partial wave of workgroups with another's).
+    int live = 0;
+    for (const auto& c : cls) live += c.count > 0;
+    const bool fork = live > 1 && p->forks.size() + 1 >= (size_t)live && p->joins.size() >= p->forks.size();
+    auto stage = [&](int which, auto&& launch) {
+      StageTimer t(p, which, s, timed);
+      if (!fork) {
+        for (const auto& c : cls)
+          if (c.count && e == hipSuccess) e = launch(c, s);
+        return;
+      }
+      if (e == hipSuccess) e = hipEventRecord(p->fork_ev, s);
+      size_t k = 0;
+      bool first = true;
+      for (const auto& c : cls) {
+        if (c.count == 0 || e != hipSuccess) continue;
+        hipStream_t t2 = first ? s : p->forks[k];
+        if (!first) e = hipStreamWaitEvent(t2, p->fork_ev, 0);
+        if (e == hipSuccess) e = launch(c, t2);
+        if (!first) {
+          if (e == hipSuccess) e = hipEventRecord(p->joins[k], t2);
+          if (e == hipSuccess) e = hipStreamWaitEvent(s, p->joins[k], 0);
+          ++k;
+        }
+        first = false;
+      }
+    };
+    stage(MPBP_STAGE_PROJECT, [&](const mpbp_plan_t::SizeClass& c, hipStream_t t2) {
+      return mpbp::launch_project(c.G, class_args(c), p->lds_project[c.G], t2);
+    });
+    stage(MPBP_STAGE_FRAMES, [&](const mpbp_plan_t::SizeClass& c, hipStream_t t2) {
+      return mpbp::launch_frames(c.D, c.FB, class_args(c), grad ? c.lds_grad : c.lds_fwd, t2);
+    });
     return e;
   }
   e = hipEventRecord(p->fork_ev, s);
