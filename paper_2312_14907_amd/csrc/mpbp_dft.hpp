@@ -239,12 +239,14 @@ template <bool INV> struct DFT<16, INV> { __device__ __forceinline__ static void
 template <bool INV> struct DFT<10, INV> { __device__ __forceinline__ static void run(cplx* x) { dft_pq<5, 2, INV>(x); } };
 template <bool INV> struct DFT<15, INV> { __device__ __forceinline__ static void run(cplx* x) { dft_pq<5, 3, INV>(x); } };
 
-// Line configuration: D = P * Q; TPL lanes per line (power of two >= max(P, Q)).
+// Line configuration: D = P * Q; TPL lanes per line, a power of two >= Q, and >= P or a
+// divisor of P (then each lane of the second pass takes P / TPL of the P columns, so no
+// lane idles in either pass).
 template <int D> struct LineCfg;
 template <> struct LineCfg<32>  { static constexpr int P = 8,  Q = 4,  TPL = 8;  };
 template <> struct LineCfg<64>  { static constexpr int P = 8,  Q = 8,  TPL = 8;  };
 template <> struct LineCfg<96>  { static constexpr int P = 12, Q = 8,  TPL = 16; };
-template <> struct LineCfg<128> { static constexpr int P = 16, Q = 8,  TPL = 16; };
+template <> struct LineCfg<128> { static constexpr int P = 16, Q = 8,  TPL = 8;  };
 template <> struct LineCfg<192> { static constexpr int P = 16, Q = 12, TPL = 16; };
 template <> struct LineCfg<256> { static constexpr int P = 16, Q = 16, TPL = 16; };
 template <> struct LineCfg<50>  { static constexpr int P = 10, Q = 5,  TPL = 16; };

@@ -52,9 +52,13 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   constexpr int CLINES = NT / CT;
   constexpr int EXL = RQ * (RP + 1);  // exchange buffer per row line (floats: one part at a time)
   constexpr int NAR = (FB + RQ - 1) / RQ < RP ? (FB + RQ - 1) / RQ : RP;  // live row inputs
-  // lane t takes part in a pass of Q (or P) lanes; true for every lane when Q == TPL
+  // lane t takes part in a pass of Q (or P) lanes; true for every lane when Q == TPL.
+  // When P is a multiple of TPL, each lane of the second row pass owns RJ = P / TPL
+  // columns c = t + TPL j (every lane busy in both passes).
+  static_assert(RQ <= RT && (RP <= RT || RP % RT == 0), "row line configuration");
+  constexpr int RJ = RP > RT ? RP / RT : 1;
   auto rowq = [](int t) { return RQ == RT || t < RQ; };
-  auto rowp = [](int t) { return RP == RT || t < RP; };
+  auto rowp = [](int t) { return RP >= RT || t < RP; };
   auto colq = [](int t) { return CQ == CT || t < CQ; };
   auto colp = [](int t) { return CP == CT || t < CP; };
   constexpr int NAC = (FB + CQ - 1) / CQ < CP ? (FB + CQ - 1) / CQ : CP;  // live column inputs
@@ -105,17 +109,25 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
   // Intensities are prefetched one row-iteration ahead (across chunk boundaries) so the
   // HBM latency overlaps the transforms of the current rows.
   const int rline = tid / RT, rt = tid % RT;
-  float ynext[RQ], bnext[BG ? RQ : 1], yalt[RQ], balt[BG ? RQ : 1];
-  if (has_y && rowp(rt)) {
+  // a lane's detector pixels of a row: columns t + RT j + RP d (j < RJ, d < RQ), in
+  // slot j RQ + d
+  constexpr int RY = RJ * RQ;
+  constexpr bool kAhead = RJ == 1;   // intensities prefetched one row iteration ahead
+  float ynext[RY], bnext[BG ? RY : 1], yalt[RY], balt[BG ? RY : 1];
+  if (kAhead && has_y && rowp(rt)) {
     const float* yr = yf + (long long)(R * rline) * D;
 #pragma unroll
-    for (int d = 0; d < RQ; ++d) ynext[d] = __builtin_nontemporal_load(yr + rt + RP * d);
+    for (int j = 0; j < RJ; ++j)
+#pragma unroll
+      for (int d = 0; d < RQ; ++d) ynext[j * RQ + d] = __builtin_nontemporal_load(yr + rt + RT * j + RP * d);
   }
   if constexpr (BG) {
-    if (rowp(rt)) {
+    if (kAhead && rowp(rt)) {
       const float* br = bgf + (long long)(R * rline) * D;
 #pragma unroll
-      for (int d = 0; d < RQ; ++d) bnext[d] = __builtin_nontemporal_load(br + rt + RP * d);
+      for (int j = 0; j < RJ; ++j)
+#pragma unroll
+        for (int d = 0; d < RQ; ++d) bnext[j * RQ + d] = __builtin_nontemporal_load(br + rt + RT * j + RP * d);
     }
   }
 
@@ -180,27 +192,55 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
       const int line = tid / RT, t = tid % RT;
       float* ex = reinterpret_cast<float*>(exch) + line * EXL;
       // One row iteration: the intensities (and background) of its rows are in yv (bv);
-      // those of the next iteration are prefetched into ynx (bnx).
-      auto row_iter = [&](int k0, const float (&yv)[RQ], float (&ynx)[RQ], const float (&bv)[BG ? RQ : 1],
-                          float (&bnx)[BG ? RQ : 1]) __attribute__((always_inline)) {
+      // those of the next iteration are prefetched into ynx (bnx).  With several columns
+      // per lane (RJ > 1) the prefetch would hold twice the registers: the rows'
+      // intensities are then loaded at the start of the iteration instead, ahead of the
+      // first pass, and yv, ynx (bv, bnx) are not used.
+      auto row_iter = [&](int k0, const float (&yv)[RY], float (&ynx)[RY], const float (&bv)[BG ? RY : 1],
+                          float (&bnx)[BG ? RY : 1]) __attribute__((always_inline)) {
         const int kp = k0 + line;
         const int k = R * kp + r;
         // chunk rows beyond L (when L is not a multiple of the lines per pass) have no work
         const bool lok = (L % RLINES == 0) || kp < L;
-        {
+        float yl[kAhead ? 1 : RY], bl[BG && !kAhead ? RY : 1];
+        if constexpr (!kAhead) {
+          if (has_y && rowp(t) && lok) {
+            const float* yr = yf + (long long)k * D;
+#pragma unroll
+            for (int j = 0; j < RJ; ++j)
+#pragma unroll
+              for (int d = 0; d < RQ; ++d) yl[j * RQ + d] = __builtin_nontemporal_load(yr + t + RT * j + RP * d);
+          }
+          if constexpr (BG) {
+            if (rowp(t) && lok) {
+              const float* br = bgf + (long long)k * D;
+#pragma unroll
+              for (int j = 0; j < RJ; ++j)
+#pragma unroll
+                for (int d = 0; d < RQ; ++d) bl[j * RQ + d] = __builtin_nontemporal_load(br + t + RT * j + RP * d);
+            }
+          }
+        }
+        const float* yc = kAhead ? yv : yl;
+        const float* bc = kAhead ? bv : bl;
+        if constexpr (kAhead) {
           const int nk0 = k0 + RLINES < L ? k0 + RLINES : 0;
           const int nr = k0 + RLINES < L ? r : r + 1;
           const bool nok = (L % RLINES == 0) || nk0 + line < L;
           if (has_y && rowp(t) && nr < R && nok) {
             const float* yr = yf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
-            for (int d = 0; d < RQ; ++d) ynx[d] = __builtin_nontemporal_load(yr + t + RP * d);
+            for (int j = 0; j < RJ; ++j)
+#pragma unroll
+              for (int d = 0; d < RQ; ++d) ynx[j * RQ + d] = __builtin_nontemporal_load(yr + t + RT * j + RP * d);
           }
           if constexpr (BG) {
             if (rowp(t) && nr < R && nok) {
               const float* br = bgf + (long long)(R * (nk0 + line) + nr) * D;
 #pragma unroll
-              for (int d = 0; d < RQ; ++d) bnx[d] = __builtin_nontemporal_load(br + t + RP * d);
+              for (int j = 0; j < RJ; ++j)
+#pragma unroll
+                for (int d = 0; d < RQ; ++d) bnx[j * RQ + d] = __builtin_nontemporal_load(br + t + RT * j + RP * d);
             }
           }
         }
@@ -224,11 +264,15 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
             ex[t * (RP + 1) + c] = v[c].x;
           }
         }
+        // second pass: column c = t + RT j of the line's exchange, its Q values in
+        // v[j RQ .. j RQ + RQ); X[c + P d] ends in v[j RQ + d]
         wave_sync();
-        float re[RQ];
+        float re[RY];
         if (rowp(t)) {
 #pragma unroll
-          for (int b = 0; b < RQ; ++b) re[b] = ex[b * (RP + 1) + t];
+          for (int j = 0; j < RJ; ++j)
+#pragma unroll
+            for (int b = 0; b < RQ; ++b) re[j * RQ + b] = ex[b * (RP + 1) + t + RT * j];
         }
         wave_sync();
         if (rowq(t)) {
@@ -238,37 +282,43 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         wave_sync();
         if (rowp(t)) {
 #pragma unroll
-          for (int b = 0; b < RQ; ++b) v[b] = {re[b], ex[b * (RP + 1) + t]};
-          DFT<RQ, false>::run(v);
+          for (int j = 0; j < RJ; ++j) {
+#pragma unroll
+            for (int b = 0; b < RQ; ++b) v[j * RQ + b] = {re[j * RQ + b], ex[b * (RP + 1) + t + RT * j]};
+            DFT<RQ, false>::run(v + j * RQ);
+          }
           if (mif) {
 #pragma unroll
-            for (int d = 0; d < RQ; ++d) {
-              const float i2 = fmaf(v[d].x, v[d].x, v[d].y * v[d].y) * invD2;
-              mif[(long long)k * D + t + RP * d] = BG ? i2 + bv[BG ? d : 0] : i2;
-            }
+            for (int j = 0; j < RJ; ++j)
+#pragma unroll
+              for (int d = 0; d < RQ; ++d) {
+                const int e = j * RQ + d;
+                const float i2 = fmaf(v[e].x, v[e].x, v[e].y * v[e].y) * invD2;
+                mif[(long long)k * D + t + RT * j + RP * d] = BG ? i2 + bc[BG ? e : 0] : i2;
+              }
           }
           if (has_y) {
             float rowl = 0.f;
 #pragma unroll
-            for (int d = 0; d < RQ; ++d) {
-              const cplx X = v[d];
+            for (int e = 0; e < RY; ++e) {
+              const cplx X = v[e];
               const float s2 = fmaf(X.x, X.x, X.y * X.y);
               if constexpr (BG) {
                 // I = |Psi|^2 + b; r = sqrt(I) - sqrt(y); gradient r Psi / sqrt(I), Psi = X / D.
-                const float I = fmaf(s2, invD2, bv[BG ? d : 0]);
+                const float I = fmaf(s2, invD2, bc[BG ? e : 0]);
                 const float ri = __builtin_amdgcn_rsqf(I + 1.17549435e-38f);
-                const float res = fmaf(I, ri, -__builtin_amdgcn_sqrtf(yv[d]));
+                const float res = fmaf(I, ri, -__builtin_amdgcn_sqrtf(yc[e]));
                 rowl = fmaf(res, res, rowl);
-                v[d] = cscale(X, res * ri * invD);
+                v[e] = cscale(X, res * ri * invD);
               } else {
                 // X = D Psi.  r = |Psi| - sqrt(y); gradient r X / |X|.  The reciprocal
                 // square root is taken of |X|^2 + FLT_MIN: finite where X = 0 (there the
                 // modulus and the gradient come out exactly 0), absorbed for |X|^2 above
                 // about 1e-31.
                 const float rinv = __builtin_amdgcn_rsqf(s2 + 1.17549435e-38f);
-                const float res = fmaf(s2 * rinv, invD, -__builtin_amdgcn_sqrtf(yv[d]));
+                const float res = fmaf(s2 * rinv, invD, -__builtin_amdgcn_sqrtf(yc[e]));
                 rowl = fmaf(res, res, rowl);
-                v[d] = cscale(X, res * rinv);
+                v[e] = cscale(X, res * rinv);
               }
             }
             lsum += 0.5 * (double)rowl;
@@ -277,9 +327,12 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         if (A.grad) {
           wave_sync();
           if (rowp(t)) {
-            DFT<RQ, true>::run(v);
 #pragma unroll
-            for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t] = v[b].x;
+            for (int j = 0; j < RJ; ++j) {
+              DFT<RQ, true>::run(v + j * RQ);
+#pragma unroll
+              for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t + RT * j] = v[j * RQ + b].x;
+            }
           }
           wave_sync();
           float rex[RP];
@@ -290,7 +343,9 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
           wave_sync();
           if (rowp(t)) {
 #pragma unroll
-            for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t] = v[b].y;
+            for (int j = 0; j < RJ; ++j)
+#pragma unroll
+              for (int b = 0; b < RQ; ++b) ex[b * (RP + 1) + t + RT * j] = v[j * RQ + b].y;
           }
           wave_sync();
           if (rowq(t)) {
@@ -319,12 +374,12 @@ __device__ void frame_body(const FrameArgs& A, const PeakDev& pk, int fid, cplx*
         }
       } else {
         for (int k0 = 0; k0 < L; k0 += RLINES) {
-          float yv[RQ], bv[BG ? RQ : 1];
+          float yv[RY], bv[BG ? RY : 1];
 #pragma unroll
-          for (int d = 0; d < RQ; ++d) yv[d] = ynext[d];
+          for (int d = 0; d < RY; ++d) yv[d] = ynext[d];
           if constexpr (BG) {
 #pragma unroll
-            for (int d = 0; d < RQ; ++d) bv[d] = bnext[d];
+            for (int d = 0; d < RY; ++d) bv[d] = bnext[d];
           }
           row_iter(k0, yv, ynext, bv, bnext);
         }
