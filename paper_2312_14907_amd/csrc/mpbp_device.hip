@@ -446,33 +446,69 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_gather(GradArgs A) {
   const int nact = min(__builtin_amdgcn_readfirstlane(*ncand_s), A.max_cand);
   const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
   cplx* G = reinterpret_cast<cplx*>(A.rs) + (long long)pk.run_base * A.nlat + (long long)(inb ? y : 0) * A.nx + (inb ? x : 0);
-  for (int run = wv; run < pk.nruns; run += kBpThreads / kGradTile) {
-    const int2 ro = A.roff[m * nz + run];
-    const int roy = __builtin_amdgcn_readfirstlane(ro.x), rox = __builtin_amdgcn_readfirstlane(ro.y);
-    cplx acc = {0.f, 0.f};
+  // Wavefront wv sums runs wv, wv + 4, ..., up to kBpRunGroup of them per pass over the
+  // frame list: a frame's window position, probe value and footprint offset are worked
+  // out once and serve each of those runs, which differ only by the run's offset.
+  constexpr int NW = kBpThreads / kGradTile;
+  const int lane_p = y * np + x, lane_f = y * pk.fx + x;
+  for (int run0 = wv; run0 < pk.nruns; run0 += NW * kBpRunGroup) {
+    int rof[kBpRunGroup];   // footprint offset of each run of the group (uniform)
+#pragma unroll
+    for (int g = 0; g < kBpRunGroup; ++g) {
+      const int run = run0 + NW * g;
+      const int2 ro = A.roff[m * nz + (run < pk.nruns ? run : run0)];
+      rof[g] = __builtin_amdgcn_readfirstlane(ro.x * pk.fx + ro.y);
+    }
+    cplx acc[kBpRunGroup];
+#pragma unroll
+    for (int g = 0; g < kBpRunGroup; ++g) acc[g] = {0.f, 0.f};
     for (int c0 = 0; c0 < nact; c0 += B) {
-      cplx gv[B], pv[B];
+      // one LDS read brings the batch's B list entries (lane l holds entry c0 + l mod B;
+      // past the list: the batch's first entry), then each is taken from its lane
+      const int cl = c0 + lane % B < nact ? c0 + lane % B : c0;
+      const GradCand mine = cand[cl];
+      const unsigned so_lo = (unsigned)mine.so, so_hi = (unsigned)((unsigned long long)mine.so >> 32);
+      cplx pv[B];
+      unsigned off[B];   // byte offset of (y, x)'s footprint pixel at zero run offset
+      const char* sl[B];
 #pragma unroll
       for (int k = 0; k < B; ++k) {
-        const int c = c0 + k < nact ? c0 + k : c0;   // past the list: its first entry
-        const int fpy = __builtin_amdgcn_readfirstlane(cand[c].fpy);
-        const int fpx = __builtin_amdgcn_readfirstlane(cand[c].fpx);
-        const long long so = cand[c].so;
+        const int fpy = __builtin_amdgcn_readlane(mine.fpy, k);
+        const int fpx = __builtin_amdgcn_readlane(mine.fpx, k);
+        const long long so = (long long)(((unsigned long long)__builtin_amdgcn_readlane(so_hi, k) << 32) |
+                                         (unsigned)__builtin_amdgcn_readlane(so_lo, k));
         const int a = y - fpy, b = x - fpx;
         const bool inw = inb && (unsigned)a < (unsigned)np && (unsigned)b < (unsigned)np;
-        const int ac = inw ? a : 0, bc = inw ? b : 0;
-        const cplx pr = Ps[ac * np + bc];
+        // (a, b) = (y, x) - window origin: the probe index and the footprint offset are
+        // the lane's own value at origin 0 minus a uniform one
+        const int pi = inw ? lane_p - (fpy * np + fpx) : 0;
+        const cplx pr = Ps[pi];
         pv[k] = inw ? pr : cplx{0.f, 0.f};
-        const char* sl = reinterpret_cast<const char*>(slots + so);
-        const unsigned off = (unsigned)((ac + roy) * pk.fx + bc + rox) * (unsigned)sizeof(cplx);
-        const bool okg = MPBP_CHECK(A.dbg, off / sizeof(cplx) < (unsigned)(pk.fy * pk.fx), kDbgSlot);
-        gv[k] = *reinterpret_cast<const cplx*>(okg ? sl + off : sl);
+        sl[k] = reinterpret_cast<const char*>(slots + so);
+        off[k] = inw ? (unsigned)(lane_f - (fpy * pk.fx + fpx)) : 0u;
       }
 #pragma unroll
-      for (int k = 0; k < B; ++k)
-        if (c0 + k < nact) acc = cmulc_acc(acc, gv[k], pv[k]);   // conj(P) g_psi
+      for (int g = 0; g < kBpRunGroup; ++g) {
+        if (run0 + NW * g < pk.nruns) {   // uniform
+          cplx gv[B];
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            const unsigned o = off[k] + (unsigned)rof[g];
+            const bool okg = MPBP_CHECK(A.dbg, o < (unsigned)(pk.fy * pk.fx), kDbgSlot);
+            gv[k] = *reinterpret_cast<const cplx*>(sl[k] + (okg ? o : 0u) * (unsigned)sizeof(cplx));
+          }
+#pragma unroll
+          for (int k = 0; k < B; ++k)
+            if (c0 + k < nact) acc[g] = cmulc_acc(acc[g], gv[k], pv[k]);   // conj(P) g_psi
+        }
+      }
     }
-    if (inb && MPBP_CHECK(A.dbg, pk.run_base + run < A.n_runs, kDbgRunSum)) G[(long long)run * A.nlat] = acc;
+#pragma unroll
+    for (int g = 0; g < kBpRunGroup; ++g) {
+      const int run = run0 + NW * g;
+      if (run < pk.nruns && inb && MPBP_CHECK(A.dbg, pk.run_base + run < A.n_runs, kDbgRunSum))
+        G[(long long)run * A.nlat] = acc[g];
+    }
   }
 }
 

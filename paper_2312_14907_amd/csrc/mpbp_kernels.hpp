@@ -126,6 +126,7 @@ constexpr int kGradBatches[] = {1, 2, 4};               // compiled batch sizes 
 constexpr int kGradRunBatches[] = {4, 8, 16};           // compiled batch sizes of the run gather
 constexpr int kBpThreads = 256;                         // workgroup of k_bp_gather and k_bp_chain
 constexpr int kBpZ = 4;                                 // slices per lane of k_bp_chain
+constexpr int kBpRunGroup = 3;                          // runs per wavefront per pass of k_bp_gather
 constexpr int kDefaultGradBatch = 8;
 constexpr int kMaxPeaksDev = 16;
 constexpr int kMapThreads = 256;                        // workgroup of the detector-map kernels
