@@ -6,6 +6,7 @@
 
 #include "mpbp_dft.hpp"
 #include "mpbp_kernels.hpp"
+#include "mpbp_phase.hpp"
 
 namespace mpbp {
 
@@ -40,7 +41,7 @@ __device__ __forceinline__ void chain_voxel(const PeakDev& pk, cplx g, float ux,
                                             float al, float& gux, float& guy, float& guz, float& gch, float& ap) {
   const float phi = fmaf(pk.gz, uz, fmaf(pk.gy, uy, pk.gx * ux));   // as k_object
   float s, c;
-  sincosf(phi, &s, &c);                                             // as k_object
+  phase_sincos(phi, s, c);                                          // as k_object
   const float re = fmaf(g.y, s, g.x * c);                           // Re(conj(g) e^{i phi})
   const float dphi = (al * ch) * fmaf(g.y, c, -(g.x * s));          // Im(g conj(O))
   gux = fmaf(pk.gx, dphi, gux);

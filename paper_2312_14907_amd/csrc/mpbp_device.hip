@@ -20,6 +20,7 @@
 #include "mpbp_frame.hpp"
 #include "mpbp_project.hpp"
 #include "mpbp_chain.hpp"
+#include "mpbp_phase.hpp"
 #include "mpbp_kernels.hpp"
 #include "mpbp_launch.hpp"
 
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void k_object(const float* __restrict__ u,
     // G . u with explicit FMAs: the gradient kernel forms the same phase bit for bit
     float phi = fmaf(peaks[m].gz, uz, fmaf(peaks[m].gy, uy, peaks[m].gx * ux));
     float s, c;
-    sincosf(phi, &s, &c);
+    phase_sincos(phi, s, c);
     float a = alpha[m] * ch;
     float2* o = reinterpret_cast<float2*>(obj) + (long long)m * nvox + v;
     *o = make_float2(a * c, a * s);
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void k_runsum(const float* __restrict__ u, con
       const float gx = peaks[m].gx, gy = peaks[m].gy, gz = peaks[m].gz;
       const float phi = fmaf(gz, uz, fmaf(gy, uy, gx * ux));   // as k_object
       float s, c;
-      sincosf(phi, &s, &c);
+      phase_sincos(phi, s, c);
       const float a = alpha[m] * ch;
       const float2 o = make_float2(a * c, a * s);
       const int* zr = zrun + m * nz;

@@ -11,6 +11,7 @@
 #include "mpbp_dft.hpp"
 #include "mpbp_launch.hpp"
 #include "mpbp_plain.hpp"
+#include "mpbp_phase.hpp"
 
 namespace mpbp {
 
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_pl_chain(const float* __restrict__ gobj
       const PeakDev pk = peaks[m];
       const float phi = fmaf(pk.gz, uz, fmaf(pk.gy, uy, pk.gx * ux));   // as k_object
       float s, c;
-      sincosf(phi, &s, &c);
+      phase_sincos(phi, s, c);
       const float al = alpha[m];
       for (long long k = 0; k < nslices; ++k) {
         const cplx g = reinterpret_cast<const cplx*>(gobj)[(long long)m * nvox + k * nf + v];
