@@ -631,6 +631,7 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_chain(GradArgs A) {
 // order: the sums are deterministic.
 constexpr int kFinThreads = 1024;
 constexpr int kFinBatch = 8;
+constexpr int kFinPeaks = 4;
 
 __device__ __forceinline__ double fin_block_sum(double s, double* red) {
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -670,20 +671,33 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* __restri
     if (tid == 0 && loss) *loss = t;
   }
   if (grad_alpha) {
-    for (int m = 0; m < n_peaks; ++m) {
-      double s = 0.0;
+    // kFinPeaks peaks per pass over the partials (a partial's peaks are adjacent), each
+    // peak's values added in the same order as alone
+    for (int m0 = 0; m0 < n_peaks; m0 += kFinPeaks) {
+      double s[kFinPeaks];
+#pragma unroll
+      for (int j = 0; j < kFinPeaks; ++j) s[j] = 0.0;
       for (int i0 = 0; i0 < n_part; i0 += kFinBatch * kFinThreads) {
-        double v[kFinBatch];
+        double v[kFinBatch][kFinPeaks];
 #pragma unroll
         for (int u = 0; u < kFinBatch; ++u) {
           const int i = i0 + u * kFinThreads + tid;
-          v[u] = i < n_part ? apart[(long long)i * n_peaks + m] : 0.0;
+#pragma unroll
+          for (int j = 0; j < kFinPeaks; ++j)
+            v[u][j] = i < n_part && m0 + j < n_peaks ? apart[(long long)i * n_peaks + m0 + j] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kFinBatch; ++u) s += v[u];
+        for (int u = 0; u < kFinBatch; ++u)
+#pragma unroll
+          for (int j = 0; j < kFinPeaks; ++j) s[j] += v[u][j];
       }
-      const double t = fin_block_sum(s, red);
-      if (tid == 0) grad_alpha[m] = (float)t;
+#pragma unroll
+      for (int j = 0; j < kFinPeaks; ++j) {
+        if (m0 + j < n_peaks) {   // uniform
+          const double t = fin_block_sum(s[j], red);
+          if (tid == 0) grad_alpha[m0 + j] = (float)t;
+        }
+      }
     }
   }
 }
