@@ -100,10 +100,14 @@ def step_bytes(prob):
 
 
 def kernel_source_hash():
+    """sha256 (first 16 hex digits) of every device source of the library (the .hip and
+    .hpp files, in name order): a committed counter summary applies while it matches."""
     h = hashlib.sha256()
-    for f in ("mpbp_device.hip", "mpbp_dft.hpp", "mpbp_frame.hpp", "mpbp_kernels.hpp", "mpbp_project.hpp"):
-        with open(os.path.join(ROOT, "paper_2312_14907_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2312_14907_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
