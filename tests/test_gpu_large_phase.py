@@ -3,7 +3,7 @@
 Adding a lattice vector a n (n integer per voxel) to u changes every phase G_hkl . u by
 2 pi (h, k, l) . n, a multiple of 2 pi (eq. (6)-(7): intensities unchanged).  With n up
 to 5 per component the phases reach about 90 rad; the object build and the gradient
-kernel both reduce these arguments (sincosf) and must match the oracle there, and the
+kernel both reduce these arguments (by multiples of pi/2) and must match the oracle there, and the
 loss must equal the loss at the unshifted field.
 """
 import numpy as np
