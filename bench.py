@@ -427,8 +427,14 @@ def main():
         plan.mpbp_autotune(*args_t)
     tuning = plan.mpbp_tuning()
     copy_gbps = measured_copy_gbps(torch)
-    plan.mpbp_set_option(MPBP_OPT_PROFILE, 1)
+    # The timed steps: direct launches with HIP events around the frame stage only (the
+    # dominant kernel's duration for the roofline; the least the events add to a step).
+    plan.mpbp_set_option(MPBP_OPT_PROFILE, 2)
     dt, stages, loss = time_steps(plan, args_t, args.steps, args.warmup, torch)
+    # every stage timed, in a pass of its own (the breakdown; its events cost a few
+    # percent of the step)
+    plan.mpbp_set_option(MPBP_OPT_PROFILE, 1)
+    sdt, all_stages, _ = time_steps(plan, args_t, args.steps, 1, torch)
     nfr = prob.n_frames()
     value = nfr * args.steps / dt
     ms_step = 1e3 * dt / args.steps
@@ -481,7 +487,8 @@ def main():
             "measured_copy_GBps": round(copy_gbps, 1),
             "frac_of_measured_copy": round(step_bytes(prob) / (dt / args.steps) / 1e9 / copy_gbps, 4),
         },
-        "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in stages.items() if v[1]},
+        "stages_ms_per_step": {k: round(v[0] / max(args.steps, 1), 4) for k, v in all_stages.items() if v[1]},
+        "stages_pass_ms_per_step": round(1e3 * sdt / args.steps, 4),
         "loss": loss,
         "launch": {"source": tuning["source"], "grad_batch": tuning["grad_batch"],
                    "frame_classes": [{k: c[k] for k in ("D", "frames", "FB", "G", "xcd", "us")}

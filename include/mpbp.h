@@ -135,7 +135,10 @@ enum {
                                 are bitwise those of direct launches.                    */
   MPBP_OPT_XCD_ORDER = 3,    /* 1 = hand each XCD a contiguous band of frames (default) */
   MPBP_OPT_PROFILE = 4,      /* 1 = record HIP events around every kernel stage on the
-                                call's stream (read with mpbp_stage_times); default 0    */
+                                call's stream (read with mpbp_stage_times); 2 = around
+                                the frame stage (MPBP_STAGE_FRAMES) only, the least
+                                added to the step; default 0.  Profiled calls launch
+                                directly (no graph replay)                               */
   MPBP_OPT_GRAD_BATCH = 5,   /* footprint gradients the back-projection kernel reads at
                                 once: 1, 2, 4, 8 (default) or 16; the run gather takes
                                 at least 4, the per-slice walk at most 4; set by
@@ -295,7 +298,7 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value);
 mpbp_status mpbp_get_option(mpbp_plan plan, int option, int64_t* value);
 
 /* Accumulated device time of each stage (MPBP_STAGE_*) over the calls enqueued since
-   the previous mpbp_stage_times call while MPBP_OPT_PROFILE was 1:
+   the previous mpbp_stage_times call while MPBP_OPT_PROFILE was 1 (2: the frame stage):
      ms     (host) double [MPBP_NUM_STAGES]  summed milliseconds
      counts (host) int64  [MPBP_NUM_STAGES]  number of launches timed
    Waits for the recorded events, then resets the accumulators.  Either pointer may be

@@ -685,7 +685,7 @@ struct StageTimer {
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   StageTimer(mpbp_plan_t* p_, int stage_, hipStream_t s_, bool on = true) : p(p_), stage(stage_), s(s_) {
-    if (!p->profile || !on) return;
+    if (!on || !(p->profile == 1 || (p->profile == 2 && stage == MPBP_STAGE_FRAMES))) return;
     while (p->ev_pool.size() < p->ev_used + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return;
@@ -703,14 +703,14 @@ struct StageTimer {
   }
 };
 
-// Enqueue the per-frame kernel for every detector-size class of the call.  With
-// `branch` (graph capture), the classes after the first run on fork streams joined back
-// into `s`, so the captured graph holds them as parallel nodes: the classes write
-// disjoint slots and frame losses.
+// Enqueue the per-frame kernel for every detector-size class of the call.  The classes
+// after the first run on fork streams joined back into `s` (under graph capture the
+// graph then holds them as parallel nodes): the classes write disjoint slots and frame
+// losses.
 // Each class runs the projection kernel (exit waves into the frames' slots), then the
-// frame kernel.  Direct launches run every class's projection first, then every class's
-// frame kernel, each group under its stage timer (the classes of a group side by side on
-// the fork streams, which the plan creates with its device buffers).
+// frame kernel.  Profiled direct launches instead run every class's projection first,
+// then every class's frame kernel, each group under its stage timer (the classes of a
+// group side by side).  The plan creates the fork streams with its device buffers.
 hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset, bool grad, hipStream_t s,
                           bool branch = false, bool timed = true) {
   const auto& cls = subset ? p->sub_classes : p->classes;
@@ -723,11 +723,12 @@ hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset,
     return a;
   };
   hipError_t e = hipSuccess;
-  if (!branch) {
-    // Direct launches: every class's projection, then every class's frame kernel.  With
-    // more than one class, the classes of each stage run concurrently on the plan's fork
-    // streams, joined back into `s` before the next stage (the GPU then fills one
-    // class's last partial wave of workgroups with another's).
+  if (!branch && p->profile && timed) {
+    // Profiled direct launches: every class's projection, then every class's frame
+    // kernel, each stage under its timer.  With more than one class, the classes of a
+    // stage run concurrently on the plan's fork streams, joined back into `s` before the
+    // next stage (the GPU then fills one class's last partial wave of workgroups with
+    // another's).
     int live = 0;
     for (const auto& c : cls) live += c.count > 0;
     const bool fork = live > 1 && p->forks.size() + 1 >= (size_t)live && p->joins.size() >= p->forks.size();
@@ -762,6 +763,9 @@ hipError_t enqueue_frames(mpbp_plan p, const mpbp::FrameArgs& base, bool subset,
     });
     return e;
   }
+  // Otherwise (graph captures, unprofiled direct launches) each class's projection and
+  // frame kernel form one chain on its own fork stream, so one class's projection
+  // overlaps another's frame kernel.
   e = hipEventRecord(p->fork_ev, s);
   size_t k = 0;
   bool first = true;
@@ -1656,7 +1660,7 @@ mpbp_status mpbp_set_option(mpbp_plan plan, int option, int64_t value) {
       }
       return MPBP_OK;
     case MPBP_OPT_PROFILE:
-      if (value != 0 && value != 1) return fail(MPBP_ERR_INVALID, "profile must be 0 or 1");
+      if (value < 0 || value > 2) return fail(MPBP_ERR_INVALID, "profile must be 0, 1 or 2");
       plan->profile = (int)value;
       return MPBP_OK;
     case MPBP_OPT_GRAD_BATCH:
