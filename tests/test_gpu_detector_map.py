@@ -133,3 +133,14 @@ def test_plain_path_refuses_the_map(c1):
     with pytest.raises(B.MPBPError) as e:
         plan.mpbp_set_option(B.MPBP_OPT_PATH, 1)
     assert e.value.status == 6                            # MPBP_ERR_UNSUPPORTED
+
+
+def test_c2_minibatch_detector_map_z_tied():
+    prob, f, y = _case("c2_forward", C2_MAPS)
+    say("detector map c2 minibatch z-tied")
+    u2 = (f["u"] + f["delta"])[:, :1].astype(np.float32)
+    chi2 = f["chi"].max(axis=0, keepdims=True).astype(np.float32)
+    plan = B.Plan(prob, 0, flags=B.MPBP_DETECTOR_MAP | B.MPBP_Z_TIED)
+    frames = np.random.default_rng(133).choice(prob.n_frames(), 40, replace=False)
+    got = gpu_loss_grad(plan, u2, chi2, f["alpha"], f["probe"], y, frames=frames)
+    _check(got, O.loss_grad_ztied(u2, chi2, f["alpha"], f["probe"], y, prob, frames=frames))
