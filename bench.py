@@ -99,15 +99,24 @@ def step_bytes(prob):
     return y + 32.0 * nvox + 8.0 * prob.n_peaks * prob.probe_n ** 2
 
 
+def code_text(src):
+    """A source file's code without its comments and with runs of white space made one
+    space (edits to comments leave it unchanged)."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return re.sub(r"\s+", " ", src).strip()
+
+
 def kernel_source_hash():
-    """sha256 (first 16 hex digits) of every device source of the library (the .hip and
-    .hpp files, in name order): a committed counter summary applies while it matches."""
+    """sha256 (first 16 hex digits) of the code of every device source of the library
+    (the .hip and .hpp files, in name order, comments left out): a committed counter
+    summary applies while it matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2312_14907_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+            with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+                h.update(f.encode() + b"\0" + code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

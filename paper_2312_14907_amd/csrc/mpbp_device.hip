@@ -1,11 +1,16 @@
-// mpbp_device.hip - HIP kernels (gfx950) of the MPBP objective-and-gradient path.
+// mpbp_device.hip - HIP kernels (gfx950) of the MPBP objective-and-gradient path, and
+// the host launchers of every kernel of the fused path.
 //
-//   k_object   eq. (1)/(3): O_m = alpha_m chi exp(i G_m . u) for every voxel and peak
-//   k_frames   one workgroup per frame (m, j): eq. (2) forward model, eq. (4) residual,
-//              and the adjoint back to the exit-wave footprint
-//   k_grad     gather back-projection of the footprint gradients over all frames that
-//              cover a voxel tile, then the chain rule to df/du, df/dchi, df/dalpha
-//   k_finalize deterministic FP64 sums of the per-frame losses and alpha partials
+//   k_object    eq. (1)/(3): O_m = alpha_m chi exp(i G_m . u) for every voxel and peak
+//   k_runsum    the same objects summed over each run of consecutive slices with equal
+//               exit-beam offset (one probe for all slices, rounded offsets)
+//   (k_project_runs, k_project: mpbp_project.hpp; k_frames: mpbp_frame.hpp, one
+//    instance file per detector size; k_project_map, k_grad_map: mpbp_map.hip)
+//   k_grad      per-slice gather back-projection of the footprint gradients over all
+//               frames that cover a voxel tile, then the chain rule to df/du, df/dchi,
+//               df/dalpha (3D probes, interpolated offsets)
+//   k_bp_gather, k_bp_chain  the same per run: frame sums per run, then the chain rule
+//   k_finalize  deterministic FP64 sums of the per-frame losses and alpha partials
 //   k_step     p <- p - eta g
 //   k_adam     one Adam update (Kingma and Ba), optionally of a log-parameter (eq. (8))
 //   k_norm2    deterministic FP64 sum of squares (two passes)

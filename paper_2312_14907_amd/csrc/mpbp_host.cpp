@@ -195,7 +195,7 @@ struct mpbp_plan_t {
   unsigned* d_dbg = nullptr;       // status word of the device bounds checks (debug library)
   float* d_obj = nullptr;
   float* d_slots = nullptr;        // exit waves (k_project -> k_frames)
-  float* d_gslots = nullptr;       // footprint gradients (k_frames -> k_grad)
+  float* d_gslots = nullptr;       // footprint gradients (k_frames -> the back-projection)
   double* d_floss = nullptr;
   double* d_apart = nullptr;
   double* d_red = nullptr;         // sum-of-squares partials (kRedParts)

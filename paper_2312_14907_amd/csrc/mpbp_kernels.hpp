@@ -57,9 +57,9 @@ struct FrameArgs {
   const PeakDev* peaks;    // [M]
   const int* shear;        // [M][nz][2]
   float* slots;            // complex64 exit waves, one F_y x F_x slot per frame (written
-                           // by k_project, read by k_frames)
+                           // by the projection, read by k_frames)
   float* gslots;           // complex64 footprint gradients in the same slot layout (written
-                           // by k_frames, read by k_grad)
+                           // by k_frames, read by the back-projection)
   double* floss;           // per-frame loss, indexed by global frame id
   const float* tw;         // complex64 twiddle tables of all peaks
   float* mi;               // model intensity (ragged like y) or null
