@@ -432,10 +432,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         calib = {"kernel": "torch neg (elementwise)", "bytes_read": 4 * n, "bytes_written": 4 * n}
+    copy_gbps = measured_copy_gbps(torch)
     if not args.no_autotune:
         plan.mpbp_autotune(*args_t)
     tuning = plan.mpbp_tuning()
-    copy_gbps = measured_copy_gbps(torch)
     # The timed steps: direct launches with HIP events around the frame stage only (the
     # dominant kernel's duration for the roofline; the least the events add to a step).
     plan.mpbp_set_option(MPBP_OPT_PROFILE, 2)
