@@ -130,7 +130,9 @@ enum {
                                 size classes run as parallel graph branches.  At most 8
                                 graphs are kept per plan (least recently used dropped,
                                 after a device synchronisation).  Subset calls, the plain
-                                path and profiled calls launch directly.  0 = direct
+                                path and profiled calls launch directly; direct launches
+                                also run the classes side by side on the plan's own
+                                streams (joined into the caller's stream).  0 = direct
                                 launches always (and drop the plan's graphs).  Results
                                 are bitwise those of direct launches.                    */
   MPBP_OPT_XCD_ORDER = 3,    /* 1 = hand each XCD a contiguous band of frames (default) */
@@ -147,7 +149,8 @@ enum {
                                 (8 x 8 voxels on a grid aligned with the first peak's
                                 raster); set by mpbp_autotune                            */
   MPBP_OPT_RUNS = 7          /* 1 (default): with one probe for all slices and rounded
-                                offsets (neither MPBP_PROBE_3D nor MPBP_SHEAR_LINEAR),
+                                offsets (none of MPBP_PROBE_3D, MPBP_SHEAR_LINEAR and
+                                MPBP_DETECTOR_MAP),
                                 eq. (2)'s sum over slices is grouped into runs of
                                 consecutive slices with equal exit-beam offset: the
                                 objects are summed over each run once per call, every
