@@ -5,7 +5,7 @@
 //   k_runsum    the same objects summed over each run of consecutive slices with equal
 //               exit-beam offset (one probe for all slices, rounded offsets)
 //   (k_project_runs, k_project: mpbp_project.hpp; k_frames: mpbp_frame.hpp, one
-//    instance file per detector size; k_project_map, k_grad_map: mpbp_map.hip)
+//    instance file per detector size; k_project_map, k_bp_map_color: mpbp_map.hip)
 //   k_grad      per-slice gather back-projection of the footprint gradients over all
 //               frames that cover a voxel tile, then the chain rule to df/du, df/dchi,
 //               df/dalpha (3D probes, interpolated offsets)
@@ -928,19 +928,24 @@ hipError_t prepare_kernels() {
                             160 * 1024);
   MPBP_GRAD_RUN_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
+  if (e == hipSuccess) e = prepare_map_kernels();
   return e;
 }
 
 bool grad_uses_runs(const GradArgs& a) { return a.runs && !a.probe3 && !a.shw && !a.mapz; }
 
 int grad_partials(const GradArgs& a) {
-  if (a.mapz) return grad_map_partials(a);
-  if (!grad_uses_runs(a)) return a.tiles_x * a.tiles_y;
+  if (!grad_uses_runs(a) && !a.mapz) return a.tiles_x * a.tiles_y;
   return (int)nblk(a.tied ? a.nlat : a.nlat * ((a.nz + kBpZ - 1) / kBpZ), kBpThreads);
 }
 
 int grad_effective_batch(int batch, bool runs) {
   return runs ? std::min(std::max(batch, 4), 16) : std::min(batch, 4);
+}
+
+hipError_t launch_bp_chain(const GradArgs& a, hipStream_t s) {
+  k_bp_chain<<<dim3(grad_partials(a)), dim3(kBpThreads), 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, hipStream_t s) {
@@ -958,8 +963,7 @@ hipError_t launch_grad(int batch, int tile_x, const GradArgs& a, int lds_bytes, 
     MPBP_GRAD_RUN_INSTANCES(MPBP_CASE)
 #undef MPBP_CASE
     if (e != hipSuccess) return e;
-    k_bp_chain<<<dim3(grad_partials(a)), dim3(kBpThreads), 0, s>>>(a);
-    return hipGetLastError();
+    return launch_bp_chain(a, s);
   }
   batch = grad_effective_batch(batch, false);
 #define MPBP_CASE(b, tx)                                                       \

@@ -134,6 +134,8 @@ struct mpbp_plan_t {
   std::vector<float> shw;          // [M][nz][2] their fractions (MPBP_SHEAR_LINEAR)
   int mapped = 0;                  // MPBP_DETECTOR_MAP: R interpolates in each detector frame
   std::vector<float> mapz;         // [M][nz][2] window centre of slice z, footprint coordinates
+  std::vector<int32_t> color_list; // the frames grouped by colour (no two frames of one
+  std::vector<int32_t> color_off;  // peak and colour overlap), and each colour's offset
   int64_t F = 0, ylen = 0;
   std::vector<mpbp_peak> peaks;
   std::vector<PeakDev> pdev;
@@ -187,6 +189,7 @@ struct mpbp_plan_t {
   int* d_roff = nullptr;           // [M][nz][2]
   float* d_shw = nullptr;          // [M][nz][2] fractional offsets (MPBP_SHEAR_LINEAR)
   float* d_mapz = nullptr;         // [M][nz][2] (MPBP_DETECTOR_MAP)
+  int* d_color_list = nullptr;     // [F] (MPBP_DETECTOR_MAP)
   int* d_order = nullptr;          // full-batch processing order
   int* d_list = nullptr;           // caller's list (subset calls)
   int* d_list_sorted = nullptr;    // the caller's list grouped by detector size
@@ -257,6 +260,7 @@ void free_device(mpbp_plan_t* p) {
   (void)hipFree(p->d_roff);
   (void)hipFree(p->d_shw);
   (void)hipFree(p->d_mapz);
+  (void)hipFree(p->d_color_list);
   (void)hipFree(p->d_order);
   (void)hipFree(p->d_list);
   (void)hipFree(p->d_list_sorted);
@@ -432,6 +436,12 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
       p->zrun[(size_t)m * p->nz + z] = k;
       d.nruns = k + 1;
     }
+    if (p->mapped) {
+      // the detector-map back-projection sums the frames per slice into the objects'
+      // buffer, [M][nz][ny][nx]: its chain rule reads slice z of peak m as "run" m nz + z
+      for (int z = 0; z < p->nz; ++z) p->zrun[(size_t)m * p->nz + z] = z;
+      d.nruns = p->nz;
+    }
     d.run_base = n_runs;
     n_runs += d.nruns;
     p->n_runs = n_runs;
@@ -544,13 +554,31 @@ mpbp_status build_tables(const mpbp_problem* pr, mpbp_plan_t* p) {
             p->order.push_back(d.frame_base + iy * d.cols + ix);
   }
   p->seen.assign(p->F, 0);
+  // MPBP_DETECTOR_MAP: the frames' colours for the back-projection.  Frame (iy, ix) of a
+  // peak takes colour (iy mod cy) cx + (ix mod cx), cy = ceil(np / sy), cx = ceil(np / sx):
+  // two frames of one peak and colour lie at least np apart along a raster axis, so their
+  // windows do not overlap and one launch per colour adds each voxel's frames one at a
+  // time, in colour order.
+  p->color_list.clear();
+  p->color_off.clear();
+  if (p->mapped) {
+    int nc = 0;
+    for (const auto& d : p->pdev) nc = std::max(nc, ((np + d.sy - 1) / d.sy) * ((np + d.sx - 1) / d.sx));
+    std::vector<std::vector<int32_t>> by((size_t)nc);
+    for (const auto& d : p->pdev) {
+      const int cy = (np + d.sy - 1) / d.sy, cx = (np + d.sx - 1) / d.sx;
+      for (int iy = 0; iy < d.rows; ++iy)
+        for (int ix = 0; ix < d.cols; ++ix) by[(size_t)((iy % cy) * cx + ix % cx)].push_back(d.frame_base + iy * d.cols + ix);
+    }
+    p->color_off.assign((size_t)nc + 1, 0);
+    for (int c = 0; c < nc; ++c) {
+      p->color_off[c + 1] = p->color_off[c] + (int)by[c].size();
+      p->color_list.insert(p->color_list.end(), by[c].begin(), by[c].end());
+    }
+  }
   {
     const long long lanes = (long long)p->ny * p->nx * (p->tied ? 1 : (p->nz + mpbp::kBpZ - 1) / mpbp::kBpZ);
     p->max_parts = std::max<long long>(p->max_tiles, (lanes + mpbp::kBpThreads - 1) / mpbp::kBpThreads);
-    if (p->mapped) {   // the detector-map back-projection: one partial per workgroup of voxels
-      const long long tasks = p->tied ? (long long)p->ny * p->nx : p->nvox;
-      p->max_parts = std::max<long long>(p->max_parts, (tasks + mpbp::kMapThreads - 1) / mpbp::kMapThreads);
-    }
   }
   p->sub_classes.reserve(p->classes.size());
   return MPBP_OK;
@@ -575,6 +603,7 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   ALLOC(p->d_shear, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_shw, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_mapz, (size_t)p->M * p->nz * 2);
+  ALLOC(p->d_color_list, std::max<int64_t>(p->F, 1));
   ALLOC(p->d_zrun, (size_t)p->M * p->nz);
   ALLOC(p->d_roff, (size_t)p->M * p->nz * 2);
   ALLOC(p->d_order, p->F);
@@ -601,6 +630,8 @@ mpbp_status alloc_device(mpbp_plan_t* p) {
   if (e == hipSuccess) e = hipMemcpy(p->d_shear, p->shear.data(), p->shear.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_shw, p->shw.data(), p->shw.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_mapz, p->mapz.data(), p->mapz.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p->color_list.empty())
+    e = hipMemcpy(p->d_color_list, p->color_list.data(), p->color_list.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_zrun, p->zrun.data(), p->zrun.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_roff, p->roff.data(), p->roff.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_order, p->order.data(), p->order.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -861,11 +892,7 @@ int bp_parts(mpbp_plan p) {
 }
 
 int grad_parts(mpbp_plan p) {
-  if (p->mapped) {
-    const long long tasks = p->tied ? (long long)p->ny * p->nx : p->nvox;
-    return (int)((tasks + mpbp::kMapThreads - 1) / mpbp::kMapThreads);
-  }
-  if (uses_runs(p)) return bp_parts(p);
+  if (p->mapped || uses_runs(p)) return bp_parts(p);
   return grad_tiling(p).nx * grad_tiling(p).ny;
 }
 
@@ -897,6 +924,12 @@ mpbp::GradArgs grad_args(mpbp_plan p, const Work& w, const float* u, const float
   g.zrun = p->d_zrun;
   g.roff = reinterpret_cast<const int2*>(p->d_roff);
   g.mapz = p->mapped ? reinterpret_cast<const float2*>(p->d_mapz) : nullptr;
+  g.peak_of = p->d_peak_of;
+  g.scan = p->d_scan;
+  g.color_list = p->d_color_list;
+  g.color_off = p->color_off.data();
+  g.n_colors = p->color_off.empty() ? 0 : (int)p->color_off.size() - 1;
+  g.map_pix = p->acc_pix;
   g.grad_u = grad_u; g.grad_chi = grad_chi;
   g.alpha_part = w.apart;
   return g;
@@ -1838,6 +1871,8 @@ mpbp_status mpbp_autotune(mpbp_plan plan, const float* u, const float* chi, cons
                                             : std::vector<int>(std::begin(mpbp::kGradBatches), std::end(mpbp::kGradBatches));
       for (int B : batches) {
         if (e != hipSuccess) break;
+        // the detector-map back-projection has no batch or tile width: time it once
+        if (g.mapz && (TX != mpbp::kGradTileXs[0] || B != batches[0])) continue;
         double us = 1e300;
         for (int round = 0; round < 2 && e == hipSuccess; ++round) {
           double t = 0.0;

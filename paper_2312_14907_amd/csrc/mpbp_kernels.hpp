@@ -106,6 +106,13 @@ struct GradArgs {
   const int* zrun;           // [M][nz] run of each slice (consecutive slices of equal offset)
   const int2* roff;          // [M][nz] footprint offset (s_y - min s_y, s_x - min s_x) of run k
   const float2* mapz;        // MPBP_DETECTOR_MAP: as FrameArgs::mapz (null: no map)
+  const int* peak_of;        // [F]
+  const int* scan;           // [F][2] (py, px)
+  const int* color_list;     // MPBP_DETECTOR_MAP: the frames grouped by colour (no two
+                             // frames of one peak and colour overlap)
+  const int* color_off;      // (host) [n_colors + 1] offset of each colour in color_list
+  int n_colors;
+  int map_pix;               // the plan's largest footprint fy * fx (multiple of 4)
   float* grad_u;
   float* grad_chi;
   double* alpha_part;      // [n_blocks][M]

@@ -46,7 +46,9 @@ int grad_effective_batch(int batch, bool runs);
 // launch_grad dispatch to them.
 hipError_t launch_project_map(const FrameArgs& a, hipStream_t s);
 hipError_t launch_grad_map(const GradArgs& a, hipStream_t s);
-int grad_map_partials(const GradArgs& a);
+hipError_t prepare_map_kernels();
+// The chain rule per voxel from the frame sums per run in a.rs (k_bp_chain).
+hipError_t launch_bp_chain(const GradArgs& a, hipStream_t s);
 hipError_t launch_finalize(const double* floss, const int* out_list, int n_out, double* loss,
                            float* frame_loss, const double* apart, int n_part, int n_peaks,
                            float* grad_alpha, hipStream_t s);

@@ -6,14 +6,17 @@
 // each exit-wave pixel takes the bilinear interpolation of the illuminated slice P_z O_z
 // (zero off the probe support and off the object) at its pre-image, and the slices are
 // summed.
-//   k_project_map  one workgroup per frame: each lane owns footprint pixels and sums, over
-//                  the slices, the four taps around the pixel's pre-image (a gather: no
-//                  two lanes write one pixel, so no accumulator in LDS)
-//   k_grad_map     one lane per voxel (per lateral pixel when z-tied): for each covering
-//                  frame of the minibatch, the footprint pixels whose pre-image lies
-//                  within one sample of the voxel's probe-window point, with the same tent
-//                  weights (the adjoint of the interpolation), times conj(P_z); then the
-//                  chain rule of eq. (1)/(3).  Every sum runs in a fixed order.
+//   k_project_map  one workgroup per frame: each illuminated slice is staged on the probe
+//                  window in LDS (with a zero border), and each lane sums, over the
+//                  slices, the four taps around its footprint pixels' pre-images (a
+//                  gather: no two lanes write one pixel)
+//   k_bp_map_color the adjoint, per colour of frames (frames of one peak and colour do
+//                  not overlap): one workgroup per frame stages its footprint gradient in
+//                  LDS; for each slice and window point, the footprint pixels whose
+//                  pre-image lies within one sample of the point, with the same tent
+//                  weights, times conj(P_z), are added to the slice's frame sum G_{m,z}.
+//                  The colours run in order, so every sum has a fixed order; k_bp_chain
+//                  then applies the chain rule of eq. (1)/(3) per voxel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -34,6 +37,10 @@ __device__ __forceinline__ float2 preimage(const PeakDev& pk, float2 c, float h,
   return make_float2(fmaf(pk.mi[0], ry, fmaf(pk.mi[1], rx, h)), fmaf(pk.mi[2], ry, fmaf(pk.mi[3], rx, h)));
 }
 
+// Footprint pixels a lane sums in registers per pass over the slices (a footprint of
+// more than kMapThreads * kMapQ pixels takes several passes).
+constexpr int kMapQ = 16;
+
 template <bool P3>
 __global__ __launch_bounds__(kMapThreads) void k_project_map(FrameArgs A) {
   extern __shared__ cplx smem[];
@@ -49,123 +56,188 @@ __global__ __launch_bounds__(kMapThreads) void k_project_map(FrameArgs A) {
   const long long plane = (long long)A.ny * A.nx;
   const cplx* O = reinterpret_cast<const cplx*>(A.obj) + (long long)m * nz * plane;
   const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * (P3 ? nz : 1) * np * np;
-  float2* cz = reinterpret_cast<float2*>(smem);   // [nz] window centre of each slice
-  cplx* Ps = smem + nz;                           // [np][np] (one probe for all slices)
-  for (int z = threadIdx.x; z < nz; z += kMapThreads) cz[z] = A.mapz[(long long)m * nz + z];
+  // LDS: the slices' window centres, the probe, and two buffers of an illuminated slice
+  // on the probe window with a zero border of one sample (W x W, W = np + 2): a tap off
+  // the support or off the object reads an exact zero, so the interpolation needs no
+  // bounds checks
+  const int W = np + 2;
+  float2* cz = reinterpret_cast<float2*>(smem);   // [nz]
+  cplx* Ps = smem + nz;                           // [np][np]
+  cplx* ill = Ps + np * np;                       // [2][W][W]
+  const int tid = threadIdx.x;
+  for (int z = tid; z < nz; z += kMapThreads) cz[z] = A.mapz[(long long)m * nz + z];
   if (!P3)
-    for (int k = threadIdx.x; k < np * np; k += kMapThreads) Ps[k] = probe[k];
+    for (int k = tid; k < np * np; k += kMapThreads) Ps[k] = probe[k];
+  for (int k = tid; k < 2 * W * W; k += kMapThreads) ill[k] = {0.f, 0.f};
   __syncthreads();
-  // taps (a, b) are live inside the probe support and over the object grid
-  const int a0 = max(0, -py), a1 = min(np, A.ny - py);
-  const int b0 = max(0, -px), b1 = min(np, A.nx - px);
   const float h = 0.5f * (float)np;
-  for (int q = threadIdx.x; q < fy * fx; q += kMapThreads) {
-    const int qy = q / fx, qx = q - (q / fx) * fx;
-    cplx acc = {0.f, 0.f};
+  const int npix = fy * fx;
+  for (int q0 = 0; q0 < npix; q0 += kMapThreads * kMapQ) {
+    cplx acc[kMapQ];
+#pragma unroll
+    for (int i = 0; i < kMapQ; ++i) acc[i] = {0.f, 0.f};
     for (int z = 0; z < nz; ++z) {
-      const float2 p = preimage(pk, cz[z], h, qy, qx);
-      if (!(p.x > -1.f && p.x < (float)np && p.y > -1.f && p.y < (float)np)) continue;
-      const float y0 = floorf(p.x), x0 = floorf(p.y);
-      const float ty = p.x - y0, tx = p.y - x0;
-      const int iy = (int)y0, ix = (int)x0;
+      // stage P_z O_z of this frame's window (its interior; the border stays zero).  The
+      // other buffer still serves the previous slice: one barrier per slice suffices.
+      cplx* buf = ill + (z & 1) * W * W;
       const cplx* Oz = O + (long long)z * plane;
       const cplx* Pz = P3 ? probe + (long long)z * np * np : Ps;
+      for (int e = tid; e < np * np; e += kMapThreads) {
+        const int a = e / np, b = e - (e / np) * np;
+        const int oy = py + a, ox = px + b;
+        const bool in = (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
+        const cplx v = in ? cmul(Pz[e], Oz[(long long)oy * A.nx + ox]) : cplx{0.f, 0.f};
+        buf[(a + 1) * W + b + 1] = v;
+      }
+      __syncthreads();
+      const float2 c = cz[z];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int a = iy + (t >> 1), b = ix + (t & 1);
-        if (a >= a0 && a < a1 && b >= b0 && b < b1) {
-          const float w = ((t >> 1) ? ty : 1.f - ty) * ((t & 1) ? tx : 1.f - tx);
-          const cplx v = cmul(Pz[a * np + b], Oz[(long long)(py + a) * A.nx + (px + b)]);
-          acc = cadd(acc, cscale(v, w));
+      for (int i = 0; i < kMapQ; ++i) {
+        const int q = q0 + tid + kMapThreads * i;
+        if (q < npix) {
+          const int qy = q / fx, qx = q - (q / fx) * fx;
+          const float2 p = preimage(pk, c, h, qy, qx);
+          if (p.x > -1.f && p.x < (float)np && p.y > -1.f && p.y < (float)np) {
+            const float y0 = floorf(p.x), x0 = floorf(p.y);
+            const float ty = p.x - y0, tx = p.y - x0;
+            const cplx* t = buf + ((int)y0 + 1) * W + (int)x0 + 1;   // tap (y0, x0)
+            const cplx v00 = t[0], v01 = t[1], v10 = t[W], v11 = t[W + 1];
+            // bilinear: along x, then along y
+            const cplx top = {fmaf(tx, v01.x - v00.x, v00.x), fmaf(tx, v01.y - v00.y, v00.y)};
+            const cplx bot = {fmaf(tx, v11.x - v10.x, v10.x), fmaf(tx, v11.y - v10.y, v10.y)};
+            acc[i] = {acc[i].x + fmaf(ty, bot.x - top.x, top.x), acc[i].y + fmaf(ty, bot.y - top.y, top.y)};
+          }
         }
       }
     }
-    slot[q] = acc;
-  }
-}
-
-template <bool P3>
-__global__ __launch_bounds__(kMapThreads) void k_grad_map(GradArgs A) {
-  __shared__ float red[kMapThreads / 64];
-  __shared__ double apl[kMaxPeaksDev];
-  const int tid = threadIdx.x;
-  const int np = A.np, nz = A.nz;
-  const long long nlat = (long long)A.ny * A.nx;
-  const long long nvox = nlat * nz;
-  const long long task = (long long)blockIdx.x * kMapThreads + tid;
-  const bool live = task < (A.tied ? nlat : nvox);
-  const long long lat = live ? task % nlat : 0;
-  const int zlo = (A.tied || !live) ? 0 : (int)(task / nlat);
-  const int zhi = !live ? 0 : A.tied ? nz : zlo + 1;
-  const int y = (int)(lat / A.nx), x = (int)(lat - (lat / A.nx) * A.nx);
-  const long long fstride = A.tied ? nlat : nvox;   // field component stride
-  const float h = 0.5f * (float)np;
-  const cplx* slots = reinterpret_cast<const cplx*>(A.slots);
-  if (tid < kMaxPeaksDev) apl[tid] = 0.0;
-  float gux = 0.f, guy = 0.f, guz = 0.f, gch = 0.f;
-  for (int m = 0; m < A.n_peaks; ++m) {
-    const PeakDev pk = uniform_peak(A.peaks + m);
-    const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * (P3 ? nz : 1) * np * np;
-    const float al = A.alpha[m];
-    // frames whose window covers (y, x): window origin p with p <= (y, x) < p + np
-    const int iy_lo = max(0, -floordiv(-(y - np + 1 - pk.oy), pk.sy));
-    const int iy_hi = min(pk.rows - 1, floordiv(y - pk.oy, pk.sy));
-    const int ix_lo = max(0, -floordiv(-(x - np + 1 - pk.ox), pk.sx));
-    const int ix_hi = min(pk.cols - 1, floordiv(x - pk.ox, pk.sx));
-    // exit-wave pixels within one sample of a point: the image of a 2 x 2 square
-    const float hy = fabsf(pk.mm[0]) + fabsf(pk.mm[1]), hx = fabsf(pk.mm[2]) + fabsf(pk.mm[3]);
-    float ap = 0.f;
-    for (int z = zlo; z < zhi; ++z) {
-      const float2 c = A.mapz[(long long)m * nz + z];
-      const cplx* Pz = probe + (P3 ? (long long)z * np * np : 0);
-      cplx acc = {0.f, 0.f};
-      for (int iy = iy_lo; iy <= iy_hi; ++iy)
-        for (int ix = ix_lo; ix <= ix_hi; ++ix) {
-          const int f = iy * pk.cols + ix;
-          if (!A.all_active && !A.active[pk.frame_base + f]) continue;
-          const int a = y - (pk.oy + iy * pk.sy), b = x - (pk.ox + ix * pk.sx);
-          const float ca = (float)a - h, cb = (float)b - h;
-          const float qcy = fmaf(pk.mm[0], ca, fmaf(pk.mm[1], cb, c.x));
-          const float qcx = fmaf(pk.mm[2], ca, fmaf(pk.mm[3], cb, c.y));
-          const int qy0 = (int)floorf(qcy - hy), qx0 = (int)floorf(qcx - hx);
-          const cplx* g = slots + pk.slot_off + (long long)f * pk.fy * pk.fx;
-          cplx s = {0.f, 0.f};
-          for (int dy = 0; dy < pk.ncy; ++dy) {
-            const int qy = qy0 + dy;
-            if ((unsigned)qy >= (unsigned)pk.fy) continue;
-            for (int dx = 0; dx < pk.ncx; ++dx) {
-              const int qx = qx0 + dx;
-              if ((unsigned)qx >= (unsigned)pk.fx) continue;
-              const float2 p = preimage(pk, c, h, qy, qx);
-              const float wy = 1.f - fabsf(p.x - (float)a), wx = 1.f - fabsf(p.y - (float)b);
-              if (wy > 0.f && wx > 0.f) s = cadd(s, cscale(g[qy * pk.fx + qx], wy * wx));
-            }
-          }
-          acc = cmulc_acc(acc, s, Pz[a * np + b]);   // conj(P_z) times the weighted sum
-        }
-      const long long v = A.tied ? lat : (long long)z * nlat + lat;
-      chain_voxel(pk, acc, A.u[v], A.u[fstride + v], A.u[2 * fstride + v], A.chi[v], al, gux, guy, guz, gch, ap);
+#pragma unroll
+    for (int i = 0; i < kMapQ; ++i) {
+      const int q = q0 + tid + kMapThreads * i;
+      if (q < npix) slot[q] = acc[i];
     }
-    const float apb = block_sum_f(ap, red);
-    if (tid == 0) apl[m] += (double)apb;
+    __syncthreads();   // the next pass restages the slices
   }
-  if (live) {
-    const long long v = A.tied ? lat : (long long)zlo * nlat + lat;
-    A.grad_u[v] = gux;
-    A.grad_u[fstride + v] = guy;
-    A.grad_u[2 * fstride + v] = guz;
-    A.grad_chi[v] = gch;
-  }
-  __syncthreads();
-  if (tid < A.n_peaks) A.alpha_part[(long long)blockIdx.x * A.n_peaks + tid] = apl[tid];
 }
 
-static unsigned map_blocks(long long n) { return (unsigned)((n + kMapThreads - 1) / kMapThreads); }
+// Window points a lane back-projects (probe_n^2 <= kMapThreads * kMapE).
+constexpr int kMapE = 4;
+
+// Footprint pixels q whose pre-image p(q) lies within one sample of window point (a, b):
+// the rows are the image of the 2 x 2 square around (a, b); in each row both tent
+// conditions |p - (a, b)| < 1 are linear in q_x and give an interval.  The intervals are
+// widened by kMapSlack (pixels) against the rounding of their ends, and each pixel's
+// weight is then the projection's (its pre-image and tents): a pixel of weight zero adds
+// nothing.
+constexpr float kMapSlack = 1e-3f;
+
+__device__ __forceinline__ cplx map_gather(const PeakDev& pk, const cplx* __restrict__ gs, float2 c, float h,
+                                           float hy, float inv1, float inv3, int a, int b) {
+  const float fa = (float)a, fb = (float)b;
+  const float qcy = fmaf(pk.mm[0], fa - h, fmaf(pk.mm[1], fb - h, c.x));
+  const int qy_lo = max(0, (int)ceilf(qcy - hy - kMapSlack));
+  const int qy_hi = min(pk.fy - 1, (int)floorf(qcy + hy + kMapSlack));
+  cplx s = {0.f, 0.f};
+  for (int qy = qy_lo; qy <= qy_hi; ++qy) {
+    const float ry = (float)qy - c.x;
+    // p_y - a = by + mi1 (q_x - c_x), p_x - b = bx + mi3 (q_x - c_x), with q_x - c_x = t
+    const float by = fmaf(pk.mi[0], ry, h - fa), bx = fmaf(pk.mi[2], ry, h - fb);
+    float lo = -1e30f, hi = 1e30f;
+    if (inv1 != 0.f) {
+      const float t0 = (-1.f - by) * inv1, t1 = (1.f - by) * inv1;
+      lo = fmaxf(lo, fminf(t0, t1));
+      hi = fminf(hi, fmaxf(t0, t1));
+    } else if (fabsf(by) >= 1.f) {
+      continue;
+    }
+    if (inv3 != 0.f) {
+      const float t0 = (-1.f - bx) * inv3, t1 = (1.f - bx) * inv3;
+      lo = fmaxf(lo, fminf(t0, t1));
+      hi = fminf(hi, fmaxf(t0, t1));
+    } else if (fabsf(bx) >= 1.f) {
+      continue;
+    }
+    const int qx_lo = max(0, (int)ceilf(fmaxf(lo + c.y - kMapSlack, -1.f)));
+    const int qx_hi = min(pk.fx - 1, (int)floorf(fminf(hi + c.y + kMapSlack, (float)pk.fx)));
+    for (int qx = qx_lo; qx <= qx_hi; ++qx) {
+      const float2 p = preimage(pk, c, h, qy, qx);
+      const float wy = 1.f - fabsf(p.x - fa), wx = 1.f - fabsf(p.y - fb);
+      if (wy > 0.f && wx > 0.f) s = cadd(s, cscale(gs[qy * pk.fx + qx], wy * wx));
+    }
+  }
+  return s;
+}
+
+// Back-projection of the frames of one colour (list[0 .. n)): one workgroup per frame
+// stages the frame's footprint gradient in LDS and, for every slice z and window point
+// (a, b), adds conj(P_z[a, b]) times the tent-weighted sum of its pixels (map_gather) to
+// G_{m,z} at object pixel (p_y + a, p_x + b) (read, add, write: the colour's frames of one
+// peak do not overlap).  G is complex64 [M][nz][ny][nx] in A.rs.
+template <bool P3>
+__global__ __launch_bounds__(kMapThreads) void k_bp_map_color(GradArgs A, const int* __restrict__ list, int n) {
+  extern __shared__ cplx smem[];
+  if ((int)blockIdx.x >= n) return;
+  const int fid = list[blockIdx.x];
+  if (!A.all_active && !A.active[fid]) return;
+  const int m = A.peak_of[fid];
+  const PeakDev pk = uniform_peak(A.peaks + m);
+  const int np = A.np, nz = A.nz;
+  const int py = A.scan[2 * fid], px = A.scan[2 * fid + 1];
+  const int npix = pk.fy * pk.fx;
+  const cplx* g = reinterpret_cast<const cplx*>(A.slots) + pk.slot_off + (long long)(fid - pk.frame_base) * npix;
+  const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * (P3 ? nz : 1) * np * np;
+  cplx* Ps = smem;             // [np][np] (one probe for all slices)
+  cplx* gs = smem + np * np;   // [fy][fx]
+  const int tid = threadIdx.x;
+  if (!P3)
+    for (int k = tid; k < np * np; k += kMapThreads) Ps[k] = probe[k];
+  for (int k = tid; k < npix; k += kMapThreads) gs[k] = g[k];
+  __syncthreads();
+  const float h = 0.5f * (float)np;
+  const float hy = fabsf(pk.mm[0]) + fabsf(pk.mm[1]);
+  const float inv1 = pk.mi[1] != 0.f ? 1.f / pk.mi[1] : 0.f;
+  const float inv3 = pk.mi[3] != 0.f ? 1.f / pk.mi[3] : 0.f;
+  cplx* G = reinterpret_cast<cplx*>(A.rs) + (long long)m * nz * A.nlat;
+  int a[kMapE], b[kMapE];
+  long long off[kMapE];   // object pixel of window point e (-1: off the window or the grid)
+#pragma unroll
+  for (int i = 0; i < kMapE; ++i) {
+    const int e = tid + kMapThreads * i;
+    a[i] = e / np;
+    b[i] = e - a[i] * np;
+    const int oy = py + a[i], ox = px + b[i];
+    const bool in = e < np * np && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
+    off[i] = in ? (long long)oy * A.nx + ox : -1;
+  }
+  for (int z = 0; z < nz; ++z) {
+    const float2 c = A.mapz[(long long)m * nz + z];
+    const cplx* Pz = P3 ? probe + (long long)z * np * np : Ps;
+    cplx* Gz = G + (long long)z * A.nlat;
+    cplx old[kMapE];
+#pragma unroll
+    for (int i = 0; i < kMapE; ++i) old[i] = off[i] >= 0 ? Gz[off[i]] : cplx{0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < kMapE; ++i) {
+      if (off[i] >= 0) {
+        const cplx s = map_gather(pk, gs, c, h, hy, inv1, inv3, a[i], b[i]);
+        Gz[off[i]] = cmulc_acc(old[i], s, Pz[a[i] * np + b[i]]);
+      }
+    }
+  }
+}
+
+hipError_t prepare_map_kernels() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_bp_map_color<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_bp_map_color<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  return e;
+}
 
 hipError_t launch_project_map(const FrameArgs& a, hipStream_t s) {
   const unsigned grid = a.xcd ? (unsigned)(((a.n_list + 7) / 8) * 8) : (unsigned)a.n_list;
   if (grid == 0) return hipSuccess;
-  const size_t lds = (size_t)a.nz * sizeof(float2) + (size_t)a.np * a.np * sizeof(cplx);
+  const size_t W = (size_t)a.np + 2;
+  const size_t lds = (size_t)a.nz * sizeof(float2) + ((size_t)a.np * a.np + 2 * W * W) * sizeof(cplx);
   if (a.probe3)
     k_project_map<true><<<dim3(grid), dim3(kMapThreads), lds, s>>>(a);
   else
@@ -173,18 +245,27 @@ hipError_t launch_project_map(const FrameArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int grad_map_partials(const GradArgs& a) {
-  const long long nlat = (long long)a.ny * a.nx;
-  return (int)map_blocks(a.tied ? nlat : nlat * a.nz);
-}
-
+// G = 0, one launch of k_bp_map_color per colour (in colour order: each object pixel
+// adds its frames in a fixed order), then the chain rule per voxel (k_bp_chain, with
+// slice z of peak m as run m nz + z).
 hipError_t launch_grad_map(const GradArgs& a, hipStream_t s) {
-  const unsigned grid = (unsigned)grad_map_partials(a);
-  if (a.probe3)
-    k_grad_map<true><<<dim3(grid), dim3(kMapThreads), 0, s>>>(a);
-  else
-    k_grad_map<false><<<dim3(grid), dim3(kMapThreads), 0, s>>>(a);
-  return hipGetLastError();
+  static_assert((kProjMaxPix + kMapThreads * kMapE) * sizeof(cplx) <= 160 * 1024, "k_bp_map_color's LDS");
+  if (!a.color_off || a.n_colors < 1 || a.np * a.np > kMapThreads * kMapE || a.map_pix > kProjMaxPix)
+    return hipErrorInvalidValue;
+  hipError_t e = launch_fill(a.rs, 2LL * a.n_peaks * a.nz * a.nlat, 0.f, s);
+  const size_t lds = ((size_t)a.np * a.np + (size_t)a.map_pix) * sizeof(cplx);
+  for (int c = 0; c < a.n_colors && e == hipSuccess; ++c) {
+    const int n = a.color_off[c + 1] - a.color_off[c];
+    if (n <= 0) continue;
+    const int* list = a.color_list + a.color_off[c];
+    if (a.probe3)
+      k_bp_map_color<true><<<dim3((unsigned)n), dim3(kMapThreads), lds, s>>>(a, list, n);
+    else
+      k_bp_map_color<false><<<dim3((unsigned)n), dim3(kMapThreads), lds, s>>>(a, list, n);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  return launch_bp_chain(a, s);
 }
 
 }  // namespace mpbp
