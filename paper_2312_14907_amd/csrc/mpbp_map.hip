@@ -167,6 +167,47 @@ __device__ __forceinline__ cplx map_gather(const PeakDev& pk, const cplx* __rest
   return s;
 }
 
+// map_gather for a map whose inverse has no zero in its second column (mi1, mi3 != 0):
+// along a row the tent arguments p - (a, b) and both interval ends change by fixed steps,
+// so they are carried from pixel to pixel and from row to row instead of being formed
+// anew (pixels of non-positive weight that the slack lets in take weight zero).
+__device__ __forceinline__ cplx map_gather_steps(const PeakDev& pk, const cplx* __restrict__ gs, float2 c, float h,
+                                                 float hy, float inv1, float inv3, int a, int b) {
+  const float fa = (float)a, fb = (float)b;
+  const float qcy = fmaf(pk.mm[0], fa - h, fmaf(pk.mm[1], fb - h, c.x));
+  const int qy_lo = max(0, (int)ceilf(qcy - hy - kMapSlack));
+  const int qy_hi = min(pk.fy - 1, (int)floorf(qcy + hy + kMapSlack));
+  const float ry = (float)qy_lo - c.x;
+  float by = fmaf(pk.mi[0], ry, h - fa), bx = fmaf(pk.mi[2], ry, h - fb);
+  // ends, in t = q_x - c_x, of the intervals of |by + mi1 t| < 1 and |bx + mi3 t| < 1
+  const float sg1 = inv1 > 0.f ? 1.f : -1.f, sg3 = inv3 > 0.f ? 1.f : -1.f;
+  float loy = (-sg1 - by) * inv1, hiy = (sg1 - by) * inv1;
+  float lox = (-sg3 - bx) * inv3, hix = (sg3 - bx) * inv3;
+  const float sty = -pk.mi[0] * inv1, stx = -pk.mi[2] * inv3;   // their change per row
+  cplx s = {0.f, 0.f};
+  const cplx* row = gs + qy_lo * pk.fx;
+  for (int qy = qy_lo; qy <= qy_hi; ++qy) {
+    const float lo = fmaxf(loy, lox) + c.y, hi = fminf(hiy, hix) + c.y;
+    const int qx_lo = max(0, (int)ceilf(fmaxf(lo - kMapSlack, -1.f)));
+    const int qx_hi = min(pk.fx - 1, (int)floorf(fminf(hi + kMapSlack, (float)pk.fx)));
+    float dy = fmaf(pk.mi[1], (float)qx_lo - c.y, by), dx = fmaf(pk.mi[3], (float)qx_lo - c.y, bx);
+    for (int qx = qx_lo; qx <= qx_hi; ++qx) {
+      const float w = fmaxf(1.f - fabsf(dy), 0.f) * fmaxf(1.f - fabsf(dx), 0.f);
+      const cplx v = row[qx];
+      s.x = fmaf(w, v.x, s.x);
+      s.y = fmaf(w, v.y, s.y);
+      dy += pk.mi[1];
+      dx += pk.mi[3];
+    }
+    by += pk.mi[0];
+    bx += pk.mi[2];
+    loy += sty; hiy += sty;
+    lox += stx; hix += stx;
+    row += pk.fx;
+  }
+  return s;
+}
+
 // Back-projection of the frames of one colour (list[0 .. n)): one workgroup per frame
 // stages the frame's footprint gradient in LDS and, for every slice z and window point
 // (a, b), adds conj(P_z[a, b]) times the tent-weighted sum of its pixels (map_gather) to
@@ -196,6 +237,7 @@ __global__ __launch_bounds__(kMapThreads) void k_bp_map_color(GradArgs A, const 
   const float hy = fabsf(pk.mm[0]) + fabsf(pk.mm[1]);
   const float inv1 = pk.mi[1] != 0.f ? 1.f / pk.mi[1] : 0.f;
   const float inv3 = pk.mi[3] != 0.f ? 1.f / pk.mi[3] : 0.f;
+  const bool steps = inv1 != 0.f && inv3 != 0.f;   // uniform
   cplx* G = reinterpret_cast<cplx*>(A.rs) + (long long)m * nz * A.nlat;
   int a[kMapE], b[kMapE];
   long long off[kMapE];   // object pixel of window point e (-1: off the window or the grid)
@@ -218,7 +260,8 @@ __global__ __launch_bounds__(kMapThreads) void k_bp_map_color(GradArgs A, const 
 #pragma unroll
     for (int i = 0; i < kMapE; ++i) {
       if (off[i] >= 0) {
-        const cplx s = map_gather(pk, gs, c, h, hy, inv1, inv3, a[i], b[i]);
+        const cplx s = steps ? map_gather_steps(pk, gs, c, h, hy, inv1, inv3, a[i], b[i])
+                             : map_gather(pk, gs, c, h, hy, inv1, inv3, a[i], b[i]);
         Gz[off[i]] = cmulc_acc(old[i], s, Pz[a[i] * np + b[i]]);
       }
     }
