@@ -147,7 +147,9 @@ enum {
                                 mpbp_autotune                                            */
   MPBP_OPT_GRAD_TILE = 6,    /* back-projection tile: 16 (16 x 4 voxels, default) or 8
                                 (8 x 8 voxels on a grid aligned with the first peak's
-                                raster); set by mpbp_autotune                            */
+                                raster); set by mpbp_autotune.  Neither this nor
+                                MPBP_OPT_GRAD_BATCH affects MPBP_DETECTOR_MAP plans,
+                                whose back-projection walks each frame once per slice */
   MPBP_OPT_RUNS = 7          /* 1 (default): with one probe for all slices and rounded
                                 offsets (none of MPBP_PROBE_3D, MPBP_SHEAR_LINEAR and
                                 MPBP_DETECTOR_MAP),
