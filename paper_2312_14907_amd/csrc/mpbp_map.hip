@@ -99,6 +99,10 @@ __global__ __launch_bounds__(kMapThreads) void k_project_map(FrameArgs A) {
           const float2 p = preimage(pk, c, h, qy, qx);
           if (p.x > -1.f && p.x < (float)np && p.y > -1.f && p.y < (float)np) {
             const float y0 = floorf(p.x), x0 = floorf(p.y);
+            // the four taps lie in the bordered window: y0, x0 in [-1, np - 1]
+            if (!MPBP_CHECK(A.dbg, y0 >= -1.f && y0 <= (float)(np - 1) && x0 >= -1.f && x0 <= (float)(np - 1),
+                            kDbgSlot))
+              continue;
             const float ty = p.x - y0, tx = p.y - x0;
             const cplx* t = buf + ((int)y0 + 1) * W + (int)x0 + 1;   // tap (y0, x0)
             const cplx v00 = t[0], v01 = t[1], v10 = t[W], v11 = t[W + 1];
@@ -224,6 +228,7 @@ __global__ __launch_bounds__(kMapThreads) void k_bp_map_color(GradArgs A, const 
   const int np = A.np, nz = A.nz;
   const int py = A.scan[2 * fid], px = A.scan[2 * fid + 1];
   const int npix = pk.fy * pk.fx;
+  if (!MPBP_CHECK(A.dbg, npix <= A.map_pix && m >= 0 && m < A.n_peaks, kDbgSlot)) return;   // LDS holds map_pix
   const cplx* g = reinterpret_cast<const cplx*>(A.slots) + pk.slot_off + (long long)(fid - pk.frame_base) * npix;
   const cplx* probe = reinterpret_cast<const cplx*>(A.probe) + (long long)m * (P3 ? nz : 1) * np * np;
   cplx* Ps = smem;             // [np][np] (one probe for all slices)

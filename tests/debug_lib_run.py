@@ -16,7 +16,7 @@ import torch  # noqa: E402
 from oracle import mpbp_oracle as O  # noqa: E402
 from paper_2312_14907_amd import binding as B  # noqa: E402
 from synth import get_config, make_fields, make_problem, photon_rng, poisson_counts  # noqa: E402
-from synth.inputs import incident_probe_3d  # noqa: E402
+from synth.inputs import detector_map, incident_probe_3d  # noqa: E402
 from tests.conftest import ragged  # noqa: E402
 
 assert os.path.basename(B.LIB_PATH) == "libmpbp_debug.so", B.LIB_PATH
@@ -79,6 +79,21 @@ for name, kw in cases:
         assert np.linalg.norm(gu.reshape(ref["grad_u"].shape) - ref["grad_u"]) <= 1e-3 * np.linalg.norm(ref["grad_u"])
 loss, _ = run(lin, f, y, flags=B.MPBP_SHEAR_LINEAR)
 print("c1 interpolated offsets", loss, flush=True)
+# detector maps: per peak a pixel ratio and a detector-frame angle (the last one a quarter
+# turn and more), then the identity (the map's general back-projection walk)
+for maps in ([(1.1, 0.4), (0.85, -1.0), (1.0, np.pi / 2 + 0.2)], [(1.0, 0.0)] * 3):
+    mp = dataclasses.replace(prob, lateral_map=np.stack([detector_map(r, a) for r, a in maps]))
+    ym = ragged(O.model_intensity(f["u"], f["chi"], f["alpha"], f["probe"], mp)).astype(np.float32)
+    refm = O.loss_grad((f["u"] + f["delta"]).astype(np.float32), f["chi"], f["alpha"], f["probe"], ym, mp)
+    for name, kw in [("full batch", {}), ("minibatch", dict(frames=list(range(3, 70, 4)))),
+                     ("z-tied", dict(flags=B.MPBP_Z_TIED)), ("3d probe", dict(flags=B.MPBP_PROBE_3D, probe=p3))]:
+        kw = dict(kw, flags=kw.get("flags", 0) | B.MPBP_DETECTOR_MAP)
+        loss, gu = run(mp, f, ym, **kw)
+        print("c1 detector map", maps[0], name, loss, flush=True)
+        if name == "full batch":
+            assert abs(loss - refm["loss"]) <= 1e-5 * refm["loss"], (loss, refm["loss"])
+            assert np.linalg.norm(gu.reshape(refm["grad_u"].shape) - refm["grad_u"]) <= \
+                1e-3 * np.linalg.norm(refm["grad_u"])
 for name in ("c2_forward", "c4_batch", "c6_paper100"):
     cfg = get_config(name)
     prob = make_problem(cfg)

@@ -1,6 +1,7 @@
 """The bounds-checked debug library (libmpbp_debug.so, MPBP_DEBUG): every code path of
 the projection and the back-projection on c1 (fused per run and per slice, plain, a
-minibatch, z-tied, 3D probes, interpolated offsets, the allocation-free call, graph off),
+minibatch, z-tied, 3D probes, interpolated offsets, detector maps, the allocation-free
+call, graph off),
 c2, c4 and the 100-slice paper-shaped workload, with no device-side check firing
 (a check that fires makes the call return MPBP_ERR_INTERNAL), and the c1 results within
 the parity tolerances of the oracle.  Runs in a child process that loads the debug
