@@ -107,16 +107,31 @@ def code_text(src):
     return re.sub(r"\s+", " ", src).strip()
 
 
-def kernel_source_hash():
-    """sha256 (first 16 hex digits) of the code of every device source of the library
-    (the .hip and .hpp files, in name order, comments left out): a committed counter
-    summary applies while it matches."""
+def frame_kernel_sources(root=ROOT):
+    """The frame kernel's translation units (mpbp_frames_<D>.hip) and every header of the
+    library they include, directly or through other headers, in name order."""
+    csrc = os.path.join(root, "paper_2312_14907_amd", "csrc")
+    todo = [f for f in os.listdir(csrc) if re.fullmatch(r"mpbp_frames_\d+\.hip", f)]
+    seen = set()
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(csrc, f)):
+            continue
+        seen.add(f)
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            todo += re.findall(r'#include\s+"([^"]+)"', fh.read())
+    return sorted(seen)
+
+
+def kernel_source_hash(root=ROOT):
+    """sha256 (first 16 hex digits) of the code of the frame kernel's sources
+    (frame_kernel_sources(), comments left out): a committed counter summary of the
+    frame kernel applies while it matches."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2312_14907_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, f), encoding="utf-8") as fh:
-                h.update(f.encode() + b"\0" + code_text(fh.read()).encode())
+    csrc = os.path.join(root, "paper_2312_14907_amd", "csrc")
+    for f in frame_kernel_sources(root):
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(f.encode() + b"\0" + code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
