@@ -323,9 +323,6 @@ mpbp_status map_footprint(const mpbp_peak& k, int m, int np, int nz, int zref, P
     d.mm[i] = (float)M[i];
     d.mi[i] = (float)inv[i];
   }
-  // whole pixels within one sample of a point (per axis, plus one for float rounding)
-  d.ncy = (int)std::floor(2.0 * (std::fabs(M[0]) + std::fabs(M[1]))) + 3;
-  d.ncx = (int)std::floor(2.0 * (std::fabs(M[2]) + std::fabs(M[3]))) + 3;
   for (int z = 0; z < nz; ++z) {
     mapz[2 * z] = (float)(centre + (double)(z - zref) * k.shear[0] - d.r0);
     mapz[2 * z + 1] = (float)(centre + (double)(z - zref) * k.shear[1] - d.c0);
@@ -836,7 +833,7 @@ Work plan_work(mpbp_plan p) { return {p->d_obj, p->d_slots, p->d_gslots, p->d_fl
 
 // Projection and back-projection per run of equal exit-beam offset (one probe for all
 // slices, rounded offsets): the objects are then stored as run sums.
-bool uses_runs(mpbp_plan p) { return p->runs && !p->probe3 && !p->linear && !p->mapped; }
+bool uses_runs(const mpbp_plan_t* p) { return p->runs && !p->probe3 && !p->linear && !p->mapped; }
 
 // The objects of eq. (1)/(3) into the workspace: per slice, or summed over each run.
 hipError_t launch_objects(mpbp_plan p, const Work& w, const float* u, const float* chi, const float* alpha,
@@ -1319,21 +1316,36 @@ static void trace_plan(const mpbp_plan_t* p, const char* when) {
     trace("  peak %d: D %d, footprint %dx%d at (%d, %d), %d runs of equal offset over %d slices, raster %dx%d", m,
           d.D, d.fy, d.fx, d.r0, d.c0, d.nruns, p->nz, d.rows, d.cols);
     if (p->mapped)
-      trace("    detector map [%g %g; %g %g], %dx%d pixels within one sample", d.mm[0], d.mm[1], d.mm[2], d.mm[3],
-            d.ncy, d.ncx);
+      trace("    detector map [%g %g; %g %g]", d.mm[0], d.mm[1], d.mm[2], d.mm[3]);
+  }
+  if (p->mapped && !p->color_off.empty()) {
+    int lo = 1 << 30, hi = 0;
+    for (size_t c = 0; c + 1 < p->color_off.size(); ++c) {
+      lo = std::min(lo, p->color_off[c + 1] - p->color_off[c]);
+      hi = std::max(hi, p->color_off[c + 1] - p->color_off[c]);
+    }
+    trace("  back-projection: %zu colours of non-overlapping frames, %d to %d frames each, %d in all",
+          p->color_off.size() - 1, lo, hi, p->color_off.back());
   }
   for (size_t k = 0; k < p->classes.size(); ++k) {
     const auto& c = p->classes[k];
     trace("  class %zu: D %d, %d frames, footprint bound %d (smallest %d), projection depth %d, xcd order %d%s", k,
           c.D, c.count, c.FB, c.key, c.G, c.xcd, c.tuned_us > 0 ? " (tuned)" : "");
   }
-  trace("  path: %s; objects %s; back-projection %s, batch %d, tile %d; tuning source %s",
-        p->path ? "plain" : "batched fused", (p->runs && !p->probe3 && !p->linear && !p->mapped) ? "summed per run" : "per slice",
-        (p->runs && !p->probe3 && !p->linear && !p->mapped) ? "per run (gather + chain rule)" : "per slice", p->grad_batch,
-        p->grad_tile, p->tune_source.c_str());
+  const bool runs = uses_runs(p);
+  char bp[96];
+  if (p->mapped)
+    snprintf(bp, sizeof(bp), "per colour of frames, then the chain rule per voxel");
+  else
+    snprintf(bp, sizeof(bp), "%s, batch %d, tile %d", runs ? "per run (gather + chain rule)" : "per slice",
+             p->grad_batch, p->grad_tile);
+  trace("  path: %s; objects %s; back-projection %s; tuning source %s", p->path ? "plain" : "batched fused",
+        runs ? "summed per run" : "per slice", bp, p->tune_source.c_str());
+  const int lds_bp = p->mapped ? (p->np * p->np + p->acc_pix) * (int)sizeof(float) * 2 : runs ? p->lds_runs : p->lds_grad;
+  const int W = p->np + 2;   // the detector-map projection's bordered window
+  const int lds_pr = p->mapped ? p->nz * 8 + (p->np * p->np + 2 * W * W) * 8 : p->lds_project[mpbp::kDefaultSlab];
   trace("  LDS bytes: frame kernel %d, projection %d, back-projection %d; projection accumulator %d pixels",
-        p->lds_grad_frame, p->lds_project[mpbp::kDefaultSlab], (p->runs && !p->probe3 && !p->linear && !p->mapped) ? p->lds_runs : p->lds_grad,
-        p->acc_pix);
+        p->lds_grad_frame, lds_pr, lds_bp, p->acc_pix);
   if (p->device >= 0)
     trace("  device workspace: objects %zu B, two footprint slots of %zu B each, %d alpha partials per peak",
           sizeof(float) * 2 * (size_t)p->M * (size_t)p->nvox, sizeof(float) * 2 * (size_t)p->slots_cplx, p->max_parts);

@@ -38,10 +38,8 @@ struct PeakDev {
   int nruns;        // runs of consecutive slices with equal exit-beam offset
   int run_base;     // index of this peak's first run over all peaks
   // MPBP_DETECTOR_MAP: the 2 x 2 map M of probe-window coordinates to exit-wave pixels
-  // (row-major), its inverse, and the extent of the exit-wave pixels that one sample
-  // reaches (ncy x ncx pixels: the image of a 2 x 2 sample square, rounded outwards)
+  // (row-major) and its inverse
   float mm[4], mi[4];
-  int ncy, ncx;
 };
 
 struct FrameArgs {
