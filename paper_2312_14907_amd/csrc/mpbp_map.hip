@@ -7,9 +7,10 @@
 // (zero off the probe support and off the object) at its pre-image, and the slices are
 // summed.
 //   k_project_map  one workgroup per frame: each illuminated slice is staged on the probe
-//                  window in LDS (with a zero border), and each lane sums, over the
-//                  slices, the four taps around its footprint pixels' pre-images (a
-//                  gather: no two lanes write one pixel)
+//                  window in LDS (with a zero border; the next slice's object values load
+//                  while this slice is summed), and each lane sums, over the slices, the
+//                  four taps around its footprint pixels' pre-images (a gather: no two
+//                  lanes write one pixel)
 //   k_bp_map_color the adjoint, per colour of frames (frames of one peak and colour do
 //                  not overlap): one workgroup per frame stages its footprint gradient in
 //                  LDS; for each slice and window point, the footprint pixels whose
@@ -40,6 +41,9 @@ __device__ __forceinline__ float2 preimage(const PeakDev& pk, float2 c, float h,
 // Footprint pixels a lane sums in registers per pass over the slices (a footprint of
 // more than kMapThreads * kMapQ pixels takes several passes).
 constexpr int kMapQ = 16;
+// Probe-window points per lane (probe_n^2 <= kMapThreads * kMapE): the projection stages
+// them, the back-projection sums them.
+constexpr int kMapE = 4;
 
 template <bool P3>
 __global__ __launch_bounds__(kMapThreads) void k_project_map(FrameArgs A) {
@@ -69,6 +73,24 @@ __global__ __launch_bounds__(kMapThreads) void k_project_map(FrameArgs A) {
   if (!P3)
     for (int k = tid; k < np * np; k += kMapThreads) Ps[k] = probe[k];
   for (int k = tid; k < 2 * W * W; k += kMapThreads) ill[k] = {0.f, 0.f};
+  // the lane's window points: their place in a staging buffer (-1: none) and their
+  // object pixel (-1: off the object, staged as zero)
+  int sidx[kMapE];
+  long long goff[kMapE];
+#pragma unroll
+  for (int i = 0; i < kMapE; ++i) {
+    const int e = tid + kMapThreads * i, a = e / np, b = e - (e / np) * np;
+    const int oy = py + a, ox = px + b;
+    sidx[i] = e < np * np ? (a + 1) * W + b + 1 : -1;
+    goff[i] = e < np * np && (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx
+                  ? (long long)oy * A.nx + ox : -1;
+  }
+  cplx ov[kMapE];   // the next slice's object values, in flight during this slice's taps
+  auto fetch = [&](int z) {
+    const cplx* Oz = O + (long long)z * plane;
+#pragma unroll
+    for (int i = 0; i < kMapE; ++i) ov[i] = goff[i] >= 0 ? Oz[goff[i]] : cplx{0.f, 0.f};
+  };
   __syncthreads();
   const float h = 0.5f * (float)np;
   const int npix = fy * fx;
@@ -76,20 +98,17 @@ __global__ __launch_bounds__(kMapThreads) void k_project_map(FrameArgs A) {
     cplx acc[kMapQ];
 #pragma unroll
     for (int i = 0; i < kMapQ; ++i) acc[i] = {0.f, 0.f};
+    fetch(0);
     for (int z = 0; z < nz; ++z) {
       // stage P_z O_z of this frame's window (its interior; the border stays zero).  The
       // other buffer still serves the previous slice: one barrier per slice suffices.
       cplx* buf = ill + (z & 1) * W * W;
-      const cplx* Oz = O + (long long)z * plane;
       const cplx* Pz = P3 ? probe + (long long)z * np * np : Ps;
-      for (int e = tid; e < np * np; e += kMapThreads) {
-        const int a = e / np, b = e - (e / np) * np;
-        const int oy = py + a, ox = px + b;
-        const bool in = (unsigned)oy < (unsigned)A.ny && (unsigned)ox < (unsigned)A.nx;
-        const cplx v = in ? cmul(Pz[e], Oz[(long long)oy * A.nx + ox]) : cplx{0.f, 0.f};
-        buf[(a + 1) * W + b + 1] = v;
-      }
+#pragma unroll
+      for (int i = 0; i < kMapE; ++i)
+        if (sidx[i] >= 0) buf[sidx[i]] = goff[i] >= 0 ? cmul(Pz[tid + kMapThreads * i], ov[i]) : cplx{0.f, 0.f};
       __syncthreads();
+      if (z + 1 < nz) fetch(z + 1);
       const float2 c = cz[z];
 #pragma unroll
       for (int i = 0; i < kMapQ; ++i) {
@@ -122,9 +141,6 @@ __global__ __launch_bounds__(kMapThreads) void k_project_map(FrameArgs A) {
     __syncthreads();   // the next pass restages the slices
   }
 }
-
-// Window points a lane back-projects (probe_n^2 <= kMapThreads * kMapE).
-constexpr int kMapE = 4;
 
 // Footprint pixels q whose pre-image p(q) lies within one sample of window point (a, b):
 // the rows are the image of the 2 x 2 square around (a, b); in each row both tent
