@@ -86,11 +86,12 @@ for maps in ([(1.1, 0.4), (0.85, -1.0), (1.0, np.pi / 2 + 0.2)], [(1.0, 0.0)] * 
     ym = ragged(O.model_intensity(f["u"], f["chi"], f["alpha"], f["probe"], mp)).astype(np.float32)
     refm = O.loss_grad((f["u"] + f["delta"]).astype(np.float32), f["chi"], f["alpha"], f["probe"], ym, mp)
     for name, kw in [("full batch", {}), ("minibatch", dict(frames=list(range(3, 70, 4)))),
-                     ("z-tied", dict(flags=B.MPBP_Z_TIED)), ("3d probe", dict(flags=B.MPBP_PROBE_3D, probe=p3))]:
+                     ("z-tied", dict(flags=B.MPBP_Z_TIED)), ("3d probe", dict(flags=B.MPBP_PROBE_3D, probe=p3)),
+                     ("no-alloc", dict(static=True))]:
         kw = dict(kw, flags=kw.get("flags", 0) | B.MPBP_DETECTOR_MAP)
         loss, gu = run(mp, f, ym, **kw)
         print("c1 detector map", maps[0], name, loss, flush=True)
-        if name == "full batch":
+        if name in ("full batch", "no-alloc"):
             assert abs(loss - refm["loss"]) <= 1e-5 * refm["loss"], (loss, refm["loss"])
             assert np.linalg.norm(gu.reshape(refm["grad_u"].shape) - refm["grad_u"]) <= \
                 1e-3 * np.linalg.norm(refm["grad_u"])
