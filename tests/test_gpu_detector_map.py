@@ -6,8 +6,9 @@ Slice z's probe-window point (a, b) lands on q = M_m ((a, b) - n/2) + centre + (
 and each exit-wave pixel interpolates the illuminated slice bilinearly at its pre-image.
 Checked: loss, per-frame losses, model intensities and gradients on c1 with a different
 map per peak (turns, magnifications and a reduction); the z-tied parameterisation; 3D
-illumination volumes with a background; a c2 minibatch; identity maps against the
-interpolated-offset model (MPBP_SHEAR_LINEAR) on the GPU; the plain path's refusal.
+illumination volumes with a background; c2 minibatches; a c5 minibatch (the full
+geometry); identity maps against the interpolated-offset model (MPBP_SHEAR_LINEAR) on the
+GPU; the plain path's refusal.
 Tolerances as in the other parity tests.
 """
 import dataclasses
@@ -144,3 +145,35 @@ def test_c2_minibatch_detector_map_z_tied():
     frames = np.random.default_rng(133).choice(prob.n_frames(), 40, replace=False)
     got = gpu_loss_grad(plan, u2, chi2, f["alpha"], f["probe"], y, frames=frames)
     _check(got, O.loss_grad_ztied(u2, chi2, f["alpha"], f["probe"], y, prob, frames=frames))
+
+
+def test_c5_minibatch_detector_map_sampled():
+    """The detector map at the full c5 geometry (32 x 512 x 512 voxels, 256 x 256 windows,
+    16 colours of frames, mapped footprints up to 62 x 62): a minibatch of 4 frames per
+    peak, spread over each raster, against the oracle on the same frames.  The counts are
+    the oracle's model intensities at the true fields on those frames (zero elsewhere:
+    no listed frame reads them)."""
+    cfg = get_config("c5_full")
+    base = make_problem(cfg)
+    prob = dataclasses.replace(base, lateral_map=np.stack([detector_map(r, a) for r, a in C2_MAPS]))
+    f = make_fields(cfg, base)
+    tab = O.tables(prob)
+    rng = np.random.default_rng(134)
+    frames, start = [], 0
+    for m in range(prob.n_peaks):
+        nfr = int(prob.scan_n[m][0]) * int(prob.scan_n[m][1])
+        frames += [start + int(j) for j in rng.choice(nfr, 4, replace=False)]
+        start += nfr
+    frames = sorted(frames)
+    say("detector map c5 minibatch (oracle on 12 frames)")
+    y = np.zeros(int(tab["y_off"][-1]), dtype=np.float32)
+    for fid, inten in zip(frames, O.model_intensity(f["u"], f["chi"], f["alpha"], f["probe"], prob, frames=frames)):
+        m, j = int(tab["peak_of_frame"][fid]), int(tab["local_index"][fid])
+        d2 = int(prob.det[m]) ** 2
+        y[int(tab["y_off"][m]) + j * d2:int(tab["y_off"][m]) + (j + 1) * d2] = inten.ravel()
+    u = (f["u"] + f["delta"]).astype(np.float32)
+    plan = B.Plan(prob, 0, flags=B.MPBP_DETECTOR_MAP)
+    got = gpu_loss_grad(plan, u, f["chi"], f["alpha"], f["probe"], y, frames=frames)
+    ref = O.loss_grad(u, f["chi"], f["alpha"], f["probe"], y, prob, frames=frames)
+    _check(got, ref)
+    assert np.allclose(got["frame_loss"], ref["frame_loss"], rtol=1e-4, atol=0)
