@@ -6,6 +6,7 @@ positions) of the workload, inputs resident in HBM.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5_full]
                     [--no-cpu-baseline] [--no-plain] [--no-extras]
     python bench.py --loop 200     # the full-batch descent loop from u = 0 (loss curve)
+    python bench.py --options-only # the forward-model options alone (profiling their kernels)
 """
 import argparse
 import hashlib
@@ -34,7 +35,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-plain", action="store_true")
     p.add_argument("--no-extras", action="store_true",
-                   help="skip the unwrap projector and paper-shaped workload timings (profiling runs)")
+                   help="skip the unwrap projector, paper-shaped workload and option timings (profiling runs)")
+    p.add_argument("--options-only", action="store_true",
+                   help="instead of the step benchmark: only the forward-model option timings of the "
+                        "workload (one JSON line; profiling runs of the option kernels)")
     p.add_argument("--no-autotune", action="store_true", help="keep the default launch parameters")
     p.add_argument("--loop", type=int, default=0,
                    help="instead of the step benchmark: this many iterations of full-batch gradient "
@@ -355,6 +359,70 @@ def time_paper_shape(torch, name="c6_paper", steps=20):
             "launch": [{k: c[k] for k in ("fy", "fx", "FB", "G", "xcd")} for c in t["classes"]]}
 
 
+# Per peak: (ratio of voxel pitch to exit-wave pixel pitch, detector-frame angle in rad)
+# of the detector maps timed in the option extras.
+OPTION_MAPS = [(1.2, 0.4), (0.9, 2.5), (1.05, -0.7)]
+
+
+def time_options(torch, name, steps=10):
+    """The forward-model options on workload `name` (not part of `value`): interpolated
+    exit-beam offsets, 3D illumination volumes, detector maps, the z-tied
+    parameterisation and the background, each autotuned and timed over `steps`
+    loss+gradient steps with every stage timed (HIP events per stage).  Counts are
+    Poisson draws of the library's own model intensities at the true fields of each
+    option's model."""
+    import dataclasses
+    import numpy as np
+    from paper_2312_14907_amd import binding as B
+    from synth import get_config, incident_probe_3d, make_fields, make_problem
+    from synth.inputs import detector_map
+    cfg = get_config(name)
+    base = make_problem(cfg)
+    f = make_fields(cfg, base)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    rng = np.random.default_rng(cfg["seed"] + 1)
+    p3 = np.stack([incident_probe_3d(f["probe"][m], base.nz, rng.uniform(-0.4, 0.4, 2))
+                   for m in range(base.n_peaks)]).astype(np.complex64)
+    u_t, u_e = f["u"], (f["u"] + f["delta"]).astype(np.float32)
+    chi2 = np.full((1, base.ny, base.nx), float(f["chi"].max()), dtype=np.float32)
+    cases = [
+        ("interpolated_offsets", dataclasses.replace(base, shear_linear=True), B.MPBP_SHEAR_LINEAR, f["probe"],
+         u_t, u_e, f["chi"], False),
+        ("probe_3d", base, B.MPBP_PROBE_3D, p3, u_t, u_e, f["chi"], False),
+        ("detector_map", dataclasses.replace(base, lateral_map=np.stack([detector_map(r, a) for r, a in OPTION_MAPS])),
+         B.MPBP_DETECTOR_MAP, f["probe"], u_t, u_e, f["chi"], False),
+        ("z_tied", base, B.MPBP_Z_TIED, f["probe"], np.ascontiguousarray(u_t[:, :1]),
+         np.ascontiguousarray(u_e[:, :1]), chi2, False),
+        ("background", base, 0, f["probe"], u_t, u_e, f["chi"], True),
+    ]
+    out = {}
+    for key, prob, flags, probe, ut, ue, chi, with_bg in cases:
+        plan = B.Plan(prob, 0, flags=flags)
+        dchi, alpha, dprobe = d(chi), d(f["alpha"]), d(probe)
+        if with_bg:
+            g = torch.Generator(device="cuda:0")
+            g.manual_seed(cfg["seed"] + 2)
+            bg = 0.5 * torch.rand(plan.intensity_size, generator=g, device="cuda:0")
+            plan.mpbp_set_background(bg)
+        inten = torch.zeros(plan.intensity_size, dtype=torch.float32, device="cuda:0")
+        plan.mpbp_forward(d(ut), dchi, alpha, dprobe, model_intensity=inten)
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(cfg["seed"])
+        y = torch.poisson(inten, generator=g)
+        del inten
+        args_t = (d(ue), dchi, alpha, dprobe, y)
+        plan.mpbp_autotune(*args_t)
+        plan.mpbp_set_option(B.MPBP_OPT_PROFILE, 1)
+        dt, st, _ = time_steps(plan, args_t, steps, 3, torch)
+        plan.close()
+        del y, args_t
+        out[key] = {"ms_per_step": round(1e3 * dt / steps, 4),
+                    "stages_ms_per_step": {k: round(v[0] / steps, 4) for k, v in st.items() if v[1]}}
+    out["note"] = (f"{name}, every stage timed (its events add a few percent); detector maps per peak "
+                   f"(pixel ratio, angle in rad): {OPTION_MAPS}")
+    return out
+
+
 def cpu_unwrap(prob):
     """The unwrap oracle on the z-tied maps of the workload (one per peak), seconds."""
     from threadpoolctl import threadpool_limits
@@ -435,6 +503,10 @@ def main():
 
     if args.loop > 0:
         run_loop(args, torch)
+        return
+    if args.options_only:
+        print(json.dumps({"workload": args.workload, "options": time_options(torch, args.workload, args.steps)}),
+              flush=True)
         return
 
     cfg, prob, f, plan, args_t = make_inputs(args.workload, torch)
@@ -541,6 +613,7 @@ def main():
         out["unwrap"] = time_unwrap(prob, torch, 10)
         out["paper_shape"] = time_paper_shape(torch)
         out["paper_shape_100_slices"] = time_paper_shape(torch, "c6_paper100")
+        out["options"] = time_options(torch, args.workload)
 
     if not args.no_cpu_baseline:
         rate, sample, acc = cpu_baseline(args.workload, plan, args_t, torch)
