@@ -6,12 +6,16 @@ graph branches.  The kernels and their arguments are those of the direct launche
 the path has no atomics, so every replay must match the direct launches bit for bit.
 Each check replays several times, with the program's own device work and
 synchronisations between replays, and with the inputs rewritten in place between
-replays (a replay must read the buffers' current contents).
+replays (a replay must read the buffers' current contents).  Also with detector maps
+(one back-projection launch per colour of frames in the graph) and interpolated offsets.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
 from synth import get_config, make_fields, make_problem
+from synth.inputs import detector_map
 from tests.gpu_util import dev, say, speckle_y
 
 pytestmark = pytest.mark.gpu
@@ -22,11 +26,19 @@ if not torch.cuda.is_available():
 B = pytest.importorskip("paper_2312_14907_amd.binding")
 
 
-def _setup(name):
+def _setup(name, option=None):
     cfg = get_config(name)
     prob = make_problem(cfg)
     f = make_fields(cfg, prob)
-    plan = B.Plan(prob, 0)
+    flags = 0
+    if option == "detector_map":       # a turned and scaled detector frame per peak
+        prob = dataclasses.replace(prob, lateral_map=np.stack(
+            [detector_map(r, a) for r, a in [(1.2, 0.4), (0.9, 2.5), (1.05, -0.7)]][:prob.n_peaks]))
+        flags = B.MPBP_DETECTOR_MAP
+    elif option == "interpolated_offsets":
+        prob = dataclasses.replace(prob, shear_linear=True)
+        flags = B.MPBP_SHEAR_LINEAR
+    plan = B.Plan(prob, 0, flags=flags)
     y = speckle_y(prob, cfg["seed"])
     ua = dev((f["u"] + f["delta"]).astype(np.float32))
     ub = dev((f["u"] - 0.5 * f["delta"]).astype(np.float32))
@@ -52,10 +64,11 @@ def _same(a, b, what):
         assert torch.equal(x, y), f"{what}: output {i} differs (max {(x - y).abs().max().item():.3e})"
 
 
-@pytest.mark.parametrize("name", ["c1_tiny", "c4_batch"])
-def test_loss_grad_replays_match_direct(name):
-    say(f"graph replay vs direct launches, loss_grad, {name}")
-    plan, prob, f, y, ua, ub = _setup(name)
+@pytest.mark.parametrize("name, option", [("c1_tiny", None), ("c4_batch", None), ("c2_forward", "detector_map"),
+                                          ("c2_forward", "interpolated_offsets")])
+def test_loss_grad_replays_match_direct(name, option):
+    say(f"graph replay vs direct launches, loss_grad, {name} {option or ''}")
+    plan, prob, f, y, ua, ub = _setup(name, option)
     chi, alpha, probe = dev(f["chi"]), dev(f["alpha"]), dev(f["probe"])
     u = ua.clone()
     out = _outputs(plan, u)
